@@ -1,0 +1,210 @@
+"""Benchmark of the CVA / PCA page-enhancement hot path on one MI355X.
+
+Workload: a synthetic 7216 x 5412 x 33-band uint16 page (2.58 GB, resident
+in HBM before timing), 8 classes with 200,000 training pixels each.  One
+step is one pass of the whole hot path over that page:
+
+  CVA fit (labels -> counts, class moments, S_w, S_b, FP64 eigensolve)
+  CVA project (7 canonical variates, min-max stretch to 8 bits)
+  PCA fit (whole-page covariance) and PCA project (3 components)
+  soft-label CVA forward + backward on the 1.6M training pixels
+
+The headline value is CVA fit + project throughput in Gpix*band/s
+(page pixels x bands / (t_fit + t_project)); ms_per_step is the whole step.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(case, rows: int):
+    """The FP64 oracle, as it stands, on the first `rows` rows of the page:
+    CVA fit on the training pixels inside those rows and projection +
+    stretch of those rows.  Returns (Gpix*band/s, seconds, threads, sample)."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    cube = case.cube[:rows]
+    labels = case.labels[:rows]
+    t0 = time.perf_counter()
+    fit = oracle.cva_fit(cube, labels, case.K)
+    oracle.cva_project(cube, fit["W"], fit["mean"])
+    dt = time.perf_counter() - t0
+    pixbands = rows * case.W * case.B
+    sample = (f"first {rows} of {case.H} rows ({rows * case.W} pixels, "
+              f"{int((labels >= 0).sum())} training pixels): CVA fit + project + stretch")
+    return pixbands / dt / 1e9, dt, threads, sample
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "f16x3"])
+    ap.add_argument("--cpu-rows", type=int, default=1024)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no multi-GPU "
+              "launch: pages are independent, so several GPUs run several pages.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1612_06457_amd as cx
+    from synth import make_case, soft_weights, border_map
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    case = make_case(5, threads=16)
+    log(f"page generated in {time.time() - t0:.1f}s: {case.H}x{case.W}x{case.B} u16, K={case.K}")
+    H, W, B, K = case.H, case.W, case.B, case.K
+    P = H * W
+    cube = torch.from_numpy(case.cube).to(dev)
+    labels = torch.from_numpy(case.labels).to(dev)
+    # soft-label inputs: the training pixels, gathered once (outside the timed region)
+    flat = case.labels.reshape(-1)
+    idx = np.flatnonzero(flat >= 0)
+    cls = flat[idx].astype(np.int64)
+    rng = np.random.default_rng([case.seed, 0x50F7])
+    nb = border_map(case.class_map)[np.unravel_index(idx, case.labels.shape)]
+    wts = soft_weights(cls, nb, K, rng)
+    X = cube.view(-1, B)[torch.from_numpy(idx).to(dev)].float().contiguous()
+    w = torch.from_numpy(wts).to(dev)
+    N = X.shape[0]
+    C = K - 1
+    img = torch.empty((C, H, W), dtype=torch.uint8, device=dev)
+    pimg = torch.empty((3, H, W), dtype=torch.uint8, device=dev)
+    dw = torch.empty((N, K), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+
+    phases = ["cva_fit", "cva_project", "pca_fit", "pca_project", "soft_fwd", "soft_bwd"]
+
+    def step(ev=None):
+        def mark(i):
+            if ev is not None:
+                ev[i].record()
+        mark(0)
+        fit = cx.cva_fit(cube, labels, K, precision=args.precision)
+        mark(1)
+        cx.cva_project(cube, fit.W, fit.mean, out=img)
+        mark(2)
+        V, lam, mean, _ = cx.pca_fit(cube, n_comp=3, precision=args.precision)
+        mark(3)
+        cx.pca_project(cube, V, mean, out=pimg)
+        mark(4)
+        sf = cx.cva_soft_forward(X, w, precision=args.precision)
+        mark(5)
+        cx.cva_soft_backward(X, sf, 1.0, K, out=dw)
+        mark(6)
+        return fit
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    cx.profile_enable(True)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = cx.profile_report()
+    cx.profile_enable(False)
+
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    per = {p: float(np.median([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)]))
+           for i, p in enumerate(phases)}
+    mean_fp = float(np.mean([evs[k][0].elapsed_time(evs[k][2]) for k in range(args.steps)]))
+    value = P * B / (mean_fp * 1e-3) / 1e9
+
+    # roofline of the dominant kernel (the projection pass that writes the
+    # images): algorithmic bytes = page read once + the planar bytes written
+    cube_bytes = P * B * 2
+    n_str, ms_str = prof.get("project_stretch", (0, 0.0))
+    n_rng, ms_rng = prof.get("project_range", (0, 0.0))
+    # per launch: CVA launches write 7 planes, PCA launches 3; average over both
+    str_bytes = (cube_bytes + P * C + cube_bytes + P * 3) / 2.0
+    avg_str = ms_str / max(n_str, 1)
+    achieved = str_bytes / (avg_str * 1e-3) / 1e9
+    avg_rng = ms_rng / max(n_rng, 1)
+    fit_proj_bytes = 2 * cube_bytes + P * C + (labels.numel() + N * B * 2)
+    roof = {
+        "kernel": "k_project_stretch",
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "avg_launch_ms": round(avg_str, 4),
+        "range_pass": {"avg_launch_ms": round(avg_rng, 4),
+                       "achieved_GBps": round(cube_bytes / (avg_rng * 1e-3) / 1e9, 1)},
+        "fit_plus_project": {"algorithmic_MB": round(fit_proj_bytes / 1e6, 1),
+                             "ms": round(mean_fp, 4),
+                             "frac_of_8TBps": round(fit_proj_bytes / (mean_fp * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+    }
+    traffic_file = os.path.join(ROOT, "profiles", "traffic_project_stretch.json")
+    if os.path.exists(traffic_file):
+        try:
+            tr = json.load(open(traffic_file))
+            import hashlib
+            src = open(os.path.join(ROOT, "paper_1612_06457_amd", "csrc", "k_project.hip"), "rb").read()
+            if tr.get("source_sha1") == hashlib.sha1(src).hexdigest():
+                roof["traffic"] = tr.get("bytes_per_launch")
+        except Exception:
+            pass
+
+    out = {
+        "metric": "CVA fit+project Gpix*band/s (7216x5412x33 u16 page, K=8)",
+        "value": round(value, 2),
+        "unit": "Gpix*band/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16 in, f32 accumulate (" + args.precision + " scatter), f64 solve",
+        "data": "synthetic",
+        "config": {"workload": "cva_pca_page_7216x5412x33_u16_k8", "H": H, "W": W, "B": B, "K": K,
+                   "train_pixels": int(N), "cva_components": C, "pca_components": 3,
+                   "precision": args.precision},
+        "phases_ms": {k: round(v, 4) for k, v in per.items()},
+        "soft_fwd_bwd_ms": round(per["soft_fwd"] + per["soft_bwd"], 4),
+        "kernels_ms_per_launch": {k: round(v[1] / max(v[0], 1), 4) for k, v in prof.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        gbs, dt, threads, sample = cpu_baseline(case, args.cpu_rows)
+        out["cpu_baseline"] = {"value": round(gbs, 4), "unit": "Gpix*band/s", "cores": threads,
+                               "kind": "oracle", "sample": sample, "seconds": round(dt, 2)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,206 @@
+/*
+ * cvamx: canonical variates analysis (CVA) and PCA enhancement of
+ * multispectral page images on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Every entry point takes plain pointers and sizes; "device" means
+ * memory allocated on the context's GPU (hipMalloc, or a torch CUDA/HIP
+ * tensor), "host" means ordinary CPU memory.  The caller owns every buffer;
+ * the library never frees caller memory.  Scratch space lives in the
+ * context.  All functions return CVAMX_OK (0) or a negative CVAMX_E_* code;
+ * on error no host output is written and cvamx_last_error() describes the
+ * failure.  A context is not thread safe; use one per host thread/stream.
+ *
+ * Method (paper: Section 2, canonical variates paragraph; Section 4, the
+ * GSL implementation with a generalized symmetric-definite eigensolver;
+ * Section 2, regression coefficients multiplied with every band of the
+ * page and the rescale to 0..255):
+ *   n_k = #{p : label_p = k},  m_k = mean of class k,  m = mean of all
+ *   training pixels,  S_w = sum_k sum_{p in k} (x_p - m_k)(x_p - m_k)^T,
+ *   S_b = sum_k n_k (m_k - m)(m_k - m)^T,
+ *   S_b w = lambda (S_w + ridge I) w,  w^T (S_w + ridge I) w = 1,
+ *   lambda descending, C = min(K-1, B) components, the largest-magnitude
+ *   entry of each w positive (ties: lowest band),
+ *   y_jp = w_j^T (x_p - m),  q_jp = clamp(floor(255 (y_jp - a_j) /
+ *   (b_j - a_j) + 1/2), 0, 255) with a_j, b_j the page-wide min and max.
+ * Scatter, not covariance: no division by degrees of freedom.
+ *
+ * Layouts.  A page ("cube") is band-interleaved by pixel (BIP): element
+ * (y, x, b) sits at offset (y * width + x) * bands + b; its base address
+ * must be 16-byte aligned.  Label maps are int8 height x width, -1 = not a
+ * training pixel, 0..K-1 = class.  Matrices are row-major float64:
+ * W is bands x n_comp (W[b * n_comp + j]), S_w and S_b are bands x bands,
+ * class means K x bands.  Output images are planar uint8
+ * n_comp x height x width.
+ */
+#ifndef CVAMX_H
+#define CVAMX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define CVAMX_OK             0
+#define CVAMX_E_INVALID_ARG (-1) /* null pointer, bad size, K < 2, n_comp out of range, label outside -1..K-1 */
+#define CVAMX_E_UNSUPPORTED (-2) /* dtype/precision not supported, bands > CVAMX_MAX_BANDS, misaligned cube */
+#define CVAMX_E_EMPTY_CLASS (-3) /* some class has no training pixel (or zero total weight) */
+#define CVAMX_E_NOT_PD      (-4) /* S_w (+ ridge I) is not positive definite: Cholesky failed */
+#define CVAMX_E_DEVICE      (-5) /* HIP runtime error, or a context without a device */
+#define CVAMX_E_NO_MEMORY   (-6) /* device or pinned host allocation failed */
+#define CVAMX_E_NUMERIC     (-7) /* eigensolver did not converge */
+
+#define CVAMX_MAX_BANDS   64
+#define CVAMX_MAX_CLASSES 127
+
+/* ---- element types and precisions -------------------------------------- */
+typedef enum {
+  CVAMX_U16 = 0,   /* unsigned 16-bit detector counts */
+  CVAMX_F32 = 1,
+  CVAMX_BF16 = 2,
+  CVAMX_F16 = 3
+} cvamx_dtype;
+
+typedef enum {
+  CVAMX_PREC_FP32 = 0,    /* plain FP32 products and sums, FP64 combine */
+  CVAMX_PREC_BF16X3 = 1,  /* MFMA, values split hi+lo in bf16, hi*hi + hi*lo + lo*hi (+ lo*lo for integer pages), FP32 accumulate, FP64 combine */
+  CVAMX_PREC_F16X3 = 2    /* same with an fp16 split */
+} cvamx_prec;
+
+typedef struct cvamx_ctx cvamx_ctx;
+
+/* A page resident in device memory. */
+typedef struct {
+  const void* data;   /* device, height*width*bands elements, BIP, 16-byte aligned */
+  int64_t height;
+  int64_t width;
+  int64_t bands;      /* 1..CVAMX_MAX_BANDS */
+  int32_t dtype;      /* cvamx_dtype */
+} cvamx_cube;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` (>= 0).  device = -1 makes a
+ * context without a GPU: argument checking and the host-only calls work,
+ * every compute call returns CVAMX_E_DEVICE.  *out receives the context. */
+int cvamx_create(cvamx_ctx** out, int device);
+void cvamx_destroy(cvamx_ctx* ctx);
+const char* cvamx_status_str(int status);
+const char* cvamx_last_error(const cvamx_ctx* ctx);   /* never NULL */
+
+/* ---- CVA ---------------------------------------------------------------- */
+
+/* Fit CVA on the training pixels of a page (paper Section 2, canonical
+ * variates paragraph; Section 4, generalized symmetric-definite solve).
+ *   labels   device, height*width int8 (-1 or 0..K-1)
+ *   K        number of classes, 2..CVAMX_MAX_CLASSES
+ *   prec     cvamx_prec for the scatter accumulation
+ *   ridge    >= 0, added to the diagonal of S_w before the solve
+ *   n_comp   1..min(K-1, bands)
+ * Host outputs (row-major float64): W bands x n_comp, eigvals n_comp,
+ * mean bands (the grand mean, used to centre projections), counts K
+ * (int64, exact).  Optional (may be NULL): class_means K x bands,
+ * Sw and Sb bands x bands.
+ * Runs on `stream` (a hipStream_t, NULL = default stream) and synchronises
+ * it before returning (the outputs are host memory). */
+int cva_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels,
+            int32_t K, int32_t prec, double ridge, int32_t n_comp,
+            double* W, double* eigvals, double* mean, int64_t* counts,
+            double* class_means, double* Sw, double* Sb, void* stream);
+
+/* Project every pixel onto n_comp vectors and stretch each component to
+ * 8 bits by its page-wide min and max (paper Section 2, regression
+ * coefficients multiplied with the whole page; first rescale mode).
+ *   W        host, bands x n_comp row-major float64 (from cva_fit / pca_fit)
+ *   center   host, bands float64 (the mean returned by the fit)
+ *   n_comp   1..CVAMX_MAX_BANDS
+ *   images   device, n_comp x height x width uint8 (planar)
+ *   range    host, 2*n_comp float (min_j, max_j pairs) or NULL
+ * Asynchronous on `stream` unless `range` is non-NULL (then it
+ * synchronises).  W and center are read before the call returns. */
+int cva_project(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W,
+                const double* center, int32_t n_comp, uint8_t* images,
+                float* range, void* stream);
+
+/* ---- PCA ---------------------------------------------------------------- */
+
+/* Covariance PCA of the page (paper Section 2, PCA paragraph: centre,
+ * covariance, eigenvectors; unsupervised whole-page variant).
+ *   mask     device, height*width uint8 (non-zero = use pixel) or NULL for
+ *            every pixel
+ * Host outputs: V bands x n_comp, eigvals n_comp (covariance eigenvalues,
+ * divisor P-1, descending), mean bands; cov bands x bands or NULL.
+ * Synchronises `stream`. */
+int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask,
+            int32_t n_comp, int32_t prec, double* V, double* eigvals,
+            double* mean, double* cov, void* stream);
+
+/* Same as cva_project with (V, mean) from pca_fit. */
+int pca_project(cvamx_ctx* ctx, const cvamx_cube* cube, const double* V,
+                const double* mean, int32_t n_comp, uint8_t* images,
+                float* range, void* stream);
+
+/* ---- soft-label CVA ------------------------------------------------------ */
+
+/* Fisher criterion J = sum of the C = min(K-1, B) generalized eigenvalues
+ * of the weighted problem, with real per-pixel class weights w_pc
+ * (n_c = sum_p w_pc, m_c, m and the scatters weighted accordingly).  Not in
+ * the paper: it reduces to the paper's CVA for one-hot weights.
+ *   X        device, N x B float32 (row-major)
+ *   w        device, N x K float32 (row-major)
+ * Host outputs: J; W B x C, eigvals C, mean B, class_means K x B (all
+ * float64; keep them for cva_soft_backward).  Synchronises `stream`. */
+int cva_soft_forward(cvamx_ctx* ctx, const float* X, const float* w,
+                     int64_t N, int32_t B, int32_t K, int32_t prec,
+                     double ridge, double* J, double* W, double* eigvals,
+                     double* mean, double* class_means, void* stream);
+
+/* Gradient of J with respect to the weights, scaled by dJ:
+ *   dw_pc = dJ * sum_{k<C} [ (w_k^T (x_p - m))^2
+ *                            - (1 + lambda_k) (w_k^T (x_p - m_c))^2 ]
+ * (the terms for the null-space directions of S_b cancel).
+ *   W, eigvals, mean, class_means   host, from cva_soft_forward
+ *   dw       device, N x K float32
+ * Asynchronous on `stream`. */
+int cva_soft_backward(cvamx_ctx* ctx, const float* X, const double* W,
+                      const double* eigvals, const double* mean,
+                      const double* class_means, int64_t N, int32_t B,
+                      int32_t K, double dJ, float* dw, void* stream);
+
+/* ---- kernel timing ------------------------------------------------------ */
+
+/* Enable (1) or disable (0) per-kernel timing on this context: every kernel
+ * the library launches is bracketed by a pair of HIP events on the caller's
+ * stream.  Enabling clears the accumulated totals.  Costs two event records
+ * per launch while enabled. */
+int cvamx_profile_enable(cvamx_ctx* ctx, int enable);
+
+/* Wait for the timed kernels and write one text line per kernel name,
+ * "name launches total_ms\n", into buf (NUL terminated, truncated to len).
+ * Returns the length needed including the NUL, or a negative status. */
+int64_t cvamx_profile_report(cvamx_ctx* ctx, char* buf, int64_t len);
+
+/* ---- host-only FP64 finishers (no GPU needed) ---------------------------- */
+
+/* The CVA solve from class moments: S_b from counts and class means,
+ * Cholesky of S_w + ridge I, generalized symmetric-definite eigenproblem,
+ * descending order, sign rule (paper Section 4, generalized
+ * symmetric-definite eigensolver).  counts K, class_means K x B, Sw B x B
+ * (host).  Outputs W B x n_comp, eigvals n_comp, mean B (may be NULL). */
+int cva_solve_moments(const int64_t* counts, const double* class_means,
+                      const double* Sw, int32_t K, int32_t B, double ridge,
+                      int32_t n_comp, double* W, double* eigvals, double* mean);
+
+/* Full symmetric eigendecomposition of an n x n row-major matrix A (host,
+ * only its lower triangle is read): eigenvalues descending into w[n],
+ * orthonormal eigenvectors as the columns of V (n x n row-major), sign rule
+ * applied.  Householder tridiagonalisation then implicit QR steps with a
+ * Wilkinson shift. */
+int cvamx_sym_eig(int32_t n, const double* A, double* w, double* V);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CVAMX_H */

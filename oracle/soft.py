@@ -86,16 +86,17 @@ def soft_grad(X, w, chunk: int = 1 << 18):
     return g
 
 
-def soft_delta_J(X, w, p: int, c: int, h: float) -> float:
+def soft_delta_J(X, w, p: int, c: int, h: float, moments=None) -> float:
     """Exact change of J = trace(S_w^-1 S_b) when w_pc becomes w_pc + h.
 
     Uses the weighted rank-one moment updates
       S_w' = S_w + a u u^T,  a = n_c h / (n_c + h),  u = x_p - m_c,
       S_t' = S_t + b v v^T,  b = N h / (N + h),      v = x_p - m,
     with J = trace(S_w^-1 S_t) - B and Sherman-Morrison for S_w'^-1, so the
-    O(h) change is formed without subtracting two large traces."""
+    O(h) change is formed without subtracting two large traces.  `moments`
+    may carry soft_moments(X, w) to avoid recomputing them."""
     X = np.asarray(X, dtype=np.float64)
-    n, mc, m, Sw, Sb = soft_moments(X, w)
+    n, mc, m, Sw, Sb = soft_moments(X, w) if moments is None else moments
     St = Sw + Sb
     N = n.sum()
     A = np.linalg.inv(Sw)

@@ -1,0 +1,271 @@
+"""Python binding of the cvamx C ABI: torch tensors in, argument marshalling
+only.  Every step of the computation runs in the HIP library; this module
+checks shapes and devices, passes pointers and the current torch stream,
+and wraps host outputs as NumPy float64 arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import Cube, check, context, lib
+
+_DTYPES = {torch.uint16: _lib.DT_U16, torch.float32: _lib.DT_F32,
+           torch.bfloat16: _lib.DT_BF16, torch.float16: _lib.DT_F16}
+
+
+def _ptr(a) -> ctypes.c_void_p:
+    if a is None:
+        return ctypes.c_void_p(0)
+    if isinstance(a, np.ndarray):
+        return ctypes.c_void_p(a.ctypes.data)
+    return ctypes.c_void_p(a.data_ptr())
+
+
+def _stream(dev: torch.device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _dev_index(t: torch.Tensor) -> int:
+    if t.device.type != "cuda":
+        raise ValueError("tensor must be on a HIP (cuda) device")
+    return t.device.index if t.device.index is not None else torch.cuda.current_device()
+
+
+def _cube(cube: torch.Tensor) -> Cube:
+    if cube.dim() != 3:
+        raise ValueError("cube must be H x W x B (band-interleaved by pixel)")
+    if not cube.is_contiguous():
+        raise ValueError("cube must be contiguous")
+    if cube.dtype not in _DTYPES:
+        raise ValueError(f"unsupported cube dtype {cube.dtype}")
+    H, W, B = cube.shape
+    return Cube(cube.data_ptr(), H, W, B, _DTYPES[cube.dtype])
+
+
+def _f64(a, n=None) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if n is not None and a.size != n:
+        raise ValueError("wrong size")
+    return a
+
+
+@dataclass
+class CvaFit:
+    W: np.ndarray            # B x n_comp
+    eigvals: np.ndarray      # n_comp
+    mean: np.ndarray         # B
+    counts: np.ndarray       # K (int64)
+    class_means: np.ndarray  # K x B
+    Sw: np.ndarray           # B x B
+    Sb: np.ndarray           # B x B
+
+
+def cva_fit(cube: torch.Tensor, labels: torch.Tensor, K: int, precision: str = "fp32",
+            ridge: float = 0.0, n_comp: Optional[int] = None) -> CvaFit:
+    """CVA fit on the labelled pixels (labels: int8 H x W, -1 = none)."""
+    c = _cube(cube)
+    if labels.dtype != torch.int8 or tuple(labels.shape) != tuple(cube.shape[:2]):
+        raise ValueError("labels must be int8 with the page's H x W shape")
+    if labels.device != cube.device or not labels.is_contiguous():
+        raise ValueError("labels must be contiguous and on the cube's device")
+    B = c.bands
+    C = min(K - 1, B)
+    n_comp = C if n_comp is None else int(n_comp)
+    W = np.empty((B, n_comp))
+    lam = np.empty(n_comp)
+    mean = np.empty(B)
+    counts = np.empty(K, dtype=np.int64)
+    cm = np.empty((K, B))
+    Sw = np.empty((B, B))
+    Sb = np.empty((B, B))
+    dev = _dev_index(cube)
+    ctx = context(dev)
+    st = lib().cva_fit(ctx, ctypes.byref(c), _ptr(labels), K, _lib.PREC[precision], float(ridge),
+                       n_comp, _ptr(W), _ptr(lam), _ptr(mean), _ptr(counts), _ptr(cm), _ptr(Sw),
+                       _ptr(Sb), _stream(cube.device))
+    check(st, ctx)
+    return CvaFit(W, lam, mean, counts, cm, Sw, Sb)
+
+
+def cva_project(cube: torch.Tensor, W, center, out: Optional[torch.Tensor] = None,
+                return_range: bool = False):
+    """Project every pixel on the columns of W (B x n) about `center` and
+    stretch each component to uint8 by its page-wide min/max.  Returns an
+    n x H x W uint8 tensor (and the n x 2 float32 (min, max) when asked)."""
+    c = _cube(cube)
+    B = c.bands
+    W = _f64(W)
+    if W.ndim != 2 or W.shape[0] != B:
+        raise ValueError("W must be B x n")
+    n = W.shape[1]
+    center = _f64(center, B)
+    H, Wd = cube.shape[0], cube.shape[1]
+    if out is None:
+        out = torch.empty((n, H, Wd), dtype=torch.uint8, device=cube.device)
+    elif out.dtype != torch.uint8 or tuple(out.shape) != (n, H, Wd) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous uint8 n x H x W tensor")
+    rng = np.empty((n, 2), dtype=np.float32) if return_range else None
+    dev = _dev_index(cube)
+    ctx = context(dev)
+    st = lib().cva_project(ctx, ctypes.byref(c), _ptr(W), _ptr(center), n, _ptr(out), _ptr(rng),
+                           _stream(cube.device))
+    check(st, ctx)
+    return (out, rng) if return_range else out
+
+
+def pca_fit(cube: torch.Tensor, mask: Optional[torch.Tensor] = None, n_comp: int = 3,
+            precision: str = "fp32"):
+    """Covariance PCA of the page (or of the pixels where mask != 0).
+    Returns (V B x n, eigvals n, mean B, cov B x B)."""
+    c = _cube(cube)
+    B = c.bands
+    if mask is not None:
+        if mask.dtype != torch.uint8 or tuple(mask.shape) != tuple(cube.shape[:2]):
+            raise ValueError("mask must be uint8 with the page's H x W shape")
+        if mask.device != cube.device or not mask.is_contiguous():
+            raise ValueError("mask must be contiguous and on the cube's device")
+    V = np.empty((B, n_comp))
+    lam = np.empty(n_comp)
+    mean = np.empty(B)
+    cov = np.empty((B, B))
+    dev = _dev_index(cube)
+    ctx = context(dev)
+    st = lib().pca_fit(ctx, ctypes.byref(c), _ptr(mask), n_comp, _lib.PREC[precision], _ptr(V),
+                       _ptr(lam), _ptr(mean), _ptr(cov), _stream(cube.device))
+    check(st, ctx)
+    return V, lam, mean, cov
+
+
+def pca_project(cube: torch.Tensor, V, mean, out=None, return_range: bool = False):
+    return cva_project(cube, V, mean, out=out, return_range=return_range)
+
+
+@dataclass
+class SoftFit:
+    J: float
+    W: np.ndarray            # B x C
+    eigvals: np.ndarray      # C
+    mean: np.ndarray         # B
+    class_means: np.ndarray  # K x B
+
+
+def _soft_inputs(X: torch.Tensor, w: torch.Tensor):
+    if X.dtype != torch.float32 or w.dtype != torch.float32:
+        raise ValueError("X and w must be float32")
+    if X.dim() != 2 or w.dim() != 2 or X.shape[0] != w.shape[0]:
+        raise ValueError("X must be N x B and w N x K")
+    if not (X.is_contiguous() and w.is_contiguous()) or X.device != w.device:
+        raise ValueError("X and w must be contiguous and on one device")
+    return X.shape[0], X.shape[1], w.shape[1]
+
+
+def cva_soft_forward(X: torch.Tensor, w: torch.Tensor, precision: str = "fp32",
+                     ridge: float = 0.0) -> SoftFit:
+    N, B, K = _soft_inputs(X, w)
+    C = min(K - 1, B)
+    J = np.empty(1)
+    W = np.empty((B, C))
+    lam = np.empty(C)
+    mean = np.empty(B)
+    cm = np.empty((K, B))
+    dev = _dev_index(X)
+    ctx = context(dev)
+    st = lib().cva_soft_forward(ctx, _ptr(X), _ptr(w), N, B, K, _lib.PREC[precision], float(ridge),
+                                _ptr(J), _ptr(W), _ptr(lam), _ptr(mean), _ptr(cm), _stream(X.device))
+    check(st, ctx)
+    return SoftFit(float(J[0]), W, lam, mean, cm)
+
+
+def cva_soft_backward(X: torch.Tensor, fit: SoftFit, dJ: float, K: int,
+                      out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    N, B = X.shape
+    if out is None:
+        out = torch.empty((N, K), dtype=torch.float32, device=X.device)
+    W = _f64(fit.W)
+    lam = _f64(fit.eigvals)
+    mean = _f64(fit.mean)
+    cm = _f64(fit.class_means)
+    dev = _dev_index(X)
+    ctx = context(dev)
+    st = lib().cva_soft_backward(ctx, _ptr(X), _ptr(W), _ptr(lam), _ptr(mean), _ptr(cm), N, B, K,
+                                 float(dJ), _ptr(out), _stream(X.device))
+    check(st, ctx)
+    return out
+
+
+class SoftCVA(torch.autograd.Function):
+    """J = sum of the canonical eigenvalues of the soft-label problem, with
+    the hand-written backward kernel for dJ/dw.  X carries no gradient."""
+
+    @staticmethod
+    def forward(ctx, X, w, precision="fp32", ridge=0.0):
+        fit = cva_soft_forward(X.detach(), w.detach(), precision, ridge)
+        ctx.fit = fit
+        ctx.K = w.shape[1]
+        ctx.save_for_backward(X)
+        return torch.tensor(fit.J, dtype=torch.float64, device=w.device)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        (X,) = ctx.saved_tensors
+        dJ = float(gJ.item())
+        dw = cva_soft_backward(X.detach(), ctx.fit, dJ, ctx.K)
+        return None, dw, None, None
+
+
+# ------------------------------------------------------------ host-only calls
+
+def cva_solve_moments(counts, class_means, Sw, ridge: float = 0.0, n_comp: Optional[int] = None):
+    """FP64 CVA solve from class counts, class means and S_w (no GPU)."""
+    counts = np.ascontiguousarray(np.asarray(counts, dtype=np.int64))
+    cm = _f64(class_means)
+    Sw = _f64(Sw)
+    K, B = cm.shape
+    n_comp = min(K - 1, B) if n_comp is None else n_comp
+    W = np.empty((B, n_comp))
+    lam = np.empty(n_comp)
+    mean = np.empty(B)
+    st = lib().cva_solve_moments(_ptr(counts), _ptr(cm), _ptr(Sw), K, B, float(ridge), n_comp,
+                                 _ptr(W), _ptr(lam), _ptr(mean))
+    check(st)
+    return W, lam, mean
+
+
+def sym_eig(A):
+    """Descending symmetric eigendecomposition (no GPU)."""
+    A = _f64(A)
+    n = A.shape[0]
+    w = np.empty(n)
+    V = np.empty((n, n))
+    check(lib().cvamx_sym_eig(n, _ptr(A), _ptr(w), _ptr(V)))
+    return w, V
+
+
+# ------------------------------------------------------------ kernel timing
+
+def profile_enable(enable: bool = True, device: int = 0) -> None:
+    """Bracket every kernel the library launches on `device` with HIP events
+    (on the stream it is launched on); clears earlier totals."""
+    ctx = context(device)
+    check(lib().cvamx_profile_enable(ctx, 1 if enable else 0), ctx)
+
+
+def profile_report(device: int = 0) -> dict:
+    """{kernel name: (launches, total milliseconds)} since profile_enable."""
+    ctx = context(device)
+    need = lib().cvamx_profile_report(ctx, None, 0)
+    if need < 0:
+        check(int(need), ctx)
+    buf = ctypes.create_string_buffer(int(need))
+    lib().cvamx_profile_report(ctx, buf, need)
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, n, ms = line.split()
+        out[name] = (int(n), float(ms))
+    return out

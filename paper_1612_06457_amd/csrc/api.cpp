@@ -1,0 +1,659 @@
+// C ABI of the cvamx library: argument checking, scratch management,
+// kernel orchestration on the caller's HIP stream, and the FP64 finish of
+// every fit on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "cvamx.h"
+#include "finisher.h"
+#include "launch.hpp"
+
+namespace {
+
+enum Buf { B_TILECNT, B_IDX, B_PART, B_RES, B_PROJPART, B_FIRST, B_MCF, B_COUNT };
+
+}  // namespace
+
+struct cvamx_ctx {
+  int device = -1;
+  int num_cu = 256;
+  int proj_blocks = 0;   // 0 = automatic
+  int gram_blocks = 0;
+  std::string err;
+  void* buf[B_COUNT] = {};
+  size_t cap[B_COUNT] = {};
+  void* pinned = nullptr;
+  size_t pinned_cap = 0;
+  unsigned* tickets = nullptr;   // [0] projection range, [1] soft first moments
+  float* range_dev = nullptr;    // 16 floats: lo[8], scale[8] of the current group
+  float* ab_dev = nullptr;       // 2 * CVAMX_MAX_BANDS floats: (min, max) per component
+  // kernel timing (cvamx_profile_enable)
+  bool prof = false;
+  struct Pending {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Pending> pending;
+  std::map<std::string, std::pair<long, double>> prof_acc;
+};
+
+namespace {
+
+int fail(cvamx_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+int hip_fail(cvamx_ctx* ctx, hipError_t e, const char* where) {
+  return fail(ctx, CVAMX_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, where)                         \
+  do {                                               \
+    hipError_t _e = (call);                          \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, where); \
+  } while (0)
+
+int ensure(cvamx_ctx* ctx, Buf b, size_t bytes) {
+  if (ctx->cap[b] >= bytes && ctx->buf[b]) return 0;
+  if (ctx->buf[b]) {
+    hipError_t e = hipFree(ctx->buf[b]);
+    ctx->buf[b] = nullptr;
+    ctx->cap[b] = 0;
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipFree");
+  }
+  size_t want = std::max<size_t>(bytes, 256);
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) return fail(ctx, CVAMX_E_NO_MEMORY, "hipMalloc of scratch failed");
+  ctx->buf[b] = p;
+  ctx->cap[b] = want;
+  return 0;
+}
+
+int ensure_pinned(cvamx_ctx* ctx, size_t bytes) {
+  if (ctx->pinned_cap >= bytes && ctx->pinned) return 0;
+  if (ctx->pinned) {
+    (void)hipHostFree(ctx->pinned);
+    ctx->pinned = nullptr;
+    ctx->pinned_cap = 0;
+  }
+  void* p = nullptr;
+  if (hipHostMalloc(&p, std::max<size_t>(bytes, 4096), hipHostMallocDefault) != hipSuccess)
+    return fail(ctx, CVAMX_E_NO_MEMORY, "hipHostMalloc of staging failed");
+  ctx->pinned = p;
+  ctx->pinned_cap = std::max<size_t>(bytes, 4096);
+  return 0;
+}
+
+hipEvent_t get_event(cvamx_ctx* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Bracket one kernel launch with events when timing is enabled.
+void prof_begin(cvamx_ctx* ctx, hipStream_t s, const char* name) {
+  if (!ctx->prof) return;
+  hipEvent_t a = get_event(ctx);
+  if (!a) return;
+  (void)hipEventRecord(a, s);
+  ctx->pending.push_back({name, a, nullptr});
+}
+
+void prof_end(cvamx_ctx* ctx, hipStream_t s) {
+  if (!ctx->prof || ctx->pending.empty() || ctx->pending.back().b) return;
+  hipEvent_t b = get_event(ctx);
+  if (!b) return;
+  (void)hipEventRecord(b, s);
+  ctx->pending.back().b = b;
+}
+
+void prof_collect(cvamx_ctx* ctx) {
+  for (auto& p : ctx->pending) {
+    if (p.b) {
+      float ms = 0.f;
+      if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        auto& e = ctx->prof_acc[p.name];
+        e.first += 1;
+        e.second += ms;
+      }
+      ctx->ev_pool.push_back(p.b);
+    }
+    ctx->ev_pool.push_back(p.a);
+  }
+  ctx->pending.clear();
+}
+
+size_t esize(int dtype) { return dtype == CVAMX_F32 ? 4 : 2; }
+
+int check_cube(cvamx_ctx* ctx, const cvamx_cube* c) {
+  if (!c) return fail(ctx, CVAMX_E_INVALID_ARG, "cube is NULL");
+  if (!c->data) return fail(ctx, CVAMX_E_INVALID_ARG, "cube data is NULL");
+  if (c->height < 1 || c->width < 1 || c->bands < 1)
+    return fail(ctx, CVAMX_E_INVALID_ARG, "cube dimensions must be positive");
+  if (c->bands > CVAMX_MAX_BANDS)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "bands > CVAMX_MAX_BANDS");
+  if (c->dtype < CVAMX_U16 || c->dtype > CVAMX_F16)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "unknown dtype");
+  if (c->height > (int64_t(1) << 31) || c->width > (int64_t(1) << 31))
+    return fail(ctx, CVAMX_E_INVALID_ARG, "cube dimensions overflow");
+  const int64_t P = c->height * c->width;
+  if (P >= (int64_t(1) << 31) - 1)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "pages with 2^31 or more pixels are not supported");
+  if ((reinterpret_cast<uintptr_t>(c->data) & 15u) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "cube data must be 16-byte aligned");
+  return 0;
+}
+
+int check_device(cvamx_ctx* ctx) {
+  if (ctx->device < 0) return fail(ctx, CVAMX_E_DEVICE, "context has no device");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  return 0;
+}
+
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+// Expand the packed upper-triangular 4x4 tiles of an (B+1) x (B+1)
+// augmented Gram into a full symmetric matrix.
+void unpack_gram(int B, const double* packed, std::vector<double>& G) {
+  const int BP = cvx::padded_bp(B), nb = BP / 4, n1 = B + 1;
+  G.assign((size_t)n1 * n1, 0.0);
+  int blk = 0;
+  for (int bi = 0; bi < nb; ++bi)
+    for (int bj = bi; bj < nb; ++bj, ++blk)
+      for (int e = 0; e < 16; ++e) {
+        const int i = 4 * bi + e / 4, j = 4 * bj + e % 4;
+        if (i < n1 && j < n1) {
+          G[(size_t)i * n1 + j] = packed[blk * 16 + e];
+          G[(size_t)j * n1 + i] = packed[blk * 16 + e];
+        }
+      }
+}
+
+// Layout of the fit result region (device, copied to host in one go).
+struct FitLayout {
+  size_t counts, offsets, err, shift, gram, total;
+  FitLayout(int K, int B, int L) {
+    counts = 0;
+    offsets = counts + 8 * (size_t)K;
+    err = offsets + ((4 * (size_t)(K + 1) + 7) & ~size_t(7));
+    shift = err + 8;
+    gram = shift + 8 * (size_t)K * B;
+    total = gram + 8 * (size_t)K * L;
+  }
+};
+
+int proj_groups(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const double* center,
+                int n_comp, uint8_t* images, hipStream_t s) {
+  const int B = (int)cube->bands;
+  const int64_t P = cube->height * cube->width;
+  const int S = (cube->dtype == CVAMX_F32) ? B : ((B & 1) ? B : B / 2);
+  const int g2 = (cube->dtype != CVAMX_F32 && (B & 1)) ? 2 : 1;
+  const int64_t nt = (P + 64 * g2 - 1) / (64 * g2);
+  int nblocks = ctx->proj_blocks > 0 ? ctx->proj_blocks : ctx->num_cu * 8;
+  nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(nblocks, (nt + cvx::kWaves - 1) / cvx::kWaves));
+  (void)S;
+  if (int st = ensure(ctx, B_PROJPART, (size_t)nblocks * 16 * sizeof(float))) return st;
+  for (int g0 = 0; g0 < n_comp; g0 += 8) {
+    const int nc = std::min(8, n_comp - g0);
+    const int NC = nc <= 4 ? 4 : 8;
+    cvx::ProjArgs a;
+    std::memset(&a, 0, sizeof(a));
+    std::vector<double> c(B);
+    for (int b = 0; b < B; ++b) {
+      c[b] = (cube->dtype == CVAMX_U16) ? std::nearbyint(center[b]) : (double)(float)center[b];
+      a.c[b] = (float)c[b];
+    }
+    for (int j = 0; j < nc; ++j) {
+      double off = 0.0;
+      for (int b = 0; b < B; ++b) {
+        const double wv = W[(size_t)b * n_comp + g0 + j];
+        a.w[b * NC + j] = (float)wv;
+        off += wv * (c[b] - center[b]);
+      }
+      a.off[j] = (float)off;
+    }
+    prof_begin(ctx, s, "project_range");
+    hipError_t e = cvx::launch_project_range(cube->dtype, cube->data, B, P, nc, a, nblocks,
+                                             (float*)ctx->buf[B_PROJPART], ctx->tickets,
+                                             ctx->range_dev, ctx->ab_dev + 2 * g0, s);
+    prof_end(ctx, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "project range launch");
+    prof_begin(ctx, s, "project_stretch");
+    e = cvx::launch_project_stretch(cube->dtype, cube->data, B, P, nc, nc, a, nblocks,
+                                    ctx->range_dev, images + (int64_t)g0 * P, s);
+    prof_end(ctx, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "project stretch launch");
+  }
+  return 0;
+}
+
+int project_common(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const double* center,
+                   int32_t n_comp, uint8_t* images, float* range, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (int st = check_cube(ctx, cube)) return st;
+  if (!W || !center || !images) return fail(ctx, CVAMX_E_INVALID_ARG, "W, center and images must be non-NULL");
+  if (n_comp < 1 || n_comp > CVAMX_MAX_BANDS)
+    return fail(ctx, CVAMX_E_INVALID_ARG, "n_comp must lie in 1..CVAMX_MAX_BANDS");
+  const int B = (int)cube->bands;
+  for (int i = 0; i < B * n_comp; ++i)
+    if (!std::isfinite(W[i])) return fail(ctx, CVAMX_E_INVALID_ARG, "W has a non-finite entry");
+  for (int b = 0; b < B; ++b)
+    if (!std::isfinite(center[b])) return fail(ctx, CVAMX_E_INVALID_ARG, "center has a non-finite entry");
+  if (int st = check_device(ctx)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (int st = proj_groups(ctx, cube, W, center, n_comp, images, s)) return st;
+  if (range) {
+    if (int st = ensure_pinned(ctx, 2 * sizeof(float) * n_comp)) return st;
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, ctx->ab_dev, 2 * sizeof(float) * n_comp, hipMemcpyDeviceToHost, s),
+            "range copy");
+    HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+    std::memcpy(range, ctx->pinned, 2 * sizeof(float) * n_comp);
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cvamx_status_str(int st) {
+  switch (st) {
+    case CVAMX_OK: return "ok";
+    case CVAMX_E_INVALID_ARG: return "invalid argument";
+    case CVAMX_E_UNSUPPORTED: return "unsupported";
+    case CVAMX_E_EMPTY_CLASS: return "empty class";
+    case CVAMX_E_NOT_PD: return "within-class scatter not positive definite";
+    case CVAMX_E_DEVICE: return "device error";
+    case CVAMX_E_NO_MEMORY: return "out of memory";
+    case CVAMX_E_NUMERIC: return "eigensolver did not converge";
+    default: return "unknown status";
+  }
+}
+
+const char* cvamx_last_error(const cvamx_ctx* ctx) {
+  if (!ctx) return "no context";
+  return ctx->err.c_str();
+}
+
+int cvamx_create(cvamx_ctx** out, int device) {
+  if (!out) return CVAMX_E_INVALID_ARG;
+  *out = nullptr;
+  cvamx_ctx* ctx = new (std::nothrow) cvamx_ctx();
+  if (!ctx) return CVAMX_E_NO_MEMORY;
+  if (device < -1) {
+    delete ctx;
+    return CVAMX_E_INVALID_ARG;
+  }
+  if (device >= 0) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device >= n) {
+      delete ctx;
+      return CVAMX_E_DEVICE;
+    }
+    ctx->device = device;
+    if (hipSetDevice(device) != hipSuccess) {
+      delete ctx;
+      return CVAMX_E_DEVICE;
+    }
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
+      ctx->num_cu = cu;
+    if (const char* v = std::getenv("CVAMX_PROJ_BLOCKS")) ctx->proj_blocks = std::atoi(v);
+    if (const char* v = std::getenv("CVAMX_GRAM_BLOCKS")) ctx->gram_blocks = std::atoi(v);
+    void* p = nullptr;
+    const size_t small = 256 + 256 + 2 * CVAMX_MAX_BANDS * sizeof(float);
+    if (hipMalloc(&p, small) != hipSuccess) {
+      delete ctx;
+      return CVAMX_E_NO_MEMORY;
+    }
+    if (hipMemset(p, 0, small) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+      (void)hipFree(p);
+      delete ctx;
+      return CVAMX_E_DEVICE;
+    }
+    ctx->tickets = static_cast<unsigned*>(p);
+    ctx->range_dev = reinterpret_cast<float*>(static_cast<char*>(p) + 256);
+    ctx->ab_dev = reinterpret_cast<float*>(static_cast<char*>(p) + 512);
+  }
+  *out = ctx;
+  return CVAMX_OK;
+}
+
+void cvamx_destroy(cvamx_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->device >= 0) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (int b = 0; b < B_COUNT; ++b)
+      if (ctx->buf[b]) (void)hipFree(ctx->buf[b]);
+    if (ctx->tickets) (void)hipFree(ctx->tickets);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    prof_collect(ctx);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  }
+  delete ctx;
+}
+
+int cva_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels, int32_t K, int32_t prec,
+            double ridge, int32_t n_comp, double* W, double* eigvals, double* mean, int64_t* counts,
+            double* class_means, double* Sw, double* Sb, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (int st = check_cube(ctx, cube)) return st;
+  if (!labels) return fail(ctx, CVAMX_E_INVALID_ARG, "labels is NULL");
+  if ((reinterpret_cast<uintptr_t>(labels) & 3u) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "labels must be 4-byte aligned");
+  if (K < 2 || K > CVAMX_MAX_CLASSES) return fail(ctx, CVAMX_E_INVALID_ARG, "K must lie in 2..127");
+  if (prec < CVAMX_PREC_FP32 || prec > CVAMX_PREC_F16X3)
+    return fail(ctx, CVAMX_E_INVALID_ARG, "unknown precision");
+  if (!finite_nonneg(ridge)) return fail(ctx, CVAMX_E_INVALID_ARG, "ridge must be finite and >= 0");
+  const int B = (int)cube->bands;
+  const int C = std::min(K - 1, B);
+  if (n_comp < 1 || n_comp > C) return fail(ctx, CVAMX_E_INVALID_ARG, "n_comp must lie in 1..min(K-1, bands)");
+  if (!W || !eigvals || !mean || !counts)
+    return fail(ctx, CVAMX_E_INVALID_ARG, "W, eigvals, mean and counts must be non-NULL");
+  if (prec != CVAMX_PREC_FP32)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "only the FP32 scatter path is built in this library");
+  if (int st = check_device(ctx)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t P = cube->height * cube->width;
+  const int nT = (int)((P + cvx::kLabelTile - 1) / cvx::kLabelTile);
+  const int L = cvx::tri_blocks(B) * 16;
+  const int G = std::max(1, std::min(64, 4096 / K));
+  const FitLayout lay(K, B, L);
+  if (int st = ensure(ctx, B_TILECNT, (size_t)nT * K * 4)) return st;
+  if (int st = ensure(ctx, B_IDX, (size_t)P * 4)) return st;
+  if (int st = ensure(ctx, B_PART, (size_t)K * G * L * 8)) return st;
+  if (int st = ensure(ctx, B_RES, lay.total)) return st;
+  if (int st = ensure_pinned(ctx, lay.total)) return st;
+  char* res = static_cast<char*>(ctx->buf[B_RES]);
+  HIP_TRY(hipMemsetAsync(res + lay.err, 0, 8, s), "memset");
+  hipError_t e;
+  prof_begin(ctx, s, "label_count");
+  e = cvx::launch_label_count(labels, P, K, nT, (int32_t*)ctx->buf[B_TILECNT], (int32_t*)(res + lay.err), s);
+  prof_end(ctx, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "label count launch");
+  prof_begin(ctx, s, "label_index");
+  e = cvx::launch_label_index(labels, P, K, nT, (const int32_t*)ctx->buf[B_TILECNT], (int32_t*)ctx->buf[B_IDX],
+                              (int64_t*)(res + lay.counts), (int32_t*)(res + lay.offsets), s);
+  prof_end(ctx, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "label index launch");
+  prof_begin(ctx, s, "class_moments");
+  e = cvx::launch_class_moments(cube->dtype, cube->data, B, (const int32_t*)ctx->buf[B_IDX],
+                                (const int32_t*)(res + lay.offsets), K, G, (double*)ctx->buf[B_PART],
+                                (double*)(res + lay.shift), s);
+  prof_end(ctx, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "class moments launch");
+  prof_begin(ctx, s, "reduce_partials");
+  e = cvx::launch_reduce_part((const double*)ctx->buf[B_PART], K, G, L, (double*)(res + lay.gram), s);
+  prof_end(ctx, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
+  HIP_TRY(hipMemcpyAsync(ctx->pinned, res, lay.total, hipMemcpyDeviceToHost, s), "result copy");
+  HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+
+  const char* h = static_cast<const char*>(ctx->pinned);
+  int32_t errflag;
+  std::memcpy(&errflag, h + lay.err, 4);
+  if (errflag) return fail(ctx, CVAMX_E_INVALID_ARG, "a label lies outside -1..K-1");
+  std::vector<int64_t> cnt(K);
+  std::memcpy(cnt.data(), h + lay.counts, 8 * (size_t)K);
+  for (int k = 0; k < K; ++k)
+    if (cnt[k] < 1) return fail(ctx, CVAMX_E_EMPTY_CLASS, "class " + std::to_string(k) + " has no training pixel");
+  const double* shift = reinterpret_cast<const double*>(h + lay.shift);
+  const double* gram = reinterpret_cast<const double*>(h + lay.gram);
+  std::vector<double> cm((size_t)K * B), Swv((size_t)B * B, 0.0), G1, cntd(K);
+  for (int k = 0; k < K; ++k) {
+    unpack_gram(B, gram + (size_t)k * L, G1);
+    const double n = (double)cnt[k];
+    cntd[k] = n;
+    const int n1 = B + 1;
+    for (int i = 0; i < B; ++i) cm[(size_t)k * B + i] = shift[(size_t)k * B + i] + G1[(size_t)i * n1 + B] / n;
+    for (int i = 0; i < B; ++i)
+      for (int j = 0; j < B; ++j)
+        Swv[(size_t)i * B + j] += G1[(size_t)i * n1 + j] - G1[(size_t)i * n1 + B] * G1[(size_t)j * n1 + B] / n;
+  }
+  std::vector<double> Wt((size_t)B * n_comp), lam(n_comp), m(B), Sbv((size_t)B * B);
+  const int st = cvamx::cva_solve(K, B, cntd.data(), cm.data(), Swv.data(), ridge, n_comp, Wt.data(),
+                                  lam.data(), m.data(), Sbv.data(), &ctx->err);
+  if (st != 0) return st;
+  std::copy(Wt.begin(), Wt.end(), W);
+  std::copy(lam.begin(), lam.end(), eigvals);
+  std::copy(m.begin(), m.end(), mean);
+  std::copy(cnt.begin(), cnt.end(), counts);
+  if (class_means) std::copy(cm.begin(), cm.end(), class_means);
+  if (Sw) std::copy(Swv.begin(), Swv.end(), Sw);
+  if (Sb) std::copy(Sbv.begin(), Sbv.end(), Sb);
+  return CVAMX_OK;
+}
+
+int cva_project(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const double* center,
+                int32_t n_comp, uint8_t* images, float* range, void* stream) {
+  return project_common(ctx, cube, W, center, n_comp, images, range, stream);
+}
+
+int pca_project(cvamx_ctx* ctx, const cvamx_cube* cube, const double* V, const double* mean,
+                int32_t n_comp, uint8_t* images, float* range, void* stream) {
+  return project_common(ctx, cube, V, mean, n_comp, images, range, stream);
+}
+
+int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t n_comp, int32_t prec,
+            double* V, double* eigvals, double* mean, double* cov, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (int st = check_cube(ctx, cube)) return st;
+  const int B = (int)cube->bands;
+  if (n_comp < 1 || n_comp > B) return fail(ctx, CVAMX_E_INVALID_ARG, "n_comp must lie in 1..bands");
+  if (prec < CVAMX_PREC_FP32 || prec > CVAMX_PREC_F16X3)
+    return fail(ctx, CVAMX_E_INVALID_ARG, "unknown precision");
+  if (!V || !eigvals || !mean) return fail(ctx, CVAMX_E_INVALID_ARG, "V, eigvals and mean must be non-NULL");
+  if (prec != CVAMX_PREC_FP32)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "only the FP32 scatter path is built in this library");
+  if (int st = check_device(ctx)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t P = cube->height * cube->width;
+  const int L = cvx::tri_blocks(B) * 16;
+  int nblocks = ctx->gram_blocks > 0 ? ctx->gram_blocks : ctx->num_cu * 4;
+  nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(nblocks, (P + cvx::kChunk - 1) / cvx::kChunk));
+  const size_t res_bytes = 8 * (size_t)B + 8 * (size_t)L;
+  if (int st = ensure(ctx, B_PART, (size_t)nblocks * L * 8)) return st;
+  if (int st = ensure(ctx, B_RES, res_bytes)) return st;
+  if (int st = ensure_pinned(ctx, res_bytes)) return st;
+  char* res = static_cast<char*>(ctx->buf[B_RES]);
+  prof_begin(ctx, s, "pca_gram");
+  hipError_t e = cvx::launch_pca_gram(cube->dtype, cube->data, B, P, mask, nblocks, (double*)ctx->buf[B_PART],
+                                      (double*)res, s);
+  prof_end(ctx, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "pca gram launch");
+  prof_begin(ctx, s, "reduce_partials");
+  e = cvx::launch_reduce_part((const double*)ctx->buf[B_PART], 1, nblocks, L, (double*)(res + 8 * B), s);
+  prof_end(ctx, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
+  HIP_TRY(hipMemcpyAsync(ctx->pinned, res, res_bytes, hipMemcpyDeviceToHost, s), "result copy");
+  HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+  const double* shift = static_cast<const double*>(ctx->pinned);
+  std::vector<double> G1;
+  unpack_gram(B, shift + B, G1);
+  const int n1 = B + 1;
+  const double n = G1[(size_t)B * n1 + B];
+  if (!(n >= 2.0)) return fail(ctx, CVAMX_E_INVALID_ARG, "PCA needs at least two selected pixels");
+  std::vector<double> C((size_t)B * B), w(B), Vf((size_t)B * B), mu(B);
+  for (int i = 0; i < B; ++i) mu[i] = shift[i] + G1[(size_t)i * n1 + B] / n;
+  for (int i = 0; i < B; ++i)
+    for (int j = 0; j < B; ++j)
+      C[(size_t)i * B + j] = (G1[(size_t)i * n1 + j] - G1[(size_t)i * n1 + B] * G1[(size_t)j * n1 + B] / n) / (n - 1.0);
+  const int st = cvamx::sym_eig_desc(B, C.data(), w.data(), Vf.data());
+  if (st != 0) return fail(ctx, st, "PCA eigensolver did not converge");
+  std::vector<double> Vo((size_t)B * n_comp);
+  for (int i = 0; i < B; ++i)
+    for (int j = 0; j < n_comp; ++j) Vo[(size_t)i * n_comp + j] = Vf[(size_t)i * B + j];
+  cvamx::sign_rule(B, n_comp, Vo.data());
+  std::copy(Vo.begin(), Vo.end(), V);
+  std::copy(w.begin(), w.begin() + n_comp, eigvals);
+  std::copy(mu.begin(), mu.end(), mean);
+  if (cov) std::copy(C.begin(), C.end(), cov);
+  return CVAMX_OK;
+}
+
+int cva_soft_forward(cvamx_ctx* ctx, const float* X, const float* w, int64_t N, int32_t B, int32_t K,
+                     int32_t prec, double ridge, double* J, double* W, double* eigvals, double* mean,
+                     double* class_means, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (!X || !w) return fail(ctx, CVAMX_E_INVALID_ARG, "X and w must be non-NULL");
+  if (N < 2 || N >= (int64_t(1) << 31)) return fail(ctx, CVAMX_E_INVALID_ARG, "N must lie in 2..2^31-1");
+  if (B < 1 || B > CVAMX_MAX_BANDS) return fail(ctx, CVAMX_E_INVALID_ARG, "B must lie in 1..64");
+  if (K < 2 || K > 32) return fail(ctx, CVAMX_E_INVALID_ARG, "soft-label CVA supports K in 2..32");
+  if (prec < CVAMX_PREC_FP32 || prec > CVAMX_PREC_F16X3)
+    return fail(ctx, CVAMX_E_INVALID_ARG, "unknown precision");
+  if (!finite_nonneg(ridge)) return fail(ctx, CVAMX_E_INVALID_ARG, "ridge must be finite and >= 0");
+  if (!J || !W || !eigvals || !mean || !class_means)
+    return fail(ctx, CVAMX_E_INVALID_ARG, "J, W, eigvals, mean and class_means must be non-NULL");
+  if ((reinterpret_cast<uintptr_t>(X) & 15u) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "X must be 16-byte aligned");
+  if (prec != CVAMX_PREC_FP32)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "only the FP32 scatter path is built in this library");
+  if (int st = check_device(ctx)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int BP = cvx::padded_bp(B), KP = (K + 3) & ~3;
+  const int L = cvx::tri_blocks(B) * 16;
+  const int nb1 = (int)std::max<int64_t>(1, std::min<int64_t>(ctx->num_cu, (N + cvx::kChunk - 1) / cvx::kChunk));
+  const int G = std::max(1, std::min(128, 1024 / K));
+  const size_t first_bytes = 8 * (size_t)K * (B + 1);
+  const size_t mcf_off = first_bytes;
+  const size_t gram_off = (mcf_off + 4 * (size_t)K * B + 7) & ~size_t(7);
+  const size_t res_bytes = gram_off + 8 * (size_t)K * L;
+  if (int st = ensure(ctx, B_FIRST, (size_t)nb1 * KP * BP * 8)) return st;
+  if (int st = ensure(ctx, B_PART, (size_t)K * G * L * 8)) return st;
+  if (int st = ensure(ctx, B_RES, res_bytes)) return st;
+  if (int st = ensure_pinned(ctx, res_bytes)) return st;
+  char* res = static_cast<char*>(ctx->buf[B_RES]);
+  prof_begin(ctx, s, "soft_first");
+  hipError_t e = cvx::launch_soft_first(X, w, N, B, K, nb1, (double*)ctx->buf[B_FIRST], ctx->tickets + 1,
+                                        (double*)res, (float*)(res + mcf_off), s);
+  prof_end(ctx, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "soft first launch");
+  prof_begin(ctx, s, "soft_scatter");
+  e = cvx::launch_soft_scatter(X, w, N, B, K, G, (const float*)(res + mcf_off), (double*)ctx->buf[B_PART], s);
+  prof_end(ctx, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "soft scatter launch");
+  prof_begin(ctx, s, "reduce_partials");
+  e = cvx::launch_reduce_part((const double*)ctx->buf[B_PART], K, G, L, (double*)(res + gram_off), s);
+  prof_end(ctx, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
+  HIP_TRY(hipMemcpyAsync(ctx->pinned, res, res_bytes, hipMemcpyDeviceToHost, s), "result copy");
+  HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+  const char* h = static_cast<const char*>(ctx->pinned);
+  const float* mcf = reinterpret_cast<const float*>(h + mcf_off);
+  const double* gram = reinterpret_cast<const double*>(h + gram_off);
+  std::vector<double> cm((size_t)K * B), Swv((size_t)B * B, 0.0), G1, n(K);
+  const int n1 = B + 1;
+  for (int c = 0; c < K; ++c) {
+    unpack_gram(B, gram + (size_t)c * L, G1);
+    const double nc = G1[(size_t)B * n1 + B];
+    if (!(nc > 0.0)) return fail(ctx, CVAMX_E_EMPTY_CLASS, "class " + std::to_string(c) + " has no positive weight");
+    n[c] = nc;
+    for (int i = 0; i < B; ++i) cm[(size_t)c * B + i] = (double)mcf[(size_t)c * B + i] + G1[(size_t)i * n1 + B] / nc;
+    for (int i = 0; i < B; ++i)
+      for (int j = 0; j < B; ++j)
+        Swv[(size_t)i * B + j] += G1[(size_t)i * n1 + j] - G1[(size_t)i * n1 + B] * G1[(size_t)j * n1 + B] / nc;
+  }
+  const int C = std::min(K - 1, B);
+  std::vector<double> Wt((size_t)B * C), lam(C), m(B);
+  const int st = cvamx::cva_solve(K, B, n.data(), cm.data(), Swv.data(), ridge, C, Wt.data(), lam.data(),
+                                  m.data(), nullptr, &ctx->err);
+  if (st != 0) return st;
+  double Jv = 0.0;
+  for (int j = 0; j < C; ++j) Jv += lam[j];
+  *J = Jv;
+  std::copy(Wt.begin(), Wt.end(), W);
+  std::copy(lam.begin(), lam.end(), eigvals);
+  std::copy(m.begin(), m.end(), mean);
+  std::copy(cm.begin(), cm.end(), class_means);
+  return CVAMX_OK;
+}
+
+int cva_soft_backward(cvamx_ctx* ctx, const float* X, const double* W, const double* eigvals,
+                      const double* mean, const double* class_means, int64_t N, int32_t B, int32_t K,
+                      double dJ, float* dw, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (!X || !W || !eigvals || !mean || !class_means || !dw)
+    return fail(ctx, CVAMX_E_INVALID_ARG, "pointer arguments must be non-NULL");
+  if (N < 1 || N >= (int64_t(1) << 31)) return fail(ctx, CVAMX_E_INVALID_ARG, "N must lie in 1..2^31-1");
+  if (B < 1 || B > CVAMX_MAX_BANDS) return fail(ctx, CVAMX_E_INVALID_ARG, "B must lie in 1..64");
+  if (K < 2 || K > 32) return fail(ctx, CVAMX_E_INVALID_ARG, "soft-label CVA supports K in 2..32");
+  if (!std::isfinite(dJ)) return fail(ctx, CVAMX_E_INVALID_ARG, "dJ must be finite");
+  if ((reinterpret_cast<uintptr_t>(X) & 15u) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "X must be 16-byte aligned");
+  if (int st = check_device(ctx)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int C = std::min(K - 1, B);
+  const int64_t nt = (N + 63) / 64;
+  const int nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(ctx->num_cu * 8, (nt + 3) / 4));
+  for (int g0 = 0; g0 < C; g0 += 8) {
+    const int nc = std::min(8, C - g0);
+    cvx::SoftBwdArgs a;
+    std::memset(&a, 0, sizeof(a));
+    for (int b = 0; b < B; ++b) a.m[b] = (float)mean[b];
+    for (int j = 0; j < nc; ++j) {
+      for (int b = 0; b < B; ++b) a.w[b * 8 + j] = (float)W[(size_t)b * C + g0 + j];
+      a.lam1[j] = (float)(1.0 + eigvals[g0 + j]);
+      for (int c = 0; c < K; ++c) {
+        double d = 0.0;
+        for (int b = 0; b < B; ++b) d += W[(size_t)b * C + g0 + j] * (class_means[(size_t)c * B + b] - mean[b]);
+        a.d[c * 8 + j] = (float)d;
+      }
+    }
+    a.scale = (float)dJ;
+    prof_begin(ctx, s, "soft_backward");
+    hipError_t e = cvx::launch_soft_backward(X, N, B, K, a, g0 > 0, nblocks, dw, s);
+    prof_end(ctx, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "soft backward launch");
+  }
+  return CVAMX_OK;
+}
+
+int cvamx_profile_enable(cvamx_ctx* ctx, int enable) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (ctx->device < 0) return fail(ctx, CVAMX_E_DEVICE, "context has no device");
+  prof_collect(ctx);
+  ctx->prof_acc.clear();
+  ctx->prof = enable != 0;
+  return CVAMX_OK;
+}
+
+int64_t cvamx_profile_report(cvamx_ctx* ctx, char* buf, int64_t len) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (ctx->device >= 0) {
+    (void)hipSetDevice(ctx->device);
+    prof_collect(ctx);
+  }
+  std::string out;
+  char line[160];
+  for (const auto& kv : ctx->prof_acc) {
+    std::snprintf(line, sizeof(line), "%s %ld %.6f\n", kv.first.c_str(), kv.second.first, kv.second.second);
+    out += line;
+  }
+  const int64_t need = (int64_t)out.size() + 1;
+  if (buf && len > 0) {
+    const int64_t n = std::min<int64_t>(len - 1, (int64_t)out.size());
+    std::memcpy(buf, out.data(), (size_t)n);
+    buf[n] = 0;
+  }
+  return need;
+}
+
+}  // extern "C"

@@ -1,0 +1,283 @@
+// Soft-label CVA on the training pixels X (N x B float32) with real class
+// weights w (N x K float32).  Not in the paper: with one-hot weights it is
+// the paper's CVA (Section 2, canonical variates paragraph).
+//
+// Forward, two passes over X:
+//   1. n_c = sum_p w_pc and t_c = sum_p w_pc x_p (register-tiled w^T [X, 1]);
+//      the last block combines the block partials in a fixed order and
+//      stores the class means m_c = t_c / n_c;
+//   2. per class, the weighted augmented Gram of [x - m_c, 1]: sum w d d^T,
+//      sum w d and sum w (d = x - float(m_c)); the host removes the tiny
+//      offset between float(m_c) and m_c exactly.
+// Backward: per pixel, u = x - m, z_j = w_j^T u for the C canonical
+// vectors, and dJ/dw_pc = sum_j z_j^2 - sum_j (1 + lambda_j)(z_j - d_jc)^2
+// with d_jc = w_j^T (m_c - m).
+#include "k_common.hpp"
+#include "launch.hpp"
+
+namespace cvx {
+
+namespace {
+
+// Stage rows [r0, r0 + rows) of a row-major N x L float matrix into LDS
+// (kChunk x ld, zero-filled beyond `rows` and beyond L).
+__device__ __forceinline__ void stage_rows(const float* __restrict__ src, int L, int ld, int64_t r0,
+                                           int rows, float* __restrict__ dst) {
+  const int per = kChunk * L;
+  const int nel = rows * L;
+  const float* s = src + r0 * L;
+  const int rstep = kBlock / L, bstep = kBlock % L;
+  int r = threadIdx.x / L, b = threadIdx.x % L;
+  for (int e = threadIdx.x; e < per; e += kBlock) {
+    dst[r * ld + b] = (e < nel) ? s[e] : 0.f;
+    r += rstep;
+    b += bstep;
+    if (b >= L) {
+      b -= L;
+      ++r;
+    }
+  }
+  for (int e = threadIdx.x; e < kChunk * (ld - L); e += kBlock) {
+    const int rr = e / (ld - L), cc = L + e % (ld - L);
+    dst[rr * ld + cc] = 0.f;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_soft_first(const float* __restrict__ X,
+                                                       const float* __restrict__ W, int64_t N,
+                                                       int B, int K, double* __restrict__ part,
+                                                       unsigned* __restrict__ ticket,
+                                                       double* __restrict__ first,
+                                                       float* __restrict__ mc_f) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int BP = (B + 1 + 3) & ~3, KP = (K + 3) & ~3;
+  float* xs = reinterpret_cast<float*>(smem_raw);       // kChunk x BP
+  float* ws = xs + kChunk * BP;                          // kChunk x KP
+  double* red = reinterpret_cast<double*>(smem_raw);
+  __shared__ bool am_last;
+  const int nbi = KP / 4, nbj = BP / 4, nblk = nbi * nbj;
+  const int nslice = kBlock / nblk;
+  const int blk = threadIdx.x % nblk, slice = threadIdx.x / nblk;
+  const bool active = slice < nslice;
+  const int bi = blk / nbj, bj = blk % nbj;
+  float acc[16];
+  double accd[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    acc[e] = 0.f;
+    accd[e] = 0.0;
+  }
+  const int64_t nch = (N + kChunk - 1) / kChunk;
+  for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    const int64_t r0 = ch * kChunk;
+    const int rows = (N - r0 < kChunk) ? (int)(N - r0) : kChunk;
+    stage_rows(X, B, BP, r0, rows, xs);
+    stage_rows(W, K, KP, r0, rows, ws);
+    __syncthreads();
+    if (threadIdx.x < kChunk) xs[threadIdx.x * BP + B] = (threadIdx.x < rows) ? 1.f : 0.f;
+    __syncthreads();
+    if (active) tile_acc(ws, KP, xs, BP, bi, bj, slice, kChunk, nslice, acc);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      accd[e] += (double)acc[e];
+      acc[e] = 0.f;
+    }
+  }
+  // slice reduction -> block partial laid out as [c][e] for c < KP, e < BP
+  __syncthreads();
+  if (active)
+    for (int e = 0; e < 16; ++e) red[(slice * nblk + blk) * 16 + e] = accd[e];
+  __syncthreads();
+  const int L = KP * BP;
+  double* mine = part + (int64_t)blockIdx.x * L;
+  for (int t = threadIdx.x; t < nblk * 16; t += kBlock) {
+    double s = 0.0;
+    for (int sl = 0; sl < nslice; ++sl) s += red[sl * nblk * 16 + t];
+    const int bk = t / 16, e = t % 16;
+    const int c = 4 * (bk / nbj) + e / 4, col = 4 * (bk % nbj) + e % 4;
+    mine[c * BP + col] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    am_last = (atomicAdd(ticket, 1u) == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (am_last) {
+    __threadfence();
+    for (int t = threadIdx.x; t < K * (B + 1); t += kBlock) {
+      const int c = t / (B + 1), col = t % (B + 1);
+      double s = 0.0;
+      for (unsigned bk = 0; bk < gridDim.x; ++bk)
+        s += __builtin_nontemporal_load(part + (int64_t)bk * L + c * BP + col);
+      first[t] = s;
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int t = threadIdx.x; t < K * B; t += kBlock) {
+      const int c = t / B, b = t % B;
+      const double n = first[c * (B + 1) + B];
+      mc_f[t] = (n != 0.0) ? (float)(first[c * (B + 1) + b] / n) : 0.f;
+    }
+    if (threadIdx.x == 0) *ticket = 0u;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_soft_scatter(const float* __restrict__ X,
+                                                         const float* __restrict__ W, int64_t N,
+                                                         int B, int K, int G,
+                                                         const float* __restrict__ mc_f,
+                                                         double* __restrict__ part) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int BP = (B + 1 + 3) & ~3;
+  float* ds = reinterpret_cast<float*>(smem_raw);   // kChunk x BP: [x - m_c, 1]
+  float* as = ds + kChunk * BP;                      // kChunk x BP: w_pc * ds
+  double* red = reinterpret_cast<double*>(smem_raw);
+  __shared__ float mcs[kMaxB];
+  __shared__ float wrow[kChunk];
+  const int c = blockIdx.y, g = blockIdx.x;
+  for (int b = threadIdx.x; b < B; b += kBlock) mcs[b] = mc_f[c * B + b];
+  const int nb = BP / 4, nblk = nb * (nb + 1) / 2, nslice = kBlock / nblk;
+  const int blk = threadIdx.x % nblk, slice = threadIdx.x / nblk;
+  int bi = 0, bj = 0;
+  const bool active = slice < nslice && tri_tile(blk, nb, bi, bj);
+  float acc[16];
+  double accd[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    acc[e] = 0.f;
+    accd[e] = 0.0;
+  }
+  __syncthreads();
+  const int64_t nch = (N + kChunk - 1) / kChunk;
+  for (int64_t ch = g; ch < nch; ch += G) {
+    const int64_t r0 = ch * kChunk;
+    const int rows = (N - r0 < kChunk) ? (int)(N - r0) : kChunk;
+    if (threadIdx.x < kChunk)
+      wrow[threadIdx.x] = (threadIdx.x < rows) ? W[(r0 + threadIdx.x) * K + c] : 0.f;
+    stage_rows(X, B, BP, r0, rows, ds);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kChunk * BP; e += kBlock) {
+      const int r = e / BP, col = e % BP;
+      float d = 0.f;
+      if (r < rows) {
+        if (col < B) d = ds[e] - mcs[col];
+        else if (col == B) d = 1.f;
+      }
+      ds[e] = d;
+      as[e] = wrow[r] * d;
+    }
+    __syncthreads();
+    if (active) tile_acc(as, BP, ds, BP, bi, bj, slice, kChunk, nslice, acc);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      accd[e] += (double)acc[e];
+      acc[e] = 0.f;
+    }
+  }
+  __syncthreads();
+  if (active)
+    for (int e = 0; e < 16; ++e) red[(slice * nblk + blk) * 16 + e] = accd[e];
+  __syncthreads();
+  double* out = part + ((int64_t)c * G + g) * nblk * 16;
+  for (int t = threadIdx.x; t < nblk * 16; t += kBlock) {
+    double s = 0.0;
+    for (int sl = 0; sl < nslice; ++sl) s += red[sl * nblk * 16 + t];
+    out[t] = s;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_soft_backward(const float* __restrict__ X, int64_t N, int B,
+                                                          int K, SoftBwdArgs a, int accumulate,
+                                                          float* __restrict__ dw) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int S = B;                         // one row = B dwords
+  uint32_t* my = lds + w * 64 * S;
+  const int64_t nt = (N + 63) / 64;
+  const int64_t total_bytes = N * B * 4;
+  const unsigned char* base = reinterpret_cast<const unsigned char*>(X);
+  for (int64_t t = (int64_t)blockIdx.x * kWaves + w; t < nt; t += (int64_t)gridDim.x * kWaves) {
+    const int64_t tb = t * 256 * (int64_t)S;
+    for (int j = lane; j < 16 * S; j += 64) {
+      const int64_t ob = tb + 16 * (int64_t)j;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (ob + 16 <= total_bytes) {
+        v = *reinterpret_cast<const uint4*>(base + ob);
+      } else {
+        uint32_t h[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          h[q] = (ob + 4 * q + 4 <= total_bytes) ? *reinterpret_cast<const uint32_t*>(base + ob + 4 * q) : 0u;
+        v = make_uint4(h[0], h[1], h[2], h[3]);
+      }
+      *reinterpret_cast<uint4*>(my + 4 * j) = v;
+    }
+    wave_lds_sync();
+    const int64_t row = t * 64 + lane;
+    float z[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) z[j] = 0.f;
+    const uint32_t* d = my + lane * S;
+    for (int b = 0; b < B; ++b) {
+      const float u = __uint_as_float(d[b]) - a.m[b];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) z[j] = fmaf(a.w[b * 8 + j], u, z[j]);
+    }
+    wave_lds_sync();
+    if (row < N) {
+      float tz = 0.f;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) tz = fmaf(z[j], z[j], tz);
+      for (int c = 0; c < K; ++c) {
+        float q = 0.f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const float e = z[j] - a.d[c * 8 + j];
+          q = fmaf(a.lam1[j] * e, e, q);
+        }
+        const float g = a.scale * (tz - q);
+        float* o = dw + row * K + c;
+        *o = accumulate ? (*o + g) : g;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_soft_first(const float* X, const float* w, int64_t N, int B, int K, int nblocks,
+                             double* part, unsigned* ticket, double* first, float* mc_f,
+                             hipStream_t s) {
+  const int BP = padded_bp(B), KP = (K + 3) & ~3;
+  const size_t a = (size_t)kChunk * (BP + KP) * sizeof(float);
+  const int nblk = (KP / 4) * (BP / 4);
+  const size_t r = (size_t)(kBlock / nblk) * nblk * 16 * sizeof(double);
+  const size_t sm = a > r ? a : r;
+  hipLaunchKernelGGL(k_soft_first, dim3(nblocks), dim3(kBlock), sm, s, X, w, N, B, K, part, ticket,
+                     first, mc_f);
+  return hipGetLastError();
+}
+
+hipError_t launch_soft_scatter(const float* X, const float* w, int64_t N, int B, int K, int G,
+                               const float* mc_f, double* part, hipStream_t s) {
+  const int BP = padded_bp(B);
+  const size_t a = (size_t)2 * kChunk * BP * sizeof(float);
+  const int nblk = tri_blocks(B);
+  const size_t r = (size_t)(kBlock / nblk) * nblk * 16 * sizeof(double);
+  const size_t sm = a > r ? a : r;
+  hipLaunchKernelGGL(k_soft_scatter, dim3(G, K), dim3(kBlock), sm, s, X, w, N, B, K, G, mc_f, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_soft_backward(const float* X, int64_t N, int B, int K, const SoftBwdArgs& a,
+                                bool accumulate, int nblocks, float* dw, hipStream_t s) {
+  const size_t sm = (size_t)kWaves * 64 * B * 4;
+  hipLaunchKernelGGL(k_soft_backward, dim3(nblocks), dim3(kBlock), sm, s, X, N, B, K, a,
+                     accumulate ? 1 : 0, dw);
+  return hipGetLastError();
+}
+
+}  // namespace cvx

@@ -1,0 +1,74 @@
+// Host-side launchers for the gfx950 kernels (defined in the k_*.hip files).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cvx {
+
+constexpr int kLabelTile = 65536;   // label pixels per block in the label kernels
+constexpr int kBlock = 256;         // threads per block in every kernel
+constexpr int kWaves = kBlock / 64; // waves per block
+constexpr int kChunk = 128;         // rows staged per chunk in the scatter kernels
+constexpr int kMaxB = 64;
+
+// Parameters of one projection pass, passed by value in the kernel
+// arguments (fits the 4 KiB argument limit).
+struct ProjArgs {
+  float w[64 * 8];   // W[b * nc + j] for this group of nc <= 8 components
+  float c[64];       // per-band centre (integer for uint16 pages)
+  float off[8];      // sum_b W[b][j] (c_b - centre_b), added to each y_j
+};
+
+struct SoftBwdArgs {
+  float w[64 * 8];   // W[b * 8 + j] for this group of 8 components (zero padded)
+  float m[64];       // grand mean
+  float d[32 * 8];   // d[c * 8 + j] = w_j^T (m_c - m)
+  float lam1[8];     // 1 + lambda_j (zero for padded components)
+  float scale;       // dJ
+};
+
+// label bookkeeping
+hipError_t launch_label_count(const int8_t* labels, int64_t P, int K, int nT,
+                              int32_t* tile_counts, int32_t* err_flag, hipStream_t s);
+hipError_t launch_label_index(const int8_t* labels, int64_t P, int K, int nT,
+                              const int32_t* tile_counts, int32_t* idx,
+                              int64_t* counts_out, int32_t* offsets_out, hipStream_t s);
+
+// class moments: per-class augmented Gram of [x - c_k, 1] about a per-class
+// shift c_k; partials part[(k * G + g) * L + t], L = nblk * 16.
+hipError_t launch_class_moments(int dtype, const void* cube, int B, const int32_t* idx,
+                                const int32_t* offsets, int K, int G, double* part,
+                                double* shift_out, hipStream_t s);
+// PCA: augmented Gram of [x - s, 1] over all (or masked) pixels.
+hipError_t launch_pca_gram(int dtype, const void* cube, int B, int64_t P,
+                           const uint8_t* mask, int nblocks, double* part,
+                           double* shift_out, hipStream_t s);
+// out[s * L + t] = sum_g part[(s * G + g) * L + t]
+hipError_t launch_reduce_part(const double* part, int nsets, int G, int L, double* out,
+                              hipStream_t s);
+
+// projection, pass 1 (range) and pass 2 (stretch to uint8)
+hipError_t launch_project_range(int dtype, const void* cube, int B, int64_t P, int nc,
+                                const ProjArgs& a, int nblocks, float* part,
+                                unsigned* ticket, float* range_dev, float* ab_dev,
+                                hipStream_t s);
+hipError_t launch_project_stretch(int dtype, const void* cube, int B, int64_t P, int nc,
+                                  int nvalid, const ProjArgs& a, int nblocks,
+                                  const float* range_dev, uint8_t* images, hipStream_t s);
+
+// soft-label CVA
+hipError_t launch_soft_first(const float* X, const float* w, int64_t N, int B, int K,
+                             int nblocks, double* part, unsigned* ticket, double* first,
+                             float* mc_f, hipStream_t s);
+hipError_t launch_soft_scatter(const float* X, const float* w, int64_t N, int B, int K,
+                               int G, const float* mc_f, double* part, hipStream_t s);
+hipError_t launch_soft_backward(const float* X, int64_t N, int B, int K, const SoftBwdArgs& a,
+                                bool accumulate, int nblocks, float* dw, hipStream_t s);
+
+inline int padded_bp(int B) { return (B + 1 + 3) & ~3; }
+inline int tri_blocks(int B) {
+  const int nb = padded_bp(B) / 4;
+  return nb * (nb + 1) / 2;
+}
+
+}  // namespace cvx

@@ -1,0 +1,319 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, on the
+same seeded inputs.
+
+Tolerances (FP32 path): class counts bit-exact; S_w, S_b within 1e-5 of the
+largest entry; eigenvalues within 1e-5 relative; sign-aligned canonical
+vectors within 1e-4; projection ranges within 1e-4 of b - a; 8-bit images
+within one grey level.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import make_case, make_soft_case, to_half_cube
+from tests._parity import (TOL_LAM, TOL_S, TOL_Y, check_images, check_vectors, rel_max)
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1612_06457_amd  # noqa: F401  (raises if the library is missing)
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    import torch
+    if hasattr(a, "to"):
+        return a.contiguous().to(dev)
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _fit_parity(cube_host, labels, K, dev, ridge=0.0):
+    import paper_1612_06457_amd as cx
+    ref = oracle.cva_fit(cube_host, labels, K, ridge=ridge)
+    got = cx.cva_fit(_t(cube_host, dev), _t(labels, dev), K, ridge=ridge)
+    assert got.counts.tolist() == ref["counts"].tolist()
+    assert rel_max(got.class_means, ref["class_means"]) <= 1e-7
+    assert rel_max(got.Sw, ref["Sw"]) <= TOL_S
+    assert rel_max(got.Sb, ref["Sb"]) <= TOL_S
+    assert np.max(np.abs(got.eigvals - ref["eigvals"]) / ref["eigvals"]) <= TOL_LAM
+    signs, _ = check_vectors(got.W, ref["W"], ref["eigvals"])
+    assert rel_max(got.mean, ref["mean"]) <= 1e-7
+    return ref, got, signs
+
+
+def _project_parity(cube_host, W, center, dev, signs=None):
+    import paper_1612_06457_amd as cx
+    q_ref, ab_ref = oracle.cva_project(cube_host, W, center)
+    q, ab = cx.cva_project(_t(cube_host, dev), W, center, return_range=True)
+    q = q.cpu().numpy()
+    span = ab_ref[:, 1] - ab_ref[:, 0]
+    assert np.max(np.abs(ab - ab_ref) / span[:, None]) <= TOL_Y
+    frac = check_images(q, q_ref, None)
+    return q, q_ref, frac
+
+
+# ------------------------------------------------------------------ configs
+
+def test_cfg1_fit_and_project(dev):
+    say("cfg1 512x512x16 u16 K=3")
+    c = make_case(1)
+    ref, got, signs = _fit_parity(c.cube, c.labels, c.K, dev)
+    # projection with the oracle's own vectors isolates the projection kernel
+    _project_parity(c.cube, ref["W"], ref["mean"], dev)
+    # end to end: the GPU fit's vectors, compared after sign alignment
+    import paper_1612_06457_amd as cx
+    q = cx.cva_project(_t(c.cube, dev), got.W, got.mean).cpu().numpy()
+    q_ref, _ = oracle.cva_project(c.cube, ref["W"], ref["mean"])
+    frac = check_images(q, q_ref, signs)
+    say(f"cfg1 differing bytes {frac:.2e}")
+
+
+def test_cfg2_scaled_cva_and_pca(dev):
+    say("cfg2 at 1024x1024x23 u16 K=4")
+    import paper_1612_06457_amd as cx
+    c = make_case(2, scale=0.25)
+    ref, got, signs = _fit_parity(c.cube, c.labels, c.K, dev)
+    _project_parity(c.cube, ref["W"], ref["mean"], dev)
+    pr = oracle.pca_fit(c.cube, n_comp=3)
+    V, lam, mean, cov = cx.pca_fit(_t(c.cube, dev), n_comp=3)
+    assert rel_max(cov, pr["cov"]) <= TOL_S
+    assert np.max(np.abs(lam - pr["eigvals"]) / pr["eigvals"]) <= TOL_LAM
+    assert rel_max(mean, pr["mean"]) <= 1e-9
+    s, _ = check_vectors(V, pr["V"], pr["all_eigvals"][:3])
+    _project_parity(c.cube, pr["V"], pr["mean"], dev)
+
+
+@pytest.mark.parametrize("H,W,B,K", [
+    (37, 53, 7, 3), (5, 7, 3, 2), (64, 64, 16, 4), (33, 31, 33, 5), (40, 41, 64, 3),
+    (19, 23, 1, 2), (50, 50, 2, 3), (128, 96, 23, 8), (3, 300, 9, 2)])
+def test_shapes_and_ragged_tails(dev, H, W, B, K):
+    say(f"shape H={H} W={W} B={B} K={K}")
+    rng = np.random.default_rng(H * 1000 + W * 10 + B)
+    mu = rng.uniform(800, 3500, (K, B))
+    cls = rng.integers(0, K, H * W)
+    cube = np.clip(np.rint(mu[cls] + rng.normal(0, 60, (H * W, B))), 0, 4095).astype(np.uint16)
+    cube = cube.reshape(H, W, B)
+    lab = np.where(rng.random(H * W) < 0.5, cls, -1).astype(np.int8)
+    for k in range(K):                         # at least B + 2 pixels per class
+        idx = np.flatnonzero(cls == k)
+        if idx.size < B + 2:
+            extra = rng.choice(H * W, B + 2, replace=False)
+            cls[extra] = k
+            cube.reshape(-1, B)[extra] = np.clip(np.rint(mu[k] + rng.normal(0, 60, (B + 2, B))), 0, 4095)
+            idx = extra
+        lab[idx[: B + 2]] = k
+    labels = lab.reshape(H, W)
+    ref, got, signs = _fit_parity(cube, labels, K, dev)
+    _project_parity(cube, ref["W"], ref["mean"], dev)
+
+
+def test_single_pixel_class(dev):
+    say("class with one training pixel")
+    c = make_case(1, scale=0.25)
+    lab = c.labels.copy()
+    k2 = np.flatnonzero(lab.reshape(-1) == 2)
+    lab.reshape(-1)[k2[1:]] = -1
+    _fit_parity(c.cube, lab, 3, dev)
+
+
+@pytest.mark.parametrize("kind", ["f32", "bf16", "f16"])
+def test_float_pages(dev, kind):
+    say(f"float page {kind}")
+    import paper_1612_06457_amd as cx
+    c = make_case(2, scale=0.12)
+    if kind == "f32":
+        cube = c.cube.astype(np.float32) / np.float32(4095.0)
+    else:
+        cube = to_half_cube(c.cube, kind)
+    host = cube if kind == "f32" else cube.float().numpy()
+    ref = oracle.cva_fit(host, c.labels, c.K)
+    got = cx.cva_fit(_t(cube, dev), _t(c.labels, dev), c.K)
+    assert got.counts.tolist() == ref["counts"].tolist()
+    assert rel_max(got.Sw, ref["Sw"]) <= TOL_S
+    assert rel_max(got.Sb, ref["Sb"]) <= TOL_S
+    assert np.max(np.abs(got.eigvals - ref["eigvals"]) / ref["eigvals"]) <= TOL_LAM
+    check_vectors(got.W, ref["W"], ref["eigvals"])
+    q_ref, ab_ref = oracle.cva_project(host, ref["W"], ref["mean"])
+    q, ab = cx.cva_project(_t(cube, dev), ref["W"], ref["mean"], return_range=True)
+    span = ab_ref[:, 1] - ab_ref[:, 0]
+    assert np.max(np.abs(ab - ab_ref) / span[:, None]) <= TOL_Y
+    check_images(q.cpu().numpy(), q_ref)
+    pr = oracle.pca_fit(host, n_comp=3)
+    V, lam, mean, cov = cx.pca_fit(_t(cube, dev), n_comp=3)
+    assert rel_max(cov, pr["cov"]) <= TOL_S
+    check_vectors(V, pr["V"], pr["all_eigvals"][:3])
+
+
+def test_pca_mask(dev):
+    say("pca with mask")
+    import paper_1612_06457_amd as cx
+    c = make_case(1, scale=0.5)
+    rng = np.random.default_rng(7)
+    mask = (rng.random((c.H, c.W)) < 0.3).astype(np.uint8)
+    pr = oracle.pca_fit(c.cube, mask=mask, n_comp=4)
+    V, lam, mean, cov = cx.pca_fit(_t(c.cube, dev), mask=_t(mask, dev), n_comp=4)
+    assert rel_max(cov, pr["cov"]) <= TOL_S
+    assert rel_max(mean, pr["mean"]) <= 1e-9
+    check_vectors(V, pr["V"], pr["all_eigvals"][:4])
+
+
+def test_many_components_and_groups(dev):
+    say("projection with 11 components (two groups)")
+    rng = np.random.default_rng(3)
+    cube = rng.integers(0, 4096, (61, 47, 23)).astype(np.uint16)
+    W = rng.standard_normal((23, 11))
+    center = rng.uniform(1000, 3000, 23)
+    _project_parity(cube, W, center, dev)
+
+
+def test_errors(dev):
+    say("error paths")
+    import paper_1612_06457_amd as cx
+    c = make_case(1, scale=0.2)
+    cube = _t(c.cube, dev)
+    bad = c.labels.copy()
+    bad[0, 0] = 5
+    with pytest.raises(cx.CvamxError) as e:
+        cx.cva_fit(cube, _t(bad, dev), 3)
+    assert e.value.status == -1
+    lab = c.labels.copy()
+    lab[lab == 1] = -1
+    with pytest.raises(cx.CvamxError) as e:
+        cx.cva_fit(cube, _t(lab, dev), 3)
+    assert e.value.status == -3
+    dup = c.cube.copy()
+    dup[..., 5] = dup[..., 4]
+    with pytest.raises(cx.CvamxError) as e:
+        cx.cva_fit(_t(dup, dev), _t(c.labels, dev), 3)
+    assert e.value.status == -4
+    # the library still works after errors
+    _fit_parity(c.cube, c.labels, 3, dev)
+
+
+def test_repeatable(dev):
+    say("bitwise repeatability")
+    import paper_1612_06457_amd as cx
+    c = make_case(2, scale=0.1)
+    cube, lab = _t(c.cube, dev), _t(c.labels, dev)
+    a = cx.cva_fit(cube, lab, c.K)
+    b = cx.cva_fit(cube, lab, c.K)
+    assert np.array_equal(a.W, b.W) and np.array_equal(a.Sw, b.Sw)
+    qa, ra = cx.cva_project(cube, a.W, a.mean, return_range=True)
+    qb, rb = cx.cva_project(cube, a.W, a.mean, return_range=True)
+    assert np.array_equal(ra, rb)
+    assert bool((qa == qb).all())
+    p1 = cx.pca_fit(cube, n_comp=3)
+    p2 = cx.pca_fit(cube, n_comp=3)
+    assert np.array_equal(p1[3], p2[3])
+
+
+# ---------------------------------------------------------------- soft label
+
+def _soft_parity(X, w, dev, gtol=1e-4):
+    import paper_1612_06457_amd as cx
+    ref = oracle.soft_fit(X, w)
+    g_ref = oracle.soft_grad(X, w)
+    Xd, wd = _t(X, dev), _t(w, dev)
+    fit = cx.cva_soft_forward(Xd, wd)
+    assert abs(fit.J - ref["J"]) <= TOL_LAM * ref["J"]
+    assert np.max(np.abs(fit.eigvals - ref["eigvals"]) / ref["eigvals"]) <= TOL_LAM
+    check_vectors(fit.W, ref["W"], ref["eigvals"])
+    g = cx.cva_soft_backward(Xd, fit, 1.0, w.shape[1]).cpu().numpy()
+    gmax = np.max(np.abs(g_ref))
+    assert np.max(np.abs(g - g_ref)) <= gtol * gmax
+    return fit, g, g_ref
+
+
+def test_soft_label_small(dev):
+    say("soft-label CVA, cfg4 structure at 1/16 scale")
+    X, w, cls, idx, case = make_soft_case(4, scale=0.25)
+    _soft_parity(X, w, dev)
+
+
+def test_soft_label_one_hot_equals_hard_fit(dev):
+    say("soft-label with one-hot weights")
+    import paper_1612_06457_amd as cx
+    c = make_case(1, scale=0.5)
+    flat = c.labels.reshape(-1)
+    idx = np.flatnonzero(flat >= 0)
+    X = c.cube.reshape(-1, c.B)[idx].astype(np.float32)
+    w = np.zeros((idx.size, c.K), np.float32)
+    w[np.arange(idx.size), flat[idx]] = 1
+    fit = cx.cva_soft_forward(_t(X, dev), _t(w, dev))
+    hard = cx.cva_fit(_t(c.cube, dev), _t(c.labels, dev), c.K)
+    assert abs(fit.J - hard.eigvals.sum()) <= 1e-5 * fit.J
+
+
+def test_soft_label_autograd(dev):
+    say("SoftCVA autograd")
+    import torch
+    import paper_1612_06457_amd as cx
+    X, w, cls, idx, case = make_soft_case(4, scale=0.1)
+    Xd = _t(X, dev)
+    wd = _t(w, dev).requires_grad_(True)
+    J = cx.SoftCVA.apply(Xd, wd)
+    (2.5 * J).backward()
+    fit = cx.cva_soft_forward(Xd, wd.detach())
+    g = cx.cva_soft_backward(Xd, fit, 2.5, w.shape[1])
+    assert torch.allclose(wd.grad, g, rtol=0, atol=1e-6 * float(g.abs().max()))
+    assert abs(float(J) - fit.J) <= 1e-12 * fit.J
+
+
+# ------------------------------------------------------------ full sizes
+
+@pytest.mark.timeout(900)
+def test_full_page_cfg5(dev):
+    """7216 x 5412 x 33 uint16 page, K = 8, 200k training pixels per class:
+    fit parity, every pixel of the 7 projected images, and PCA."""
+    say("cfg5 full page 7216x5412x33 u16 K=8")
+    import paper_1612_06457_amd as cx
+    c = make_case(5, threads=16)
+    say("cfg5 generated")
+    ref, got, signs = _fit_parity(c.cube, c.labels, c.K, dev)
+    say("cfg5 fit ok", got.eigvals)
+    cube = _t(c.cube, dev)
+    q, ab = cx.cva_project(cube, ref["W"], ref["mean"], return_range=True)
+    q = q.cpu().numpy()
+    q_ref, ab_ref = oracle.cva_project(c.cube, ref["W"], ref["mean"])
+    span = ab_ref[:, 1] - ab_ref[:, 0]
+    assert np.max(np.abs(ab - ab_ref) / span[:, None]) <= TOL_Y
+    frac = check_images(q, q_ref)
+    say(f"cfg5 project ok, differing bytes {frac:.2e}")
+    del q, q_ref
+    pr = oracle.pca_fit(c.cube, n_comp=3)
+    V, lam, mean, cov = cx.pca_fit(cube, n_comp=3)
+    assert rel_max(cov, pr["cov"]) <= TOL_S
+    assert np.max(np.abs(lam - pr["eigvals"]) / pr["eigvals"]) <= TOL_LAM
+    check_vectors(V, pr["V"], pr["all_eigvals"][:3])
+    say("cfg5 pca ok")
+
+
+@pytest.mark.timeout(600)
+def test_full_soft_cfg4(dev):
+    """1,000,000 x 23 float32 training pixels, K = 5, Dirichlet(0.5) weights
+    near class borders: J, gradient against the closed form, and central
+    differences of the exact finite change on 64 random pixels."""
+    say("cfg4 soft label 1M x 23, K=5")
+    X, w, cls, idx, case = make_soft_case(4)
+    fit, g, g_ref = _soft_parity(X, w, dev)
+    rng = np.random.default_rng(4)
+    gmax = np.max(np.abs(g_ref))
+    h = 1e-3
+    mom = oracle.soft_moments(X, w)
+    for _ in range(64):
+        p = int(rng.integers(0, X.shape[0]))
+        k = int(rng.integers(0, w.shape[1]))
+        fd = (oracle.soft_delta_J(X, w, p, k, h, mom) - oracle.soft_delta_J(X, w, p, k, -h, mom)) / (2 * h)
+        assert abs(g[p, k] - fd) <= 1e-4 * gmax

@@ -1,0 +1,171 @@
+"""CPU tests of the C ABI library: it loads, exports every declared symbol,
+its FP64 finisher agrees with LAPACK, and argument checking returns the
+documented status codes without touching a GPU (context with device -1).
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cvamx.h")
+
+
+def _lib():
+    from paper_1612_06457_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libcvamx.so not built")
+    return L
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    text = open(HEADER).read()
+    names = re.findall(r"^\s*(?:int|int64_t|void|const char\*)\s+(\w+)\s*\(", text, re.M)
+    assert len(names) >= 12
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTS)
+
+
+def test_sym_eig_matches_lapack():
+    _lib()
+    from paper_1612_06457_amd import sym_eig
+    rng = np.random.default_rng(0)
+    for n in (1, 2, 3, 7, 16, 23, 33, 64):
+        G = rng.standard_normal((n, n))
+        A = G + G.T
+        w, V = sym_eig(A)
+        ref = np.sort(np.linalg.eigvalsh(A))[::-1]
+        assert np.max(np.abs(w - ref)) <= 1e-12 * max(1, np.abs(ref).max())
+        assert np.max(np.abs(V.T @ V - np.eye(n))) <= 1e-12
+        assert np.max(np.abs(A @ V - V * w)) <= 1e-11 * max(1, np.abs(ref).max())
+        for j in range(n):                          # sign rule
+            i = int(np.argmax(np.abs(V[:, j])))
+            assert V[i, j] > 0
+
+
+def _scatter_case(rng, K, B, cond=1e2):
+    counts = rng.integers(1, 5000, K)
+    cm = rng.uniform(800, 3500, (K, B))
+    Q, _ = np.linalg.qr(rng.standard_normal((B, B)))
+    ev = np.logspace(0, np.log10(cond), B) * 1e4
+    Sw = (Q * ev) @ Q.T
+    return counts, cm, 0.5 * (Sw + Sw.T)
+
+
+@pytest.mark.parametrize("K,B", [(2, 3), (3, 16), (4, 23), (8, 33), (5, 4), (12, 5), (40, 33), (3, 64)])
+def test_cva_solve_moments_matches_lapack(K, B):
+    _lib()
+    import oracle
+    from paper_1612_06457_amd import cva_solve_moments
+    rng = np.random.default_rng(K * 100 + B)
+    for cond in (1e1, 1e4):
+        counts, cm, Sw = _scatter_case(rng, K, B, cond)
+        C = min(K - 1, B)
+        W, lam, mean = cva_solve_moments(counts, cm, Sw)
+        Sb = oracle.between_scatter(counts, cm)
+        lam_r, W_r = oracle.generalized_eig(Sb, Sw)
+        W_r = oracle.sign_rule(W_r[:, :C])
+        assert np.max(np.abs(lam - lam_r[:C])) <= 1e-10 * lam_r[0]
+        assert np.max(np.abs(W.T @ Sw @ W - np.eye(C))) <= 1e-9
+        # eigenvectors of distinct eigenvalues agree (sign rule applied on both)
+        lr = lam_r[:C + 1] if C < B else np.append(lam_r[:C], -np.inf)
+        gaps = np.abs(np.diff(lr)) / lam_r[0]
+        for j in range(C):
+            lo = gaps[j - 1] if j > 0 else 1.0
+            if min(lo, gaps[j]) > 1e-6:
+                assert np.max(np.abs(W[:, j] - W_r[:, j])) <= 1e-8 * np.max(np.abs(W_r[:, j]))
+        n = counts.astype(float)
+        assert np.allclose(mean, (n[:, None] * cm).sum(0) / n.sum(), rtol=1e-14, atol=0)
+
+
+def test_cva_solve_moments_error_codes():
+    L = _lib()
+    from paper_1612_06457_amd import cva_solve_moments, CvamxError
+    rng = np.random.default_rng(3)
+    counts, cm, Sw = _scatter_case(rng, 4, 6)
+    Sw2 = Sw.copy()
+    Sw2[:, 1] = Sw2[:, 0]
+    Sw2[1, :] = Sw2[0, :]
+    with pytest.raises(CvamxError) as e:
+        cva_solve_moments(counts, cm, Sw2)
+    assert e.value.status == L.E_NOT_PD
+    c0 = counts.copy()
+    c0[2] = 0
+    with pytest.raises(CvamxError) as e:
+        cva_solve_moments(c0, cm, Sw)
+    assert e.value.status == L.E_EMPTY_CLASS
+    with pytest.raises(CvamxError) as e:
+        cva_solve_moments(counts, cm, Sw, n_comp=4)
+    assert e.value.status == L.E_INVALID_ARG
+    # a ridge makes a singular S_w solvable
+    W, lam, _ = cva_solve_moments(counts, cm, Sw2, ridge=1.0)
+    assert np.isfinite(W).all() and (lam >= 0).all()
+
+
+def test_argument_checks_without_a_device():
+    L = _lib()
+    lib = L.lib()
+    ctx = ctypes.c_void_p()
+    assert lib.cvamx_create(ctypes.byref(ctx), -1) == L.OK
+    try:
+        buf = (ctypes.c_double * 4096)()
+        i64 = (ctypes.c_int64 * 128)()
+        aligned = ctypes.c_void_p(0x10000)           # never dereferenced: checks come first
+        lab = ctypes.c_void_p(0x20000)
+
+        def fit(cube, labels=lab, K=3, prec=0, ridge=0.0, n_comp=2, W=buf):
+            return lib.cva_fit(ctx, ctypes.byref(cube) if cube is not None else None, labels, K,
+                               prec, ridge, n_comp, W, buf, buf, i64, None, None, None, None)
+
+        good = L.Cube(aligned.value, 16, 16, 8, L.DT_U16)
+        assert fit(None) == L.E_INVALID_ARG
+        assert fit(L.Cube(None, 16, 16, 8, 0)) == L.E_INVALID_ARG
+        assert fit(L.Cube(aligned.value, 0, 16, 8, 0)) == L.E_INVALID_ARG
+        assert fit(L.Cube(aligned.value, 16, 16, 65, 0)) == L.E_UNSUPPORTED
+        assert fit(L.Cube(aligned.value, 16, 16, 8, 9)) == L.E_UNSUPPORTED
+        assert fit(L.Cube(aligned.value + 2, 16, 16, 8, 0)) == L.E_UNSUPPORTED
+        assert fit(L.Cube(aligned.value, 1 << 16, 1 << 16, 8, 0)) == L.E_UNSUPPORTED
+        assert fit(good, labels=None) == L.E_INVALID_ARG
+        assert fit(good, labels=ctypes.c_void_p(0x20001)) == L.E_UNSUPPORTED
+        assert fit(good, K=1) == L.E_INVALID_ARG
+        assert fit(good, K=128) == L.E_INVALID_ARG
+        assert fit(good, prec=7) == L.E_INVALID_ARG
+        assert fit(good, ridge=-1.0) == L.E_INVALID_ARG
+        assert fit(good, ridge=float("nan")) == L.E_INVALID_ARG
+        assert fit(good, n_comp=3) == L.E_INVALID_ARG
+        assert fit(good, n_comp=0) == L.E_INVALID_ARG
+        assert fit(good, W=None) == L.E_INVALID_ARG
+        assert fit(good) == L.E_DEVICE
+        assert b"no device" in lib.cvamx_last_error(ctx)
+        # projection
+        W = np.zeros((8, 2))
+        c = np.zeros(8)
+        assert lib.cva_project(ctx, ctypes.byref(good), W.ctypes.data, c.ctypes.data, 0, aligned,
+                               None, None) == L.E_INVALID_ARG
+        W[0, 0] = np.nan
+        assert lib.cva_project(ctx, ctypes.byref(good), W.ctypes.data, c.ctypes.data, 2, aligned,
+                               None, None) == L.E_INVALID_ARG
+        W[0, 0] = 0
+        assert lib.cva_project(ctx, ctypes.byref(good), W.ctypes.data, c.ctypes.data, 2, aligned,
+                               None, None) == L.E_DEVICE
+        # pca
+        assert lib.pca_fit(ctx, ctypes.byref(good), None, 9, 0, buf, buf, buf, None, None) == L.E_INVALID_ARG
+        assert lib.pca_fit(ctx, ctypes.byref(good), None, 3, 0, buf, buf, buf, None, None) == L.E_DEVICE
+        # soft
+        X = ctypes.c_void_p(0x30000)
+        assert lib.cva_soft_forward(ctx, X, X, 100, 8, 1, 0, 0.0, buf, buf, buf, buf, buf, None) == L.E_INVALID_ARG
+        assert lib.cva_soft_forward(ctx, X, X, 100, 8, 33, 0, 0.0, buf, buf, buf, buf, buf, None) == L.E_INVALID_ARG
+        assert lib.cva_soft_forward(ctx, ctypes.c_void_p(0x30004), X, 100, 8, 3, 0, 0.0, buf, buf, buf, buf,
+                                    buf, None) == L.E_UNSUPPORTED
+        assert lib.cva_soft_forward(ctx, X, X, 100, 8, 3, 0, 0.0, buf, buf, buf, buf, buf, None) == L.E_DEVICE
+        assert lib.cva_soft_backward(ctx, X, buf, buf, buf, buf, 100, 8, 3, float("inf"), X, None) == L.E_INVALID_ARG
+        assert lib.cva_soft_backward(ctx, X, buf, buf, buf, buf, 100, 8, 3, 1.0, X, None) == L.E_DEVICE
+    finally:
+        lib.cvamx_destroy(ctx)
+    assert lib.cvamx_status_str(L.E_NOT_PD) == b"within-class scatter not positive definite"
