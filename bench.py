@@ -90,7 +90,7 @@ def main():
     rng = np.random.default_rng([case.seed, 0x50F7])
     nb = border_map(case.class_map)[np.unravel_index(idx, case.labels.shape)]
     wts = soft_weights(cls, nb, K, rng)
-    X = cube.view(-1, B)[torch.from_numpy(idx).to(dev)].float().contiguous()
+    X = torch.from_numpy(case.cube.reshape(-1, B)[idx].astype(np.float32)).to(dev)
     w = torch.from_numpy(wts).to(dev)
     N = X.shape[0]
     C = K - 1

@@ -33,7 +33,7 @@ struct cvamx_ctx {
   void* pinned = nullptr;
   size_t pinned_cap = 0;
   unsigned* tickets = nullptr;   // [0] projection range, [1] soft first moments
-  float* range_dev = nullptr;    // 16 floats: lo[8], scale[8] of the current group
+  float* range_dev = nullptr;    // 16 floats: scale[8], offset[8] of the current group
   float* ab_dev = nullptr;       // 2 * CVAMX_MAX_BANDS floats: (min, max) per component
   // kernel timing (cvamx_profile_enable)
   bool prof = false;
@@ -212,7 +212,7 @@ int proj_groups(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const d
   if (int st = ensure(ctx, B_PROJPART, (size_t)nblocks * 16 * sizeof(float))) return st;
   for (int g0 = 0; g0 < n_comp; g0 += 8) {
     const int nc = std::min(8, n_comp - g0);
-    const int NC = nc <= 4 ? 4 : 8;
+    const int NC = nc;   // the kernels are instantiated for 1..8 components
     cvx::ProjArgs a;
     std::memset(&a, 0, sizeof(a));
     std::vector<double> c(B);
@@ -368,8 +368,6 @@ int cva_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels, int32_
   if (n_comp < 1 || n_comp > C) return fail(ctx, CVAMX_E_INVALID_ARG, "n_comp must lie in 1..min(K-1, bands)");
   if (!W || !eigvals || !mean || !counts)
     return fail(ctx, CVAMX_E_INVALID_ARG, "W, eigvals, mean and counts must be non-NULL");
-  if (prec != CVAMX_PREC_FP32)
-    return fail(ctx, CVAMX_E_UNSUPPORTED, "only the FP32 scatter path is built in this library");
   if (int st = check_device(ctx)) return st;
   hipStream_t s = (hipStream_t)stream;
   const int64_t P = cube->height * cube->width;
@@ -394,10 +392,17 @@ int cva_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels, int32_
                               (int64_t*)(res + lay.counts), (int32_t*)(res + lay.offsets), s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "label index launch");
-  prof_begin(ctx, s, "class_moments");
-  e = cvx::launch_class_moments(cube->dtype, cube->data, B, (const int32_t*)ctx->buf[B_IDX],
-                                (const int32_t*)(res + lay.offsets), K, G, (double*)ctx->buf[B_PART],
-                                (double*)(res + lay.shift), s);
+  if (prec == CVAMX_PREC_FP32) {
+    prof_begin(ctx, s, "class_moments");
+    e = cvx::launch_class_moments(cube->dtype, cube->data, B, (const int32_t*)ctx->buf[B_IDX],
+                                  (const int32_t*)(res + lay.offsets), K, G, (double*)ctx->buf[B_PART],
+                                  (double*)(res + lay.shift), s);
+  } else {
+    prof_begin(ctx, s, "class_moments_mfma");
+    e = cvx::launch_class_moments_mfma(cube->dtype, prec == CVAMX_PREC_BF16X3 ? 0 : 1, cube->data, B,
+                                       (const int32_t*)ctx->buf[B_IDX], (const int32_t*)(res + lay.offsets), K,
+                                       G, (double*)ctx->buf[B_PART], (double*)(res + lay.shift), s);
+  }
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "class moments launch");
   prof_begin(ctx, s, "reduce_partials");
@@ -461,8 +466,6 @@ int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t
   if (prec < CVAMX_PREC_FP32 || prec > CVAMX_PREC_F16X3)
     return fail(ctx, CVAMX_E_INVALID_ARG, "unknown precision");
   if (!V || !eigvals || !mean) return fail(ctx, CVAMX_E_INVALID_ARG, "V, eigvals and mean must be non-NULL");
-  if (prec != CVAMX_PREC_FP32)
-    return fail(ctx, CVAMX_E_UNSUPPORTED, "only the FP32 scatter path is built in this library");
   if (int st = check_device(ctx)) return st;
   hipStream_t s = (hipStream_t)stream;
   const int64_t P = cube->height * cube->width;
@@ -474,9 +477,16 @@ int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t
   if (int st = ensure(ctx, B_RES, res_bytes)) return st;
   if (int st = ensure_pinned(ctx, res_bytes)) return st;
   char* res = static_cast<char*>(ctx->buf[B_RES]);
-  prof_begin(ctx, s, "pca_gram");
-  hipError_t e = cvx::launch_pca_gram(cube->dtype, cube->data, B, P, mask, nblocks, (double*)ctx->buf[B_PART],
-                                      (double*)res, s);
+  hipError_t e;
+  if (prec == CVAMX_PREC_FP32) {
+    prof_begin(ctx, s, "pca_gram");
+    e = cvx::launch_pca_gram(cube->dtype, cube->data, B, P, mask, nblocks, (double*)ctx->buf[B_PART],
+                             (double*)res, s);
+  } else {
+    prof_begin(ctx, s, "pca_gram_mfma");
+    e = cvx::launch_pca_gram_mfma(cube->dtype, prec == CVAMX_PREC_BF16X3 ? 0 : 1, cube->data, B, P, mask,
+                                  nblocks, (double*)ctx->buf[B_PART], (double*)res, s);
+  }
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "pca gram launch");
   prof_begin(ctx, s, "reduce_partials");
@@ -525,7 +535,7 @@ int cva_soft_forward(cvamx_ctx* ctx, const float* X, const float* w, int64_t N, 
   if ((reinterpret_cast<uintptr_t>(X) & 15u) != 0)
     return fail(ctx, CVAMX_E_UNSUPPORTED, "X must be 16-byte aligned");
   if (prec != CVAMX_PREC_FP32)
-    return fail(ctx, CVAMX_E_UNSUPPORTED, "only the FP32 scatter path is built in this library");
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "soft-label CVA runs the FP32 scatter path only");
   if (int st = check_device(ctx)) return st;
   hipStream_t s = (hipStream_t)stream;
   const int BP = cvx::padded_bp(B), KP = (K + 3) & ~3;

@@ -7,20 +7,24 @@
 // that is a whole number of dwords (two pixels for 16-bit elements and an
 // odd band count, else one pixel), so a tile is 256 * S bytes with S the
 // dwords per lane group.  The tile is fetched with coalesced 16-byte loads
-// into the wave's LDS slice and each lane then reads its own S dwords; with
-// S odd those reads hit distinct LDS banks.  y_j = sum_b W[b][j] (x_b - c_b)
-// + off_j is accumulated in FP32 on the VALU (this is a streaming, HBM-bound
-// pass with about 6 flop per byte: no matrix cores).  Pass 1 keeps running
-// min/max per component; the last block to finish combines the block
-// partials in a fixed order and stores (a_j, 255 / (b_j - a_j)).  Pass 2
-// recomputes y bit for bit, quantises q = floor((y - a) s + 1/2) clamped to
-// 0..255 and writes planar bytes.
+// into registers one tile ahead (the loads of tile t + 1 are in flight while
+// tile t is computed), stored into the wave's LDS slice, and each lane then
+// reads its own S dwords; with S odd those reads hit distinct LDS banks.
+// y_j = sum_b W[b][j] (x_b - c_b) + off_j is accumulated in FP32 on the
+// VALU (a streaming, HBM-bound pass with about 6 flop per byte: no matrix
+// cores).  Pass 1 keeps running min/max per component; the last block to
+// finish combines the block partials (all its threads, fixed assignment)
+// and stores the affine map of the stretch, q = floor(y s + o) with
+// s = 255 / (b - a), o = 1/2 - a s.  Pass 2 recomputes y bit for bit,
+// quantises, clamps to 0..255 and writes planar bytes.
 #include "k_common.hpp"
 #include "launch.hpp"
 
 namespace cvx {
 
 namespace {
+
+constexpr int kMaxQ = 16;   // 16-byte chunks per lane per tile: 16 * S / 64 <= 16 for S <= 64
 
 template <int DT>
 struct Geo {
@@ -47,27 +51,43 @@ __device__ __forceinline__ void accum(float (&acc)[NC], const ProjArgs& a, int b
   for (int j = 0; j < NC; ++j) acc[j] = fmaf(a.w[b * NC + j], x, acc[j]);
 }
 
-// Fetch wave tile t (64 lane groups) into this wave's LDS slice.
-__device__ __forceinline__ void fetch_tile(const unsigned char* __restrict__ base, int64_t total_bytes,
-                                           int64_t t, int S, uint32_t* __restrict__ my, int lane) {
+// Issue the loads of wave tile t into registers (chunk j = lane + 64 q).
+__device__ __forceinline__ void load_tile(const unsigned char* __restrict__ base, int64_t total_bytes,
+                                          int64_t t, int S, int lane, uint4 (&r)[kMaxQ]) {
   const int64_t tb = t * 256 * (int64_t)S;
   const int nchunk = 16 * S;
-  for (int j = lane; j < nchunk; j += 64) {
-    const int64_t ob = tb + 16 * (int64_t)j;
-    uint4 v;
-    if (ob + 16 <= total_bytes) {
-      v = *reinterpret_cast<const uint4*>(base + ob);
-    } else {
-      uint16_t h[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        h[q] = (ob + 2 * q + 2 <= total_bytes) ? *reinterpret_cast<const uint16_t*>(base + ob + 2 * q) : 0;
-      v.x = h[0] | ((uint32_t)h[1] << 16);
-      v.y = h[2] | ((uint32_t)h[3] << 16);
-      v.z = h[4] | ((uint32_t)h[5] << 16);
-      v.w = h[6] | ((uint32_t)h[7] << 16);
+  for (int q = 0; q < kMaxQ; ++q) {
+    if (64 * q < nchunk) {
+      const int j = lane + 64 * q;
+      if (j < nchunk) {
+        const int64_t ob = tb + 16 * (int64_t)j;
+        if (ob + 16 <= total_bytes) {
+          r[q] = *reinterpret_cast<const uint4*>(base + ob);
+        } else {
+          uint16_t h[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            h[e] = (ob + 2 * e + 2 <= total_bytes) ? *reinterpret_cast<const uint16_t*>(base + ob + 2 * e) : 0;
+          r[q].x = h[0] | ((uint32_t)h[1] << 16);
+          r[q].y = h[2] | ((uint32_t)h[3] << 16);
+          r[q].z = h[4] | ((uint32_t)h[5] << 16);
+          r[q].w = h[6] | ((uint32_t)h[7] << 16);
+        }
+      }
     }
-    *reinterpret_cast<uint4*>(my + 4 * j) = v;
+  }
+}
+
+__device__ __forceinline__ void store_tile(uint32_t* __restrict__ my, int S, int lane,
+                                           const uint4 (&r)[kMaxQ]) {
+  const int nchunk = 16 * S;
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) {
+    if (64 * q < nchunk) {
+      const int j = lane + 64 * q;
+      if (j < nchunk) *reinterpret_cast<uint4*>(my + 4 * j) = r[q];
+    }
   }
 }
 
@@ -111,16 +131,10 @@ __device__ __forceinline__ void project_group(const uint32_t* __restrict__ d, in
   }
 }
 
-template <int DT, int NC>
-__global__ __launch_bounds__(kBlock) void k_project_range(const void* __restrict__ cube, int B,
-                                                          int64_t P, int nc, ProjArgs a,
-                                                          float* __restrict__ part,
-                                                          unsigned* __restrict__ ticket,
-                                                          float* __restrict__ range_dev,
-                                                          float* __restrict__ ab_dev) {
-  extern __shared__ __align__(16) uint32_t lds[];
-  __shared__ float wred[kWaves][2 * NC];
-  __shared__ bool am_last;
+// The tile loop shared by both passes: body(pix, y0, y1) per lane group.
+template <int DT, int NC, typename Body>
+__device__ __forceinline__ void tile_loop(const void* __restrict__ cube, int B, int64_t P,
+                                          const ProjArgs& a, uint32_t* __restrict__ lds, Body body) {
   const Geo<DT> geo(B);
   const int S = geo.S, g2 = geo.g2;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -129,18 +143,39 @@ __global__ __launch_bounds__(kBlock) void k_project_range(const void* __restrict
   const int64_t nt = (P + tp - 1) / tp;
   const int64_t total_bytes = P * B * Geo<DT>::esize;
   const unsigned char* base = reinterpret_cast<const unsigned char*>(cube);
+  const int64_t stride = (int64_t)gridDim.x * kWaves;
+  uint4 r[kMaxQ];
+  int64_t t = (int64_t)blockIdx.x * kWaves + w;
+  if (t < nt) load_tile(base, total_bytes, t, S, lane, r);
+  for (; t < nt; t += stride) {
+    store_tile(my, S, lane, r);
+    wave_lds_sync();
+    if (t + stride < nt) load_tile(base, total_bytes, t + stride, S, lane, r);
+    float y0[NC], y1[NC];
+    project_group<DT, NC>(my + lane * S, B, g2, a, y0, y1);
+    body(t * tp + (int64_t)lane * g2, g2, y0, y1);
+    wave_lds_sync();
+  }
+}
+
+template <int DT, int NC>
+__global__ __launch_bounds__(kBlock) void k_project_range(const void* __restrict__ cube, int B,
+                                                          int64_t P, ProjArgs a,
+                                                          float* __restrict__ part,
+                                                          unsigned* __restrict__ ticket,
+                                                          float* __restrict__ range_dev,
+                                                          float* __restrict__ ab_dev) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  __shared__ float wred[kWaves][2 * NC];
+  __shared__ bool am_last;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float mn[NC], mx[NC];
 #pragma unroll
   for (int j = 0; j < NC; ++j) {
     mn[j] = __builtin_inff();
     mx[j] = -__builtin_inff();
   }
-  for (int64_t t = (int64_t)blockIdx.x * kWaves + w; t < nt; t += (int64_t)gridDim.x * kWaves) {
-    fetch_tile(base, total_bytes, t, S, my, lane);
-    wave_lds_sync();
-    float y0[NC], y1[NC];
-    project_group<DT, NC>(my + lane * S, B, g2, a, y0, y1);
-    const int64_t pix = t * tp + (int64_t)lane * g2;
+  tile_loop<DT, NC>(cube, B, P, a, lds, [&](int64_t pix, int g2, const float (&y0)[NC], const float (&y1)[NC]) {
     if (pix < P) {
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
@@ -155,8 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_project_range(const void* __restrict
         mx[j] = fmaxf(mx[j], y1[j]);
       }
     }
-    wave_lds_sync();
-  }
+  });
 #pragma unroll
   for (int j = 0; j < NC; ++j) {
     mn[j] = wave_min(mn[j]);
@@ -185,142 +219,93 @@ __global__ __launch_bounds__(kBlock) void k_project_range(const void* __restrict
     am_last = (prev == gridDim.x - 1);
   }
   __syncthreads();
-  if (am_last) {
-    __threadfence();
-    if (threadIdx.x < NC) {
-      const int j = threadIdx.x;
-      float lo = __builtin_inff(), hi = -__builtin_inff();
-      for (unsigned bk = 0; bk < gridDim.x; ++bk) {
-        lo = fminf(lo, __builtin_nontemporal_load(part + (int64_t)bk * 2 * NC + j));
-        hi = fmaxf(hi, __builtin_nontemporal_load(part + (int64_t)bk * 2 * NC + NC + j));
-      }
-      const float s = (hi > lo) ? 255.f / (hi - lo) : 0.f;
-      range_dev[j] = lo;
-      range_dev[NC + j] = s;
-      if (j < nc) {
-        ab_dev[2 * j] = lo;
-        ab_dev[2 * j + 1] = hi;
-      }
-    }
-    if (threadIdx.x == 0) *ticket = 0u;
+  if (!am_last) return;
+  // last block: every thread folds a strided subset of the block partials
+  __threadfence();
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    mn[j] = __builtin_inff();
+    mx[j] = -__builtin_inff();
   }
+  for (unsigned bk = threadIdx.x; bk < gridDim.x; bk += kBlock) {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      mn[j] = fminf(mn[j], __builtin_nontemporal_load(part + (int64_t)bk * 2 * NC + j));
+      mx[j] = fmaxf(mx[j], __builtin_nontemporal_load(part + (int64_t)bk * 2 * NC + NC + j));
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    mn[j] = wave_min(mn[j]);
+    mx[j] = wave_max(mx[j]);
+  }
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      wred[w][j] = mn[j];
+      wred[w][NC + j] = mx[j];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < NC) {
+    const int j = threadIdx.x;
+    float lo = wred[0][j], hi = wred[0][NC + j];
+    for (int ww = 1; ww < kWaves; ++ww) {
+      lo = fminf(lo, wred[ww][j]);
+      hi = fmaxf(hi, wred[ww][NC + j]);
+    }
+    const float s = (hi > lo) ? 255.f / (hi - lo) : 0.f;
+    range_dev[j] = s;
+    range_dev[8 + j] = 0.5f - lo * s;
+    ab_dev[2 * j] = lo;
+    ab_dev[2 * j + 1] = hi;
+  }
+  if (threadIdx.x == 0) *ticket = 0u;
 }
 
-__device__ __forceinline__ uint32_t quant(float y, float lo, float s) {
-  float t = floorf((y - lo) * s + 0.5f);
+__device__ __forceinline__ uint32_t quant(float y, float s, float o) {
+  float t = floorf(fmaf(y, s, o));
   t = fminf(fmaxf(t, 0.f), 255.f);
   return (uint32_t)t;
 }
 
 template <int DT, int NC>
 __global__ __launch_bounds__(kBlock) void k_project_stretch(const void* __restrict__ cube, int B,
-                                                            int64_t P, int nvalid, ProjArgs a,
+                                                            int64_t P, ProjArgs a,
                                                             const float* __restrict__ range_dev,
                                                             uint8_t* __restrict__ images) {
   extern __shared__ __align__(16) uint32_t lds[];
-  const Geo<DT> geo(B);
-  const int S = geo.S, g2 = geo.g2;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  uint32_t* my = lds + w * 64 * S;
-  const int64_t tp = 64 * (int64_t)g2;
-  const int64_t nt = (P + tp - 1) / tp;
-  const int64_t total_bytes = P * B * Geo<DT>::esize;
-  const unsigned char* base = reinterpret_cast<const unsigned char*>(cube);
-  float lo[NC], sc[NC];
+  float sc[NC], of[NC];
 #pragma unroll
   for (int j = 0; j < NC; ++j) {
-    lo[j] = range_dev[j];
-    sc[j] = range_dev[NC + j];
+    sc[j] = range_dev[j];
+    of[j] = range_dev[8 + j];
   }
-  for (int64_t t = (int64_t)blockIdx.x * kWaves + w; t < nt; t += (int64_t)gridDim.x * kWaves) {
-    fetch_tile(base, total_bytes, t, S, my, lane);
-    wave_lds_sync();
-    float y0[NC], y1[NC];
-    project_group<DT, NC>(my + lane * S, B, g2, a, y0, y1);
-    const int64_t pix = t * tp + (int64_t)lane * g2;
+  const bool even = (P & 1) == 0;
+  tile_loop<DT, NC>(cube, B, P, a, lds, [&](int64_t pix, int g2, const float (&y0)[NC], const float (&y1)[NC]) {
     if (g2 == 2) {
-      if (pix + 1 < P && (P & 1) == 0) {
+      if (pix + 1 < P && even) {
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
-          if (j < nvalid) {
-            const uint32_t q = quant(y0[j], lo[j], sc[j]) | (quant(y1[j], lo[j], sc[j]) << 8);
-            *reinterpret_cast<uint16_t*>(images + (int64_t)j * P + pix) = (uint16_t)q;
-          }
+          const uint32_t q = quant(y0[j], sc[j], of[j]) | (quant(y1[j], sc[j], of[j]) << 8);
+          *reinterpret_cast<uint16_t*>(images + (int64_t)j * P + pix) = (uint16_t)q;
         }
       } else if (pix + 1 < P) {
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
-          if (j < nvalid) {
-            images[(int64_t)j * P + pix] = (uint8_t)quant(y0[j], lo[j], sc[j]);
-            images[(int64_t)j * P + pix + 1] = (uint8_t)quant(y1[j], lo[j], sc[j]);
-          }
+          images[(int64_t)j * P + pix] = (uint8_t)quant(y0[j], sc[j], of[j]);
+          images[(int64_t)j * P + pix + 1] = (uint8_t)quant(y1[j], sc[j], of[j]);
         }
       } else if (pix < P) {
 #pragma unroll
-        for (int j = 0; j < NC; ++j)
-          if (j < nvalid) images[(int64_t)j * P + pix] = (uint8_t)quant(y0[j], lo[j], sc[j]);
+        for (int j = 0; j < NC; ++j) images[(int64_t)j * P + pix] = (uint8_t)quant(y0[j], sc[j], of[j]);
       }
     } else if (pix < P) {
 #pragma unroll
-      for (int j = 0; j < NC; ++j)
-        if (j < nvalid) images[(int64_t)j * P + pix] = (uint8_t)quant(y0[j], lo[j], sc[j]);
+      for (int j = 0; j < NC; ++j) images[(int64_t)j * P + pix] = (uint8_t)quant(y0[j], sc[j], of[j]);
     }
-    wave_lds_sync();
-  }
-}
-
-template <int NC>
-hipError_t range_nc(int dtype, const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
-                    int nblocks, float* part, unsigned* ticket, float* range_dev, float* ab_dev,
-                    size_t sm, hipStream_t s) {
-  switch (dtype) {
-    case DT_U16:
-      hipLaunchKernelGGL((k_project_range<DT_U16, NC>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P,
-                         nc, a, part, ticket, range_dev, ab_dev);
-      break;
-    case DT_F32:
-      hipLaunchKernelGGL((k_project_range<DT_F32, NC>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P,
-                         nc, a, part, ticket, range_dev, ab_dev);
-      break;
-    case DT_BF16:
-      hipLaunchKernelGGL((k_project_range<DT_BF16, NC>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P,
-                         nc, a, part, ticket, range_dev, ab_dev);
-      break;
-    case DT_F16:
-      hipLaunchKernelGGL((k_project_range<DT_F16, NC>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P,
-                         nc, a, part, ticket, range_dev, ab_dev);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-template <int NC>
-hipError_t stretch_nc(int dtype, const void* cube, int B, int64_t P, int nvalid, const ProjArgs& a,
-                      int nblocks, const float* range_dev, uint8_t* images, size_t sm,
-                      hipStream_t s) {
-  switch (dtype) {
-    case DT_U16:
-      hipLaunchKernelGGL((k_project_stretch<DT_U16, NC>), dim3(nblocks), dim3(kBlock), sm, s, cube, B,
-                         P, nvalid, a, range_dev, images);
-      break;
-    case DT_F32:
-      hipLaunchKernelGGL((k_project_stretch<DT_F32, NC>), dim3(nblocks), dim3(kBlock), sm, s, cube, B,
-                         P, nvalid, a, range_dev, images);
-      break;
-    case DT_BF16:
-      hipLaunchKernelGGL((k_project_stretch<DT_BF16, NC>), dim3(nblocks), dim3(kBlock), sm, s, cube, B,
-                         P, nvalid, a, range_dev, images);
-      break;
-    case DT_F16:
-      hipLaunchKernelGGL((k_project_stretch<DT_F16, NC>), dim3(nblocks), dim3(kBlock), sm, s, cube, B,
-                         P, nvalid, a, range_dev, images);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  });
 }
 
 size_t proj_smem(int dtype, int B) {
@@ -330,22 +315,68 @@ size_t proj_smem(int dtype, int B) {
   return (size_t)kWaves * 64 * S * 4;
 }
 
+template <int DT>
+hipError_t range_dt(int nc, const void* cube, int B, int64_t P, const ProjArgs& a, int nblocks, float* part,
+                    unsigned* ticket, float* range_dev, float* ab_dev, size_t sm, hipStream_t s) {
+#define CVX_RANGE(N)                                                                                      \
+  case N:                                                                                                 \
+    hipLaunchKernelGGL((k_project_range<DT, N>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a, part, \
+                       ticket, range_dev, ab_dev);                                                        \
+    break;
+  switch (nc) {
+    CVX_RANGE(1) CVX_RANGE(2) CVX_RANGE(3) CVX_RANGE(4) CVX_RANGE(5) CVX_RANGE(6) CVX_RANGE(7) CVX_RANGE(8)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef CVX_RANGE
+  return hipGetLastError();
+}
+
+template <int DT>
+hipError_t stretch_dt(int nc, const void* cube, int B, int64_t P, const ProjArgs& a, int nblocks,
+                      const float* range_dev, uint8_t* images, size_t sm, hipStream_t s) {
+#define CVX_STRETCH(N)                                                                                      \
+  case N:                                                                                                   \
+    hipLaunchKernelGGL((k_project_stretch<DT, N>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a,       \
+                       range_dev, images);                                                                  \
+    break;
+  switch (nc) {
+    CVX_STRETCH(1) CVX_STRETCH(2) CVX_STRETCH(3) CVX_STRETCH(4) CVX_STRETCH(5) CVX_STRETCH(6) CVX_STRETCH(7)
+    CVX_STRETCH(8)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef CVX_STRETCH
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_project_range(int dtype, const void* cube, int B, int64_t P, int nc,
                                 const ProjArgs& a, int nblocks, float* part, unsigned* ticket,
                                 float* range_dev, float* ab_dev, hipStream_t s) {
   const size_t sm = proj_smem(dtype, B);
-  if (nc <= 4) return range_nc<4>(dtype, cube, B, P, nc, a, nblocks, part, ticket, range_dev, ab_dev, sm, s);
-  return range_nc<8>(dtype, cube, B, P, nc, a, nblocks, part, ticket, range_dev, ab_dev, sm, s);
+  switch (dtype) {
+    case DT_U16: return range_dt<DT_U16>(nc, cube, B, P, a, nblocks, part, ticket, range_dev, ab_dev, sm, s);
+    case DT_F32: return range_dt<DT_F32>(nc, cube, B, P, a, nblocks, part, ticket, range_dev, ab_dev, sm, s);
+    case DT_BF16: return range_dt<DT_BF16>(nc, cube, B, P, a, nblocks, part, ticket, range_dev, ab_dev, sm, s);
+    case DT_F16: return range_dt<DT_F16>(nc, cube, B, P, a, nblocks, part, ticket, range_dev, ab_dev, sm, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_project_stretch(int dtype, const void* cube, int B, int64_t P, int nc, int nvalid,
                                   const ProjArgs& a, int nblocks, const float* range_dev,
                                   uint8_t* images, hipStream_t s) {
+  (void)nvalid;
   const size_t sm = proj_smem(dtype, B);
-  if (nc <= 4) return stretch_nc<4>(dtype, cube, B, P, nvalid, a, nblocks, range_dev, images, sm, s);
-  return stretch_nc<8>(dtype, cube, B, P, nvalid, a, nblocks, range_dev, images, sm, s);
+  switch (dtype) {
+    case DT_U16: return stretch_dt<DT_U16>(nc, cube, B, P, a, nblocks, range_dev, images, sm, s);
+    case DT_F32: return stretch_dt<DT_F32>(nc, cube, B, P, a, nblocks, range_dev, images, sm, s);
+    case DT_BF16: return stretch_dt<DT_BF16>(nc, cube, B, P, a, nblocks, range_dev, images, sm, s);
+    case DT_F16: return stretch_dt<DT_F16>(nc, cube, B, P, a, nblocks, range_dev, images, sm, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace cvx

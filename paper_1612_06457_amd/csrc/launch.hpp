@@ -14,7 +14,7 @@ constexpr int kMaxB = 64;
 // Parameters of one projection pass, passed by value in the kernel
 // arguments (fits the 4 KiB argument limit).
 struct ProjArgs {
-  float w[64 * 8];   // W[b * nc + j] for this group of nc <= 8 components
+  float w[64 * 8];   // W[b * nc + j] for this group of nc <= 8 components (row stride nc)
   float c[64];       // per-band centre (integer for uint16 pages)
   float off[8];      // sum_b W[b][j] (c_b - centre_b), added to each y_j
 };
@@ -43,6 +43,14 @@ hipError_t launch_class_moments(int dtype, const void* cube, int B, const int32_
 hipError_t launch_pca_gram(int dtype, const void* cube, int B, int64_t P,
                            const uint8_t* mask, int nblocks, double* part,
                            double* shift_out, hipStream_t s);
+// The same two Gram matrices on the matrix cores with a compensated
+// 16-bit split (split 0 = bf16, 1 = fp16); identical output layout.
+hipError_t launch_class_moments_mfma(int dtype, int split, const void* cube, int B,
+                                     const int32_t* idx, const int32_t* offsets, int K, int G,
+                                     double* part, double* shift_out, hipStream_t s);
+hipError_t launch_pca_gram_mfma(int dtype, int split, const void* cube, int B, int64_t P,
+                                const uint8_t* mask, int nblocks, double* part,
+                                double* shift_out, hipStream_t s);
 // out[s * L + t] = sum_g part[(s * G + g) * L + t]
 hipError_t launch_reduce_part(const double* part, int nsets, int G, int L, double* out,
                               hipStream_t s);

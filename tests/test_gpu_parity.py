@@ -317,3 +317,132 @@ def test_full_soft_cfg4(dev):
         k = int(rng.integers(0, w.shape[1]))
         fd = (oracle.soft_delta_J(X, w, p, k, h, mom) - oracle.soft_delta_J(X, w, p, k, -h, mom)) / (2 * h)
         assert abs(g[p, k] - fd) <= 1e-4 * gmax
+
+
+# ------------------------------------------------- compensated MFMA scatter
+
+def _abs_gram(cube_host, labels, K):
+    """sum over training pixels of |x_i - m_ki| |x_j - m_kj| (FP64), the
+    scale of the a-priori rounding bound of a scatter entry."""
+    from oracle.cva import _rows
+    X = _rows(cube_host).astype(np.float64)
+    lab = np.asarray(labels).reshape(-1)
+    B = X.shape[1]
+    A = np.zeros((B, B))
+    for k in range(K):
+        D = np.abs(X[lab == k] - X[lab == k].mean(0))
+        A += D.T @ D
+    return A
+
+
+def _mixed_fit_check(cube_dev, cube_host, labels, K, dev, prec, rel):
+    import paper_1612_06457_amd as cx
+    ref = oracle.cva_fit(cube_host, labels, K)
+    got = cx.cva_fit(cube_dev, _t(labels, dev), K, precision=prec)
+    assert got.counts.tolist() == ref["counts"].tolist()
+    bound = rel * _abs_gram(cube_host, labels, K)
+    err = np.abs(got.Sw - ref["Sw"])
+    worst = float(np.max(err / bound))
+    say(f"{prec}: S_w error / stated bound = {worst:.3f}, max rel {rel_max(got.Sw, ref['Sw']):.2e}")
+    assert worst <= 1.0
+    assert rel_max(got.Sb, ref["Sb"]) <= TOL_S
+    assert np.max(np.abs(got.eigvals - ref["eigvals"]) / ref["eigvals"]) <= 10 * rel + TOL_LAM
+    check_vectors(got.W, ref["W"], ref["eigvals"])
+    return ref, got
+
+
+# a-priori bounds on |dS_ij| / sum_p |x_pi||x_pj|: exact split (integer and
+# half pages): FP32 accumulation only, (32 + 16) * 2^-24 < 3e-6, stated as
+# 1e-5; fp32 pages: plus the split residual 2 u_h^2 (bf16: 2^-15, fp16: 2^-21)
+BOUND_EXACT = 1e-5
+BOUND_F32 = {"bf16x3": 2.0 ** -15 + 1e-5, "f16x3": 2.0 ** -21 + 1e-5}
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "f16x3"])
+def test_mixed_cva_and_pca_u16(dev, prec):
+    say(f"mixed {prec} on cfg2 at 1024x1024x23 u16")
+    import paper_1612_06457_amd as cx
+    c = make_case(2, scale=0.25)
+    cube = _t(c.cube, dev)
+    ref, got = _mixed_fit_check(cube, c.cube, c.labels, c.K, dev, prec, BOUND_EXACT)
+    _project_parity(c.cube, got.W, got.mean, dev)
+    pr = oracle.pca_fit(c.cube, n_comp=3)
+    V, lam, mean, cov = cx.pca_fit(cube, n_comp=3, precision=prec)
+    assert rel_max(cov, pr["cov"]) <= TOL_S
+    assert np.max(np.abs(lam - pr["eigvals"]) / pr["eigvals"]) <= TOL_LAM
+    check_vectors(V, pr["V"], pr["all_eigvals"][:3])
+
+
+@pytest.mark.parametrize("kind,prec", [("bf16", "bf16x3"), ("f16", "f16x3"), ("bf16", "f16x3"),
+                                       ("f16", "bf16x3")])
+def test_mixed_half_pages(dev, kind, prec):
+    say(f"mixed {prec} on a {kind} page (cfg3 structure at 1/4 scale)")
+    import paper_1612_06457_amd as cx
+    c = make_case(2, scale=0.25)
+    cube = to_half_cube(c.cube, kind)
+    host = cube.float().numpy()
+    exact = (kind == "bf16") or (prec == "f16x3")
+    rel = BOUND_EXACT if exact else BOUND_F32[prec]
+    _mixed_fit_check(_t(cube, dev), host, c.labels, c.K, dev, prec, rel)
+    pr = oracle.pca_fit(host, n_comp=3)
+    V, lam, mean, cov = cx.pca_fit(_t(cube, dev), n_comp=3, precision=prec)
+    assert rel_max(cov, pr["cov"]) <= 10 * rel + TOL_S
+    check_vectors(V, pr["V"], pr["all_eigvals"][:3])
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "f16x3"])
+def test_mixed_f32_page(dev, prec):
+    say(f"mixed {prec} on an fp32 page")
+    c = make_case(2, scale=0.15)
+    cube = (c.cube.astype(np.float32) + np.float32(0.25))
+    _mixed_fit_check(_t(cube, dev), cube, c.labels, c.K, dev, prec, BOUND_F32[prec])
+
+
+@pytest.mark.parametrize("H,W,B,K", [(37, 53, 7, 3), (33, 31, 33, 5), (40, 41, 64, 3), (19, 23, 1, 2),
+                                     (50, 50, 47, 3)])
+def test_mixed_shapes(dev, H, W, B, K):
+    say(f"mixed shapes H={H} W={W} B={B} K={K}")
+    import paper_1612_06457_amd as cx
+    rng = np.random.default_rng(H * 7 + B)
+    mu = rng.uniform(800, 3500, (K, B))
+    cls = rng.integers(0, K, H * W)
+    cls[: K * (B + 2)] = np.repeat(np.arange(K), B + 2)
+    cube = np.clip(np.rint(mu[cls] + rng.normal(0, 60, (H * W, B))), 0, 4095).astype(np.uint16).reshape(H, W, B)
+    labels = np.where(rng.random(H * W) < 0.6, cls, -1).astype(np.int8)
+    labels[: K * (B + 2)] = cls[: K * (B + 2)]
+    labels = labels.reshape(H, W)
+    for prec in ("bf16x3", "f16x3"):
+        _mixed_fit_check(_t(cube, dev), cube, labels, K, dev, prec, BOUND_EXACT)
+        pr = oracle.pca_fit(cube, n_comp=1)
+        V, lam, mean, cov = cx.pca_fit(_t(cube, dev), n_comp=1, precision=prec)
+        assert rel_max(cov, pr["cov"]) <= TOL_S
+
+
+def test_mixed_pca_mask(dev):
+    say("mixed pca with mask")
+    import paper_1612_06457_amd as cx
+    c = make_case(1, scale=0.5)
+    rng = np.random.default_rng(8)
+    mask = (rng.random((c.H, c.W)) < 0.4).astype(np.uint8)
+    pr = oracle.pca_fit(c.cube, mask=mask, n_comp=2)
+    V, lam, mean, cov = cx.pca_fit(_t(c.cube, dev), mask=_t(mask, dev), n_comp=2, precision="bf16x3")
+    assert rel_max(cov, pr["cov"]) <= TOL_S
+    check_vectors(V, pr["V"], pr["all_eigvals"][:2])
+
+
+@pytest.mark.timeout(900)
+def test_full_page_cfg5_mixed(dev):
+    """The benchmark configuration: 7216 x 5412 x 33 uint16, K = 8, BF16
+    compensated scatter on MFMA, FP64 eigensolve; PCA on all pixels."""
+    say("cfg5 full page, bf16x3")
+    import paper_1612_06457_amd as cx
+    c = make_case(5, threads=16)
+    cube = _t(c.cube, dev)
+    ref, got = _mixed_fit_check(cube, c.cube, c.labels, c.K, dev, "bf16x3", BOUND_EXACT)
+    say("cfg5 mixed fit ok", got.eigvals)
+    pr = oracle.pca_fit(c.cube, n_comp=3)
+    V, lam, mean, cov = cx.pca_fit(cube, n_comp=3, precision="bf16x3")
+    assert rel_max(cov, pr["cov"]) <= TOL_S
+    assert np.max(np.abs(lam - pr["eigvals"]) / pr["eigvals"]) <= TOL_LAM
+    check_vectors(V, pr["V"], pr["all_eigvals"][:3])
+    say("cfg5 mixed pca ok")
