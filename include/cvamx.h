@@ -94,7 +94,7 @@ const char* cvamx_last_error(const cvamx_ctx* ctx);   /* never NULL */
 
 /* Fit CVA on the training pixels of a page (paper Section 2, canonical
  * variates paragraph; Section 4, generalized symmetric-definite solve).
- *   labels   device, height*width int8 (-1 or 0..K-1)
+ *   labels   device, height*width int8 (-1 or 0..K-1), 16-byte aligned
  *   K        number of classes, 2..CVAMX_MAX_CLASSES
  *   prec     cvamx_prec for the scatter accumulation
  *   ridge    >= 0, added to the diagonal of S_w before the solve

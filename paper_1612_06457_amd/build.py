@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcvamx.so")
 
-HIP_SOURCES = ["k_labels.hip", "k_moments.hip", "k_project.hip", "k_soft.hip", "k_mfma.hip"]
+HIP_SOURCES = ["k_labels.hip", "k_moments.hip", "k_project.hip", "k_project_mfma.hip", "k_soft.hip",
+               "k_mfma.hip"]
 HOST_SOURCES = ["api.cpp", "finisher.cpp"]
 
 ARCH = os.environ.get("CVAMX_ARCH", "gfx950")

@@ -141,6 +141,25 @@ void prof_collect(cvamx_ctx* ctx) {
 
 size_t esize(int dtype) { return dtype == CVAMX_F32 ? 4 : 2; }
 
+// Round to the nearest bf16 / fp16 value (ties to even), returned as double.
+double bf16_round(double x) {
+  float f = (float)x;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+  std::memcpy(&f, &u, 4);
+  return (double)f;
+}
+
+double f16_round(double x) {
+  // fp16 has 11 significant bits; values here lie well inside its normal range
+  if (x == 0.0 || !std::isfinite(x)) return x;
+  int e;
+  std::frexp(x, &e);
+  const double q = std::ldexp(1.0, e - 11);
+  return std::nearbyint(x / q) * q;
+}
+
 int check_cube(cvamx_ctx* ctx, const cvamx_cube* c) {
   if (!c) return fail(ctx, CVAMX_E_INVALID_ARG, "cube is NULL");
   if (!c->data) return fail(ctx, CVAMX_E_INVALID_ARG, "cube data is NULL");
@@ -209,7 +228,8 @@ int proj_groups(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const d
   int nblocks = ctx->proj_blocks > 0 ? ctx->proj_blocks : ctx->num_cu * 8;
   nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(nblocks, (nt + cvx::kWaves - 1) / cvx::kWaves));
   (void)S;
-  if (int st = ensure(ctx, B_PROJPART, (size_t)nblocks * 16 * sizeof(float))) return st;
+  // block partials: 16 floats (VALU kernels) or 32 (matrix-core kernels)
+  if (int st = ensure(ctx, B_PROJPART, (size_t)nblocks * 32 * sizeof(float))) return st;
   for (int g0 = 0; g0 < n_comp; g0 += 8) {
     const int nc = std::min(8, n_comp - g0);
     const int NC = nc;   // the kernels are instantiated for 1..8 components
@@ -217,8 +237,17 @@ int proj_groups(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const d
     std::memset(&a, 0, sizeof(a));
     std::vector<double> c(B);
     for (int b = 0; b < B; ++b) {
-      c[b] = (cube->dtype == CVAMX_U16) ? std::nearbyint(center[b]) : (double)(float)center[b];
-      a.c[b] = (float)c[b];
+      // uint16 pages: an integer centre, passed as 2^23 + c (exact in FP32),
+      // which the kernels subtract from the bit-built float 2^23 + x
+      // bf16 / fp16 pages: a centre of the page's own type, so x - c has at
+      // most 16 (bf16) or 22 (fp16) significant bits and splits exactly
+      switch (cube->dtype) {
+        case CVAMX_U16: c[b] = std::nearbyint(center[b]); break;
+        case CVAMX_BF16: c[b] = bf16_round(center[b]); break;
+        case CVAMX_F16: c[b] = f16_round(center[b]); break;
+        default: c[b] = (double)(float)center[b]; break;
+      }
+      a.c[b] = (cube->dtype == CVAMX_U16) ? (float)(8388608.0 + c[b]) : (float)c[b];
     }
     for (int j = 0; j < nc; ++j) {
       double off = 0.0;
@@ -229,13 +258,19 @@ int proj_groups(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const d
       }
       a.off[j] = (float)off;
     }
-    prof_begin(ctx, s, "project_range");
+    static const char* kRangeName[9] = {"", "project_range_nc1", "project_range_nc2", "project_range_nc3",
+                                        "project_range_nc4", "project_range_nc5", "project_range_nc6",
+                                        "project_range_nc7", "project_range_nc8"};
+    static const char* kStretchName[9] = {"", "project_stretch_nc1", "project_stretch_nc2", "project_stretch_nc3",
+                                          "project_stretch_nc4", "project_stretch_nc5", "project_stretch_nc6",
+                                          "project_stretch_nc7", "project_stretch_nc8"};
+    prof_begin(ctx, s, kRangeName[nc]);
     hipError_t e = cvx::launch_project_range(cube->dtype, cube->data, B, P, nc, a, nblocks,
                                              (float*)ctx->buf[B_PROJPART], ctx->tickets,
                                              ctx->range_dev, ctx->ab_dev + 2 * g0, s);
     prof_end(ctx, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "project range launch");
-    prof_begin(ctx, s, "project_stretch");
+    prof_begin(ctx, s, kStretchName[nc]);
     e = cvx::launch_project_stretch(cube->dtype, cube->data, B, P, nc, nc, a, nblocks,
                                     ctx->range_dev, images + (int64_t)g0 * P, s);
     prof_end(ctx, s);
@@ -357,8 +392,8 @@ int cva_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels, int32_
   if (!ctx) return CVAMX_E_INVALID_ARG;
   if (int st = check_cube(ctx, cube)) return st;
   if (!labels) return fail(ctx, CVAMX_E_INVALID_ARG, "labels is NULL");
-  if ((reinterpret_cast<uintptr_t>(labels) & 3u) != 0)
-    return fail(ctx, CVAMX_E_UNSUPPORTED, "labels must be 4-byte aligned");
+  if ((reinterpret_cast<uintptr_t>(labels) & 15u) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "labels must be 16-byte aligned");
   if (K < 2 || K > CVAMX_MAX_CLASSES) return fail(ctx, CVAMX_E_INVALID_ARG, "K must lie in 2..127");
   if (prec < CVAMX_PREC_FP32 || prec > CVAMX_PREC_F16X3)
     return fail(ctx, CVAMX_E_INVALID_ARG, "unknown precision");

@@ -1,9 +1,18 @@
 // Label bookkeeping: per-class counts and a class-grouped, raster-ordered
 // list of training-pixel indices (paper Section 2: the analyst's input
-// points per class).  Two passes over the int8 label map: per-tile class
-// counts, then every tile computes its output offsets from the counts of
-// the tiles before it and writes its indices in raster order.  Integer
-// only, so the result is exact and independent of scheduling.
+// points per class).  Integer only, so the result is exact and independent
+// of scheduling.
+//
+// Both kernels read the int8 label map in 16-byte chunks: a wave step covers
+// 64 chunks = 1024 consecutive pixels, lane l holding pixels 16 l .. 16 l + 15.
+// The labelled pixels of a step (a few percent of the page) are first
+// compacted, in raster order, into a small per-wave LDS list; ranks within a
+// class then come from one ballot per distinct class over that list.
+//   k_label_count:  per-tile class counts (tile = 64 Ki pixels per block);
+//   k_label_index:  every block derives its output offsets from the counts
+//                   of the tiles before it; each wave walks its quarter of
+//                   the tile with wave-private running offsets, so the main
+//                   loop has no block barrier.
 #include "k_common.hpp"
 #include "launch.hpp"
 
@@ -11,79 +20,118 @@ namespace cvx {
 
 namespace {
 
-// Load the labels of this thread's 4 consecutive pixels starting at p
-// (p is a multiple of 4); out-of-range pixels read as -1.  Invalid label
-// values are reported through `bad` and treated as -1.
-__device__ __forceinline__ void load4(const int8_t* __restrict__ labels, int64_t p, int64_t end,
-                                      int K, int v[4], bool& bad) {
-  if (p + 3 < end) {
-    const char4 c = *reinterpret_cast<const char4*>(labels + p);
-    v[0] = c.x; v[1] = c.y; v[2] = c.z; v[3] = c.w;
-  } else {
+constexpr int kSub = kLabelTile / kWaves;   // pixels per wave in a tile
+constexpr int kStep = 64 * 16;              // pixels per wave step
+
+// Load the 16 labels of chunk c (pixel 16 c ..) within [0, end); missing
+// pixels read as -1 (0xff).
+__device__ __forceinline__ uint4 load_chunk(const int8_t* __restrict__ labels, int64_t p, int64_t end) {
+  if (p + 16 <= end) return *reinterpret_cast<const uint4*>(labels + p);
+  uint32_t d[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) v[s] = (p + s < end) ? (int)labels[p + s] : -1;
-  }
+  for (int q = 0; q < 4; ++q) {
+    uint32_t v = 0;
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    if (v[s] < -1 || v[s] >= K) {
-      bad = true;
-      v[s] = -1;
+    for (int b = 0; b < 4; ++b) {
+      const int64_t pp = p + 4 * q + b;
+      const uint32_t byte = (pp < end) ? (uint32_t)(uint8_t)labels[pp] : 0xffu;
+      v |= byte << (8 * b);
     }
+    d[q] = v;
   }
+  return make_uint4(d[0], d[1], d[2], d[3]);
 }
 
-// For the 4 x 64 pixels held by a wave (lane-major raster order), give each
-// labelled slot its rank among the wave's pixels of the same class, and
-// call fn(k, total) once per distinct class present (uniformly, all lanes).
-template <typename Fn>
-__device__ __forceinline__ void wave_rank(const int v[4], int rank[4], Fn fn) {
+// Bit i of the result is set when byte i (of the 16) is >= 0 (labelled).
+// Sets `bad` when a negative byte is not -1.
+__device__ __forceinline__ uint32_t labelled_mask(uint4 c, bool& bad) {
+  const uint32_t d[4] = {c.x, c.y, c.z, c.w};
+  uint32_t m = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t x = d[q];
+    const uint32_t neg = x & 0x80808080u;
+    const uint32_t y = ~x;                                            // -1 bytes -> 0
+    const uint32_t nz = ((y & 0x7f7f7f7fu) + 0x7f7f7f7fu) | y;       // high bit: byte of y != 0
+    if (nz & neg & 0x80808080u) bad = true;                           // negative but not -1
+    const uint32_t pos = (~x) & 0x80808080u;                          // high bit: byte >= 0
+    m |= ((pos >> 7) & 1u) << (4 * q) | ((pos >> 15) & 1u) << (4 * q + 1) |
+         ((pos >> 23) & 1u) << (4 * q + 2) | ((pos >> 31) & 1u) << (4 * q + 3);
+  }
+  return m;
+}
+
+__device__ __forceinline__ int byte_at(uint4 c, int i) {
+  const uint32_t d = (i < 4) ? c.x : (i < 8) ? c.y : (i < 12) ? c.z : c.w;
+  return (int)(int8_t)((d >> (8 * (i & 3))) & 0xffu);
+}
+
+// Exclusive prefix over lanes of a per-lane count in 0..16, and the total.
+__device__ __forceinline__ int lane_prefix(int c, int& total) {
   const int lane = __lane_id();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  unsigned pending = 0;
+  int pre = 0, tot = 0;
 #pragma unroll
-  for (int s = 0; s < 4; ++s)
-    if (v[s] >= 0) pending |= 1u << s;
-  uint64_t lanes = __ballot(pending != 0);
-  while (lanes) {
-    const int leader = __ffsll((unsigned long long)lanes) - 1;
-    int first = -1;
-#pragma unroll
-    for (int s = 3; s >= 0; --s)
-      if (pending & (1u << s)) first = v[s];
-    const int k = __shfl(first, leader, 64);
-    const uint64_t b0 = __ballot(v[0] == k), b1 = __ballot(v[1] == k);
-    const uint64_t b2 = __ballot(v[2] == k), b3 = __ballot(v[3] == k);
-    const int before = __popcll(b0 & lt) + __popcll(b1 & lt) + __popcll(b2 & lt) + __popcll(b3 & lt);
-    int run = 0;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      if (v[s] == k) {
-        rank[s] = before + run;
-        ++run;
-        pending &= ~(1u << s);
-      }
-    }
-    fn(k, __popcll(b0) + __popcll(b1) + __popcll(b2) + __popcll(b3));
-    lanes = __ballot(pending != 0);
+  for (int b = 0; b < 5; ++b) {
+    const uint64_t bb = __ballot((c >> b) & 1);
+    pre += __popcll(bb & lt) << b;
+    tot += __popcll(bb) << b;
   }
+  total = tot;
+  return pre;
+}
+
+// Compact the labelled pixels of one wave step into list[] (raster order):
+// list entries are (pixel offset within the step) | (class << 16).
+// Returns the number of entries (uniform).
+__device__ __forceinline__ int compact_step(uint4 c, int K, uint32_t* __restrict__ list, bool& bad) {
+  const int lane = __lane_id();
+  uint32_t m = labelled_mask(c, bad);
+  int total;
+  int pos = lane_prefix(__popc(m), total);
+  while (m) {
+    const int i = __ffs(m) - 1;
+    m &= m - 1;
+    const int v = byte_at(c, i);
+    if (v >= K) bad = true;
+    list[pos++] = (uint32_t)(16 * lane + i) | ((uint32_t)(v < K ? v : 0) << 16);
+  }
+  return total;
 }
 
 __global__ __launch_bounds__(kBlock) void k_label_count(const int8_t* __restrict__ labels, int64_t P,
                                                         int K, int32_t* __restrict__ tile_counts,
                                                         int32_t* __restrict__ err) {
   __shared__ int cnt[128];
+  __shared__ uint32_t lists[kWaves][kStep];
   for (int i = threadIdx.x; i < 128; i += kBlock) cnt[i] = 0;
   __syncthreads();
-  const int64_t t0 = (int64_t)blockIdx.x * kLabelTile;
-  const int64_t t1 = (t0 + kLabelTile < P) ? t0 + kLabelTile : P;
-  const int lane = __lane_id();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint32_t* list = lists[w];
+  const int64_t s0 = (int64_t)blockIdx.x * kLabelTile + (int64_t)w * kSub;
+  const int64_t s1 = (s0 + kSub < P) ? s0 + kSub : P;
   bool bad = false;
-  for (int64_t base = t0; base < t1; base += 4 * kBlock) {
-    int v[4], rank[4];
-    load4(labels, base + 4 * threadIdx.x, t1, K, v, bad);
-    wave_rank(v, rank, [&](int k, int total) {
-      if (lane == 0) atomicAdd(&cnt[k], total);
-    });
+  uint4 nxt = make_uint4(~0u, ~0u, ~0u, ~0u);
+  if (s0 < s1) nxt = load_chunk(labels, s0 + 16 * lane, s1);
+  for (int64_t st = s0; st < s1; st += kStep) {
+    const uint4 cur = nxt;
+    if (st + kStep < s1) nxt = load_chunk(labels, st + kStep + 16 * lane, s1);
+    const int n = compact_step(cur, K, list, bad);
+    if (n == 0) continue;
+    wave_lds_sync();
+    for (int b0 = 0; b0 < n; b0 += 64) {
+      const int i = b0 + lane;
+      const int k = (i < n) ? (int)(list[i] >> 16) : -1;
+      uint64_t pending = __ballot(k >= 0);
+      while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int kk = __shfl(k, leader, 64);
+        const uint64_t mk = __ballot(k == kk);
+        if (lane == leader) atomicAdd(&cnt[kk], __popcll(mk));
+        pending &= ~mk;
+      }
+    }
+    wave_lds_sync();
   }
   if (bad) atomicOr(err, 1);
   __syncthreads();
@@ -96,8 +144,10 @@ __global__ __launch_bounds__(kBlock) void k_label_index(const int8_t* __restrict
                                                         int32_t* __restrict__ idx,
                                                         int64_t* __restrict__ counts_out,
                                                         int32_t* __restrict__ offsets_out) {
-  __shared__ int before[128], total[128], base[128];
+  __shared__ int before[128], total[128];
   __shared__ int wcnt[kWaves][128];
+  __shared__ int run[kWaves][128];
+  __shared__ uint32_t lists[kWaves][kStep];
   for (int i = threadIdx.x; i < 128; i += kBlock) {
     before[i] = 0;
     total[i] = 0;
@@ -114,12 +164,41 @@ __global__ __launch_bounds__(kBlock) void k_label_index(const int8_t* __restrict
       if (tt < t) atomicAdd(&before[k], c);
     }
   }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint32_t* list = lists[w];
+  const int64_t s0 = (int64_t)t * kLabelTile + (int64_t)w * kSub;
+  const int64_t s1 = (s0 + kSub < P) ? s0 + kSub : P;
+  bool bad = false;
+  // per-wave class counts of this wave's quarter of the tile
+  for (int64_t st = s0; st < s1; st += kStep) {
+    const uint4 cur = load_chunk(labels, st + 16 * lane, s1);
+    const int n = compact_step(cur, K, list, bad);
+    if (n == 0) continue;
+    wave_lds_sync();
+    for (int b0 = 0; b0 < n; b0 += 64) {
+      const int i = b0 + lane;
+      const int k = (i < n) ? (int)(list[i] >> 16) : -1;
+      uint64_t pending = __ballot(k >= 0);
+      while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int kk = __shfl(k, leader, 64);
+        const uint64_t mk = __ballot(k == kk);
+        if (lane == leader) wcnt[w][kk] += __popcll(mk);
+        pending &= ~mk;
+      }
+    }
+    wave_lds_sync();
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     int off = 0;
     for (int k = 0; k < K; ++k) {
       const int tk = total[k];
-      base[k] = off + before[k];
+      int b = off + before[k];
+      for (int ww = 0; ww < kWaves; ++ww) {
+        run[ww][k] = b;
+        b += wcnt[ww][k];
+      }
       if (t == 0) {
         counts_out[k] = tk;
         offsets_out[k] = off;
@@ -129,40 +208,34 @@ __global__ __launch_bounds__(kBlock) void k_label_index(const int8_t* __restrict
     if (t == 0) offsets_out[K] = off;
   }
   __syncthreads();
-  const int64_t t0 = (int64_t)t * kLabelTile;
-  const int64_t t1 = (t0 + kLabelTile < P) ? t0 + kLabelTile : P;
-  const int w = threadIdx.x >> 6, lane = __lane_id();
-  for (int64_t rb = t0; rb < t1; rb += 4 * kBlock) {
-    int v[4], rank[4] = {0, 0, 0, 0};
-    bool bad = false;
-    const int64_t p = rb + 4 * threadIdx.x;
-    load4(labels, p, t1, K, v, bad);
-    const int any = (v[0] >= 0) | (v[1] >= 0) | (v[2] >= 0) | (v[3] >= 0);
-    if (!__syncthreads_or(any)) continue;
-    wave_rank(v, rank, [&](int k, int tot) {
-      if (lane == 0) wcnt[w][k] = tot;
-    });
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int k = v[s];
-      if (k >= 0) {
-        int pos = base[k] + rank[s];
-        for (int ww = 0; ww < w; ++ww) pos += wcnt[ww][k];
-        idx[pos] = (int32_t)(p + s);
+  // write indices in raster order with wave-private running offsets
+  uint4 nxt = make_uint4(~0u, ~0u, ~0u, ~0u);
+  if (s0 < s1) nxt = load_chunk(labels, s0 + 16 * lane, s1);
+  for (int64_t st = s0; st < s1; st += kStep) {
+    const uint4 cur = nxt;
+    if (st + kStep < s1) nxt = load_chunk(labels, st + kStep + 16 * lane, s1);
+    const int n = compact_step(cur, K, list, bad);
+    if (n == 0) continue;
+    wave_lds_sync();
+    for (int b0 = 0; b0 < n; b0 += 64) {
+      const int i = b0 + lane;
+      const uint32_t e = (i < n) ? list[i] : 0u;
+      const int k = (i < n) ? (int)(e >> 16) : -1;
+      const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+      uint64_t pending = __ballot(k >= 0);
+      while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int kk = __shfl(k, leader, 64);
+        const uint64_t mk = __ballot(k == kk);
+        const int base = run[w][kk];
+        if (k == kk) idx[base + __popcll(mk & lt)] = (int32_t)(st + (e & 0xffffu));
+        wave_lds_sync();
+        if (lane == leader) run[w][kk] = base + __popcll(mk);
+        wave_lds_sync();
+        pending &= ~mk;
       }
     }
-    __syncthreads();
-    for (int k = threadIdx.x; k < K; k += kBlock) {
-      int add = 0;
-#pragma unroll
-      for (int ww = 0; ww < kWaves; ++ww) {
-        add += wcnt[ww][k];
-        wcnt[ww][k] = 0;
-      }
-      base[k] += add;
-    }
-    __syncthreads();
+    wave_lds_sync();
   }
 }
 

@@ -317,12 +317,20 @@ __global__ __launch_bounds__(kBlock) void k_class_moments_mfma(const void* __res
     const int rows_here = (n - r0 < kChunk) ? n - r0 : kChunk;
     // gather rows: lane -> (row offset lane / B, band lane % B)
     const int lr = lane / B, lb = lane % B;
+    int myp = -1;                                         // lane r: pixel of row r (and r + 64)
+    int myp2 = -1;
+    if (lane < rows_here) myp = idx[off + r0 + lane];
+    if (lane + 64 < rows_here) myp2 = idx[off + r0 + lane + 64];
+#pragma unroll 8
     for (int rr = 0; rr < kChunk; rr += rpi) {
       const int r = rr + lr;
+      const int p1 = __shfl(myp, r & 63, 64);
+      const int p2 = __shfl(myp2, r & 63, 64);
+      const int p = (r < 64) ? p1 : p2;
       if (lr < rpi && r < kChunk) {
         for (int b = lb; b < B; b += 64) {
           T v = (T)0;
-          if (r < rows_here) v = cx[(int64_t)idx[off + r0 + r] * B + b];
+          if (r < rows_here) v = cx[(int64_t)p * B + b];
           rows[r * B + b] = v;
         }
       }

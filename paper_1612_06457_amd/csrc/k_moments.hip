@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_class_moments(const typename Elem<DT
       const int pos = rbase + w * 32 + (lane & 31);
       if (lane < 32 && pos < n) myp = idx[off + pos];
     }
-#pragma unroll 4
+#pragma unroll 16
     for (int rr = 0; rr < 32; ++rr) {
       const int r = w * 32 + rr;
       const int p = __shfl(myp, rr, 64);
@@ -207,14 +207,34 @@ __global__ __launch_bounds__(kBlock) void k_pca_gram(const typename Elem<DT>::T*
   write_partial(ta, accd, red, part + (int64_t)blockIdx.x * ta.nblk * 16);
 }
 
+// 16 entries x 16 slices of g per block: slice j sums g = j, j + 16, ...
+// (four independent chains in flight), then the 16 slice sums are added
+// in slice order.  Fixed order throughout.
 __global__ __launch_bounds__(kBlock) void k_reduce_part(const double* __restrict__ part, int nsets,
                                                         int G, int L, double* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= (int64_t)nsets * L) return;
-  const int s = (int)(i / L), t = (int)(i % L);
-  double acc = 0.0;
-  for (int g = 0; g < G; ++g) acc += part[((int64_t)s * G + g) * L + t];
-  out[i] = acc;
+  __shared__ double red[16][17];
+  const int s = blockIdx.y;
+  const int tl = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  const int t = blockIdx.x * 16 + tl;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (t < L) {
+    const double* src = part + (int64_t)s * G * L + t;
+    int g = sl;
+    for (; g + 48 < G; g += 64) {
+      a0 += src[(int64_t)g * L];
+      a1 += src[(int64_t)(g + 16) * L];
+      a2 += src[(int64_t)(g + 32) * L];
+      a3 += src[(int64_t)(g + 48) * L];
+    }
+    for (; g < G; g += 16) a0 += src[(int64_t)g * L];
+  }
+  red[sl][tl] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (threadIdx.x < 16 && t < L) {
+    double acc = 0.0;
+    for (int j = 0; j < 16; ++j) acc += red[j][tl];
+    out[(int64_t)s * L + t] = acc;
+  }
 }
 
 size_t scatter_smem(int B) {
@@ -283,9 +303,8 @@ hipError_t launch_pca_gram(int dtype, const void* cube, int B, int64_t P, const 
 
 hipError_t launch_reduce_part(const double* part, int nsets, int G, int L, double* out,
                               hipStream_t s) {
-  const int64_t n = (int64_t)nsets * L;
-  hipLaunchKernelGGL(k_reduce_part, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                     s, part, nsets, G, L, out);
+  hipLaunchKernelGGL(k_reduce_part, dim3((unsigned)((L + 15) / 16), nsets), dim3(kBlock), 0, s, part,
+                     nsets, G, L, out);
   return hipGetLastError();
 }
 

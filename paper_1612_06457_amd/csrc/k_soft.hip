@@ -98,6 +98,7 @@ __global__ __launch_bounds__(kBlock) void k_soft_first(const float* __restrict__
     const int c = 4 * (bk / nbj) + e / 4, col = 4 * (bk % nbj) + e % 4;
     mine[c * BP + col] = s;
   }
+  __threadfence();   // every writer publishes its part before the ticket
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();

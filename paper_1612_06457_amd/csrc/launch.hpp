@@ -64,6 +64,14 @@ hipError_t launch_project_stretch(int dtype, const void* cube, int B, int64_t P,
                                   int nvalid, const ProjArgs& a, int nblocks,
                                   const float* range_dev, uint8_t* images, hipStream_t s);
 
+// matrix-core projection for 16-bit pages (same contract as above)
+hipError_t launch_project_range_mfma(int dtype, const void* cube, int B, int64_t P, int nc,
+                                     const ProjArgs& a, int nblocks, float* part, unsigned* ticket,
+                                     float* range_dev, float* ab_dev, hipStream_t s);
+hipError_t launch_project_stretch_mfma(int dtype, const void* cube, int B, int64_t P, int nc,
+                                       const ProjArgs& a, int nblocks, const float* range_dev,
+                                       uint8_t* images, hipStream_t s);
+
 // soft-label CVA
 hipError_t launch_soft_first(const float* X, const float* w, int64_t N, int B, int K,
                              int nblocks, double* part, unsigned* ticket, double* first,

@@ -6,10 +6,10 @@ of analyst-chosen training pixels and, for the soft-label variant, per-pixel
 class weights.  It holds none of the method's arithmetic (no moments, no
 scatter matrices, no eigenproblems, no projection).
 """
-from .cubes import (CONFIGS, Case, make_case, make_class_map, class_params,
+from .cubes import (WORKLOADS, Case, make_case, make_class_map, class_params,
                     render_cube, sample_labels, soft_weights, border_map,
                     make_soft_case, to_half_cube)
 
-__all__ = ["CONFIGS", "Case", "make_case", "make_class_map", "class_params",
+__all__ = ["WORKLOADS", "Case", "make_case", "make_class_map", "class_params",
            "render_cube", "sample_labels", "soft_weights", "border_map",
            "make_soft_case", "to_half_cube"]

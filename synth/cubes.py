@@ -49,7 +49,7 @@ CLASS_NAMES = {
               "stain", "ruling", "bleed"],
 }
 
-CONFIGS = {
+WORKLOADS = {
     1: dict(workload="cva_512x512x16_u16_k3", H=512, W=512, B=16, dtype="u16",
             K=3, n_per_class=2000, cov="shared", layout="text3", seed=1,
             text_spacing=30.0, pca_comps=0),
@@ -374,7 +374,7 @@ def make_case(config: int, seed: Optional[int] = None, scale: float = 1.0,
 
     ``scale`` shrinks both page sides (the training-pixel count shrinks with
     the page area) so the same structure can be drawn at test sizes."""
-    cfg = CONFIGS[config]
+    cfg = WORKLOADS[config]
     seed = cfg["seed"] if seed is None else seed
     H, W, n = _scaled(cfg, scale)
     if n_per_class is not None:

@@ -133,6 +133,7 @@ def test_argument_checks_without_a_device():
         assert fit(L.Cube(aligned.value, 1 << 16, 1 << 16, 8, 0)) == L.E_UNSUPPORTED
         assert fit(good, labels=None) == L.E_INVALID_ARG
         assert fit(good, labels=ctypes.c_void_p(0x20001)) == L.E_UNSUPPORTED
+        assert fit(good, labels=ctypes.c_void_p(0x20004)) == L.E_UNSUPPORTED
         assert fit(good, K=1) == L.E_INVALID_ARG
         assert fit(good, K=128) == L.E_INVALID_ARG
         assert fit(good, prec=7) == L.E_INVALID_ARG
