@@ -157,7 +157,7 @@ def main():
     avg_rng = ms_rng / max(n_rng, 1)
     fit_proj_bytes = 2 * cube_bytes + P * C + (labels.numel() + N * B * 2)
     roof = {
-        "kernel": f"k_project_stretch<u16, {C}> (CVA stretch pass)",
+        "kernel": f"k_stretch_mfma<u16> (CVA stretch pass, {C} components)",
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
@@ -176,7 +176,7 @@ def main():
         try:
             tr = json.load(open(traffic_file))
             import hashlib
-            src = open(os.path.join(ROOT, "paper_1612_06457_amd", "csrc", "k_project.hip"), "rb").read()
+            src = open(os.path.join(ROOT, "paper_1612_06457_amd", "csrc", "k_project_mfma.hip"), "rb").read()
             if tr.get("source_sha1") == hashlib.sha1(src).hexdigest():
                 roof["traffic"] = tr.get("bytes_per_launch")
         except Exception:

@@ -257,6 +257,12 @@ int proj_groups(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const d
         off += wv * (c[b] - center[b]);
       }
       a.off[j] = (float)off;
+      // a power of two that brings the largest |W[b][j]| into [16, 32)
+      double wmax = 0.0;
+      for (int b = 0; b < B; ++b) wmax = std::max(wmax, std::fabs((double)a.w[b * NC + j]));
+      int ex = 0;
+      if (wmax > 0.0) std::frexp(wmax, &ex);
+      a.scale[j] = (float)std::ldexp(1.0, wmax > 0.0 ? 5 - ex : 0);
     }
     static const char* kRangeName[9] = {"", "project_range_nc1", "project_range_nc2", "project_range_nc3",
                                         "project_range_nc4", "project_range_nc5", "project_range_nc6",

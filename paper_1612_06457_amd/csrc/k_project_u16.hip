@@ -1,0 +1,431 @@
+// Fused centre-project-stretch for uint16 pages on the matrix cores (paper
+// Section 2: the regression coefficients multiply every band of the whole
+// page; each float image is rescaled to 0..255 on its page range).
+//
+// y_j = sum_b (x_b - c_b) W[b][j] + off_j with c_b an integer centre.  The
+// contraction runs on v_mfma_f32_16x16x32_f16 with FP32 accumulation, and
+// the operands are built exactly with bit operations, no conversions:
+//
+//   x = 1024 h + l (h: 6 bits, l: 10 bits), c = 1024 c_h + c_l.  The fp16
+//   value with bits 0x6400 | l is 1024 + l exactly, so one AND-OR makes two
+//   of them from a dword of two elements, and one packed fp16 add of
+//   -(1024 + c_l) gives l - c_l (|.| <= 1023) exactly; likewise h - c_h
+//   (|.| <= 63).  Then x - c = 1024 (h - c_h) + (l - c_l).
+//
+//   A (16 rows x 32 slots): a row is one lane group (two pixels when B is
+//   odd, so rows stay dword aligned; else one pixel).  Lane l holds row
+//   l % 16 and, for K-block kb, the dwords q = 8 kb + 2 (l / 16) + {0, 1}
+//   of that row: the l-parts of their four elements and then the h-parts.
+//   Dwords past the row's end read the next row (or padding) and meet zero
+//   weights; their transformed values are always finite.
+//
+//   B (32 slots x 16 columns): column n = 8 p + j is component j of pixel p
+//   of the row.  The slot of element E (pixel E / B, band E % B) carries
+//   W[band][j] for p = E / B (zero otherwise), times 1024 for the h-part.
+//   The weights are scaled by a power of two per component (so the largest
+//   is in [16, 32)) and split into three fp16 terms (33 significant bits;
+//   the small terms may be subnormal, which costs at most 2^-29 of the
+//   largest weight).  Products of fp16 values are exact in FP32.
+//
+//   C (16 rows x 16 columns): lane l holds rows 4 (l / 16) + e, column l % 16.
+//
+// The scaled sum is 2^s_j (y_j): pass 1 keeps min/max of it per column and
+// the last block folds the block partials into the stretch map
+// q = floor(y' s' + o), which equals the map on y exactly because scaling by
+// 2^s_j is exact; the range reported to the host is scaled back.  Pass 2
+// quantises and writes planar bytes (8 bytes per lane for two-pixel rows).
+//
+// Tiles are streamed as in the other projection kernels (k_tile.hpp), with
+// the next tile's loads in flight while the current one is computed.  Up
+// to 40 bands (five K-blocks) the constant operands, the prefetch buffer
+// and the accumulators fit two waves per SIMD, which is enough in flight
+// to stream at full HBM rate; wider pages run one wave per SIMD.
+#include <algorithm>
+
+#include "k_tile.hpp"
+
+namespace cvx {
+
+namespace {
+
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mma(f16x8 a, f16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ uint32_t h16(_Float16 v) { return (uint32_t)__builtin_bit_cast(uint16_t, v); }
+
+// l - c_l and h - c_h for both elements of a data dword, as fp16 pairs.
+__device__ __forceinline__ uint32_t low_part(uint32_t d, uint32_t nl) {
+  const f16x2 v = __builtin_bit_cast(f16x2, (d & 0x03ff03ffu) | 0x64006400u);
+  return __builtin_bit_cast(uint32_t, v + __builtin_bit_cast(f16x2, nl));
+}
+__device__ __forceinline__ uint32_t high_part(uint32_t d, uint32_t nh) {
+  const f16x2 v = __builtin_bit_cast(f16x2, ((d >> 10) & 0x003f003fu) | 0x64006400u);
+  return __builtin_bit_cast(uint32_t, v + __builtin_bit_cast(f16x2, nh));
+}
+
+// v = t0 + t1 + t2 with each term the nearest fp16 to what is left.
+__device__ __forceinline__ void split3(float v, _Float16& t0, _Float16& t1, _Float16& t2) {
+  t0 = (_Float16)v;
+  const float r = v - (float)t0;
+  t1 = (_Float16)r;
+  t2 = (_Float16)(r - (float)t1);
+}
+
+// Per-lane constant operands for NKB K-blocks.
+template <int NKB>
+struct Ops {
+  f16x8 w[NKB][3];        // B operand: the three fp16 terms of the scaled weights
+  uint32_t nl[NKB][2];    // -(1024 + c_l) for the two elements of each data dword
+  uint32_t nh[NKB][2];    // -(1024 + c_h)
+  float acc0;             // off_j scaled, the accumulator's start
+};
+
+// The kernel argument block copied into LDS by the whole block (one
+// coalesced round of loads instead of many dependent per-lane ones).
+__device__ __forceinline__ void stage_args(const ProjArgs& a, ProjArgs& sa) {
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(&a);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&sa);
+  for (int i = threadIdx.x; i < (int)(sizeof(ProjArgs) / 4); i += kBlock) dst[i] = src[i];
+  __syncthreads();
+}
+
+// a.c holds 2^23 + c_b (c_b a non-negative integer), so its low 23 bits are c_b.
+template <int NKB, int G2>
+__device__ __forceinline__ void load_ops(const ProjArgs& a, int B, int nc, Ops<NKB>& o) {
+  const int lane = __lane_id();
+  const int col = lane & 15, g = lane >> 4;
+  const int p = col >> 3, j = col & 7;
+  const bool live = p < G2 && j < nc;
+  const float sc = live ? a.scale[j] : 0.f;
+  const int nel = G2 * B;
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q = 8 * kb + 2 * g + u;
+      uint32_t nlv = 0, nhv = 0;
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const int E = 2 * q + hh;
+        uint32_t cb = 0;
+        float wv = 0.f;
+        if (E < nel) {
+          const int pix = E >= B ? 1 : 0;
+          const int b = E - pix * B;
+          cb = __float_as_uint(a.c[b]) & 0x7fffffu;
+          if (live && pix == p) wv = a.w[b * nc + j] * sc;
+        }
+        nlv |= h16((_Float16)(-(float)(1024u + (cb & 1023u)))) << (16 * hh);
+        nhv |= h16((_Float16)(-(float)(1024u + (cb >> 10)))) << (16 * hh);
+        _Float16 t0, t1, t2;
+        split3(wv, t0, t1, t2);
+        o.w[kb][0][2 * u + hh] = t0;
+        o.w[kb][1][2 * u + hh] = t1;
+        o.w[kb][2][2 * u + hh] = t2;
+        split3(1024.f * wv, t0, t1, t2);
+        o.w[kb][0][4 + 2 * u + hh] = t0;
+        o.w[kb][1][4 + 2 * u + hh] = t1;
+        o.w[kb][2][4 + 2 * u + hh] = t2;
+      }
+      o.nl[kb][u] = nlv;
+      o.nh[kb][u] = nhv;
+    }
+  }
+  o.acc0 = live ? a.off[j] * sc : 0.f;
+}
+
+// The four 16 x 16 output blocks of a wave tile: acc[rb] for rows
+// 16 rb + (lane % 16), rp = that row's start + 2 (lane / 16) for rb = 0.
+// The four blocks' products are interleaved so that consecutive MFMAs are
+// independent.
+template <int NKB>
+__device__ __forceinline__ void project_tile(const uint32_t* __restrict__ rp, int S, const Ops<NKB>& o,
+                                             f32x4 (&acc)[4]) {
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) acc[rb] = f32x4{o.acc0, o.acc0, o.acc0, o.acc0};
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb) {
+    f16x8 A[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const uint32_t* q = rp + 16 * rb * S + 8 * kb;
+      const uint32_t d0 = q[0], d1 = q[1];
+      u32x4 v;
+      v[0] = low_part(d0, o.nl[kb][0]);
+      v[1] = low_part(d1, o.nl[kb][1]);
+      v[2] = high_part(d0, o.nh[kb][0]);
+      v[3] = high_part(d1, o.nh[kb][1]);
+      A[rb] = __builtin_bit_cast(f16x8, v);
+    }
+#pragma unroll
+    for (int m = 2; m >= 0; --m)   // smallest terms first
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) acc[rb] = mma(A[rb], o.w[kb][m], acc[rb]);
+  }
+}
+
+// Tile loop shared by both passes: body(t, acc[4]) per wave tile, acc[rb]
+// holding rows 16 rb + 4 (lane / 16) + e.
+template <int NKB, int G2, typename Body>
+__device__ __forceinline__ void run_tiles(const void* __restrict__ cube, int B, int64_t P, const Ops<NKB>& o,
+                                          uint32_t* __restrict__ lds, Body body) {
+  constexpr int Q = 2 * NKB;   // 16 S / 64 <= 2 NKB chunks per lane
+  const int S = G2 == 2 ? B : B / 2;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint32_t* my = lds + w * 64 * S;
+  const int64_t tp = 64 * G2;
+  const int64_t nt = (P + tp - 1) / tp;
+  const int64_t total_bytes = P * B * 2;
+  const unsigned char* base = reinterpret_cast<const unsigned char*>(cube);
+  const uint32_t* rp = my + (lane & 15) * S + 2 * (lane >> 4);
+  for_each_tile<Q>(base, total_bytes, nt, S, my, [&](int64_t t) {
+    f32x4 acc[4];
+    project_tile<NKB>(rp, S, o, acc);
+    body(t, acc);
+  });
+}
+
+template <int NKB, int G2>
+__global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_range_u16(const void* __restrict__ cube, int B, int64_t P, int nc,
+                                                      ProjArgs a, float* __restrict__ part,
+                                                      unsigned* __restrict__ ticket, float* __restrict__ range_dev,
+                                                      float* __restrict__ ab_dev) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  __shared__ float wred[kWaves][16];
+  __shared__ bool am_last;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, p = (lane & 15) >> 3;
+  __shared__ ProjArgs sa;
+  stage_args(a, sa);
+  Ops<NKB> o;
+  load_ops<NKB, G2>(sa, B, nc, o);
+  float mn = __builtin_inff(), mx = -__builtin_inff();
+  run_tiles<NKB, G2>(cube, B, P, o, lds, [&](int64_t t, const f32x4 (&acc)[4]) {
+    const int64_t pb = t * 64 * G2;
+    const bool full = pb + 64 * G2 <= P;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t pix = pb + (int64_t)(16 * rb + 4 * g + e) * G2 + p;
+        if (full || pix < P) {
+          mn = fminf(mn, acc[rb][e]);
+          mx = fmaxf(mx, acc[rb][e]);
+        }
+      }
+  });
+  // lanes holding the same component: l ^ 8 (other pixel of the row, if
+  // any), l ^ 16, l ^ 32 (other rows)
+  if (G2 == 2) {
+    mn = fminf(mn, __shfl_xor(mn, 8, 64));
+    mx = fmaxf(mx, __shfl_xor(mx, 8, 64));
+  }
+  mn = fminf(mn, __shfl_xor(mn, 16, 64));
+  mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+  mn = fminf(mn, __shfl_xor(mn, 32, 64));
+  mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+  if (lane < 8) {
+    wred[w][lane] = mn;
+    wred[w][8 + lane] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    const int j = threadIdx.x;
+    float lo = wred[0][j], hi = wred[0][8 + j];
+    for (int ww = 1; ww < kWaves; ++ww) {
+      lo = fminf(lo, wred[ww][j]);
+      hi = fmaxf(hi, wred[ww][8 + j]);
+    }
+    part[(int64_t)blockIdx.x * 16 + j] = lo;
+    part[(int64_t)blockIdx.x * 16 + 8 + j] = hi;
+    __threadfence();
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    am_last = (atomicAdd(ticket, 1u) == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!am_last) return;
+  __threadfence();
+  // last block: thread (slice, component) folds a strided subset of partials
+  const int j = threadIdx.x & 7, sl = threadIdx.x >> 3;
+  float lo = __builtin_inff(), hi = -__builtin_inff();
+  for (unsigned bk = sl; bk < gridDim.x; bk += kBlock / 8) {
+    lo = fminf(lo, __builtin_nontemporal_load(part + (int64_t)bk * 16 + j));
+    hi = fmaxf(hi, __builtin_nontemporal_load(part + (int64_t)bk * 16 + 8 + j));
+  }
+  lo = fminf(lo, __shfl_xor(lo, 8, 64));
+  hi = fmaxf(hi, __shfl_xor(hi, 8, 64));
+  lo = fminf(lo, __shfl_xor(lo, 16, 64));
+  hi = fmaxf(hi, __shfl_xor(hi, 16, 64));
+  lo = fminf(lo, __shfl_xor(lo, 32, 64));
+  hi = fmaxf(hi, __shfl_xor(hi, 32, 64));
+  __syncthreads();
+  if (lane < 8) {
+    wred[w][lane] = lo;
+    wred[w][8 + lane] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x < nc) {
+    const int jj = threadIdx.x;
+    float l2 = wred[0][jj], h2 = wred[0][8 + jj];
+    for (int ww = 1; ww < kWaves; ++ww) {
+      l2 = fminf(l2, wred[ww][jj]);
+      h2 = fmaxf(h2, wred[ww][8 + jj]);
+    }
+    const float s = (h2 > l2) ? 255.f / (h2 - l2) : 0.f;
+    range_dev[jj] = s;
+    range_dev[8 + jj] = 0.5f - l2 * s;
+    const float inv = 1.f / sa.scale[jj];   // a power of two: exact
+    ab_dev[2 * jj] = l2 * inv;
+    ab_dev[2 * jj + 1] = h2 * inv;
+  }
+  if (threadIdx.x == 0) *ticket = 0u;
+}
+
+__device__ __forceinline__ uint32_t quant(float y, float s, float o) {
+  float t = floorf(fmaf(y, s, o));
+  t = fminf(fmaxf(t, 0.f), 255.f);
+  return (uint32_t)t;
+}
+
+template <int NKB, int G2>
+__global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_stretch_u16(const void* __restrict__ cube, int B, int64_t P, int nc,
+                                                        ProjArgs a, const float* __restrict__ range_dev,
+                                                        uint8_t* __restrict__ images) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, col = lane & 15, p = col >> 3, j = col & 7;
+  const bool live = p < G2 && j < nc;
+  const bool writer = p == 0 && j < nc;
+  __shared__ ProjArgs sa;
+  stage_args(a, sa);
+  Ops<NKB> o;
+  load_ops<NKB, G2>(sa, B, nc, o);
+  const float sc = live ? range_dev[j] : 0.f;
+  const float of = live ? range_dev[8 + j] : 0.f;
+  uint8_t* plane = images + (int64_t)(j < nc ? j : 0) * P;
+  const int vec = G2 == 2 ? 8 : 4;
+  const bool aligned = (P % vec) == 0 && (reinterpret_cast<uintptr_t>(images) % vec) == 0;
+  run_tiles<NKB, G2>(cube, B, P, o, lds, [&](int64_t t, const f32x4 (&acc)[4]) {
+    const int64_t pb = t * 64 * G2;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const uint32_t mine = quant(acc[rb][0], sc, of) | (quant(acc[rb][1], sc, of) << 8) |
+                            (quant(acc[rb][2], sc, of) << 16) | (quant(acc[rb][3], sc, of) << 24);
+      if constexpr (G2 == 2) {
+        // even pixels of rows 16 rb + 4 g + e here, odd ones in lane ^ 8
+        const uint32_t other = __shfl_xor(mine, 8, 64);
+        if (writer) {
+          const uint32_t lo = __builtin_amdgcn_perm(other, mine, 0x05010400u);
+          const uint32_t hi = __builtin_amdgcn_perm(other, mine, 0x07030602u);
+          const int64_t px = pb + 2 * (16 * rb + 4 * g);
+          if (aligned && px + 8 <= P) {
+            *reinterpret_cast<uint2*>(plane + px) = make_uint2(lo, hi);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              if (px + e < P) plane[px + e] = (uint8_t)((e < 4 ? lo : hi) >> (8 * (e & 3)));
+          }
+        }
+      } else {
+        if (writer) {
+          const int64_t px = pb + 16 * rb + 4 * g;
+          if (aligned && px + 4 <= P) {
+            *reinterpret_cast<uint32_t*>(plane + px) = mine;
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (px + e < P) plane[px + e] = (uint8_t)(mine >> (8 * e));
+          }
+        }
+      }
+    }
+  });
+}
+
+// LDS: the wave slices plus 8 dwords that the last row's reads may reach.
+size_t smem(int B) { return ((size_t)kWaves * 64 * ((B & 1) ? B : B / 2) + 8) * 4; }
+
+int grid(const void* kernel, size_t sm, int nblocks, int64_t P, int B) {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, sm) != hipSuccess || per < 1)
+    per = 1, ncu = 1;
+  const int64_t tp = 64 * ((B & 1) ? 2 : 1);
+  const int64_t waves = (P + tp - 1) / tp;
+  int64_t n = std::min<int64_t>((int64_t)per * ncu, nblocks);
+  n = std::min<int64_t>(n, (waves + kWaves - 1) / kWaves);
+  return (int)std::max<int64_t>(n, 1);
+}
+
+template <int NKB, int G2>
+hipError_t range_k(const void* cube, int B, int64_t P, int nc, const ProjArgs& a, int nblocks, float* part,
+                   unsigned* ticket, float* range_dev, float* ab_dev, hipStream_t s) {
+  const size_t sm = smem(B);
+  const void* k = reinterpret_cast<const void*>(&k_range_u16<NKB, G2>);
+  const int nb = grid(k, sm, nblocks, P, B);
+  hipLaunchKernelGGL((k_range_u16<NKB, G2>), dim3(nb), dim3(kBlock), sm, s, cube, B, P, nc, a, part, ticket,
+                     range_dev, ab_dev);
+  return hipGetLastError();
+}
+
+template <int NKB, int G2>
+hipError_t stretch_k(const void* cube, int B, int64_t P, int nc, const ProjArgs& a, int nblocks,
+                     const float* range_dev, uint8_t* images, hipStream_t s) {
+  const size_t sm = smem(B);
+  const void* k = reinterpret_cast<const void*>(&k_stretch_u16<NKB, G2>);
+  const int nb = grid(k, sm, nblocks, P, B);
+  hipLaunchKernelGGL((k_stretch_u16<NKB, G2>), dim3(nb), dim3(kBlock), sm, s, cube, B, P, nc, a, range_dev,
+                     images);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// NKB = ceil(S / 8) K-blocks for S dwords per row (S = B for odd B, else B / 2).
+#define CVX_U16_SWITCH(CALL)                                  \
+  const int S = (B & 1) ? B : B / 2;                          \
+  const int nkb = (S + 7) / 8;                                \
+  if (B & 1) {                                                \
+    switch (nkb) {                                            \
+      case 1: return CALL(1, 2); case 2: return CALL(2, 2);   \
+      case 3: return CALL(3, 2); case 4: return CALL(4, 2);   \
+      case 5: return CALL(5, 2); case 6: return CALL(6, 2);   \
+      case 7: return CALL(7, 2); case 8: return CALL(8, 2);   \
+    }                                                         \
+  } else {                                                    \
+    switch (nkb) {                                            \
+      case 1: return CALL(1, 1); case 2: return CALL(2, 1);   \
+      case 3: return CALL(3, 1); case 4: return CALL(4, 1);   \
+    }                                                         \
+  }                                                           \
+  return hipErrorInvalidValue;
+
+hipError_t launch_project_range_u16(const void* cube, int B, int64_t P, int nc, const ProjArgs& a, int nblocks,
+                                    float* part, unsigned* ticket, float* range_dev, float* ab_dev,
+                                    hipStream_t s) {
+  if (B < 1 || B > kMaxB || nc < 1 || nc > 8) return hipErrorInvalidValue;
+#define CVX_R(N, G) range_k<N, G>(cube, B, P, nc, a, nblocks, part, ticket, range_dev, ab_dev, s)
+  CVX_U16_SWITCH(CVX_R)
+#undef CVX_R
+}
+
+hipError_t launch_project_stretch_u16(const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
+                                      int nblocks, const float* range_dev, uint8_t* images, hipStream_t s) {
+  if (B < 1 || B > kMaxB || nc < 1 || nc > 8) return hipErrorInvalidValue;
+#define CVX_S(N, G) stretch_k<N, G>(cube, B, P, nc, a, nblocks, range_dev, images, s)
+  CVX_U16_SWITCH(CVX_S)
+#undef CVX_S
+}
+
+#undef CVX_U16_SWITCH
+
+}  // namespace cvx

@@ -17,6 +17,7 @@ struct ProjArgs {
   float w[64 * 8];   // W[b * nc + j] for this group of nc <= 8 components (row stride nc)
   float c[64];       // per-band centre (integer for uint16 pages)
   float off[8];      // sum_b W[b][j] (c_b - centre_b), added to each y_j
+  float scale[8];    // power of two per component (uint16 matrix-core kernels)
 };
 
 struct SoftBwdArgs {
@@ -64,7 +65,14 @@ hipError_t launch_project_stretch(int dtype, const void* cube, int B, int64_t P,
                                   int nvalid, const ProjArgs& a, int nblocks,
                                   const float* range_dev, uint8_t* images, hipStream_t s);
 
-// matrix-core projection for 16-bit pages (same contract as above)
+// matrix-core projection (same contract as above): uint16 pages, and
+// bf16 / fp16 pages
+hipError_t launch_project_range_u16(const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
+                                    int nblocks, float* part, unsigned* ticket, float* range_dev,
+                                    float* ab_dev, hipStream_t s);
+hipError_t launch_project_stretch_u16(const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
+                                      int nblocks, const float* range_dev, uint8_t* images,
+                                      hipStream_t s);
 hipError_t launch_project_range_mfma(int dtype, const void* cube, int B, int64_t P, int nc,
                                      const ProjArgs& a, int nblocks, float* part, unsigned* ticket,
                                      float* range_dev, float* ab_dev, hipStream_t s);
