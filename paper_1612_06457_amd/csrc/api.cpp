@@ -414,7 +414,8 @@ int cva_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels, int32_
   const int64_t P = cube->height * cube->width;
   const int nT = (int)((P + cvx::kLabelTile - 1) / cvx::kLabelTile);
   const int L = cvx::tri_blocks(B) * 16;
-  const int G = std::max(1, std::min(64, 4096 / K));
+  // blocks per class: about four resident blocks per CU over all classes
+  const int G = std::max(1, std::min(256, 4 * ctx->num_cu / K));
   const FitLayout lay(K, B, L);
   if (int st = ensure(ctx, B_TILECNT, (size_t)nT * K * 4)) return st;
   if (int st = ensure(ctx, B_IDX, (size_t)P * 4)) return st;
@@ -435,12 +436,12 @@ int cva_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels, int32_
   if (e != hipSuccess) return hip_fail(ctx, e, "label index launch");
   if (prec == CVAMX_PREC_FP32) {
     prof_begin(ctx, s, "class_moments");
-    e = cvx::launch_class_moments(cube->dtype, cube->data, B, (const int32_t*)ctx->buf[B_IDX],
+    e = cvx::launch_class_moments(cube->dtype, cube->data, B, P, (const int32_t*)ctx->buf[B_IDX],
                                   (const int32_t*)(res + lay.offsets), K, G, (double*)ctx->buf[B_PART],
                                   (double*)(res + lay.shift), s);
   } else {
     prof_begin(ctx, s, "class_moments_mfma");
-    e = cvx::launch_class_moments_mfma(cube->dtype, prec == CVAMX_PREC_BF16X3 ? 0 : 1, cube->data, B,
+    e = cvx::launch_class_moments_mfma(cube->dtype, prec == CVAMX_PREC_BF16X3 ? 0 : 1, cube->data, B, P,
                                        (const int32_t*)ctx->buf[B_IDX], (const int32_t*)(res + lay.offsets), K,
                                        G, (double*)ctx->buf[B_PART], (double*)(res + lay.shift), s);
   }

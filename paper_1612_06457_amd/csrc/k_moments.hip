@@ -1,6 +1,6 @@
-// FP32 scatter accumulation (plain path): per-class augmented Gram
-// matrices of [x - c_k, 1] over the training pixels, the whole-page Gram of
-// [x - s, 1] for PCA, and the fixed-order FP64 combine of block partials.
+// FP32 scatter accumulation (plain path) for the whole-page Gram of
+// [x - s, 1] (PCA), and the fixed-order FP64 combine of block partials
+// (shared with the class moments of k_class.hip).
 //
 // Paper Section 2: the within- and between-class covariance of the training
 // points (CVA) and the covariance of the page (PCA).  The augmented Gram
@@ -12,148 +12,42 @@
 // cancellation.  Each thread accumulates a 4x4 tile in FP32 over one chunk
 // of at most 128 rows and adds it into FP64 registers; block partials are
 // combined in a fixed order, so results are bitwise repeatable.
-#include "k_common.hpp"
+#include "k_gram.hpp"
+#include "k_tile.hpp"
 #include "launch.hpp"
 
 namespace cvx {
 
 namespace {
 
-// Shared tail: accumulate the chunk xs (kChunk x BP, LDS) into acc / accd.
-struct TileAssign {
-  int bi, bj, slice, nslice, blk, nblk;
-  bool active;
-};
-
-__device__ __forceinline__ TileAssign assign_tiles(int BP) {
-  TileAssign t;
-  const int nb = BP / 4;
-  t.nblk = nb * (nb + 1) / 2;
-  t.nslice = kBlock / t.nblk;
-  t.blk = threadIdx.x % t.nblk;
-  t.slice = threadIdx.x / t.nblk;
-  t.bi = t.bj = 0;
-  t.active = (t.slice < t.nslice) && tri_tile(t.blk, nb, t.bi, t.bj);
-  return t;
-}
-
-// Combine the FP64 per-thread tiles across slices in a fixed order and
-// write one block partial (nblk * 16 doubles).
-__device__ __forceinline__ void write_partial(const TileAssign& ta, const double accd[16],
-                                              double* __restrict__ red, double* __restrict__ out) {
-  __syncthreads();
-  if (ta.active)
-    for (int e = 0; e < 16; ++e) red[(ta.slice * ta.nblk + ta.blk) * 16 + e] = accd[e];
-  __syncthreads();
-  for (int t = threadIdx.x; t < ta.nblk * 16; t += kBlock) {
-    double s = 0.0;
-    for (int sl = 0; sl < ta.nslice; ++sl) s += red[sl * ta.nblk * 16 + t];
-    out[t] = s;
-  }
-}
-
-template <int DT>
-__global__ __launch_bounds__(kBlock) void k_class_moments(const typename Elem<DT>::T* __restrict__ cube,
-                                                          int B, const int32_t* __restrict__ idx,
-                                                          const int32_t* __restrict__ offsets, int G,
-                                                          double* __restrict__ part,
-                                                          double* __restrict__ shift_out) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  float* xs = reinterpret_cast<float*>(smem_raw);
-  double* red = reinterpret_cast<double*>(smem_raw);
-  __shared__ float cs[kMaxB];
-  __shared__ float psum[kWaves][kMaxB];
-  const int k = blockIdx.y, g = blockIdx.x;
-  const int BP = (B + 1 + 3) & ~3;
-  const int off = offsets[k];
-  const int n = offsets[k + 1] - off;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-
-  // shift: mean of the class's first min(64, n) pixels, fixed order
-  const int ns = n < 64 ? n : 64;
-  for (int b = lane; b < B; b += 64) {
-    float s = 0.f;
-    const int i1 = (w * 16 + 16 < ns) ? w * 16 + 16 : ns;
-    for (int i = w * 16; i < i1; ++i) s += to_float<DT>(cube[(int64_t)idx[off + i] * B + b]);
-    psum[w][b] = s;
-  }
-  __syncthreads();
-  for (int b = tid; b < B; b += kBlock) {
-    const float s = ((psum[0][b] + psum[1][b]) + psum[2][b]) + psum[3][b];
-    float c = ns > 0 ? s / (float)ns : 0.f;
-    if (DT == DT_U16) c = rintf(c);
-    cs[b] = c;
-    if (g == 0) shift_out[(int64_t)k * B + b] = (double)c;
-  }
-  __syncthreads();
-
-  const TileAssign ta = assign_tiles(BP);
-  float acc[16];
-  double accd[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    acc[e] = 0.f;
-    accd[e] = 0.0;
-  }
-  const int nch = (n + kChunk - 1) / kChunk;
-  for (int ch = g; ch < nch; ch += G) {
-    const int rbase = ch * kChunk;
-    int myp = -1;
-    {
-      const int pos = rbase + w * 32 + (lane & 31);
-      if (lane < 32 && pos < n) myp = idx[off + pos];
-    }
-#pragma unroll 16
-    for (int rr = 0; rr < 32; ++rr) {
-      const int r = w * 32 + rr;
-      const int p = __shfl(myp, rr, 64);
-      for (int e = lane; e < BP; e += 64) {
-        float v = 0.f;
-        if (p >= 0) {
-          if (e < B) v = to_float<DT>(cube[(int64_t)p * B + e]) - cs[e];
-          else if (e == B) v = 1.f;
-        }
-        xs[r * BP + e] = v;
-      }
-    }
-    __syncthreads();
-    if (ta.active) tile_acc(xs, BP, xs, BP, ta.bi, ta.bj, ta.slice, kChunk, ta.nslice, acc);
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      accd[e] += (double)acc[e];
-      acc[e] = 0.f;
-    }
-  }
-  write_partial(ta, accd, red, part + ((int64_t)k * G + g) * ta.nblk * 16);
-}
-
-template <int DT>
+// Block tiles of kChunk pixels (kChunk B elements: a multiple of 16 bytes)
+// are streamed with the prefetching driver of k_tile.hpp; each is turned
+// into the FP32 rows [x - s, 1] in LDS and accumulated by the block.
+template <int DT, int Q>
 __global__ __launch_bounds__(kBlock) void k_pca_gram(const typename Elem<DT>::T* __restrict__ cube,
                                                      int B, int64_t P,
                                                      const uint8_t* __restrict__ mask,
                                                      double* __restrict__ part,
                                                      double* __restrict__ shift_out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  float* xs = reinterpret_cast<float*>(smem_raw);
+  constexpr int esz = DT == DT_F32 ? 4 : 2;
+  const int BP = (B + 1 + 3) & ~3;
+  const int tile_bytes = kChunk * B * esz;
+  uint32_t* raw = reinterpret_cast<uint32_t*>(smem_raw);                       // the staged tile
+  float* xs = reinterpret_cast<float*>(smem_raw + ((tile_bytes + 15) & ~15));  // kChunk x BP
   double* red = reinterpret_cast<double*>(smem_raw);
   __shared__ float cs[kMaxB];
-  __shared__ float psum[kWaves][kMaxB];
-  const int BP = (B + 1 + 3) & ~3;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  __shared__ uint8_t vrow[kChunk];
+  const int tid = threadIdx.x;
 
   // shift: mean of 64 pixels spread evenly over the page, fixed order
-  for (int b = lane; b < B; b += 64) {
-    float s = 0.f;
-    for (int i = w * 16; i < w * 16 + 16; ++i) {
-      const int64_t p = (int64_t)i * P / 64;
-      s += to_float<DT>(cube[p * B + b]);
-    }
-    psum[w][b] = s;
-  }
-  __syncthreads();
   for (int b = tid; b < B; b += kBlock) {
-    const float s = ((psum[0][b] + psum[1][b]) + psum[2][b]) + psum[3][b];
+    float x[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) x[i] = to_float<DT>(cube[((int64_t)i * P / 64) * B + b]);
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < 64; ++i) s += x[i];
     float c = s / 64.f;
     if (DT == DT_U16) c = rintf(c);
     cs[b] = c;
@@ -170,40 +64,39 @@ __global__ __launch_bounds__(kBlock) void k_pca_gram(const typename Elem<DT>::T*
     accd[e] = 0.0;
   }
   const int64_t nch = (P + kChunk - 1) / kChunk;
-  const int per = kChunk * B;                 // elements per chunk
-  const int rstep = kBlock / B, bstep = kBlock % B;
-  for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+  const int rstep = kBlock / BP, bstep = kBlock % BP;
+  const typename Elem<DT>::T* tile = reinterpret_cast<const typename Elem<DT>::T*>(raw);
+  for_each_tile_n<Q, kBlock>(reinterpret_cast<const unsigned char*>(cube), P * B * (int64_t)esz, nch, tile_bytes,
+                             raw, [&](int64_t ch) {
     const int64_t p0 = ch * kChunk;
-    const int rows = (P - p0 < kChunk) ? (int)(P - p0) : kChunk;
-    const int nel = rows * B;
-    const typename Elem<DT>::T* src = cube + p0 * B;
-    int r = tid / B, b = tid % B;
-#pragma unroll 4
-    for (int e = tid; e < per; e += kBlock) {
+    if (tid < kChunk) {
+      const int64_t p = p0 + tid;
+      vrow[tid] = (p < P && (mask == nullptr || mask[p] != 0)) ? 1 : 0;
+    }
+    __syncthreads();
+    int r = tid / BP, b = tid % BP;
+    for (int e = tid; e < kChunk * BP; e += kBlock) {
       float v = 0.f;
-      if (e < nel && (mask == nullptr || mask[p0 + r])) v = to_float<DT>(src[e]) - cs[b];
-      xs[r * BP + b] = v;
+      if (vrow[r]) {
+        if (b < B) v = to_float<DT>(tile[r * B + b]) - cs[b];
+        else if (b == B) v = 1.f;
+      }
+      xs[e] = v;
       r += rstep;
       b += bstep;
-      if (b >= B) {
-        b -= B;
+      if (b >= BP) {
+        b -= BP;
         ++r;
       }
     }
-    if (tid < kChunk) {
-      const bool ok = tid < rows && (mask == nullptr || mask[p0 + tid]);
-      xs[tid * BP + B] = ok ? 1.f : 0.f;
-      for (int e = B + 1; e < BP; ++e) xs[tid * BP + e] = 0.f;
-    }
     __syncthreads();
     if (ta.active) tile_acc(xs, BP, xs, BP, ta.bi, ta.bj, ta.slice, kChunk, ta.nslice, acc);
-    __syncthreads();
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       accd[e] += (double)acc[e];
       acc[e] = 0.f;
     }
-  }
+  });
   write_partial(ta, accd, red, part + (int64_t)blockIdx.x * ta.nblk * 16);
 }
 
@@ -237,68 +130,57 @@ __global__ __launch_bounds__(kBlock) void k_reduce_part(const double* __restrict
   }
 }
 
-size_t scatter_smem(int B) {
+size_t pca_smem(int dtype, int B) {
   const int BP = (B + 1 + 3) & ~3;
   const int nb = BP / 4, nblk = nb * (nb + 1) / 2;
-  const size_t a = (size_t)kChunk * BP * sizeof(float);
+  const size_t tile = ((size_t)kChunk * B * (dtype == DT_F32 ? 4 : 2) + 15) & ~size_t(15);
+  const size_t a = tile + (size_t)kChunk * BP * sizeof(float);
   const size_t b = (size_t)(kBlock / nblk) * nblk * 16 * sizeof(double);
   return a > b ? a : b;
 }
 
-}  // namespace
+// chunks per thread for a block tile: kChunk B esize / 16 / kBlock, rounded up to an instantiated bound
+int pca_q(int dtype, int B) {
+  const int chunks = kChunk * B * (dtype == DT_F32 ? 4 : 2) / 16;
+  const int q = (chunks + kBlock - 1) / kBlock;
+  return q <= 2 ? 2 : q <= 4 ? 4 : 8;
+}
 
-hipError_t launch_class_moments(int dtype, const void* cube, int B, const int32_t* idx,
-                                const int32_t* offsets, int K, int G, double* part,
-                                double* shift_out, hipStream_t s) {
-  const dim3 grid(G, K);
-  const size_t sm = scatter_smem(B);
-  switch (dtype) {
-    case DT_U16:
-      hipLaunchKernelGGL(k_class_moments<DT_U16>, grid, dim3(kBlock), sm, s,
-                         (const uint16_t*)cube, B, idx, offsets, G, part, shift_out);
+template <int DT>
+hipError_t pca_dt(const void* cube, int B, int64_t P, const uint8_t* mask, int nblocks, double* part,
+                  double* shift_out, hipStream_t s) {
+  using T = typename Elem<DT>::T;
+  const size_t sm = pca_smem(DT, B);
+  switch (pca_q(DT, B)) {
+    case 2:
+      hipLaunchKernelGGL((k_pca_gram<DT, 2>), dim3(nblocks), dim3(kBlock), sm, s, (const T*)cube, B, P, mask, part,
+                         shift_out);
       break;
-    case DT_F32:
-      hipLaunchKernelGGL(k_class_moments<DT_F32>, grid, dim3(kBlock), sm, s,
-                         (const float*)cube, B, idx, offsets, G, part, shift_out);
-      break;
-    case DT_BF16:
-      hipLaunchKernelGGL(k_class_moments<DT_BF16>, grid, dim3(kBlock), sm, s,
-                         (const uint16_t*)cube, B, idx, offsets, G, part, shift_out);
-      break;
-    case DT_F16:
-      hipLaunchKernelGGL(k_class_moments<DT_F16>, grid, dim3(kBlock), sm, s,
-                         (const uint16_t*)cube, B, idx, offsets, G, part, shift_out);
+    case 4:
+      hipLaunchKernelGGL((k_pca_gram<DT, 4>), dim3(nblocks), dim3(kBlock), sm, s, (const T*)cube, B, P, mask, part,
+                         shift_out);
       break;
     default:
-      return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_pca_gram<DT, 8>), dim3(nblocks), dim3(kBlock), sm, s, (const T*)cube, B, P, mask, part,
+                         shift_out);
+      break;
   }
   return hipGetLastError();
 }
 
+}  // namespace
+
+
 hipError_t launch_pca_gram(int dtype, const void* cube, int B, int64_t P, const uint8_t* mask,
                            int nblocks, double* part, double* shift_out, hipStream_t s) {
-  const size_t sm = scatter_smem(B);
+  if (B < 1 || B > kMaxB || nblocks < 1) return hipErrorInvalidValue;
   switch (dtype) {
-    case DT_U16:
-      hipLaunchKernelGGL(k_pca_gram<DT_U16>, dim3(nblocks), dim3(kBlock), sm, s,
-                         (const uint16_t*)cube, B, P, mask, part, shift_out);
-      break;
-    case DT_F32:
-      hipLaunchKernelGGL(k_pca_gram<DT_F32>, dim3(nblocks), dim3(kBlock), sm, s,
-                         (const float*)cube, B, P, mask, part, shift_out);
-      break;
-    case DT_BF16:
-      hipLaunchKernelGGL(k_pca_gram<DT_BF16>, dim3(nblocks), dim3(kBlock), sm, s,
-                         (const uint16_t*)cube, B, P, mask, part, shift_out);
-      break;
-    case DT_F16:
-      hipLaunchKernelGGL(k_pca_gram<DT_F16>, dim3(nblocks), dim3(kBlock), sm, s,
-                         (const uint16_t*)cube, B, P, mask, part, shift_out);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case DT_U16: return pca_dt<DT_U16>(cube, B, P, mask, nblocks, part, shift_out, s);
+    case DT_F32: return pca_dt<DT_F32>(cube, B, P, mask, nblocks, part, shift_out, s);
+    case DT_BF16: return pca_dt<DT_BF16>(cube, B, P, mask, nblocks, part, shift_out, s);
+    case DT_F16: return pca_dt<DT_F16>(cube, B, P, mask, nblocks, part, shift_out, s);
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_reduce_part(const double* part, int nsets, int G, int L, double* out,

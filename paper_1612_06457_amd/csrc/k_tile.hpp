@@ -30,35 +30,37 @@ struct Geo {
   static __device__ __host__ constexpr int S(int B) { return (esize == 4 || (B & 1)) ? B : B / 2; }
 };
 
-// Loads of a whole tile t into registers (Q >= 16 S / 64), with no branch:
-// a chunk index past the tile's last chunk is clamped to it (a re-read that
-// the store below drops), so every register of r is written on every path
-// and the array stays in registers.
-template <int Q>
-__device__ __forceinline__ void load_tile(const unsigned char* __restrict__ base, int64_t t, int S, int lane,
-                                          u32x4 (&r)[Q]) {
-  const unsigned char* tb = base + t * 256 * (int64_t)S;
-  const int last = 16 * S - 1;
+// Loads of a whole tile t (tile_bytes bytes, a multiple of 16) into
+// registers, by the NT threads sharing the tile (Q >= tile_bytes / 16 NT),
+// with no branch: a chunk index past the tile's last chunk is clamped to it
+// (a re-read that the store below drops), so every register of r is written
+// on every path and the array stays in registers.
+template <int Q, int NT = 64>
+__device__ __forceinline__ void load_tile(const unsigned char* __restrict__ base, int64_t t, int tile_bytes,
+                                          int tid, u32x4 (&r)[Q]) {
+  const unsigned char* tb = base + t * (int64_t)tile_bytes;
+  const int last = tile_bytes / 16 - 1;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) r[q] = *reinterpret_cast<const u32x4*>(tb + 16 * min(lane + 64 * q, last));
+  for (int q = 0; q < Q; ++q) r[q] = *reinterpret_cast<const u32x4*>(tb + 16 * min(tid + NT * q, last));
 }
 
-template <int Q>
-__device__ __forceinline__ void store_tile(uint32_t* __restrict__ my, int S, int lane, const u32x4 (&r)[Q]) {
-  const int nchunk = 16 * S;
+template <int Q, int NT = 64>
+__device__ __forceinline__ void store_tile(uint32_t* __restrict__ my, int tile_bytes, int tid, const u32x4 (&r)[Q]) {
+  const int nchunk = tile_bytes / 16;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int j = lane + 64 * q;
+    const int j = tid + NT * q;
     if (j < nchunk) *reinterpret_cast<u32x4*>(my + 4 * j) = r[q];
   }
 }
 
 // The partial last tile, straight into LDS (16-bit granularity at the end).
+template <int NT = 64>
 __device__ __forceinline__ void copy_partial_tile(const unsigned char* __restrict__ base, int64_t total_bytes,
-                                               int64_t t, int S, int lane, uint32_t* __restrict__ my) {
-  const int64_t tb = t * 256 * (int64_t)S;
-  const int nchunk = 16 * S;
-  for (int j = lane; j < nchunk; j += 64) {
+                                                  int64_t t, int tile_bytes, int tid, uint32_t* __restrict__ my) {
+  const int64_t tb = t * (int64_t)tile_bytes;
+  const int nchunk = tile_bytes / 16;
+  for (int j = tid; j < nchunk; j += NT) {
     const int64_t ob = tb + 16 * (int64_t)j;
     u32x4 v;
     if (ob + 16 <= total_bytes) {
@@ -74,43 +76,59 @@ __device__ __forceinline__ void copy_partial_tile(const unsigned char* __restric
   }
 }
 
-// Runs compute(t) for the wave's tiles t = first, first + stride, ... < nt
-// with tile t staged in the wave's LDS slice `my`, and the loads of the
-// next tile in flight meanwhile.  The prefetch is unconditional (its tile
-// index is clamped to a whole tile: past the end it re-reads the current,
-// cache-hot one), because a conditional write to the register buffer makes
-// the compiler keep that buffer in scratch memory.  A page shorter than one
-// tile takes the plain path.  A scheduling barrier keeps the prefetch
-// issued before the compute (the scheduler would otherwise sink it to the
-// end of the loop body to reuse its registers).
-template <int Q, typename Compute>
-__device__ __forceinline__ void for_each_tile(const unsigned char* __restrict__ base, int64_t total_bytes,
-                                              int64_t nt, int S, uint32_t* __restrict__ my, Compute compute) {
-  const int lane = threadIdx.x & 63;
-  const int64_t stride = (int64_t)gridDim.x * kWaves;
-  int64_t t = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-  const int64_t nfull = total_bytes / (256 * (int64_t)S);
+template <int NT>
+__device__ __forceinline__ void tile_sync() {
+  if constexpr (NT == 64) wave_lds_sync();
+  else __syncthreads();
+}
+
+// Runs compute(t) for the tiles t = first, first + stride, ... < nt of this
+// wave (NT = 64: wave tiles, `my` the wave's LDS slice) or of this block
+// (NT = kBlock), with tile t staged in `my` and the loads of the next tile
+// in flight meanwhile.  The prefetch is unconditional (its tile index is
+// clamped to a whole tile: past the end it re-reads the current, cache-hot
+// one), because a conditional write to the register buffer makes the
+// compiler keep that buffer in scratch memory.  A page shorter than one
+// tile takes the plain path.  A scheduling barrier keeps the prefetch issued
+// before the compute (the scheduler would otherwise sink it to the end of
+// the loop body to reuse its registers).
+template <int Q, int NT, typename Compute>
+__device__ __forceinline__ void for_each_tile_n(const unsigned char* __restrict__ base, int64_t total_bytes,
+                                                int64_t nt, int tile_bytes, uint32_t* __restrict__ my,
+                                                Compute compute) {
+  static_assert(NT == 64 || NT == kBlock, "tiles belong to a wave or to the block");
+  const int tid = NT == 64 ? (threadIdx.x & 63) : threadIdx.x;
+  const int64_t stride = NT == 64 ? (int64_t)gridDim.x * kWaves : (int64_t)gridDim.x;
+  int64_t t = NT == 64 ? (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6) : (int64_t)blockIdx.x;
+  const int64_t nfull = total_bytes / tile_bytes;
   if (nfull == 0) {
     for (; t < nt; t += stride) {
-      copy_partial_tile(base, total_bytes, t, S, lane, my);
-      wave_lds_sync();
+      copy_partial_tile<NT>(base, total_bytes, t, tile_bytes, tid, my);
+      tile_sync<NT>();
       compute(t);
-      wave_lds_sync();
+      tile_sync<NT>();
     }
     return;
   }
   u32x4 r[Q];
-  load_tile<Q>(base, t < nfull ? t : nfull - 1, S, lane, r);
+  load_tile<Q, NT>(base, t < nfull ? t : nfull - 1, tile_bytes, tid, r);
   for (; t < nt; t += stride) {
-    if (t < nfull) store_tile<Q>(my, S, lane, r);
-    else copy_partial_tile(base, total_bytes, t, S, lane, my);
-    wave_lds_sync();
+    if (t < nfull) store_tile<Q, NT>(my, tile_bytes, tid, r);
+    else copy_partial_tile<NT>(base, total_bytes, t, tile_bytes, tid, my);
+    tile_sync<NT>();
     const int64_t tn = t + stride;
-    load_tile<Q>(base, tn < nfull ? tn : (t < nfull ? t : nfull - 1), S, lane, r);
+    load_tile<Q, NT>(base, tn < nfull ? tn : (t < nfull ? t : nfull - 1), tile_bytes, tid, r);
     __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the compute
     compute(t);
-    wave_lds_sync();
+    tile_sync<NT>();
   }
+}
+
+// Wave tiles of 64 lane groups of S dwords.
+template <int Q, typename Compute>
+__device__ __forceinline__ void for_each_tile(const unsigned char* __restrict__ base, int64_t total_bytes,
+                                              int64_t nt, int S, uint32_t* __restrict__ my, Compute compute) {
+  for_each_tile_n<Q, 64>(base, total_bytes, nt, 256 * S, my, compute);
 }
 
 }  // namespace cvx

@@ -37,7 +37,7 @@ hipError_t launch_label_index(const int8_t* labels, int64_t P, int K, int nT,
 
 // class moments: per-class augmented Gram of [x - c_k, 1] about a per-class
 // shift c_k; partials part[(k * G + g) * L + t], L = nblk * 16.
-hipError_t launch_class_moments(int dtype, const void* cube, int B, const int32_t* idx,
+hipError_t launch_class_moments(int dtype, const void* cube, int B, int64_t P, const int32_t* idx,
                                 const int32_t* offsets, int K, int G, double* part,
                                 double* shift_out, hipStream_t s);
 // PCA: augmented Gram of [x - s, 1] over all (or masked) pixels.
@@ -46,7 +46,7 @@ hipError_t launch_pca_gram(int dtype, const void* cube, int B, int64_t P,
                            double* shift_out, hipStream_t s);
 // The same two Gram matrices on the matrix cores with a compensated
 // 16-bit split (split 0 = bf16, 1 = fp16); identical output layout.
-hipError_t launch_class_moments_mfma(int dtype, int split, const void* cube, int B,
+hipError_t launch_class_moments_mfma(int dtype, int split, const void* cube, int B, int64_t P,
                                      const int32_t* idx, const int32_t* offsets, int K, int G,
                                      double* part, double* shift_out, hipStream_t s);
 hipError_t launch_pca_gram_mfma(int dtype, int split, const void* cube, int B, int64_t P,
