@@ -69,6 +69,9 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "f16x3"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-gib", type=int, default=0,
+                    help="after the timed steps, copy this many GiB device to device (a plain copy of "
+                         "known size, to calibrate hardware byte counters against)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no multi-GPU "
@@ -157,7 +160,7 @@ def main():
     avg_rng = ms_rng / max(n_rng, 1)
     fit_proj_bytes = 2 * cube_bytes + P * C + (labels.numel() + N * B * 2)
     roof = {
-        "kernel": f"k_stretch_mfma<u16> (CVA stretch pass, {C} components)",
+        "kernel": f"k_stretch_u16 (CVA stretch pass, {C} components)",
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
@@ -176,7 +179,7 @@ def main():
         try:
             tr = json.load(open(traffic_file))
             import hashlib
-            src = open(os.path.join(ROOT, "paper_1612_06457_amd", "csrc", "k_project_mfma.hip"), "rb").read()
+            src = open(os.path.join(ROOT, "paper_1612_06457_amd", "csrc", "k_project_u16.hip"), "rb").read()
             if tr.get("source_sha1") == hashlib.sha1(src).hexdigest():
                 roof["traffic"] = tr.get("bytes_per_launch")
         except Exception:
@@ -193,16 +196,24 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u16 in, f32 accumulate (" + args.precision + " scatter), f64 solve",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "cva_pca_page_7216x5412x33_u16_k8", "H": H, "W": W, "B": B, "K": K,
                    "train_pixels": int(N), "cva_components": C, "pca_components": 3,
-                   "precision": args.precision},
+                   "precision": args.precision,
+                   "arithmetic": "u16 page; FP32 accumulation (exact fp16-split products on MFMA in the "
+                                 "projection, " + args.precision + " scatter), FP64 combine and eigensolve"},
         "phases_ms": {k: round(v, 4) for k, v in per.items()},
         "soft_fwd_bwd_ms": round(per["soft_fwd"] + per["soft_bwd"], 4),
         "kernels_ms_per_launch": {k: round(v[1] / max(v[0], 1), 4) for k, v in prof.items()},
         "roofline": roof,
     }
+    if args.copy_gib > 0:
+        src = torch.ones(args.copy_gib << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu:
         gbs, dt, threads, sample = cpu_baseline(case, args.cpu_seconds)
         out["cpu_baseline"] = {"value": round(gbs, 4), "unit": "Gpix*band/s", "cores": threads,

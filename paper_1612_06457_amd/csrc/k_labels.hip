@@ -5,7 +5,12 @@
 //
 // Both kernels read the int8 label map in 16-byte chunks: a wave step covers
 // 64 chunks = 1024 consecutive pixels, lane l holding pixels 16 l .. 16 l + 15.
-// The labelled pixels of a step (a few percent of the page) are first
+// Steps are loaded four at a time (4 KiB per wave) with the next four in
+// flight while the current ones are processed; the loads are unconditional
+// (clamped to the wave's last whole group), and only the ragged end of a
+// wave's range takes the byte-wise path.
+// Counting adds each labelled pixel into LDS class counters.  For the index
+// list, the labelled pixels of a step (a few percent of the page) are first
 // compacted, in raster order, into a small per-wave LDS list; ranks within a
 // class then come from one ballot per distinct class over that list.
 //   k_label_count:  per-tile class counts (tile = 64 Ki pixels per block);
@@ -13,7 +18,7 @@
 //                   of the tiles before it; each wave walks its quarter of
 //                   the tile with wave-private running offsets, so the main
 //                   loop has no block barrier.
-#include "k_common.hpp"
+#include "k_tile.hpp"
 #include "launch.hpp"
 
 namespace cvx {
@@ -22,11 +27,12 @@ namespace {
 
 constexpr int kSub = kLabelTile / kWaves;   // pixels per wave in a tile
 constexpr int kStep = 64 * 16;              // pixels per wave step
+constexpr int kGroup = 4 * kStep;           // pixels per group of four steps
 
 // Load the 16 labels of chunk c (pixel 16 c ..) within [0, end); missing
 // pixels read as -1 (0xff).
-__device__ __forceinline__ uint4 load_chunk(const int8_t* __restrict__ labels, int64_t p, int64_t end) {
-  if (p + 16 <= end) return *reinterpret_cast<const uint4*>(labels + p);
+__device__ __forceinline__ u32x4 load_chunk(const int8_t* __restrict__ labels, int64_t p, int64_t end) {
+  if (p + 16 <= end) return *reinterpret_cast<const u32x4*>(labels + p);
   uint32_t d[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -39,13 +45,42 @@ __device__ __forceinline__ uint4 load_chunk(const int8_t* __restrict__ labels, i
     }
     d[q] = v;
   }
-  return make_uint4(d[0], d[1], d[2], d[3]);
+  return u32x4{d[0], d[1], d[2], d[3]};
+}
+
+// The four steps of the group at st (whole, inside the map): chunk q of
+// lane l is pixels st + kStep q + 16 l ...
+__device__ __forceinline__ void load_group(const int8_t* __restrict__ labels, int64_t st, u32x4 (&g)[4]) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) g[q] = *reinterpret_cast<const u32x4*>(labels + st + kStep * q + 16 * lane);
+}
+
+// Runs step(chunk, st) for the wave's steps over [s0, s1) in raster order.
+template <typename Step>
+__device__ __forceinline__ void for_each_step(const int8_t* __restrict__ labels, int64_t s0, int64_t s1, Step step) {
+  const int lane = __lane_id();
+  const int64_t ng = (s1 > s0) ? (s1 - s0) / kGroup : 0;
+  if (ng > 0) {
+    u32x4 nx[4];
+    load_group(labels, s0, nx);
+    for (int64_t i = 0; i < ng; ++i) {
+      u32x4 cur[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cur[q] = nx[q];
+      load_group(labels, s0 + kGroup * (i + 1 < ng ? i + 1 : ng - 1), nx);
+      __builtin_amdgcn_sched_barrier(0);   // keep the next group's loads ahead of the work
+#pragma unroll
+      for (int q = 0; q < 4; ++q) step(cur[q], s0 + kGroup * i + kStep * q);
+    }
+  }
+  for (int64_t st = s0 + kGroup * ng; st < s1; st += kStep) step(load_chunk(labels, st + 16 * lane, s1), st);
 }
 
 // Bit i of the result is set when byte i (of the 16) is >= 0 (labelled).
 // Sets `bad` when a negative byte is not -1.
-__device__ __forceinline__ uint32_t labelled_mask(uint4 c, bool& bad) {
-  const uint32_t d[4] = {c.x, c.y, c.z, c.w};
+__device__ __forceinline__ uint32_t labelled_mask(u32x4 c, bool& bad) {
+  const uint32_t d[4] = {c[0], c[1], c[2], c[3]};
   uint32_t m = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -61,8 +96,8 @@ __device__ __forceinline__ uint32_t labelled_mask(uint4 c, bool& bad) {
   return m;
 }
 
-__device__ __forceinline__ int byte_at(uint4 c, int i) {
-  const uint32_t d = (i < 4) ? c.x : (i < 8) ? c.y : (i < 12) ? c.z : c.w;
+__device__ __forceinline__ int byte_at(u32x4 c, int i) {
+  const uint32_t d = (i < 4) ? c[0] : (i < 8) ? c[1] : (i < 12) ? c[2] : c[3];
   return (int)(int8_t)((d >> (8 * (i & 3))) & 0xffu);
 }
 
@@ -81,10 +116,22 @@ __device__ __forceinline__ int lane_prefix(int c, int& total) {
   return pre;
 }
 
+// Add the labelled pixels of a chunk into the LDS class counters cnt[].
+__device__ __forceinline__ void count_chunk(u32x4 c, int K, int* __restrict__ cnt, bool& bad) {
+  uint32_t m = labelled_mask(c, bad);
+  while (m) {
+    const int i = __ffs(m) - 1;
+    m &= m - 1;
+    const int v = byte_at(c, i);
+    if (v < K) atomicAdd(&cnt[v], 1);
+    else bad = true;
+  }
+}
+
 // Compact the labelled pixels of one wave step into list[] (raster order):
 // list entries are (pixel offset within the step) | (class << 16).
 // Returns the number of entries (uniform).
-__device__ __forceinline__ int compact_step(uint4 c, int K, uint32_t* __restrict__ list, bool& bad) {
+__device__ __forceinline__ int compact_step(u32x4 c, int K, uint32_t* __restrict__ list, bool& bad) {
   const int lane = __lane_id();
   uint32_t m = labelled_mask(c, bad);
   int total;
@@ -103,36 +150,13 @@ __global__ __launch_bounds__(kBlock) void k_label_count(const int8_t* __restrict
                                                         int K, int32_t* __restrict__ tile_counts,
                                                         int32_t* __restrict__ err) {
   __shared__ int cnt[128];
-  __shared__ uint32_t lists[kWaves][kStep];
   for (int i = threadIdx.x; i < 128; i += kBlock) cnt[i] = 0;
   __syncthreads();
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  uint32_t* list = lists[w];
+  const int w = threadIdx.x >> 6;
   const int64_t s0 = (int64_t)blockIdx.x * kLabelTile + (int64_t)w * kSub;
   const int64_t s1 = (s0 + kSub < P) ? s0 + kSub : P;
   bool bad = false;
-  uint4 nxt = make_uint4(~0u, ~0u, ~0u, ~0u);
-  if (s0 < s1) nxt = load_chunk(labels, s0 + 16 * lane, s1);
-  for (int64_t st = s0; st < s1; st += kStep) {
-    const uint4 cur = nxt;
-    if (st + kStep < s1) nxt = load_chunk(labels, st + kStep + 16 * lane, s1);
-    const int n = compact_step(cur, K, list, bad);
-    if (n == 0) continue;
-    wave_lds_sync();
-    for (int b0 = 0; b0 < n; b0 += 64) {
-      const int i = b0 + lane;
-      const int k = (i < n) ? (int)(list[i] >> 16) : -1;
-      uint64_t pending = __ballot(k >= 0);
-      while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int kk = __shfl(k, leader, 64);
-        const uint64_t mk = __ballot(k == kk);
-        if (lane == leader) atomicAdd(&cnt[kk], __popcll(mk));
-        pending &= ~mk;
-      }
-    }
-    wave_lds_sync();
-  }
+  for_each_step(labels, s0, s1, [&](u32x4 cur, int64_t) { count_chunk(cur, K, cnt, bad); });
   if (bad) atomicOr(err, 1);
   __syncthreads();
   for (int i = threadIdx.x; i < K; i += kBlock) tile_counts[(int64_t)blockIdx.x * K + i] = cnt[i];
@@ -156,12 +180,20 @@ __global__ __launch_bounds__(kBlock) void k_label_index(const int8_t* __restrict
   }
   __syncthreads();
   const int t = blockIdx.x;
-  for (int i = threadIdx.x; i < nT * K; i += kBlock) {
-    const int tt = i / K, k = i - tt * K;
-    const int c = tile_counts[i];
-    if (c) {
-      atomicAdd(&total[k], c);
-      if (tt < t) atomicAdd(&before[k], c);
+  {
+    // thread i < m sums the entries i, i + m, ... of the nT x K counts, all
+    // of class i % K (m a multiple of K), then adds its two sums into LDS
+    const int m = K * (kBlock / K);
+    if ((int)threadIdx.x < m) {
+      const int k = threadIdx.x % K;
+      int tot = 0, bef = 0;
+      for (int i = threadIdx.x; i < nT * K; i += m) {
+        const int c = tile_counts[i];
+        tot += c;
+        bef += (i / K < t) ? c : 0;
+      }
+      if (tot) atomicAdd(&total[k], tot);
+      if (bef) atomicAdd(&before[k], bef);
     }
   }
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -170,25 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_label_index(const int8_t* __restrict
   const int64_t s1 = (s0 + kSub < P) ? s0 + kSub : P;
   bool bad = false;
   // per-wave class counts of this wave's quarter of the tile
-  for (int64_t st = s0; st < s1; st += kStep) {
-    const uint4 cur = load_chunk(labels, st + 16 * lane, s1);
-    const int n = compact_step(cur, K, list, bad);
-    if (n == 0) continue;
-    wave_lds_sync();
-    for (int b0 = 0; b0 < n; b0 += 64) {
-      const int i = b0 + lane;
-      const int k = (i < n) ? (int)(list[i] >> 16) : -1;
-      uint64_t pending = __ballot(k >= 0);
-      while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int kk = __shfl(k, leader, 64);
-        const uint64_t mk = __ballot(k == kk);
-        if (lane == leader) wcnt[w][kk] += __popcll(mk);
-        pending &= ~mk;
-      }
-    }
-    wave_lds_sync();
-  }
+  for_each_step(labels, s0, s1, [&](u32x4 cur, int64_t) { count_chunk(cur, K, wcnt[w], bad); });
   __syncthreads();
   if (threadIdx.x == 0) {
     int off = 0;
@@ -209,13 +223,9 @@ __global__ __launch_bounds__(kBlock) void k_label_index(const int8_t* __restrict
   }
   __syncthreads();
   // write indices in raster order with wave-private running offsets
-  uint4 nxt = make_uint4(~0u, ~0u, ~0u, ~0u);
-  if (s0 < s1) nxt = load_chunk(labels, s0 + 16 * lane, s1);
-  for (int64_t st = s0; st < s1; st += kStep) {
-    const uint4 cur = nxt;
-    if (st + kStep < s1) nxt = load_chunk(labels, st + kStep + 16 * lane, s1);
+  for_each_step(labels, s0, s1, [&](u32x4 cur, int64_t st) {
     const int n = compact_step(cur, K, list, bad);
-    if (n == 0) continue;
+    if (n == 0) return;
     wave_lds_sync();
     for (int b0 = 0; b0 < n; b0 += 64) {
       const int i = b0 + lane;
@@ -236,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_label_index(const int8_t* __restrict
       }
     }
     wave_lds_sync();
-  }
+  });
 }
 
 }  // namespace

@@ -295,12 +295,17 @@ __device__ __forceinline__ uint32_t quant(float y, float s, float o) {
   return (uint32_t)t;
 }
 
+// Pass 2: the quantised bytes of a wave tile are gathered per component
+// plane in LDS (8 planes x 128 pixels) and written as 16-byte chunks, so
+// each plane receives whole 128-byte segments.
 template <int NKB, int G2>
-__global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_stretch_u16(const void* __restrict__ cube, int B, int64_t P, int nc,
-                                                        ProjArgs a, const float* __restrict__ range_dev,
-                                                        uint8_t* __restrict__ images) {
+__global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_stretch_u16(const void* __restrict__ cube, int B,
+                                                                        int64_t P, int nc, ProjArgs a,
+                                                                        const float* __restrict__ range_dev,
+                                                                        uint8_t* __restrict__ images) {
   extern __shared__ __align__(16) uint32_t lds[];
-  const int lane = threadIdx.x & 63;
+  __shared__ __align__(16) uint8_t outs[kWaves][8 * 128];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, col = lane & 15, p = col >> 3, j = col & 7;
   const bool live = p < G2 && j < nc;
   const bool writer = p == 0 && j < nc;
@@ -310,11 +315,13 @@ __global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_stretch_u16(const 
   load_ops<NKB, G2>(sa, B, nc, o);
   const float sc = live ? range_dev[j] : 0.f;
   const float of = live ? range_dev[8 + j] : 0.f;
-  uint8_t* plane = images + (int64_t)(j < nc ? j : 0) * P;
-  const int vec = G2 == 2 ? 8 : 4;
-  const bool aligned = (P % vec) == 0 && (reinterpret_cast<uintptr_t>(images) % vec) == 0;
+  uint8_t* ow = outs[w];
+  constexpr int TP = 64 * G2;   // pixels per wave tile
+  const int jj = lane >> 3, cc = lane & 7;   // copy-out: plane jj, 16-byte chunk cc
+  const bool copier = jj < nc && 16 * cc < TP;
+  const bool aligned = (P % 16) == 0 && (reinterpret_cast<uintptr_t>(images) % 16) == 0;
   run_tiles<NKB, G2>(cube, B, P, o, lds, [&](int64_t t, const f32x4 (&acc)[4]) {
-    const int64_t pb = t * 64 * G2;
+    const int64_t pb = t * TP;
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
       const uint32_t mine = quant(acc[rb][0], sc, of) | (quant(acc[rb][1], sc, of) << 8) |
@@ -325,26 +332,22 @@ __global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_stretch_u16(const 
         if (writer) {
           const uint32_t lo = __builtin_amdgcn_perm(other, mine, 0x05010400u);
           const uint32_t hi = __builtin_amdgcn_perm(other, mine, 0x07030602u);
-          const int64_t px = pb + 2 * (16 * rb + 4 * g);
-          if (aligned && px + 8 <= P) {
-            *reinterpret_cast<uint2*>(plane + px) = make_uint2(lo, hi);
-          } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-              if (px + e < P) plane[px + e] = (uint8_t)((e < 4 ? lo : hi) >> (8 * (e & 3)));
-          }
+          *reinterpret_cast<uint2*>(ow + 128 * j + 2 * (16 * rb + 4 * g)) = make_uint2(lo, hi);
         }
       } else {
-        if (writer) {
-          const int64_t px = pb + 16 * rb + 4 * g;
-          if (aligned && px + 4 <= P) {
-            *reinterpret_cast<uint32_t*>(plane + px) = mine;
-          } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (px + e < P) plane[px + e] = (uint8_t)(mine >> (8 * e));
-          }
-        }
+        if (writer) *reinterpret_cast<uint32_t*>(ow + 128 * j + 16 * rb + 4 * g) = mine;
+      }
+    }
+    wave_lds_sync();
+    if (copier) {
+      const int64_t px = pb + 16 * cc;
+      const u32x4 v = *reinterpret_cast<const u32x4*>(ow + 128 * jj + 16 * cc);
+      uint8_t* dst = images + (int64_t)jj * P + px;
+      if (aligned && px + 16 <= P) {
+        *reinterpret_cast<u32x4*>(dst) = v;
+      } else {
+        for (int e = 0; e < 16; ++e)
+          if (px + e < P) dst[e] = (uint8_t)(v[e >> 2] >> (8 * (e & 3)));
       }
     }
   });
