@@ -255,6 +255,9 @@ int proj_groups(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const d
         const double wv = W[(size_t)b * n_comp + g0 + j];
         a.w[b * NC + j] = (float)wv;
         off += wv * (c[b] - center[b]);
+        // uint16 pages: the kernels multiply 1024 + (x mod 1024) rather than
+        // its centred value, so the constant 1024 + (c mod 1024) comes off here
+        if (cube->dtype == CVAMX_U16) off -= (double)a.w[b * NC + j] * (1024.0 + std::fmod(c[b], 1024.0));
       }
       a.off[j] = (float)off;
       // a power of two that brings the largest |W[b][j]| into [16, 32)

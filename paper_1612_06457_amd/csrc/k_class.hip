@@ -22,13 +22,12 @@
 // host removes the shift exactly from the augmented Gram.
 #include "k_gram.hpp"
 #include "k_split.hpp"
+#include "k_tile.hpp"
 #include "launch.hpp"
 
 namespace cvx {
 
 namespace {
-
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 struct Gather {
   const unsigned char* base;    // page

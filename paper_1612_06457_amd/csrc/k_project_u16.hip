@@ -8,9 +8,13 @@
 //
 //   x = 1024 h + l (h: 6 bits, l: 10 bits), c = 1024 c_h + c_l.  The fp16
 //   value with bits 0x6400 | l is 1024 + l exactly, so one AND-OR makes two
-//   of them from a dword of two elements, and one packed fp16 add of
-//   -(1024 + c_l) gives l - c_l (|.| <= 1023) exactly; likewise h - c_h
-//   (|.| <= 63).  Then x - c = 1024 (h - c_h) + (l - c_l).
+//   of them from a dword of two elements; likewise 1024 + h, and one packed
+//   fp16 add of -(1024 + c_h) gives h - c_h (|.| <= 63) exactly.  Then
+//   x - c = 1024 (h - c_h) + (1024 + l) - (1024 + c_l): the last term is a
+//   constant per component, taken into the accumulator's start (the host
+//   folds sum_b (1024 + c_l) W[b][j] into off_j in FP64).  The uncentred
+//   1024 + l is at most 2047, no larger than the centred values the
+//   accumulator carries anyway, so the FP32 rounding is of the same size.
 //
 //   A (16 rows x 32 slots): a row is one lane group (two pixels when B is
 //   odd, so rows stay dword aligned; else one pixel).  Lane l holds row
@@ -36,10 +40,10 @@
 // quantises and writes planar bytes (8 bytes per lane for two-pixel rows).
 //
 // Tiles are streamed as in the other projection kernels (k_tile.hpp), with
-// the next tile's loads in flight while the current one is computed.  Up
-// to 40 bands (five K-blocks) the constant operands, the prefetch buffer
-// and the accumulators fit two waves per SIMD, which is enough in flight
-// to stream at full HBM rate; wider pages run one wave per SIMD.
+// the next tile's loads in flight while the current one is computed.  The
+// constant operands live in a per-block LDS table.  Two waves per SIMD
+// measured fastest: three (smaller tiles, or a register cap) and a second
+// prefetched tile were both slower.
 #include <algorithm>
 
 #include "k_tile.hpp"
@@ -58,13 +62,22 @@ __device__ __forceinline__ f32x4 mma(f16x8 a, f16x8 b, f32x4 c) {
 
 __device__ __forceinline__ uint32_t h16(_Float16 v) { return (uint32_t)__builtin_bit_cast(uint16_t, v); }
 
-// l - c_l and h - c_h for both elements of a data dword, as fp16 pairs.
-__device__ __forceinline__ uint32_t low_part(uint32_t d, uint32_t nl) {
-  const f16x2 v = __builtin_bit_cast(f16x2, (d & 0x03ff03ffu) | 0x64006400u);
-  return __builtin_bit_cast(uint32_t, v + __builtin_bit_cast(f16x2, nl));
+// The bit masks of the operand build, held in registers: VOP3 encodings on
+// gfx9 take no literal operand, so with the masks as literals every AND-OR
+// would be split into a VOP2 AND and a VOP2 OR.
+struct Masks {
+  uint32_t lo, hi, exp;   // 0x03ff03ff, 0x003f003f, 0x64006400
+};
+__device__ __forceinline__ Masks make_masks() {
+  Masks m{0x03ff03ffu, 0x003f003fu, 0x64006400u};
+  asm volatile("" : "+v"(m.lo), "+v"(m.hi), "+v"(m.exp));
+  return m;
 }
-__device__ __forceinline__ uint32_t high_part(uint32_t d, uint32_t nh) {
-  const f16x2 v = __builtin_bit_cast(f16x2, ((d >> 10) & 0x003f003fu) | 0x64006400u);
+
+// 1024 + l and h - c_h for both elements of a data dword, as fp16 pairs.
+__device__ __forceinline__ uint32_t low_part(uint32_t d, const Masks& m) { return (d & m.lo) | m.exp; }
+__device__ __forceinline__ uint32_t high_part(uint32_t d, uint32_t nh, const Masks& m) {
+  const f16x2 v = __builtin_bit_cast(f16x2, ((d >> 10) & m.hi) | m.exp);
   return __builtin_bit_cast(uint32_t, v + __builtin_bit_cast(f16x2, nh));
 }
 
@@ -76,13 +89,27 @@ __device__ __forceinline__ void split3(float v, _Float16& t0, _Float16& t1, _Flo
   t2 = (_Float16)(r - (float)t1);
 }
 
-// Per-lane constant operands for NKB K-blocks.
+// Constant operands for NKB K-blocks, per lane, kept in LDS (the same for
+// every wave of the block): the three fp16 terms of the scaled weights (B
+// operand) and, per data dword pair, -(1024 + c_h) for both elements of
+// each dword.
+// 16-row blocks per wave tile (fewer rows per tile, for more blocks per CU,
+// measured slower: the per-tile overhead grows faster than the overlap).
 template <int NKB>
-struct Ops {
-  f16x8 w[NKB][3];        // B operand: the three fp16 terms of the scaled weights
-  uint32_t nl[NKB][2];    // -(1024 + c_l) for the two elements of each data dword
-  uint32_t nh[NKB][2];    // -(1024 + c_h)
-  float acc0;             // off_j scaled, the accumulator's start
+constexpr int row_blocks() { return 4; }
+
+// LDS dwords per wave: a tile (16 RB rows of S dwords), and at least the
+// staged output of the stretch pass (8 planes x 16 RB G2 pixels).
+template <int NKB>
+__host__ __device__ constexpr int slice_dwords(int S, int G2) {
+  return 16 * row_blocks<NKB>() * S > 2 * 16 * row_blocks<NKB>() * G2 ? 16 * row_blocks<NKB>() * S
+                                                                        : 2 * 16 * row_blocks<NKB>() * G2;
+}
+
+template <int NKB>
+struct OpsTab {
+  u32x4 w[NKB][3][64];
+  u32x2 c[NKB][64];   // {nh(q0), nh(q1)}
 };
 
 // The kernel argument block copied into LDS by the whole block (one
@@ -94,98 +121,112 @@ __device__ __forceinline__ void stage_args(const ProjArgs& a, ProjArgs& sa) {
   __syncthreads();
 }
 
-// a.c holds 2^23 + c_b (c_b a non-negative integer), so its low 23 bits are c_b.
+// a.c holds 2^23 + c_b (c_b a non-negative integer), so its low 23 bits are
+// c_b.  The first wave fills the table; every lane returns its
+// accumulator start (off_j scaled).
 template <int NKB, int G2>
-__device__ __forceinline__ void load_ops(const ProjArgs& a, int B, int nc, Ops<NKB>& o) {
-  const int lane = __lane_id();
+__device__ __forceinline__ float build_ops(const ProjArgs& a, int B, int nc, OpsTab<NKB>& tab) {
+  const int lane = threadIdx.x & 63;
   const int col = lane & 15, g = lane >> 4;
   const int p = col >> 3, j = col & 7;
   const bool live = p < G2 && j < nc;
   const float sc = live ? a.scale[j] : 0.f;
-  const int nel = G2 * B;
+  if (threadIdx.x < 64) {
+    const int nel = G2 * B;
+    for (int kb = 0; kb < NKB; ++kb) {
+      f16x8 w[3];
+      uint32_t cv[2];
 #pragma unroll
-  for (int kb = 0; kb < NKB; ++kb) {
+      for (int u = 0; u < 2; ++u) {
+        const int q = 8 * kb + 2 * g + u;
+        uint32_t nhv = 0;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int q = 8 * kb + 2 * g + u;
-      uint32_t nlv = 0, nhv = 0;
-#pragma unroll
-      for (int hh = 0; hh < 2; ++hh) {
-        const int E = 2 * q + hh;
-        uint32_t cb = 0;
-        float wv = 0.f;
-        if (E < nel) {
-          const int pix = E >= B ? 1 : 0;
-          const int b = E - pix * B;
-          cb = __float_as_uint(a.c[b]) & 0x7fffffu;
-          if (live && pix == p) wv = a.w[b * nc + j] * sc;
+        for (int hh = 0; hh < 2; ++hh) {
+          const int E = 2 * q + hh;
+          uint32_t cb = 0;
+          float wv = 0.f;
+          if (E < nel) {
+            const int pix = E >= B ? 1 : 0;
+            const int b = E - pix * B;
+            cb = __float_as_uint(a.c[b]) & 0x7fffffu;
+            if (live && pix == p) wv = a.w[b * nc + j] * sc;
+          }
+          nhv |= h16((_Float16)(-(float)(1024u + (cb >> 10)))) << (16 * hh);
+          _Float16 t0, t1, t2;
+          split3(wv, t0, t1, t2);
+          w[0][2 * u + hh] = t0;
+          w[1][2 * u + hh] = t1;
+          w[2][2 * u + hh] = t2;
+          split3(1024.f * wv, t0, t1, t2);
+          w[0][4 + 2 * u + hh] = t0;
+          w[1][4 + 2 * u + hh] = t1;
+          w[2][4 + 2 * u + hh] = t2;
         }
-        nlv |= h16((_Float16)(-(float)(1024u + (cb & 1023u)))) << (16 * hh);
-        nhv |= h16((_Float16)(-(float)(1024u + (cb >> 10)))) << (16 * hh);
-        _Float16 t0, t1, t2;
-        split3(wv, t0, t1, t2);
-        o.w[kb][0][2 * u + hh] = t0;
-        o.w[kb][1][2 * u + hh] = t1;
-        o.w[kb][2][2 * u + hh] = t2;
-        split3(1024.f * wv, t0, t1, t2);
-        o.w[kb][0][4 + 2 * u + hh] = t0;
-        o.w[kb][1][4 + 2 * u + hh] = t1;
-        o.w[kb][2][4 + 2 * u + hh] = t2;
+        cv[u] = nhv;
       }
-      o.nl[kb][u] = nlv;
-      o.nh[kb][u] = nhv;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) tab.w[kb][m][lane] = __builtin_bit_cast(u32x4, w[m]);
+      tab.c[kb][lane] = u32x2{cv[0], cv[1]};
     }
   }
-  o.acc0 = live ? a.off[j] * sc : 0.f;
+  __syncthreads();
+  return live ? a.off[j] * sc : 0.f;
 }
 
-// The four 16 x 16 output blocks of a wave tile: acc[rb] for rows
+// The RB 16 x 16 output blocks of a wave tile: acc[rb] for rows
 // 16 rb + (lane % 16), rp = that row's start + 2 (lane / 16) for rb = 0.
-// The four blocks' products are interleaved so that consecutive MFMAs are
+// The blocks' products are interleaved so that consecutive MFMAs are
 // independent.
-template <int NKB>
-__device__ __forceinline__ void project_tile(const uint32_t* __restrict__ rp, int S, const Ops<NKB>& o,
-                                             f32x4 (&acc)[4]) {
+template <int NKB, int RB>
+__device__ __forceinline__ void project_tile(const uint32_t* __restrict__ rp, int S, const OpsTab<NKB>& tab,
+                                             float acc0, const Masks& mk, f32x4 (&acc)[RB]) {
+  const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb) acc[rb] = f32x4{o.acc0, o.acc0, o.acc0, o.acc0};
+  for (int rb = 0; rb < RB; ++rb) acc[rb] = f32x4{acc0, acc0, acc0, acc0};
 #pragma unroll
   for (int kb = 0; kb < NKB; ++kb) {
-    f16x8 A[4];
+    const u32x2 cv = tab.c[kb][lane];
+    f16x8 A[RB];
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
+    for (int rb = 0; rb < RB; ++rb) {
       const uint32_t* q = rp + 16 * rb * S + 8 * kb;
       const uint32_t d0 = q[0], d1 = q[1];
       u32x4 v;
-      v[0] = low_part(d0, o.nl[kb][0]);
-      v[1] = low_part(d1, o.nl[kb][1]);
-      v[2] = high_part(d0, o.nh[kb][0]);
-      v[3] = high_part(d1, o.nh[kb][1]);
+      v[0] = low_part(d0, mk);
+      v[1] = low_part(d1, mk);
+      v[2] = high_part(d0, cv[0], mk);
+      v[3] = high_part(d1, cv[1], mk);
       A[rb] = __builtin_bit_cast(f16x8, v);
     }
 #pragma unroll
-    for (int m = 2; m >= 0; --m)   // smallest terms first
+    for (int m = 2; m >= 0; --m) {   // smallest terms first
+      const f16x8 wm = __builtin_bit_cast(f16x8, tab.w[kb][m][lane]);
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb) acc[rb] = mma(A[rb], o.w[kb][m], acc[rb]);
+      for (int rb = 0; rb < RB; ++rb) acc[rb] = mma(A[rb], wm, acc[rb]);
+    }
   }
 }
 
-// Tile loop shared by both passes: body(t, acc[4]) per wave tile, acc[rb]
-// holding rows 16 rb + 4 (lane / 16) + e.
+// Tile loop shared by both passes: body(t, acc[RB]) per wave tile of
+// 16 RB rows (lane groups), acc[rb] holding rows 16 rb + 4 (lane / 16) + e.
 template <int NKB, int G2, typename Body>
-__device__ __forceinline__ void run_tiles(const void* __restrict__ cube, int B, int64_t P, const Ops<NKB>& o,
-                                          uint32_t* __restrict__ lds, Body body) {
-  constexpr int Q = 2 * NKB;   // 16 S / 64 <= 2 NKB chunks per lane
+__device__ __forceinline__ void run_tiles(const void* __restrict__ cube, int B, int64_t P, const OpsTab<NKB>& tab,
+                                          float acc0, uint32_t* __restrict__ lds, Body body) {
+  constexpr int RB = row_blocks<NKB>();
+  constexpr int TR = 16 * RB;                  // rows per wave tile
+  constexpr int Q = (TR * 8 * NKB + 255) / 256;  // 16-byte chunks per lane: TR S / 4 / 64, S <= 8 NKB
   const int S = G2 == 2 ? B : B / 2;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  uint32_t* my = lds + w * 64 * S;
-  const int64_t tp = 64 * G2;
+  uint32_t* my = lds + w * slice_dwords<NKB>(S, G2);
+  const int64_t tp = TR * G2;
   const int64_t nt = (P + tp - 1) / tp;
   const int64_t total_bytes = P * B * 2;
   const unsigned char* base = reinterpret_cast<const unsigned char*>(cube);
   const uint32_t* rp = my + (lane & 15) * S + 2 * (lane >> 4);
-  for_each_tile<Q>(base, total_bytes, nt, S, my, [&](int64_t t) {
-    f32x4 acc[4];
-    project_tile<NKB>(rp, S, o, acc);
+  const Masks mk = make_masks();
+  for_each_tile_n<Q, 64>(base, total_bytes, nt, TR * S * 4, my, [&](int64_t t) {
+    f32x4 acc[RB];
+    project_tile<NKB, RB>(rp, S, tab, acc0, mk, acc);
     body(t, acc);
   });
 }
@@ -200,24 +241,35 @@ __global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_range_u16(const vo
   __shared__ bool am_last;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, p = (lane & 15) >> 3;
-  __shared__ ProjArgs sa;
+  constexpr int RB = row_blocks<NKB>();
+  ProjArgs& sa = *reinterpret_cast<ProjArgs*>(lds);   // set-up only: the tiles reuse it
   stage_args(a, sa);
-  Ops<NKB> o;
-  load_ops<NKB, G2>(sa, B, nc, o);
+  __shared__ OpsTab<NKB> tab;
+  const float acc0 = build_ops<NKB, G2>(sa, B, nc, tab);
+  const float inv = 1.f / sa.scale[threadIdx.x & 7];   // a power of two: exact
+  __syncthreads();
   float mn = __builtin_inff(), mx = -__builtin_inff();
-  run_tiles<NKB, G2>(cube, B, P, o, lds, [&](int64_t t, const f32x4 (&acc)[4]) {
-    const int64_t pb = t * 64 * G2;
-    const bool full = pb + 64 * G2 <= P;
+  run_tiles<NKB, G2>(cube, B, P, tab, acc0, lds, [&](int64_t t, const f32x4 (&acc)[RB]) {
+    const int64_t pb = t * 16 * RB * G2;
+    if (pb + 16 * RB * G2 <= P) {   // whole tile: every row is a pixel
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+      for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t pix = pb + (int64_t)(16 * rb + 4 * g + e) * G2 + p;
-        if (full || pix < P) {
+        for (int e = 0; e < 4; ++e) {
           mn = fminf(mn, acc[rb][e]);
           mx = fmaxf(mx, acc[rb][e]);
         }
-      }
+    } else {
+      const int left = (int)(P - pb);   // pixels of the tile inside the page
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if ((16 * rb + 4 * g + e) * G2 + p < left) {
+            mn = fminf(mn, acc[rb][e]);
+            mx = fmaxf(mx, acc[rb][e]);
+          }
+    }
   });
   // lanes holding the same component: l ^ 8 (other pixel of the row, if
   // any), l ^ 16, l ^ 32 (other rows)
@@ -282,7 +334,6 @@ __global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_range_u16(const vo
     const float s = (h2 > l2) ? 255.f / (h2 - l2) : 0.f;
     range_dev[jj] = s;
     range_dev[8 + jj] = 0.5f - l2 * s;
-    const float inv = 1.f / sa.scale[jj];   // a power of two: exact
     ab_dev[2 * jj] = l2 * inv;
     ab_dev[2 * jj + 1] = h2 * inv;
   }
@@ -296,34 +347,38 @@ __device__ __forceinline__ uint32_t quant(float y, float s, float o) {
 }
 
 // Pass 2: the quantised bytes of a wave tile are gathered per component
-// plane in LDS (8 planes x 128 pixels) and written as 16-byte chunks, so
-// each plane receives whole 128-byte segments.
+// plane in LDS (8 planes x the tile's pixels, in the wave's own tile slice)
+// and written as 16-byte chunks, so each plane receives whole segments.
 template <int NKB, int G2>
 __global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_stretch_u16(const void* __restrict__ cube, int B,
                                                                         int64_t P, int nc, ProjArgs a,
                                                                         const float* __restrict__ range_dev,
                                                                         uint8_t* __restrict__ images) {
   extern __shared__ __align__(16) uint32_t lds[];
-  __shared__ __align__(16) uint8_t outs[kWaves][8 * 128];
+  constexpr int RB = row_blocks<NKB>();
+  constexpr int TP = 16 * RB * G2;   // pixels per wave tile
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, col = lane & 15, p = col >> 3, j = col & 7;
   const bool live = p < G2 && j < nc;
   const bool writer = p == 0 && j < nc;
-  __shared__ ProjArgs sa;
+  ProjArgs& sa = *reinterpret_cast<ProjArgs*>(lds);   // set-up only: the tiles reuse it
   stage_args(a, sa);
-  Ops<NKB> o;
-  load_ops<NKB, G2>(sa, B, nc, o);
+  __shared__ OpsTab<NKB> tab;
+  const float acc0 = build_ops<NKB, G2>(sa, B, nc, tab);
+  __syncthreads();
   const float sc = live ? range_dev[j] : 0.f;
   const float of = live ? range_dev[8 + j] : 0.f;
-  uint8_t* ow = outs[w];
-  constexpr int TP = 64 * G2;   // pixels per wave tile
+  // the output bytes of a tile are staged in the wave's own LDS slice,
+  // whose tile data is all in registers by then
+  const int S = G2 == 2 ? B : B / 2;
+  uint8_t* ow = reinterpret_cast<uint8_t*>(lds + w * slice_dwords<NKB>(S, G2));
   const int jj = lane >> 3, cc = lane & 7;   // copy-out: plane jj, 16-byte chunk cc
   const bool copier = jj < nc && 16 * cc < TP;
   const bool aligned = (P % 16) == 0 && (reinterpret_cast<uintptr_t>(images) % 16) == 0;
-  run_tiles<NKB, G2>(cube, B, P, o, lds, [&](int64_t t, const f32x4 (&acc)[4]) {
+  run_tiles<NKB, G2>(cube, B, P, tab, acc0, lds, [&](int64_t t, const f32x4 (&acc)[RB]) {
     const int64_t pb = t * TP;
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
+    for (int rb = 0; rb < RB; ++rb) {
       const uint32_t mine = quant(acc[rb][0], sc, of) | (quant(acc[rb][1], sc, of) << 8) |
                             (quant(acc[rb][2], sc, of) << 16) | (quant(acc[rb][3], sc, of) << 24);
       if constexpr (G2 == 2) {
@@ -332,16 +387,16 @@ __global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_stretch_u16(const 
         if (writer) {
           const uint32_t lo = __builtin_amdgcn_perm(other, mine, 0x05010400u);
           const uint32_t hi = __builtin_amdgcn_perm(other, mine, 0x07030602u);
-          *reinterpret_cast<uint2*>(ow + 128 * j + 2 * (16 * rb + 4 * g)) = make_uint2(lo, hi);
+          *reinterpret_cast<uint2*>(ow + TP * j + 2 * (16 * rb + 4 * g)) = make_uint2(lo, hi);
         }
       } else {
-        if (writer) *reinterpret_cast<uint32_t*>(ow + 128 * j + 16 * rb + 4 * g) = mine;
+        if (writer) *reinterpret_cast<uint32_t*>(ow + TP * j + 16 * rb + 4 * g) = mine;
       }
     }
     wave_lds_sync();
     if (copier) {
       const int64_t px = pb + 16 * cc;
-      const u32x4 v = *reinterpret_cast<const u32x4*>(ow + 128 * jj + 16 * cc);
+      const u32x4 v = *reinterpret_cast<const u32x4*>(ow + TP * jj + 16 * cc);
       uint8_t* dst = images + (int64_t)jj * P + px;
       if (aligned && px + 16 <= P) {
         *reinterpret_cast<u32x4*>(dst) = v;
@@ -353,16 +408,22 @@ __global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_stretch_u16(const 
   });
 }
 
-// LDS: the wave slices plus 8 dwords that the last row's reads may reach.
-size_t smem(int B) { return ((size_t)kWaves * 64 * ((B & 1) ? B : B / 2) + 8) * 4; }
+// LDS: the wave slices plus 8 dwords that the last row's reads may reach;
+// at least one ProjArgs, which set-up stages there.
+template <int NKB, int G2>
+size_t smem(int B) {
+  const int S = G2 == 2 ? B : B / 2;
+  const size_t tiles = ((size_t)kWaves * slice_dwords<NKB>(S, G2) + 8) * 4;
+  return std::max(tiles, sizeof(ProjArgs));
+}
 
-int grid(const void* kernel, size_t sm, int nblocks, int64_t P, int B) {
+int grid(const void* kernel, size_t sm, int nblocks, int64_t P, int B, int rows) {
   int dev = 0, ncu = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, sm) != hipSuccess || per < 1)
     per = 1, ncu = 1;
-  const int64_t tp = 64 * ((B & 1) ? 2 : 1);
+  const int64_t tp = (int64_t)rows * ((B & 1) ? 2 : 1);
   const int64_t waves = (P + tp - 1) / tp;
   int64_t n = std::min<int64_t>((int64_t)per * ncu, nblocks);
   n = std::min<int64_t>(n, (waves + kWaves - 1) / kWaves);
@@ -372,9 +433,9 @@ int grid(const void* kernel, size_t sm, int nblocks, int64_t P, int B) {
 template <int NKB, int G2>
 hipError_t range_k(const void* cube, int B, int64_t P, int nc, const ProjArgs& a, int nblocks, float* part,
                    unsigned* ticket, float* range_dev, float* ab_dev, hipStream_t s) {
-  const size_t sm = smem(B);
+  const size_t sm = smem<NKB, G2>(B);
   const void* k = reinterpret_cast<const void*>(&k_range_u16<NKB, G2>);
-  const int nb = grid(k, sm, nblocks, P, B);
+  const int nb = grid(k, sm, nblocks, P, B, 16 * row_blocks<NKB>());
   hipLaunchKernelGGL((k_range_u16<NKB, G2>), dim3(nb), dim3(kBlock), sm, s, cube, B, P, nc, a, part, ticket,
                      range_dev, ab_dev);
   return hipGetLastError();
@@ -383,9 +444,9 @@ hipError_t range_k(const void* cube, int B, int64_t P, int nc, const ProjArgs& a
 template <int NKB, int G2>
 hipError_t stretch_k(const void* cube, int B, int64_t P, int nc, const ProjArgs& a, int nblocks,
                      const float* range_dev, uint8_t* images, hipStream_t s) {
-  const size_t sm = smem(B);
+  const size_t sm = smem<NKB, G2>(B);
   const void* k = reinterpret_cast<const void*>(&k_stretch_u16<NKB, G2>);
-  const int nb = grid(k, sm, nblocks, P, B);
+  const int nb = grid(k, sm, nblocks, P, B, 16 * row_blocks<NKB>());
   hipLaunchKernelGGL((k_stretch_u16<NKB, G2>), dim3(nb), dim3(kBlock), sm, s, cube, B, P, nc, a, range_dev,
                      images);
   return hipGetLastError();
