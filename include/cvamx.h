@@ -148,10 +148,12 @@ int pca_project(cvamx_ctx* ctx, const cvamx_cube* cube, const double* V,
  * of the weighted problem, with real per-pixel class weights w_pc
  * (n_c = sum_p w_pc, m_c, m and the scatters weighted accordingly).  Not in
  * the paper: it reduces to the paper's CVA for one-hot weights.
- *   X        device, N x B float32 (row-major)
- *   w        device, N x K float32 (row-major)
+ *   X        device, N x B float32 (row-major), 16-byte aligned
+ *   w        device, N x K float32 (row-major), 16-byte aligned
+ *   prec     CVAMX_PREC_FP32 only (others: CVAMX_E_UNSUPPORTED)
  * Host outputs: J; W B x C, eigvals C, mean B, class_means K x B (all
- * float64; keep them for cva_soft_backward).  Synchronises `stream`. */
+ * float64; keep them for cva_soft_backward).  Synchronises `stream`.
+ * Misaligned X or w: CVAMX_E_UNSUPPORTED. */
 int cva_soft_forward(cvamx_ctx* ctx, const float* X, const float* w,
                      int64_t N, int32_t B, int32_t K, int32_t prec,
                      double ridge, double* J, double* W, double* eigvals,
@@ -162,6 +164,7 @@ int cva_soft_forward(cvamx_ctx* ctx, const float* X, const float* w,
  *                            - (1 + lambda_k) (w_k^T (x_p - m_c))^2 ]
  * (the terms for the null-space directions of S_b cancel).
  *   W, eigvals, mean, class_means   host, from cva_soft_forward
+ *   X        device, N x B float32, 16-byte aligned
  *   dw       device, N x K float32
  * Asynchronous on `stream`. */
 int cva_soft_backward(cvamx_ctx* ctx, const float* X, const double* W,

@@ -141,6 +141,13 @@ void prof_collect(cvamx_ctx* ctx) {
 
 size_t esize(int dtype) { return dtype == CVAMX_F32 ? 4 : 2; }
 
+// For uint16 pages the scatter kernels centre on an integer, so x - c is an
+// integer below 2^17 in magnitude and its two-term bf16 (or fp16) split is
+// exact: every matrix-core product is exact and only the FP32 accumulation
+// rounds, as on the FP32 VALU path.  FP32 requests on such pages therefore
+// take the matrix-core kernels (bf16 split).
+bool split_is_exact(int dtype) { return dtype == CVAMX_U16; }
+
 // Round to the nearest bf16 / fp16 value (ties to even), returned as double.
 double bf16_round(double x) {
   float f = (float)x;
@@ -437,14 +444,14 @@ int cva_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels, int32_
                               (int64_t*)(res + lay.counts), (int32_t*)(res + lay.offsets), s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "label index launch");
-  if (prec == CVAMX_PREC_FP32) {
+  if (prec == CVAMX_PREC_FP32 && !split_is_exact(cube->dtype)) {
     prof_begin(ctx, s, "class_moments");
     e = cvx::launch_class_moments(cube->dtype, cube->data, B, P, (const int32_t*)ctx->buf[B_IDX],
                                   (const int32_t*)(res + lay.offsets), K, G, (double*)ctx->buf[B_PART],
                                   (double*)(res + lay.shift), s);
   } else {
     prof_begin(ctx, s, "class_moments_mfma");
-    e = cvx::launch_class_moments_mfma(cube->dtype, prec == CVAMX_PREC_BF16X3 ? 0 : 1, cube->data, B, P,
+    e = cvx::launch_class_moments_mfma(cube->dtype, prec == CVAMX_PREC_F16X3 ? 1 : 0, cube->data, B, P,
                                        (const int32_t*)ctx->buf[B_IDX], (const int32_t*)(res + lay.offsets), K,
                                        G, (double*)ctx->buf[B_PART], (double*)(res + lay.shift), s);
   }
@@ -523,13 +530,13 @@ int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t
   if (int st = ensure_pinned(ctx, res_bytes)) return st;
   char* res = static_cast<char*>(ctx->buf[B_RES]);
   hipError_t e;
-  if (prec == CVAMX_PREC_FP32) {
+  if (prec == CVAMX_PREC_FP32 && !split_is_exact(cube->dtype)) {
     prof_begin(ctx, s, "pca_gram");
     e = cvx::launch_pca_gram(cube->dtype, cube->data, B, P, mask, nblocks, (double*)ctx->buf[B_PART],
                              (double*)res, s);
   } else {
     prof_begin(ctx, s, "pca_gram_mfma");
-    e = cvx::launch_pca_gram_mfma(cube->dtype, prec == CVAMX_PREC_BF16X3 ? 0 : 1, cube->data, B, P, mask,
+    e = cvx::launch_pca_gram_mfma(cube->dtype, prec == CVAMX_PREC_F16X3 ? 1 : 0, cube->data, B, P, mask,
                                   nblocks, (double*)ctx->buf[B_PART], (double*)res, s);
   }
   prof_end(ctx, s);
@@ -577,15 +584,15 @@ int cva_soft_forward(cvamx_ctx* ctx, const float* X, const float* w, int64_t N, 
   if (!finite_nonneg(ridge)) return fail(ctx, CVAMX_E_INVALID_ARG, "ridge must be finite and >= 0");
   if (!J || !W || !eigvals || !mean || !class_means)
     return fail(ctx, CVAMX_E_INVALID_ARG, "J, W, eigvals, mean and class_means must be non-NULL");
-  if ((reinterpret_cast<uintptr_t>(X) & 15u) != 0)
-    return fail(ctx, CVAMX_E_UNSUPPORTED, "X must be 16-byte aligned");
+  if ((reinterpret_cast<uintptr_t>(X) & 15u) != 0 || (reinterpret_cast<uintptr_t>(w) & 15u) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "X and w must be 16-byte aligned");
   if (prec != CVAMX_PREC_FP32)
     return fail(ctx, CVAMX_E_UNSUPPORTED, "soft-label CVA runs the FP32 scatter path only");
   if (int st = check_device(ctx)) return st;
   hipStream_t s = (hipStream_t)stream;
   const int BP = cvx::padded_bp(B), KP = (K + 3) & ~3;
   const int L = cvx::tri_blocks(B) * 16;
-  const int nb1 = (int)std::max<int64_t>(1, std::min<int64_t>(ctx->num_cu, (N + cvx::kChunk - 1) / cvx::kChunk));
+  const int nb1 = (int)std::max<int64_t>(1, std::min<int64_t>(2 * ctx->num_cu, (N + cvx::kChunk - 1) / cvx::kChunk));
   const int G = std::max(1, std::min(128, 1024 / K));
   const size_t first_bytes = 8 * (size_t)K * (B + 1);
   const size_t mcf_off = first_bytes;

@@ -9,50 +9,80 @@
 //   2. per class, the weighted augmented Gram of [x - m_c, 1]: sum w d d^T,
 //      sum w d and sum w (d = x - float(m_c)); the host removes the tiny
 //      offset between float(m_c) and m_c exactly.
+// Both passes stream chunks of kChunk rows of X and of w through a block-wide
+// prefetching driver: the next chunk's 16-byte loads are in flight while the
+// current chunk is accumulated (pass 1); pass 2 is bound by its register
+// tiles' LDS reads and stages rows directly.
 // Backward: per pixel, u = x - m, z_j = w_j^T u for the C canonical
 // vectors, and dJ/dw_pc = sum_j z_j^2 - sum_j (1 + lambda_j)(z_j - d_jc)^2
 // with d_jc = w_j^T (m_c - m).
-#include "k_common.hpp"
+#include "k_gram.hpp"
+#include "k_tile.hpp"
 #include "launch.hpp"
 
 namespace cvx {
 
 namespace {
 
-// Stage rows [r0, r0 + rows) of a row-major N x L float matrix into LDS
-// (kChunk x ld, zero-filled beyond `rows` and beyond L).
-__device__ __forceinline__ void stage_rows(const float* __restrict__ src, int L, int ld, int64_t r0,
-                                           int rows, float* __restrict__ dst) {
-  const int per = kChunk * L;
-  const int nel = rows * L;
-  const float* s = src + r0 * L;
-  const int rstep = kBlock / L, bstep = kBlock % L;
-  int r = threadIdx.x / L, b = threadIdx.x % L;
-  for (int e = threadIdx.x; e < per; e += kBlock) {
-    dst[r * ld + b] = (e < nel) ? s[e] : 0.f;
-    r += rstep;
-    b += bstep;
-    if (b >= L) {
-      b -= L;
-      ++r;
+// Chunks ch = first, first + stride, ... of X and w, staged raw in LDS
+// (xr: kChunk B floats, wr: kChunk K floats), compute(ch, rows) per chunk
+// after a block barrier; a barrier follows it.  QX, QW bound the 16-byte
+// loads per thread of the two tiles.
+template <int QX, int QW, typename Compute>
+__device__ __forceinline__ void for_each_chunk(const float* __restrict__ X, const float* __restrict__ W, int64_t N,
+                                               int B, int K, int64_t first, int64_t stride,
+                                               uint32_t* __restrict__ xr, uint32_t* __restrict__ wr,
+                                               Compute compute) {
+  const int tid = threadIdx.x;
+  const unsigned char* xb = reinterpret_cast<const unsigned char*>(X);
+  const unsigned char* wb = reinterpret_cast<const unsigned char*>(W);
+  const int xbytes = kChunk * B * 4, wbytes = kChunk * K * 4;
+  const int64_t xtotal = N * B * 4, wtotal = N * K * 4;
+  const int64_t nch = (N + kChunk - 1) / kChunk;
+  const int64_t nfull = N / kChunk;
+  auto rows_of = [&](int64_t ch) { return (int)(N - ch * kChunk < kChunk ? N - ch * kChunk : kChunk); };
+  int64_t ch = first;
+  if (nfull == 0) {
+    for (; ch < nch; ch += stride) {
+      copy_partial_tile<kBlock>(xb, xtotal, ch, xbytes, tid, xr);
+      copy_partial_tile<kBlock>(wb, wtotal, ch, wbytes, tid, wr);
+      __syncthreads();
+      compute(ch, rows_of(ch));
+      __syncthreads();
     }
+    return;
   }
-  for (int e = threadIdx.x; e < kChunk * (ld - L); e += kBlock) {
-    const int rr = e / (ld - L), cc = L + e % (ld - L);
-    dst[rr * ld + cc] = 0.f;
+  auto next = [&](int64_t x, int64_t cur) { return x < nfull ? x : (cur < nfull ? cur : nfull - 1); };
+  u32x4 rx[QX], rw[QW];
+  load_tile<QX, kBlock>(xb, next(ch, ch), xbytes, tid, rx);
+  load_tile<QW, kBlock>(wb, next(ch, ch), wbytes, tid, rw);
+  for (; ch < nch; ch += stride) {
+    if (ch < nfull) {
+      store_tile<QX, kBlock>(xr, xbytes, tid, rx);
+      store_tile<QW, kBlock>(wr, wbytes, tid, rw);
+    } else {
+      copy_partial_tile<kBlock>(xb, xtotal, ch, xbytes, tid, xr);
+      copy_partial_tile<kBlock>(wb, wtotal, ch, wbytes, tid, wr);
+    }
+    __syncthreads();
+    load_tile<QX, kBlock>(xb, next(ch + stride, ch), xbytes, tid, rx);
+    load_tile<QW, kBlock>(wb, next(ch + stride, ch), wbytes, tid, rw);
+    __builtin_amdgcn_sched_barrier(0);   // keep the next chunk's loads ahead of the work
+    compute(ch, rows_of(ch));
+    __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_soft_first(const float* __restrict__ X,
-                                                       const float* __restrict__ W, int64_t N,
-                                                       int B, int K, double* __restrict__ part,
-                                                       unsigned* __restrict__ ticket,
-                                                       double* __restrict__ first,
+__global__ __launch_bounds__(kBlock) void k_soft_first(const float* __restrict__ X, const float* __restrict__ W,
+                                                       int64_t N, int B, int K, double* __restrict__ part,
+                                                       unsigned* __restrict__ ticket, double* __restrict__ first,
                                                        float* __restrict__ mc_f) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int BP = (B + 1 + 3) & ~3, KP = (K + 3) & ~3;
-  float* xs = reinterpret_cast<float*>(smem_raw);       // kChunk x BP
-  float* ws = xs + kChunk * BP;                          // kChunk x KP
+  float* xs = reinterpret_cast<float*>(smem_raw);                 // kChunk x BP: [x, 1]
+  float* ws = xs + kChunk * BP;                                    // kChunk x KP
+  uint32_t* xr = reinterpret_cast<uint32_t*>(ws + kChunk * KP);    // raw rows of X
+  uint32_t* wr = xr + kChunk * B;                                  // raw rows of w
   double* red = reinterpret_cast<double*>(smem_raw);
   __shared__ bool am_last;
   const int nbi = KP / 4, nbj = BP / 4, nblk = nbi * nbj;
@@ -67,23 +97,27 @@ __global__ __launch_bounds__(kBlock) void k_soft_first(const float* __restrict__
     acc[e] = 0.f;
     accd[e] = 0.0;
   }
-  const int64_t nch = (N + kChunk - 1) / kChunk;
-  for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
-    const int64_t r0 = ch * kChunk;
-    const int rows = (N - r0 < kChunk) ? (int)(N - r0) : kChunk;
-    stage_rows(X, B, BP, r0, rows, xs);
-    stage_rows(W, K, KP, r0, rows, ws);
-    __syncthreads();
-    if (threadIdx.x < kChunk) xs[threadIdx.x * BP + B] = (threadIdx.x < rows) ? 1.f : 0.f;
+  const float* xf = reinterpret_cast<const float*>(xr);
+  const float* wf = reinterpret_cast<const float*>(wr);
+  auto body = [&](int64_t, int rows) {
+    for (int e = threadIdx.x; e < kChunk * BP; e += kBlock) {
+      const int r = e / BP, b = e - r * BP;
+      xs[e] = r < rows ? (b < B ? xf[r * B + b] : (b == B ? 1.f : 0.f)) : 0.f;
+    }
+    for (int e = threadIdx.x; e < kChunk * KP; e += kBlock) {
+      const int r = e / KP, c = e - r * KP;
+      ws[e] = (r < rows && c < K) ? wf[r * K + c] : 0.f;
+    }
     __syncthreads();
     if (active) tile_acc(ws, KP, xs, BP, bi, bj, slice, kChunk, nslice, acc);
-    __syncthreads();
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       accd[e] += (double)acc[e];
       acc[e] = 0.f;
     }
-  }
+  };
+  if (B <= 40 && K <= 8) for_each_chunk<5, 1>(X, W, N, B, K, blockIdx.x, gridDim.x, xr, wr, body);
+  else for_each_chunk<8, 4>(X, W, N, B, K, blockIdx.x, gridDim.x, xr, wr, body);
   // slice reduction -> block partial laid out as [c][e] for c < KP, e < BP
   __syncthreads();
   if (active)
@@ -122,6 +156,34 @@ __global__ __launch_bounds__(kBlock) void k_soft_first(const float* __restrict__
       mc_f[t] = (n != 0.0) ? (float)(first[c * (B + 1) + b] / n) : 0.f;
     }
     if (threadIdx.x == 0) *ticket = 0u;
+  }
+}
+
+// Pass 2, grid (G, K): block (g, c) takes chunks g, g + G, ... for class
+// c.  Bound by the LDS reads of the register tiles rather than by memory, so
+// it keeps a small LDS footprint (four blocks per CU) and stages rows
+// directly instead of through the prefetching driver.
+// Stage rows [r0, r0 + rows) of a row-major N x L float matrix into LDS
+// (kChunk x ld, zero-filled beyond `rows` and beyond L).
+__device__ __forceinline__ void stage_rows(const float* __restrict__ src, int L, int ld, int64_t r0,
+                                           int rows, float* __restrict__ dst) {
+  const int per = kChunk * L;
+  const int nel = rows * L;
+  const float* s = src + r0 * L;
+  const int rstep = kBlock / L, bstep = kBlock % L;
+  int r = threadIdx.x / L, b = threadIdx.x % L;
+  for (int e = threadIdx.x; e < per; e += kBlock) {
+    dst[r * ld + b] = (e < nel) ? s[e] : 0.f;
+    r += rstep;
+    b += bstep;
+    if (b >= L) {
+      b -= L;
+      ++r;
+    }
+  }
+  for (int e = threadIdx.x; e < kChunk * (ld - L); e += kBlock) {
+    const int rr = e / (ld - L), cc = L + e % (ld - L);
+    dst[rr * ld + cc] = 0.f;
   }
 }
 
@@ -195,28 +257,11 @@ __global__ __launch_bounds__(kBlock) void k_soft_backward(const float* __restric
                                                           float* __restrict__ dw) {
   extern __shared__ __align__(16) uint32_t lds[];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int S = B;                         // one row = B dwords
+  const int S = B;                         // a lane group is one row of B dwords
   uint32_t* my = lds + w * 64 * S;
   const int64_t nt = (N + 63) / 64;
-  const int64_t total_bytes = N * B * 4;
   const unsigned char* base = reinterpret_cast<const unsigned char*>(X);
-  for (int64_t t = (int64_t)blockIdx.x * kWaves + w; t < nt; t += (int64_t)gridDim.x * kWaves) {
-    const int64_t tb = t * 256 * (int64_t)S;
-    for (int j = lane; j < 16 * S; j += 64) {
-      const int64_t ob = tb + 16 * (int64_t)j;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (ob + 16 <= total_bytes) {
-        v = *reinterpret_cast<const uint4*>(base + ob);
-      } else {
-        uint32_t h[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          h[q] = (ob + 4 * q + 4 <= total_bytes) ? *reinterpret_cast<const uint32_t*>(base + ob + 4 * q) : 0u;
-        v = make_uint4(h[0], h[1], h[2], h[3]);
-      }
-      *reinterpret_cast<uint4*>(my + 4 * j) = v;
-    }
-    wave_lds_sync();
+  for_each_tile<kMaxQ>(base, N * B * 4, nt, S, my, [&](int64_t t) {
     const int64_t row = t * 64 + lane;
     float z[8];
 #pragma unroll
@@ -227,7 +272,6 @@ __global__ __launch_bounds__(kBlock) void k_soft_backward(const float* __restric
 #pragma unroll
       for (int j = 0; j < 8; ++j) z[j] = fmaf(a.w[b * 8 + j], u, z[j]);
     }
-    wave_lds_sync();
     if (row < N) {
       float tz = 0.f;
 #pragma unroll
@@ -244,7 +288,26 @@ __global__ __launch_bounds__(kBlock) void k_soft_backward(const float* __restric
         *o = accumulate ? (*o + g) : g;
       }
     }
-  }
+  });
+}
+
+// LDS of the forward kernels: padded rows plus the raw chunk tiles, or the
+// slice-combine buffer, whichever is larger.
+size_t first_smem(int B, int K) {
+  const int BP = padded_bp(B), KP = (K + 3) & ~3;
+  const size_t a = (size_t)kChunk * (BP + KP + B + K) * sizeof(float);
+  const int nblk = (KP / 4) * (BP / 4);
+  const size_t r = (size_t)(kBlock / nblk) * nblk * 16 * sizeof(double);
+  return a > r ? a : r;
+}
+
+size_t scatter_smem(int B, int K) {
+  (void)K;
+  const int BP = padded_bp(B);
+  const size_t a = (size_t)2 * kChunk * BP * sizeof(float);
+  const int nblk = tri_blocks(B);
+  const size_t r = (size_t)(kBlock / nblk) * nblk * 16 * sizeof(double);
+  return a > r ? a : r;
 }
 
 }  // namespace
@@ -252,24 +315,17 @@ __global__ __launch_bounds__(kBlock) void k_soft_backward(const float* __restric
 hipError_t launch_soft_first(const float* X, const float* w, int64_t N, int B, int K, int nblocks,
                              double* part, unsigned* ticket, double* first, float* mc_f,
                              hipStream_t s) {
-  const int BP = padded_bp(B), KP = (K + 3) & ~3;
-  const size_t a = (size_t)kChunk * (BP + KP) * sizeof(float);
-  const int nblk = (KP / 4) * (BP / 4);
-  const size_t r = (size_t)(kBlock / nblk) * nblk * 16 * sizeof(double);
-  const size_t sm = a > r ? a : r;
-  hipLaunchKernelGGL(k_soft_first, dim3(nblocks), dim3(kBlock), sm, s, X, w, N, B, K, part, ticket,
+  if (B < 1 || B > kMaxB || K < 1 || K > 32 || nblocks < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_soft_first, dim3(nblocks), dim3(kBlock), first_smem(B, K), s, X, w, N, B, K, part, ticket,
                      first, mc_f);
   return hipGetLastError();
 }
 
 hipError_t launch_soft_scatter(const float* X, const float* w, int64_t N, int B, int K, int G,
                                const float* mc_f, double* part, hipStream_t s) {
-  const int BP = padded_bp(B);
-  const size_t a = (size_t)2 * kChunk * BP * sizeof(float);
-  const int nblk = tri_blocks(B);
-  const size_t r = (size_t)(kBlock / nblk) * nblk * 16 * sizeof(double);
-  const size_t sm = a > r ? a : r;
-  hipLaunchKernelGGL(k_soft_scatter, dim3(G, K), dim3(kBlock), sm, s, X, w, N, B, K, G, mc_f, part);
+  if (B < 1 || B > kMaxB || K < 1 || K > 32 || G < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_soft_scatter, dim3(G, K), dim3(kBlock), scatter_smem(B, K), s, X, w, N, B, K, G, mc_f,
+                     part);
   return hipGetLastError();
 }
 
