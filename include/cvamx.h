@@ -110,6 +110,23 @@ int cva_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels,
             double* W, double* eigvals, double* mean, int64_t* counts,
             double* class_means, double* Sw, double* Sb, void* stream);
 
+/* The same fit from a list of training points, as the analyst picks them
+ * (paper Section 2: a set of points per class; Section 4: the points given
+ * as (x, y) coordinates), instead of a label map.
+ *   pixels   device, N int64 pixel indices y * width + x, each in
+ *            0..height*width-1, 8-byte aligned; a pixel may repeat (each
+ *            entry is one training sample)
+ *   classes  device, N int8 (-1 = skip the entry, or 0..K-1), 16-byte
+ *            aligned
+ *   N        1..2^31-1
+ * Other arguments and outputs as cva_fit; a pixel outside the page gives
+ * CVAMX_E_INVALID_ARG.  Within a class the samples keep the list order. */
+int cva_fit_points(cvamx_ctx* ctx, const cvamx_cube* cube, const int64_t* pixels,
+                   const int8_t* classes, int64_t N, int32_t K, int32_t prec,
+                   double ridge, int32_t n_comp, double* W, double* eigvals,
+                   double* mean, int64_t* counts, double* class_means,
+                   double* Sw, double* Sb, void* stream);
+
 /* Project every pixel onto n_comp vectors and stretch each component to
  * 8 bits by its page-wide min and max (paper Section 2, regression
  * coefficients multiplied with the whole page; first rescale mode).

@@ -30,7 +30,7 @@ are not unique, and are not produced (parity unpinned by construction).
 """
 from .cva import (class_counts, class_index_lists, class_moments, within_scatter,
                   between_scatter, total_scatter, generalized_eig, sign_rule,
-                  cva_fit, project, cva_project)
+                  cva_fit, cva_fit_points, project, cva_project)
 from .stretch import stretch_minmax, stretch_training_range, stretch_percentile
 from .pca import pca_fit, pca_project
 from .soft import soft_moments, soft_fit, soft_grad, soft_delta_J
@@ -38,7 +38,7 @@ from .soft import soft_moments, soft_fit, soft_grad, soft_delta_J
 __all__ = [
     "class_counts", "class_index_lists", "class_moments", "within_scatter",
     "between_scatter", "total_scatter", "generalized_eig", "sign_rule",
-    "cva_fit", "project", "cva_project", "stretch_minmax",
+    "cva_fit", "cva_fit_points", "project", "cva_project", "stretch_minmax",
     "stretch_training_range", "stretch_percentile", "pca_fit", "pca_project",
     "soft_moments", "soft_fit", "soft_grad", "soft_delta_J",
 ]

@@ -171,6 +171,24 @@ def cva_fit(cube, labels, K: int, ridge: float = 0.0, n_comp: int | None = None)
                 class_sums=sums, class_means=means, Sw=Sw, Sb=Sb)
 
 
+def cva_fit_points(cube, pixels, classes, K: int, ridge: float = 0.0, n_comp: int | None = None):
+    """Fit CVA on a list of training points (paper Section 2: a set of
+    points per class, picked by the analyst; Section 4: given as (x, y)
+    coordinates).  pixels holds y * width + x; classes holds -1 (skip) or
+    0..K-1.  Each entry is one training sample, so a repeated pixel counts
+    as often as it is listed.  The fit is the same as cva_fit over the
+    listed rows."""
+    X = _rows(cube)
+    pix = np.asarray(pixels, dtype=np.int64).reshape(-1)
+    cls = np.asarray(classes).reshape(-1)
+    if pix.shape != cls.shape:
+        raise ValueError("pixels and classes must have the same length")
+    if pix.size and (pix.min() < 0 or pix.max() >= X.shape[0]):
+        raise ValueError("a training point lies outside the page")
+    rows = X[pix][None, :, :]                # a 1 x N "page" of the listed rows
+    return cva_fit(rows, cls[None, :], K, ridge=ridge, n_comp=n_comp)
+
+
 def project(cube, W: np.ndarray, center: np.ndarray, chunk: int = 1 << 20) -> np.ndarray:
     """y_p = W^T (x_p - center) for every pixel, float64, P x C."""
     X = _rows(cube)

@@ -52,6 +52,8 @@ EXPORTS = {
     "cvamx_last_error": (ctypes.c_char_p, [_vp]),
     "cva_fit": (ctypes.c_int, [_vp, ctypes.POINTER(Cube), _vp, _i32, _i32, _f64, _i32,
                                _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cva_fit_points": (ctypes.c_int, [_vp, ctypes.POINTER(Cube), _vp, _vp, _i64, _i32, _i32, _f64, _i32,
+                                      _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cva_project": (ctypes.c_int, [_vp, ctypes.POINTER(Cube), _vp, _vp, _i32, _vp, _vp, _vp]),
     "pca_fit": (ctypes.c_int, [_vp, ctypes.POINTER(Cube), _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "pca_project": (ctypes.c_int, [_vp, ctypes.POINTER(Cube), _vp, _vp, _i32, _vp, _vp, _vp]),

@@ -93,6 +93,36 @@ def cva_fit(cube: torch.Tensor, labels: torch.Tensor, K: int, precision: str = "
     return CvaFit(W, lam, mean, counts, cm, Sw, Sb)
 
 
+def cva_fit_points(cube: torch.Tensor, pixels: torch.Tensor, classes: torch.Tensor, K: int,
+                   precision: str = "fp32", ridge: float = 0.0, n_comp: Optional[int] = None) -> CvaFit:
+    """CVA fit on a list of training points: pixels (int64 N, y * W + x) and
+    classes (int8 N, -1 = skip), both on the cube's device."""
+    c = _cube(cube)
+    if pixels.dtype != torch.int64 or classes.dtype != torch.int8 or pixels.dim() != 1 \
+            or tuple(classes.shape) != tuple(pixels.shape):
+        raise ValueError("pixels must be int64 N and classes int8 N")
+    for t in (pixels, classes):
+        if t.device != cube.device or not t.is_contiguous():
+            raise ValueError("pixels and classes must be contiguous and on the cube's device")
+    B = c.bands
+    C = min(K - 1, B)
+    n_comp = C if n_comp is None else int(n_comp)
+    W = np.empty((B, n_comp))
+    lam = np.empty(n_comp)
+    mean = np.empty(B)
+    counts = np.empty(K, dtype=np.int64)
+    cm = np.empty((K, B))
+    Sw = np.empty((B, B))
+    Sb = np.empty((B, B))
+    dev = _dev_index(cube)
+    ctx = context(dev)
+    st = lib().cva_fit_points(ctx, ctypes.byref(c), _ptr(pixels), _ptr(classes), int(pixels.numel()), K,
+                              _lib.PREC[precision], float(ridge), n_comp, _ptr(W), _ptr(lam), _ptr(mean),
+                              _ptr(counts), _ptr(cm), _ptr(Sw), _ptr(Sb), _stream(cube.device))
+    check(st, ctx)
+    return CvaFit(W, lam, mean, counts, cm, Sw, Sb)
+
+
 def cva_project(cube: torch.Tensor, W, center, out: Optional[torch.Tensor] = None,
                 return_range: bool = False):
     """Project every pixel on the columns of W (B x n) about `center` and

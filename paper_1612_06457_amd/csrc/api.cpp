@@ -402,48 +402,60 @@ void cvamx_destroy(cvamx_ctx* ctx) {
   delete ctx;
 }
 
-int cva_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels, int32_t K, int32_t prec,
-            double ridge, int32_t n_comp, double* W, double* eigvals, double* mean, int64_t* counts,
-            double* class_means, double* Sw, double* Sb, void* stream) {
-  if (!ctx) return CVAMX_E_INVALID_ARG;
+// Arguments shared by the two fit entry points.
+static int check_fit_args(cvamx_ctx* ctx, const cvamx_cube* cube, int32_t K, int32_t prec, double ridge,
+                   int32_t n_comp, const double* W, const double* eigvals, const double* mean,
+                   const int64_t* counts) {
   if (int st = check_cube(ctx, cube)) return st;
-  if (!labels) return fail(ctx, CVAMX_E_INVALID_ARG, "labels is NULL");
-  if ((reinterpret_cast<uintptr_t>(labels) & 15u) != 0)
-    return fail(ctx, CVAMX_E_UNSUPPORTED, "labels must be 16-byte aligned");
   if (K < 2 || K > CVAMX_MAX_CLASSES) return fail(ctx, CVAMX_E_INVALID_ARG, "K must lie in 2..127");
   if (prec < CVAMX_PREC_FP32 || prec > CVAMX_PREC_F16X3)
     return fail(ctx, CVAMX_E_INVALID_ARG, "unknown precision");
   if (!finite_nonneg(ridge)) return fail(ctx, CVAMX_E_INVALID_ARG, "ridge must be finite and >= 0");
-  const int B = (int)cube->bands;
-  const int C = std::min(K - 1, B);
+  const int C = std::min(K - 1, (int)cube->bands);
   if (n_comp < 1 || n_comp > C) return fail(ctx, CVAMX_E_INVALID_ARG, "n_comp must lie in 1..min(K-1, bands)");
   if (!W || !eigvals || !mean || !counts)
     return fail(ctx, CVAMX_E_INVALID_ARG, "W, eigvals, mean and counts must be non-NULL");
-  if (int st = check_device(ctx)) return st;
-  hipStream_t s = (hipStream_t)stream;
-  const int64_t P = cube->height * cube->width;
-  const int nT = (int)((P + cvx::kLabelTile - 1) / cvx::kLabelTile);
-  const int L = cvx::tri_blocks(B) * 16;
-  // blocks per class: about four resident blocks per CU over all classes
-  const int G = std::max(1, std::min(256, 4 * ctx->num_cu / K));
-  const FitLayout lay(K, B, L);
+  return 0;
+}
+
+// The class-grouped index list of training pixels: from a label map of P
+// entries (list = nullptr), or from a list of N (pixel, class) points, where
+// the label kernels run over the N classes and their positions are then
+// mapped to pixels.  Counts, offsets and the error flag land in the results
+// region; returns the number of label entries scanned.
+static int build_index(cvamx_ctx* ctx, const int8_t* labels, const int64_t* points, int64_t n, int64_t P, int K,
+                const FitLayout& lay, char* res, hipStream_t s) {
+  const int nT = (int)((n + cvx::kLabelTile - 1) / cvx::kLabelTile);
   if (int st = ensure(ctx, B_TILECNT, (size_t)nT * K * 4)) return st;
-  if (int st = ensure(ctx, B_IDX, (size_t)P * 4)) return st;
-  if (int st = ensure(ctx, B_PART, (size_t)K * G * L * 8)) return st;
-  if (int st = ensure(ctx, B_RES, lay.total)) return st;
-  if (int st = ensure_pinned(ctx, lay.total)) return st;
-  char* res = static_cast<char*>(ctx->buf[B_RES]);
+  if (int st = ensure(ctx, B_IDX, (size_t)n * 4)) return st;
   HIP_TRY(hipMemsetAsync(res + lay.err, 0, 8, s), "memset");
   hipError_t e;
   prof_begin(ctx, s, "label_count");
-  e = cvx::launch_label_count(labels, P, K, nT, (int32_t*)ctx->buf[B_TILECNT], (int32_t*)(res + lay.err), s);
+  e = cvx::launch_label_count(labels, n, K, nT, (int32_t*)ctx->buf[B_TILECNT], (int32_t*)(res + lay.err), s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "label count launch");
   prof_begin(ctx, s, "label_index");
-  e = cvx::launch_label_index(labels, P, K, nT, (const int32_t*)ctx->buf[B_TILECNT], (int32_t*)ctx->buf[B_IDX],
+  e = cvx::launch_label_index(labels, n, K, nT, (const int32_t*)ctx->buf[B_TILECNT], (int32_t*)ctx->buf[B_IDX],
                               (int64_t*)(res + lay.counts), (int32_t*)(res + lay.offsets), s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "label index launch");
+  if (points) {
+    prof_begin(ctx, s, "points_to_pixels");
+    e = cvx::launch_points_to_pixels(points, (int32_t*)ctx->buf[B_IDX], (const int32_t*)(res + lay.offsets), K, n,
+                                     P, (int32_t*)(res + lay.err), ctx->num_cu, s);
+    prof_end(ctx, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "point mapping launch");
+  }
+  return 0;
+}
+
+// Class moments, reduction, the copy to the host and the FP64 finish.
+static int fit_from_index(cvamx_ctx* ctx, const cvamx_cube* cube, int32_t K, int32_t prec, double ridge, int32_t n_comp,
+                   double* W, double* eigvals, double* mean, int64_t* counts, double* class_means, double* Sw,
+                   double* Sb, const FitLayout& lay, char* res, int G, int L, hipStream_t s) {
+  const int B = (int)cube->bands;
+  const int64_t P = cube->height * cube->width;
+  hipError_t e;
   if (prec == CVAMX_PREC_FP32 && !split_is_exact(cube->dtype)) {
     prof_begin(ctx, s, "class_moments");
     e = cvx::launch_class_moments(cube->dtype, cube->data, B, P, (const int32_t*)ctx->buf[B_IDX],
@@ -467,7 +479,8 @@ int cva_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels, int32_
   const char* h = static_cast<const char*>(ctx->pinned);
   int32_t errflag;
   std::memcpy(&errflag, h + lay.err, 4);
-  if (errflag) return fail(ctx, CVAMX_E_INVALID_ARG, "a label lies outside -1..K-1");
+  if (errflag & 1) return fail(ctx, CVAMX_E_INVALID_ARG, "a label lies outside -1..K-1");
+  if (errflag & 2) return fail(ctx, CVAMX_E_INVALID_ARG, "a training point lies outside the page");
   std::vector<int64_t> cnt(K);
   std::memcpy(cnt.data(), h + lay.counts, 8 * (size_t)K);
   for (int k = 0; k < K; ++k)
@@ -497,6 +510,61 @@ int cva_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels, int32_
   if (Sw) std::copy(Swv.begin(), Swv.end(), Sw);
   if (Sb) std::copy(Sbv.begin(), Sbv.end(), Sb);
   return CVAMX_OK;
+}
+
+static int fit_layout_and_buffers(cvamx_ctx* ctx, int K, int B, int& G, int& L, char*& res) {
+  L = cvx::tri_blocks(B) * 16;
+  // blocks per class: about four resident blocks per CU over all classes
+  G = std::max(1, std::min(256, 4 * ctx->num_cu / K));
+  const FitLayout lay(K, B, L);
+  if (int st = ensure(ctx, B_PART, (size_t)K * G * L * 8)) return st;
+  if (int st = ensure(ctx, B_RES, lay.total)) return st;
+  if (int st = ensure_pinned(ctx, lay.total)) return st;
+  res = static_cast<char*>(ctx->buf[B_RES]);
+  return 0;
+}
+
+int cva_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels, int32_t K, int32_t prec,
+            double ridge, int32_t n_comp, double* W, double* eigvals, double* mean, int64_t* counts,
+            double* class_means, double* Sw, double* Sb, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (int st = check_fit_args(ctx, cube, K, prec, ridge, n_comp, W, eigvals, mean, counts)) return st;
+  if (!labels) return fail(ctx, CVAMX_E_INVALID_ARG, "labels is NULL");
+  if ((reinterpret_cast<uintptr_t>(labels) & 15u) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "labels must be 16-byte aligned");
+  if (int st = check_device(ctx)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int B = (int)cube->bands;
+  const int64_t P = cube->height * cube->width;
+  int G, L;
+  char* res;
+  if (int st = fit_layout_and_buffers(ctx, K, B, G, L, res)) return st;
+  const FitLayout lay(K, B, L);
+  if (int st = build_index(ctx, labels, nullptr, P, P, K, lay, res, s)) return st;
+  return fit_from_index(ctx, cube, K, prec, ridge, n_comp, W, eigvals, mean, counts, class_means, Sw, Sb, lay, res,
+                        G, L, s);
+}
+
+int cva_fit_points(cvamx_ctx* ctx, const cvamx_cube* cube, const int64_t* pixels, const int8_t* classes,
+                   int64_t N, int32_t K, int32_t prec, double ridge, int32_t n_comp, double* W, double* eigvals,
+                   double* mean, int64_t* counts, double* class_means, double* Sw, double* Sb, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (int st = check_fit_args(ctx, cube, K, prec, ridge, n_comp, W, eigvals, mean, counts)) return st;
+  if (!pixels || !classes) return fail(ctx, CVAMX_E_INVALID_ARG, "pixels and classes must be non-NULL");
+  if (N < 1 || N >= (int64_t(1) << 31)) return fail(ctx, CVAMX_E_INVALID_ARG, "N must lie in 1..2^31-1");
+  if ((reinterpret_cast<uintptr_t>(classes) & 15u) != 0 || (reinterpret_cast<uintptr_t>(pixels) & 7u) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "classes must be 16-byte aligned and pixels 8-byte aligned");
+  if (int st = check_device(ctx)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int B = (int)cube->bands;
+  const int64_t P = cube->height * cube->width;
+  int G, L;
+  char* res;
+  if (int st = fit_layout_and_buffers(ctx, K, B, G, L, res)) return st;
+  const FitLayout lay(K, B, L);
+  if (int st = build_index(ctx, classes, pixels, N, P, K, lay, res, s)) return st;
+  return fit_from_index(ctx, cube, K, prec, ridge, n_comp, W, eigvals, mean, counts, class_means, Sw, Sb, lay, res,
+                        G, L, s);
 }
 
 int cva_project(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const double* center,

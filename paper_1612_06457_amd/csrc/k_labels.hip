@@ -249,7 +249,33 @@ __global__ __launch_bounds__(kBlock) void k_label_index(const int8_t* __restrict
   });
 }
 
+// Training points given as a list: the label kernels ran over the N point
+// classes, so idx[0 .. total) holds positions in the list; replace each by
+// its pixel, flagging (bit 2 of err) a pixel outside 0..P-1.
+__global__ __launch_bounds__(kBlock) void k_points_to_pixels(const int64_t* __restrict__ pixels,
+                                                             int32_t* __restrict__ idx,
+                                                             const int32_t* __restrict__ offsets, int K,
+                                                             int64_t P, int32_t* __restrict__ err) {
+  const int64_t total = offsets[K];
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
+    const int64_t p = pixels[idx[i]];
+    const bool ok = p >= 0 && p < P;
+    idx[i] = ok ? (int32_t)p : 0;
+    bad |= !ok;
+  }
+  if (bad) atomicOr(err, 2);
+}
+
 }  // namespace
+
+hipError_t launch_points_to_pixels(const int64_t* pixels, int32_t* idx, const int32_t* offsets, int K, int64_t N,
+                                   int64_t P, int32_t* err_flag, int num_cu, hipStream_t s) {
+  const int64_t need = (N + kBlock - 1) / kBlock;
+  const int nb = (int)(need < (int64_t)num_cu * 8 ? (need > 0 ? need : 1) : (int64_t)num_cu * 8);
+  hipLaunchKernelGGL(k_points_to_pixels, dim3(nb), dim3(kBlock), 0, s, pixels, idx, offsets, K, P, err_flag);
+  return hipGetLastError();
+}
 
 hipError_t launch_label_count(const int8_t* labels, int64_t P, int K, int nT,
                               int32_t* tile_counts, int32_t* err_flag, hipStream_t s) {

@@ -35,6 +35,12 @@ hipError_t launch_label_index(const int8_t* labels, int64_t P, int K, int nT,
                               const int32_t* tile_counts, int32_t* idx,
                               int64_t* counts_out, int32_t* offsets_out, hipStream_t s);
 
+// training points as a list: turn the class-grouped list positions in idx
+// (offsets[K] of them) into pixels; sets bit 2 of *err_flag for a pixel
+// outside 0..P-1
+hipError_t launch_points_to_pixels(const int64_t* pixels, int32_t* idx, const int32_t* offsets, int K, int64_t N,
+                                   int64_t P, int32_t* err_flag, int num_cu, hipStream_t s);
+
 // class moments: per-class augmented Gram of [x - c_k, 1] about a per-class
 // shift c_k; partials part[(k * G + g) * L + t], L = nblk * 16.
 hipError_t launch_class_moments(int dtype, const void* cube, int B, int64_t P, const int32_t* idx,

@@ -219,6 +219,62 @@ def test_repeatable(dev):
     assert np.array_equal(p1[3], p2[3])
 
 
+# ------------------------------------------------------ fit from point lists
+
+def _points(c, rng, n_dup=500, n_skip=37):
+    """The labelled pixels of a case as a shuffled point list, with some
+    points listed twice and some entries marked -1."""
+    flat = c.labels.reshape(-1)
+    pix = np.flatnonzero(flat >= 0)
+    cls = flat[pix]
+    order = rng.permutation(pix.size)
+    dup = rng.choice(pix.size, size=n_dup, replace=False)
+    skip = rng.integers(0, flat.size, size=n_skip)
+    pts = np.concatenate([pix[order], pix[dup], skip]).astype(np.int64)
+    cl = np.concatenate([cls[order], cls[dup], np.full(n_skip, -1)]).astype(np.int8)
+    return pts, cl
+
+
+@pytest.mark.parametrize("cfg,scale", [(1, 1.0), (5, 0.05)])
+def test_fit_points(dev, cfg, scale):
+    say(f"fit from a point list, cfg{cfg} at scale {scale}")
+    import paper_1612_06457_amd as cx
+    c = make_case(cfg, scale=scale)
+    pts, cl = _points(c, np.random.default_rng(cfg))
+    ref = oracle.cva_fit_points(c.cube, pts, cl, c.K)
+    got = cx.cva_fit_points(_t(c.cube, dev), _t(pts, dev), _t(cl, dev), c.K)
+    assert got.counts.tolist() == ref["counts"].tolist()
+    assert rel_max(got.class_means, ref["class_means"]) <= 1e-7
+    assert rel_max(got.Sw, ref["Sw"]) <= TOL_S
+    assert rel_max(got.Sb, ref["Sb"]) <= TOL_S
+    assert np.max(np.abs(got.eigvals - ref["eigvals"]) / ref["eigvals"]) <= TOL_LAM
+    check_vectors(got.W, ref["W"], ref["eigvals"])
+
+
+def test_fit_points_errors(dev):
+    say("fit from a point list: errors")
+    import paper_1612_06457_amd as cx
+    c = make_case(1, scale=0.2)
+    pts, cl = _points(c, np.random.default_rng(3), n_dup=10, n_skip=5)
+    cube = _t(c.cube, dev)
+    out = pts.copy()
+    out[7] = c.H * c.W                       # one past the last pixel
+    with pytest.raises(cx.CvamxError) as e:
+        cx.cva_fit_points(cube, _t(out, dev), _t(cl, dev), c.K)
+    assert e.value.status == -1
+    badc = cl.copy()
+    badc[3] = c.K
+    with pytest.raises(cx.CvamxError) as e:
+        cx.cva_fit_points(cube, _t(pts, dev), _t(badc, dev), c.K)
+    assert e.value.status == -1
+    # a class that no entry names
+    none = cl.copy()
+    none[none == 2] = -1
+    with pytest.raises(cx.CvamxError) as e:
+        cx.cva_fit_points(cube, _t(pts, dev), _t(none, dev), c.K)
+    assert e.value.status == -3
+
+
 # ---------------------------------------------------------------- soft label
 
 def _soft_parity(X, w, dev, gtol=1e-4):

@@ -167,6 +167,24 @@ def test_argument_checks_without_a_device():
         assert lib.cva_soft_forward(ctx, X, X, 100, 8, 3, 0, 0.0, buf, buf, buf, buf, buf, None) == L.E_DEVICE
         assert lib.cva_soft_backward(ctx, X, buf, buf, buf, buf, 100, 8, 3, float("inf"), X, None) == L.E_INVALID_ARG
         assert lib.cva_soft_backward(ctx, X, buf, buf, buf, buf, 100, 8, 3, 1.0, X, None) == L.E_DEVICE
+        assert lib.cva_soft_forward(ctx, X, ctypes.c_void_p(0x30008), 100, 8, 3, 0, 0.0, buf, buf, buf, buf,
+                                    buf, None) == L.E_UNSUPPORTED
+        # fit from a point list
+        pts, cls = ctypes.c_void_p(0x40000), ctypes.c_void_p(0x50000)
+
+        def fitp(pixels=pts, classes=cls, N=100, K=3, n_comp=2):
+            return lib.cva_fit_points(ctx, ctypes.byref(good), pixels, classes, N, K, 0, 0.0, n_comp,
+                                      buf, buf, buf, i64, None, None, None, None)
+
+        assert fitp(pixels=None) == L.E_INVALID_ARG
+        assert fitp(classes=None) == L.E_INVALID_ARG
+        assert fitp(N=0) == L.E_INVALID_ARG
+        assert fitp(N=1 << 31) == L.E_INVALID_ARG
+        assert fitp(K=1) == L.E_INVALID_ARG
+        assert fitp(n_comp=3) == L.E_INVALID_ARG
+        assert fitp(classes=ctypes.c_void_p(0x50008)) == L.E_UNSUPPORTED
+        assert fitp(pixels=ctypes.c_void_p(0x40004)) == L.E_UNSUPPORTED
+        assert fitp() == L.E_DEVICE
     finally:
         lib.cvamx_destroy(ctx)
     assert lib.cvamx_status_str(L.E_NOT_PD) == b"within-class scatter not positive definite"

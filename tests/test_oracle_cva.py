@@ -332,3 +332,48 @@ def test_fit_errors():
         oracle.cva_fit(c2, labels, 3)
     with pytest.raises(ValueError):
         oracle.cva_fit(cube, labels, 3, n_comp=3)
+
+
+def test_fit_from_points_matches_label_map_in_any_order():
+    """A list of the labelled pixels, in any order, gives the label-map fit;
+    entries marked -1 are skipped."""
+    rng = np.random.default_rng(61)
+    cube = rng.integers(0, 4096, size=(9, 11, 5)).astype(np.uint16)
+    labels = rng.integers(-1, 3, size=(9, 11)).astype(np.int8)
+    ref = oracle.cva_fit(cube, labels, 3)
+    pix = np.flatnonzero(labels.reshape(-1) >= 0)
+    cls = labels.reshape(-1)[pix]
+    order = rng.permutation(pix.size)
+    extra = rng.integers(0, 99, size=7)                  # skipped entries
+    pts = np.concatenate([pix[order], extra])
+    cl = np.concatenate([cls[order], np.full(7, -1, np.int8)])
+    got = oracle.cva_fit_points(cube, pts, cl, 3)
+    np.testing.assert_array_equal(got["counts"], ref["counts"])
+    np.testing.assert_allclose(got["Sw"], ref["Sw"], rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(got["Sb"], ref["Sb"], rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(got["eigvals"], ref["eigvals"], rtol=1e-10)
+    np.testing.assert_allclose(got["W"], ref["W"], rtol=1e-8, atol=1e-12)
+
+
+def test_fit_from_points_repeated_list_doubles_the_scatters():
+    """Listing every point twice doubles n_k, S_w and S_b: the eigenvalues of
+    S_b w = lambda S_w w are unchanged and W (with w^T S_w w = 1) shrinks by
+    1/sqrt(2)."""
+    rng = np.random.default_rng(62)
+    cube = rng.normal(1000.0, 50.0, size=(6, 8, 4))
+    pix = rng.permutation(48)[:30]
+    cls = rng.integers(0, 3, size=30).astype(np.int8)
+    cls[:3] = [0, 1, 2]
+    one = oracle.cva_fit_points(cube, pix, cls, 3)
+    two = oracle.cva_fit_points(cube, np.concatenate([pix, pix]), np.concatenate([cls, cls]), 3)
+    np.testing.assert_array_equal(two["counts"], 2 * one["counts"])
+    np.testing.assert_allclose(two["Sw"], 2 * one["Sw"], rtol=1e-12)
+    np.testing.assert_allclose(two["Sb"], 2 * one["Sb"], rtol=1e-12)
+    np.testing.assert_allclose(two["eigvals"], one["eigvals"], rtol=1e-10)
+    np.testing.assert_allclose(two["W"], one["W"] / np.sqrt(2.0), rtol=1e-8, atol=1e-14)
+
+
+def test_fit_from_points_rejects_pixels_outside_the_page():
+    cube = np.zeros((4, 4, 3), np.uint16)
+    with pytest.raises(ValueError):
+        oracle.cva_fit_points(cube, np.array([0, 16]), np.array([0, 1], np.int8), 2)
