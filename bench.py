@@ -35,37 +35,60 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(case, min_seconds: float = 10.0):
     """The FP64 oracle, as it stands, on the whole page: CVA fit on all its
     training pixels, then projection + min-max stretch of every pixel,
-    repeated until at least `min_seconds` of CPU work.  Returns
-    (Gpix*band/s, seconds per page, threads, sample)."""
+    repeated until at least `min_seconds` of CPU work; then one page on a
+    single thread.  Returns (Gpix*band/s, seconds per page, threads, sample,
+    single-thread seconds per page)."""
     import oracle
+
+    def one_page():
+        fit = oracle.cva_fit(case.cube, case.labels, case.K)
+        oracle.cva_project(case.cube, fit["W"], fit["mean"])
+
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count() or 1
     reps, t0 = 0, time.perf_counter()
     while True:
-        fit = oracle.cva_fit(case.cube, case.labels, case.K)
-        oracle.cva_project(case.cube, fit["W"], fit["mean"])
+        one_page()
         reps += 1
         dt = time.perf_counter() - t0
         if dt >= min_seconds or reps >= 10:
             break
     per = dt / reps
+    per1 = None
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            one_page()
+            per1 = time.perf_counter() - t1
     pixbands = case.H * case.W * case.B
     sample = (f"whole {case.H}x{case.W}x{case.B} page, {reps} repetition(s) of CVA fit on "
-              f"{int((case.labels >= 0).sum())} training pixels + projection + stretch of every pixel")
-    return pixbands / per / 1e9, per, threads, sample
+              f"{int((case.labels >= 0).sum())} training pixels + projection + stretch of every pixel, "
+              f"on {_cpu_model()}")
+    return pixbands / per / 1e9, per, threads, sample, per1
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "f16x3"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -145,7 +168,9 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     per = {p: float(np.median([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)]))
            for i, p in enumerate(phases)}
-    mean_fp = float(np.mean([evs[k][0].elapsed_time(evs[k][2]) for k in range(args.steps)]))
+    fp = [evs[k][0].elapsed_time(evs[k][2]) for k in range(args.steps)]
+    mean_fp = float(np.mean(fp))
+    median_fp = float(np.median(fp))
     value = P * B / (mean_fp * 1e-3) / 1e9
 
     # roofline of the dominant kernel (the projection pass that writes the
@@ -171,7 +196,7 @@ def main():
         "range_pass": {"avg_launch_ms": round(avg_rng, 4),
                        "achieved_GBps": round(cube_bytes / (avg_rng * 1e-3) / 1e9, 1)},
         "fit_plus_project": {"algorithmic_MB": round(fit_proj_bytes / 1e6, 1),
-                             "ms": round(mean_fp, 4),
+                             "ms": round(mean_fp, 4), "median_ms": round(median_fp, 4),
                              "frac_of_8TBps": round(fit_proj_bytes / (mean_fp * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
     traffic_file = os.path.join(ROOT, "profiles", "traffic_project_stretch.json")
@@ -215,9 +240,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if not args.no_cpu:
-        gbs, dt, threads, sample = cpu_baseline(case, args.cpu_seconds)
+        gbs, dt, threads, sample, dt1 = cpu_baseline(case, args.cpu_seconds)
         out["cpu_baseline"] = {"value": round(gbs, 4), "unit": "Gpix*band/s", "cores": threads,
                                "kind": "oracle", "sample": sample, "seconds_per_page": round(dt, 2)}
+        if dt1 is not None:
+            out["cpu_baseline"]["single_thread_seconds_per_page"] = round(dt1, 2)
     print(json.dumps(out), flush=True)
 
 
