@@ -159,6 +159,69 @@ int pca_project(cvamx_ctx* ctx, const cvamx_cube* cube, const double* V,
                 const double* mean, int32_t n_comp, uint8_t* images,
                 float* range, void* stream);
 
+/* ---- float images, rescaling modes, 16-bit output, colour ---------------- */
+
+/* The float images themselves: y_jp = w_j^T (x_p - center) for every pixel
+ * (paper Section 2: the regression coefficients multiplied with every band
+ * give one array of floating point numbers per component).  Works for the
+ * (W, mean) of cva_fit and the (V, mean) of pca_fit alike; the values are
+ * the very ones whose min/max and stretch cva_project takes.
+ *   W, center, n_comp   as for cva_project
+ *   y        device, n_comp x height x width float32 (planar), 4-byte
+ *            aligned (16-byte aligned with height*width % 4 == 0 for
+ *            full-width stores)
+ * Asynchronous on `stream`; W and center are read before the call returns.
+ * Misaligned y: CVAMX_E_UNSUPPORTED. */
+int cvamx_project_float(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W,
+                        const double* center, int32_t n_comp, float* y,
+                        void* stream);
+
+/* Rescaling modes (paper Section 2, the three ways of mapping the float
+ * arrays onto 0..255): */
+enum {
+  CVAMX_STRETCH_MINMAX = 1,     /* a_j, b_j = min and max over the page */
+  CVAMX_STRETCH_TRAINING = 2,   /* a_j, b_j = min and max over the training pixels */
+  CVAMX_STRETCH_PERCENTILE = 3  /* a_j, b_j = the pct-th and (100 - pct)-th
+                                   percentiles, linear interpolation between
+                                   order statistics at (P - 1) q as NumPy's
+                                   default; the values beyond are clamped */
+};
+
+/* Stretch planar float images to 8 or 16 bits:
+ *   q_jp = clamp(floor(L (y_jp - a_j) / (b_j - a_j) + 1/2), 0, L),
+ *   L = 255 or 65535, evaluated in FP64 operation by operation (exact for
+ *   the FP32 input values; cva_project evaluates the same map in FP32 as
+ *   floor(y s + o), so mode 1 here finds its range exactly and its bytes
+ *   within one level); b_j = a_j gives q = 0.
+ *   y        device, n_comp x P float32 (from cvamx_project_float),
+ *            4-byte aligned
+ *   mode     CVAMX_STRETCH_*
+ *   pct      mode 3: percentage in [0, 50) (the paper names 0.01, 0.1, 1
+ *            and 5); ignored otherwise
+ *   train_pixels, n_train   mode 2: device int64 pixel indices
+ *            (0..P-1, n_train >= 1, 8-byte aligned); ignored otherwise
+ *   bits     8 (out is uint8) or 16 (out is uint16)
+ *   out      device, n_comp x P planar, aligned to its element size
+ *   range    host, 2*n_comp float64 (a_j, b_j pairs) or NULL
+ * Order statistics are exact (radix select on the FP32 values); a_j, b_j
+ * are interpolated in FP64.  Asynchronous on `stream` except that mode 2
+ * synchronises to check the pixel list (a pixel outside 0..P-1:
+ * CVAMX_E_INVALID_ARG, nothing written) and a non-NULL range
+ * synchronises. */
+int cvamx_stretch(cvamx_ctx* ctx, const float* y, int64_t P, int32_t n_comp,
+                  int32_t mode, double pct, const int64_t* train_pixels,
+                  int64_t n_train, int32_t bits, void* out, double* range,
+                  void* stream);
+
+/* Interleave three 8-bit planes into an RGB image (paper Section 2: three
+ * grayscale images combined, the one with the clearest underwriting usually
+ * in the green channel; Section 4: that image may fill two channels).
+ *   r, g, b  device, P uint8 each, or NULL for an all-zero channel
+ *   rgb      device, 3*P uint8: rgb[3p + c]
+ * Asynchronous on `stream`. */
+int cvamx_compose_rgb(cvamx_ctx* ctx, const uint8_t* r, const uint8_t* g,
+                      const uint8_t* b, int64_t P, uint8_t* rgb, void* stream);
+
 /* ---- soft-label CVA ------------------------------------------------------ */
 
 /* Fisher criterion J = sum of the C = min(K-1, B) generalized eigenvalues

@@ -31,7 +31,7 @@ are not unique, and are not produced (parity unpinned by construction).
 from .cva import (class_counts, class_index_lists, class_moments, within_scatter,
                   between_scatter, total_scatter, generalized_eig, sign_rule,
                   cva_fit, cva_fit_points, project, cva_project)
-from .stretch import stretch_minmax, stretch_training_range, stretch_percentile
+from .stretch import compose_rgb, stretch_minmax, stretch_training_range, stretch_percentile
 from .pca import pca_fit, pca_project
 from .soft import soft_moments, soft_fit, soft_grad, soft_delta_J
 
@@ -39,6 +39,6 @@ __all__ = [
     "class_counts", "class_index_lists", "class_moments", "within_scatter",
     "between_scatter", "total_scatter", "generalized_eig", "sign_rule",
     "cva_fit", "cva_fit_points", "project", "cva_project", "stretch_minmax",
-    "stretch_training_range", "stretch_percentile", "pca_fit", "pca_project",
+    "stretch_training_range", "stretch_percentile", "compose_rgb", "pca_fit", "pca_project",
     "soft_moments", "soft_fit", "soft_grad", "soft_delta_J",
 ]

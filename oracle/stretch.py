@@ -1,4 +1,6 @@
-"""FP64 rescale of projected float images to 8 bits.
+"""FP64 rescale of projected float images to 8 or 16 bits, and the RGB
+composite.  Test infrastructure: only the tests, the smoke check and the
+benchmark's CPU baseline use this package.
 
 Paper, Section 2 (the three rescaling paragraphs):
 
@@ -15,10 +17,20 @@ q = 0 when b = a; in modes 2 and 3 values outside [a, b] clamp to 0 or 255;
 mode 3 takes a and b as the p-th and (100-p)-th percentiles with NumPy's
 linear interpolation.
 
+The 16-bit output (paper Section 2, the C implementation writes 8- and
+16-bit images) is the same map with 65535 levels.  The colour image (paper
+Section 2: three grayscale images combined as red, green and blue; Section
+4: one image may fill two channels) interleaves three 8-bit planes pixel
+by pixel; a missing channel is zero.
+
 Pinned by tests/test_oracle_cva.py: q(argmin) = 0 and q(argmax) = 255
 exactly, q is monotone in y, invariant to positive scaling and shift of y,
 and a sign flip maps q to 255 - q up to one grey level; a brute-force
-per-element loop gives the same bytes.
+per-element loop gives the same bytes, for 255 and for 65535 levels; the
+percentiles of a shuffled arithmetic sequence are known in closed form, the
+0-th percentile is the minimum and a percentile that falls between two
+order statistics interpolates them; the 16-bit image divided by 257 is the
+8-bit one within a level; the colour image holds each plane in its channel.
 """
 from __future__ import annotations
 
@@ -57,3 +69,14 @@ def stretch_percentile(y: np.ndarray, pct: float, levels: int = 255):
     a = np.percentile(y, pct, axis=0, method="linear")
     b = np.percentile(y, 100.0 - pct, axis=0, method="linear")
     return _quantise(y, a, b, levels), a, b
+
+
+def compose_rgb(r, g, b) -> np.ndarray:
+    """Planes of one shape (None = all zero) -> shape + (3,) uint8."""
+    planes = [p for p in (r, g, b) if p is not None]
+    shape = np.shape(planes[0])
+    out = np.zeros(tuple(shape) + (3,), dtype=np.uint8)
+    for c, p in enumerate((r, g, b)):
+        if p is not None:
+            out[..., c] = np.asarray(p, dtype=np.uint8)
+    return out

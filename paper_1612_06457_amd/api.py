@@ -149,6 +149,91 @@ def cva_project(cube: torch.Tensor, W, center, out: Optional[torch.Tensor] = Non
     return (out, rng) if return_range else out
 
 
+def project_float(cube: torch.Tensor, W, center, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """The float images y_j = w_j^T (x - center) of every pixel (the (W, mean)
+    of a CVA fit or the (V, mean) of a PCA fit) as an n x H x W float32
+    tensor: the values whose min/max and stretch cva_project takes."""
+    c = _cube(cube)
+    B = c.bands
+    W = _f64(W)
+    if W.ndim != 2 or W.shape[0] != B:
+        raise ValueError("W must be B x n")
+    n = W.shape[1]
+    center = _f64(center, B)
+    H, Wd = cube.shape[0], cube.shape[1]
+    if out is None:
+        out = torch.empty((n, H, Wd), dtype=torch.float32, device=cube.device)
+    elif out.dtype != torch.float32 or tuple(out.shape) != (n, H, Wd) or not out.is_contiguous() \
+            or out.device != cube.device:
+        raise ValueError("out must be a contiguous float32 n x H x W tensor on the cube's device")
+    dev = _dev_index(cube)
+    ctx = context(dev)
+    st = lib().cvamx_project_float(ctx, ctypes.byref(c), _ptr(W), _ptr(center), n, _ptr(out),
+                                   _stream(cube.device))
+    check(st, ctx)
+    return out
+
+
+STRETCH_MODES = {"minmax": 1, "training": 2, "percentile": 3}
+
+
+def stretch(y: torch.Tensor, mode: str = "minmax", pct: float = 1.0, train_pixels: Optional[torch.Tensor] = None,
+            bits: int = 8, out: Optional[torch.Tensor] = None, return_range: bool = False):
+    """Stretch planar float images (n x ... float32, e.g. from project_float)
+    to uint8 (bits=8) or uint16 (bits=16) planes of the same shape.
+    mode "minmax": each plane's own min/max; "training": the min/max over
+    train_pixels (int64 flat pixel indices on the same device); "percentile":
+    the pct-th and (100 - pct)-th percentiles, values beyond them clamped.
+    With return_range, also the n x 2 float64 (a_j, b_j)."""
+    if y.dtype != torch.float32 or y.dim() < 2 or not y.is_contiguous():
+        raise ValueError("y must be a contiguous float32 n x ... tensor")
+    if mode not in STRETCH_MODES:
+        raise ValueError(f"mode must be one of {sorted(STRETCH_MODES)}")
+    if bits not in (8, 16):
+        raise ValueError("bits must be 8 or 16")
+    n = y.shape[0]
+    P = y[0].numel()
+    odt = torch.uint8 if bits == 8 else torch.uint16
+    if out is None:
+        out = torch.empty(y.shape, dtype=odt, device=y.device)
+    elif out.dtype != odt or tuple(out.shape) != tuple(y.shape) or not out.is_contiguous() or out.device != y.device:
+        raise ValueError("out must be a contiguous tensor of y's shape, uint8 or uint16 per bits, on y's device")
+    n_train = 0
+    if mode == "training":
+        if train_pixels is None or train_pixels.dtype != torch.int64 or train_pixels.dim() != 1:
+            raise ValueError("mode 'training' needs train_pixels, an int64 vector")
+        if train_pixels.device != y.device or not train_pixels.is_contiguous():
+            raise ValueError("train_pixels must be contiguous and on y's device")
+        n_train = int(train_pixels.numel())
+    else:
+        train_pixels = None
+    rng = np.empty((n, 2)) if return_range else None
+    dev = _dev_index(y)
+    ctx = context(dev)
+    st = lib().cvamx_stretch(ctx, _ptr(y), P, n, STRETCH_MODES[mode], float(pct), _ptr(train_pixels), n_train,
+                             bits, _ptr(out), _ptr(rng), _stream(y.device))
+    check(st, ctx)
+    return (out, rng) if return_range else out
+
+
+def compose_rgb(r: Optional[torch.Tensor], g: Optional[torch.Tensor], b: Optional[torch.Tensor]) -> torch.Tensor:
+    """Interleave three uint8 planes of one shape (None = an all-zero channel)
+    into a ... x 3 uint8 RGB image."""
+    planes = [t for t in (r, g, b) if t is not None]
+    if not planes:
+        raise ValueError("at least one channel must be given")
+    ref = planes[0]
+    for t in planes:
+        if t.dtype != torch.uint8 or t.shape != ref.shape or t.device != ref.device or not t.is_contiguous():
+            raise ValueError("channels must be contiguous uint8 tensors of one shape on one device")
+    rgb = torch.empty(tuple(ref.shape) + (3,), dtype=torch.uint8, device=ref.device)
+    dev = _dev_index(ref)
+    ctx = context(dev)
+    st = lib().cvamx_compose_rgb(ctx, _ptr(r), _ptr(g), _ptr(b), int(ref.numel()), _ptr(rgb), _stream(ref.device))
+    check(st, ctx)
+    return rgb
+
+
 def pca_fit(cube: torch.Tensor, mask: Optional[torch.Tensor] = None, n_comp: int = 3,
             precision: str = "fp32"):
     """Covariance PCA of the page (or of the pixels where mask != 0).

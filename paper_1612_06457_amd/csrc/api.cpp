@@ -18,7 +18,7 @@
 
 namespace {
 
-enum Buf { B_TILECNT, B_IDX, B_PART, B_RES, B_PROJPART, B_FIRST, B_MCF, B_COUNT };
+enum Buf { B_TILECNT, B_IDX, B_PART, B_RES, B_PROJPART, B_FIRST, B_MCF, B_SPART, B_SHIST, B_SFIX, B_COUNT };
 
 }  // namespace
 
@@ -225,55 +225,66 @@ struct FitLayout {
   }
 };
 
+// Wave tiles of the projection kernels, and their block count.
+int proj_nblocks(cvamx_ctx* ctx, const cvamx_cube* cube) {
+  const int B = (int)cube->bands;
+  const int64_t P = cube->height * cube->width;
+  const int g2 = (cube->dtype != CVAMX_F32 && (B & 1)) ? 2 : 1;
+  const int64_t nt = (P + 64 * g2 - 1) / (64 * g2);
+  const int nblocks = ctx->proj_blocks > 0 ? ctx->proj_blocks : ctx->num_cu * 8;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(nblocks, (nt + cvx::kWaves - 1) / cvx::kWaves));
+}
+
+// The kernel arguments of components g0 .. g0 + nc - 1.
+void make_proj_args(const cvamx_cube* cube, const double* W, const double* center, int n_comp, int g0, int nc,
+                    cvx::ProjArgs& a) {
+  const int B = (int)cube->bands;
+  std::memset(&a, 0, sizeof(a));
+  std::vector<double> c(B);
+  for (int b = 0; b < B; ++b) {
+    // uint16 pages: an integer centre, passed as 2^23 + c (exact in FP32),
+    // which the kernels subtract from the bit-built float 2^23 + x
+    // bf16 / fp16 pages: a centre of the page's own type, so x - c has at
+    // most 16 (bf16) or 22 (fp16) significant bits and splits exactly
+    switch (cube->dtype) {
+      case CVAMX_U16: c[b] = std::nearbyint(center[b]); break;
+      case CVAMX_BF16: c[b] = bf16_round(center[b]); break;
+      case CVAMX_F16: c[b] = f16_round(center[b]); break;
+      default: c[b] = (double)(float)center[b]; break;
+    }
+    a.c[b] = (cube->dtype == CVAMX_U16) ? (float)(8388608.0 + c[b]) : (float)c[b];
+  }
+  for (int j = 0; j < nc; ++j) {
+    double off = 0.0;
+    for (int b = 0; b < B; ++b) {
+      const double wv = W[(size_t)b * n_comp + g0 + j];
+      a.w[b * nc + j] = (float)wv;
+      off += wv * (c[b] - center[b]);
+      // uint16 pages: the kernels multiply 1024 + (x mod 1024) rather than
+      // its centred value, so the constant 1024 + (c mod 1024) comes off here
+      if (cube->dtype == CVAMX_U16) off -= (double)a.w[b * nc + j] * (1024.0 + std::fmod(c[b], 1024.0));
+    }
+    a.off[j] = (float)off;
+    // a power of two that brings the largest |W[b][j]| into [16, 32)
+    double wmax = 0.0;
+    for (int b = 0; b < B; ++b) wmax = std::max(wmax, std::fabs((double)a.w[b * nc + j]));
+    int ex = 0;
+    if (wmax > 0.0) std::frexp(wmax, &ex);
+    a.scale[j] = (float)std::ldexp(1.0, wmax > 0.0 ? 5 - ex : 0);
+  }
+}
+
 int proj_groups(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const double* center,
                 int n_comp, uint8_t* images, hipStream_t s) {
   const int B = (int)cube->bands;
   const int64_t P = cube->height * cube->width;
-  const int S = (cube->dtype == CVAMX_F32) ? B : ((B & 1) ? B : B / 2);
-  const int g2 = (cube->dtype != CVAMX_F32 && (B & 1)) ? 2 : 1;
-  const int64_t nt = (P + 64 * g2 - 1) / (64 * g2);
-  int nblocks = ctx->proj_blocks > 0 ? ctx->proj_blocks : ctx->num_cu * 8;
-  nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(nblocks, (nt + cvx::kWaves - 1) / cvx::kWaves));
-  (void)S;
+  const int nblocks = proj_nblocks(ctx, cube);
   // block partials: 16 floats (VALU kernels) or 32 (matrix-core kernels)
   if (int st = ensure(ctx, B_PROJPART, (size_t)nblocks * 32 * sizeof(float))) return st;
   for (int g0 = 0; g0 < n_comp; g0 += 8) {
-    const int nc = std::min(8, n_comp - g0);
-    const int NC = nc;   // the kernels are instantiated for 1..8 components
+    const int nc = std::min(8, n_comp - g0);   // the kernels are instantiated for 1..8 components
     cvx::ProjArgs a;
-    std::memset(&a, 0, sizeof(a));
-    std::vector<double> c(B);
-    for (int b = 0; b < B; ++b) {
-      // uint16 pages: an integer centre, passed as 2^23 + c (exact in FP32),
-      // which the kernels subtract from the bit-built float 2^23 + x
-      // bf16 / fp16 pages: a centre of the page's own type, so x - c has at
-      // most 16 (bf16) or 22 (fp16) significant bits and splits exactly
-      switch (cube->dtype) {
-        case CVAMX_U16: c[b] = std::nearbyint(center[b]); break;
-        case CVAMX_BF16: c[b] = bf16_round(center[b]); break;
-        case CVAMX_F16: c[b] = f16_round(center[b]); break;
-        default: c[b] = (double)(float)center[b]; break;
-      }
-      a.c[b] = (cube->dtype == CVAMX_U16) ? (float)(8388608.0 + c[b]) : (float)c[b];
-    }
-    for (int j = 0; j < nc; ++j) {
-      double off = 0.0;
-      for (int b = 0; b < B; ++b) {
-        const double wv = W[(size_t)b * n_comp + g0 + j];
-        a.w[b * NC + j] = (float)wv;
-        off += wv * (c[b] - center[b]);
-        // uint16 pages: the kernels multiply 1024 + (x mod 1024) rather than
-        // its centred value, so the constant 1024 + (c mod 1024) comes off here
-        if (cube->dtype == CVAMX_U16) off -= (double)a.w[b * NC + j] * (1024.0 + std::fmod(c[b], 1024.0));
-      }
-      a.off[j] = (float)off;
-      // a power of two that brings the largest |W[b][j]| into [16, 32)
-      double wmax = 0.0;
-      for (int b = 0; b < B; ++b) wmax = std::max(wmax, std::fabs((double)a.w[b * NC + j]));
-      int ex = 0;
-      if (wmax > 0.0) std::frexp(wmax, &ex);
-      a.scale[j] = (float)std::ldexp(1.0, wmax > 0.0 ? 5 - ex : 0);
-    }
+    make_proj_args(cube, W, center, n_comp, g0, nc, a);
     static const char* kRangeName[9] = {"", "project_range_nc1", "project_range_nc2", "project_range_nc3",
                                         "project_range_nc4", "project_range_nc5", "project_range_nc6",
                                         "project_range_nc7", "project_range_nc8"};
@@ -295,11 +306,11 @@ int proj_groups(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const d
   return 0;
 }
 
-int project_common(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const double* center,
-                   int32_t n_comp, uint8_t* images, float* range, void* stream) {
-  if (!ctx) return CVAMX_E_INVALID_ARG;
+// Checks shared by the projection entry points.
+int check_proj_args(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const double* center,
+                    int32_t n_comp, const void* out) {
   if (int st = check_cube(ctx, cube)) return st;
-  if (!W || !center || !images) return fail(ctx, CVAMX_E_INVALID_ARG, "W, center and images must be non-NULL");
+  if (!W || !center || !out) return fail(ctx, CVAMX_E_INVALID_ARG, "W, center and the output must be non-NULL");
   if (n_comp < 1 || n_comp > CVAMX_MAX_BANDS)
     return fail(ctx, CVAMX_E_INVALID_ARG, "n_comp must lie in 1..CVAMX_MAX_BANDS");
   const int B = (int)cube->bands;
@@ -307,6 +318,13 @@ int project_common(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, cons
     if (!std::isfinite(W[i])) return fail(ctx, CVAMX_E_INVALID_ARG, "W has a non-finite entry");
   for (int b = 0; b < B; ++b)
     if (!std::isfinite(center[b])) return fail(ctx, CVAMX_E_INVALID_ARG, "center has a non-finite entry");
+  return 0;
+}
+
+int project_common(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const double* center,
+                   int32_t n_comp, uint8_t* images, float* range, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (int st = check_proj_args(ctx, cube, W, center, n_comp, images)) return st;
   if (int st = check_device(ctx)) return st;
   hipStream_t s = (hipStream_t)stream;
   if (int st = proj_groups(ctx, cube, W, center, n_comp, images, s)) return st;
@@ -575,6 +593,135 @@ int cva_project(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const d
 int pca_project(cvamx_ctx* ctx, const cvamx_cube* cube, const double* V, const double* mean,
                 int32_t n_comp, uint8_t* images, float* range, void* stream) {
   return project_common(ctx, cube, V, mean, n_comp, images, range, stream);
+}
+
+int cvamx_project_float(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const double* center,
+                        int32_t n_comp, float* y, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (int st = check_proj_args(ctx, cube, W, center, n_comp, y)) return st;
+  if ((reinterpret_cast<uintptr_t>(y) & 3u) != 0) return fail(ctx, CVAMX_E_UNSUPPORTED, "y must be 4-byte aligned");
+  if (int st = check_device(ctx)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int B = (int)cube->bands;
+  const int64_t P = cube->height * cube->width;
+  const int nblocks = proj_nblocks(ctx, cube);
+  for (int g0 = 0; g0 < n_comp; g0 += 8) {
+    const int nc = std::min(8, n_comp - g0);
+    cvx::ProjArgs a;
+    make_proj_args(cube, W, center, n_comp, g0, nc, a);
+    prof_begin(ctx, s, "project_float");
+    hipError_t e = cvx::launch_project_float(cube->dtype, cube->data, B, P, nc, a, nblocks, y + (int64_t)g0 * P, s);
+    prof_end(ctx, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "project float launch");
+  }
+  return 0;
+}
+
+int cvamx_stretch(cvamx_ctx* ctx, const float* y, int64_t P, int32_t n_comp, int32_t mode, double pct,
+                  const int64_t* train_pixels, int64_t n_train, int32_t bits, void* out, double* range,
+                  void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (!y || !out) return fail(ctx, CVAMX_E_INVALID_ARG, "y and out must be non-NULL");
+  if (P < 1 || P >= (int64_t(1) << 31) - 1) return fail(ctx, CVAMX_E_INVALID_ARG, "P must lie in 1..2^31-2");
+  if (n_comp < 1 || n_comp > CVAMX_MAX_BANDS)
+    return fail(ctx, CVAMX_E_INVALID_ARG, "n_comp must lie in 1..CVAMX_MAX_BANDS");
+  if (bits != 8 && bits != 16) return fail(ctx, CVAMX_E_INVALID_ARG, "bits must be 8 or 16");
+  if (mode < CVAMX_STRETCH_MINMAX || mode > CVAMX_STRETCH_PERCENTILE)
+    return fail(ctx, CVAMX_E_INVALID_ARG, "unknown stretch mode");
+  if (mode == CVAMX_STRETCH_TRAINING && (!train_pixels || n_train < 1))
+    return fail(ctx, CVAMX_E_INVALID_ARG, "mode 2 needs a non-empty list of training pixels");
+  if (mode == CVAMX_STRETCH_PERCENTILE && !(std::isfinite(pct) && pct >= 0.0 && pct < 50.0))
+    return fail(ctx, CVAMX_E_INVALID_ARG, "pct must lie in [0, 50)");
+  if ((reinterpret_cast<uintptr_t>(y) & 3u) != 0 || (reinterpret_cast<uintptr_t>(out) & (bits / 8 - 1)) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "y and out must be aligned to their element size");
+  if (mode == CVAMX_STRETCH_TRAINING && (reinterpret_cast<uintptr_t>(train_pixels) & 7u) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "train_pixels must be 8-byte aligned");
+  if (int st = check_device(ctx)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // fixed state: range (2 x 64 doubles), selection (64 x kSelTargets uint2), error flag
+  const size_t ab_off = 0, sel_off = ab_off + 1024, err_off = sel_off + 8 * 64 * cvx::kSelTargets;
+  if (int st = ensure(ctx, B_SFIX, err_off + 16)) return st;
+  char* fix = static_cast<char*>(ctx->buf[B_SFIX]);
+  double* ab = reinterpret_cast<double*>(fix + ab_off);
+  uint2* sel = reinterpret_cast<uint2*>(fix + sel_off);
+  int32_t* err = reinterpret_cast<int32_t*>(fix + err_off);
+  hipError_t e;
+  int nb = 1;
+  double g_lo = 0.0, g_hi = 0.0;
+  if (mode != CVAMX_STRETCH_PERCENTILE) {
+    const int64_t m = mode == CVAMX_STRETCH_TRAINING ? n_train : P;
+    nb = cvx::stretch_reduce_blocks(m, n_comp, ctx->num_cu);
+    if (int st = ensure(ctx, B_SPART, (size_t)n_comp * nb * 2 * sizeof(float))) return st;
+    if (mode == CVAMX_STRETCH_TRAINING) {
+      e = cvx::launch_zero_u32(reinterpret_cast<uint32_t*>(err), 1, s);
+      if (e != hipSuccess) return hip_fail(ctx, e, "flag clear launch");
+    }
+    prof_begin(ctx, s, "plane_minmax");
+    e = cvx::launch_plane_minmax(y, P, n_comp, mode == CVAMX_STRETCH_TRAINING ? train_pixels : nullptr, n_train, nb,
+                                 (float*)ctx->buf[B_SPART], err, s);
+    prof_end(ctx, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "min/max launch");
+    if (mode == CVAMX_STRETCH_TRAINING) {
+      if (int st = ensure_pinned(ctx, 16)) return st;
+      HIP_TRY(hipMemcpyAsync(ctx->pinned, err, 4, hipMemcpyDeviceToHost, s), "flag copy");
+      HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+      int32_t flag = 0;
+      std::memcpy(&flag, ctx->pinned, 4);
+      if (flag & 4) return fail(ctx, CVAMX_E_INVALID_ARG, "a training pixel lies outside 0..P-1");
+    }
+  } else {
+    // linear interpolation between the order statistics around the virtual
+    // index h = (P - 1) q, evaluated as NumPy does for its linear method
+    auto vindex = [&](double q, uint32_t& r0, uint32_t& r1, double& g) {
+      const double h = (double)P * q + (1.0 - q) - 1.0;
+      double f = std::floor(h);
+      if (h >= (double)(P - 1)) {
+        r0 = r1 = (uint32_t)(P - 1);
+        g = 0.0;
+        return;
+      }
+      if (h < 0.0) f = 0.0;
+      r0 = (uint32_t)f;
+      r1 = (uint32_t)std::min<int64_t>((int64_t)f + 1, P - 1);
+      g = h < 0.0 ? 0.0 : h - f;
+    };
+    uint32_t ranks[cvx::kSelTargets];
+    vindex(pct / 100.0, ranks[0], ranks[1], g_lo);
+    vindex((100.0 - pct) / 100.0, ranks[2], ranks[3], g_hi);
+    nb = cvx::stretch_reduce_blocks(P, n_comp, ctx->num_cu);
+    if (int st = ensure(ctx, B_SHIST, (size_t)2 * n_comp * cvx::kSelTargets * 256 * 4)) return st;
+    prof_begin(ctx, s, "select");
+    e = cvx::launch_select(y, P, n_comp, ranks, nb, sel, (uint32_t*)ctx->buf[B_SHIST], s);
+    prof_end(ctx, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "select launch");
+  }
+  e = cvx::launch_stretch_finish(mode, n_comp, nb, (const float*)ctx->buf[B_SPART], sel, g_lo, g_hi, ab, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "stretch range launch");
+  prof_begin(ctx, s, "stretch_planes");
+  e = cvx::launch_stretch_planes(y, P, n_comp, ab, bits, out, ctx->num_cu, s);
+  prof_end(ctx, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "stretch launch");
+  if (range) {
+    if (int st = ensure_pinned(ctx, 2 * sizeof(double) * n_comp)) return st;
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, ab, 2 * sizeof(double) * n_comp, hipMemcpyDeviceToHost, s), "range copy");
+    HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+    std::memcpy(range, ctx->pinned, 2 * sizeof(double) * n_comp);
+  }
+  return 0;
+}
+
+int cvamx_compose_rgb(cvamx_ctx* ctx, const uint8_t* r, const uint8_t* g, const uint8_t* b, int64_t P,
+                      uint8_t* rgb, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (!rgb) return fail(ctx, CVAMX_E_INVALID_ARG, "rgb must be non-NULL");
+  if (P < 1) return fail(ctx, CVAMX_E_INVALID_ARG, "P must be positive");
+  if (int st = check_device(ctx)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  prof_begin(ctx, s, "compose_rgb");
+  hipError_t e = cvx::launch_compose_rgb(r, g, b, P, rgb, ctx->num_cu, s);
+  prof_end(ctx, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "compose launch");
+  return 0;
 }
 
 int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t n_comp, int32_t prec,

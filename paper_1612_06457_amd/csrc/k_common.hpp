@@ -95,6 +95,15 @@ __device__ __forceinline__ void tile_acc(const float* __restrict__ A, int lda,
   }
 }
 
+// The linear stretch of [lo, hi] onto 0..levels as an affine map,
+// q = floor(y s + o) clamped, with s = levels / (hi - lo) and
+// o = 1/2 - lo s (a constant image maps to 0).  Every stretch in the
+// library takes its map from here, so equal ranges give identical images.
+__device__ __forceinline__ void stretch_map(float lo, float hi, float levels, float& s, float& o) {
+  s = hi > lo ? levels / (hi - lo) : 0.f;
+  o = fmaf(-lo, s, 0.5f);
+}
+
 // Ordered float <-> uint mapping so that unsigned integer min/max equals
 // float min/max (for atomics-free reductions this is only used for keys).
 __device__ __forceinline__ uint32_t f2ord(float f) {

@@ -200,9 +200,10 @@ __global__ __launch_bounds__(kBlock) void k_project_range(const void* __restrict
       lo = fminf(lo, wred[ww][j]);
       hi = fmaxf(hi, wred[ww][NC + j]);
     }
-    const float s = (hi > lo) ? 255.f / (hi - lo) : 0.f;
+    float s, o;
+    stretch_map(lo, hi, 255.f, s, o);
     range_dev[j] = s;
-    range_dev[8 + j] = 0.5f - lo * s;
+    range_dev[8 + j] = o;
     ab_dev[2 * j] = lo;
     ab_dev[2 * j + 1] = hi;
   }
@@ -253,6 +254,24 @@ __global__ __launch_bounds__(kBlock) void k_project_stretch(const void* __restri
   });
 }
 
+// The FP32 component planes themselves: y[j][p] for every pixel, the same
+// values the two passes above compute (lanes write consecutive pixels).
+template <int DT, int NC>
+__global__ __launch_bounds__(kBlock) void k_project_float(const void* __restrict__ cube, int B, int64_t P,
+                                                          ProjArgs a, float* __restrict__ y) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  tile_loop<DT, NC>(cube, B, P, a, lds, [&](int64_t pix, int g2, const float (&y0)[NC], const float (&y1)[NC]) {
+    if (pix < P) {
+#pragma unroll
+      for (int j = 0; j < NC; ++j) y[(int64_t)j * P + pix] = y0[j];
+    }
+    if (g2 == 2 && pix + 1 < P) {
+#pragma unroll
+      for (int j = 0; j < NC; ++j) y[(int64_t)j * P + pix + 1] = y1[j];
+    }
+  });
+}
+
 inline size_t smem_bytes(int dtype, int B) {
   const int S = (dtype == DT_F32 || (B & 1)) ? B : B / 2;
   return (size_t)kWaves * 64 * S * 4;
@@ -296,6 +315,23 @@ hipError_t stretch_nc(int nc, const void* cube, int B, int64_t P, const ProjArgs
   return hipGetLastError();
 }
 
+template <int DT>
+hipError_t float_nc(int nc, const void* cube, int B, int64_t P, const ProjArgs& a, int nblocks, float* y,
+                    hipStream_t s) {
+  const size_t sm = smem_bytes(DT, B);
+#define CVX_FLOAT(N)                                                                                          \
+  case N:                                                                                                     \
+    hipLaunchKernelGGL((k_project_float<DT, N>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a, y);       \
+    break;
+  switch (nc) {
+    CVX_FLOAT(1) CVX_FLOAT(2) CVX_FLOAT(3) CVX_FLOAT(4) CVX_FLOAT(5) CVX_FLOAT(6) CVX_FLOAT(7) CVX_FLOAT(8)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef CVX_FLOAT
+  return hipGetLastError();
+}
+
 }  // namespace proj
 
 // Per-translation-unit entry points (one per group of instantiations).
@@ -304,4 +340,6 @@ hipError_t project_range_generic(int dtype, int nc, const void* cube, int B, int
                                  hipStream_t s);
 hipError_t project_stretch_generic(int dtype, int nc, const void* cube, int B, int64_t P, const ProjArgs& a,
                                    int nblocks, const float* range_dev, uint8_t* images, hipStream_t s);
+hipError_t project_float_generic(int dtype, int nc, const void* cube, int B, int64_t P, const ProjArgs& a,
+                                 int nblocks, float* y, hipStream_t s);
 }  // namespace cvx

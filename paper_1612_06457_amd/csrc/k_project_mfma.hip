@@ -249,9 +249,10 @@ __global__ __launch_bounds__(kBlock) void k_range_mfma(const void* __restrict__ 
       l2 = fminf(l2, wred[ww][jj]);
       h2 = fmaxf(h2, wred[ww][16 + jj]);
     }
-    const float s = (h2 > l2) ? 255.f / (h2 - l2) : 0.f;
+    float s, o;
+    stretch_map(l2, h2, 255.f, s, o);
     range_dev[jj] = s;
-    range_dev[8 + jj] = 0.5f - l2 * s;
+    range_dev[8 + jj] = o;
     ab_dev[2 * jj] = l2;
     ab_dev[2 * jj + 1] = h2;
   }
@@ -308,6 +309,47 @@ __global__ __launch_bounds__(kBlock) void k_stretch_mfma(const void* __restrict_
   }
 }
 
+// The FP32 component planes: lane (g, j) stores the 4 consecutive pixels it
+// holds of plane j as one 16-byte write.
+template <int DT, int NKB>
+__global__ __launch_bounds__(kBlock) void k_float_mfma(const void* __restrict__ cube, int B, int64_t P, int nc,
+                                                       ProjArgs a, float* __restrict__ y) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int S = PG<DT>::S(B), g2 = PG<DT>::g2(B);
+  uint32_t* my = lds + w * 64 * S;
+  const uint16_t* tile = reinterpret_cast<const uint16_t*>(my);
+  const int tp = 64 * g2;
+  const int64_t nt = (P + tp - 1) / tp;
+  const int64_t total_bytes = P * B * 2;
+  const unsigned char* base = reinterpret_cast<const unsigned char*>(cube);
+  Ops<NKB> o;
+  load_ops<DT, NKB>(a, B, nc, o);
+  const int j = lane & 15, g = lane >> 4;
+  const bool active = j < nc;
+  float* plane = y + (int64_t)(active ? j : 0) * P;
+  const bool aligned = (P & 3) == 0 && (reinterpret_cast<uintptr_t>(y) & 15) == 0;
+  for (int64_t t = (int64_t)blockIdx.x * kWaves + w; t < nt; t += (int64_t)gridDim.x * kWaves) {
+    fetch_tile(base, total_bytes, t, S, my, lane);
+    wave_lds_sync();
+    const int64_t pix0 = t * tp;
+    for (int p0 = 0; p0 < tp; p0 += 16) {
+      const f32x4 v = project16<DT, NKB>(tile, p0, B, o);
+      if (active) {
+        const int64_t p = pix0 + p0 + 4 * g;
+        if (aligned && p + 3 < P) {
+          *reinterpret_cast<f32x4*>(plane + p) = v;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (p + e < P) plane[p + e] = v[e];
+        }
+      }
+    }
+    wave_lds_sync();
+  }
+}
+
 size_t smem(int B) { return (size_t)kWaves * 64 * ((B & 1) ? B : B / 2) * 4; }
 
 template <int DT>
@@ -334,6 +376,16 @@ hipError_t stretch_dt(int nkb, const void* cube, int B, int64_t P, int nc, const
   return hipGetLastError();
 }
 
+template <int DT>
+hipError_t float_dt(int nkb, const void* cube, int B, int64_t P, int nc, const ProjArgs& a, int nblocks, float* y,
+                    hipStream_t s) {
+  if (nkb == 1)
+    hipLaunchKernelGGL((k_float_mfma<DT, 1>), dim3(nblocks), dim3(kBlock), smem(B), s, cube, B, P, nc, a, y);
+  else
+    hipLaunchKernelGGL((k_float_mfma<DT, 2>), dim3(nblocks), dim3(kBlock), smem(B), s, cube, B, P, nc, a, y);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_project_range_mfma(int dtype, const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
@@ -355,6 +407,16 @@ hipError_t launch_project_stretch_mfma(int dtype, const void* cube, int B, int64
     case DT_U16: return stretch_dt<DT_U16>(nkb, cube, B, P, nc, a, nblocks, range_dev, images, s);
     case DT_BF16: return stretch_dt<DT_BF16>(nkb, cube, B, P, nc, a, nblocks, range_dev, images, s);
     case DT_F16: return stretch_dt<DT_F16>(nkb, cube, B, P, nc, a, nblocks, range_dev, images, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_project_float_mfma(int dtype, const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
+                                     int nblocks, float* y, hipStream_t s) {
+  const int nkb = (B + 31) / 32;
+  switch (dtype) {
+    case DT_BF16: return float_dt<DT_BF16>(nkb, cube, B, P, nc, a, nblocks, y, s);
+    case DT_F16: return float_dt<DT_F16>(nkb, cube, B, P, nc, a, nblocks, y, s);
   }
   return hipErrorInvalidValue;
 }

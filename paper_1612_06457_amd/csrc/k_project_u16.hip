@@ -331,9 +331,10 @@ __global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_range_u16(const vo
       l2 = fminf(l2, wred[ww][jj]);
       h2 = fmaxf(h2, wred[ww][8 + jj]);
     }
-    const float s = (h2 > l2) ? 255.f / (h2 - l2) : 0.f;
+    float s, o;
+    stretch_map(l2, h2, 255.f, s, o);
     range_dev[jj] = s;
-    range_dev[8 + jj] = 0.5f - l2 * s;
+    range_dev[8 + jj] = o;
     ab_dev[2 * jj] = l2 * inv;
     ab_dev[2 * jj + 1] = h2 * inv;
   }
@@ -408,6 +409,60 @@ __global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_stretch_u16(const 
   });
 }
 
+// The FP32 component planes, scaled back by 2^-s_j (exact), so they hold
+// the very values whose min/max and stretch the two passes above take.
+// Lane (g, p, j) ends with 4 consecutive pixels of plane j per row block:
+// for two-pixel rows the partner lane l ^ 8 holds the other pixel of each
+// row, and the two lanes swap halves so that each writes a 16-byte run.
+template <int NKB, int G2>
+__global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_float_u16(const void* __restrict__ cube, int B,
+                                                                      int64_t P, int nc, ProjArgs a,
+                                                                      float* __restrict__ y) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  constexpr int RB = row_blocks<NKB>();
+  constexpr int TP = 16 * RB * G2;   // pixels per wave tile
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, col = lane & 15, p = col >> 3, j = col & 7;
+  const bool live = p < G2 && j < nc;
+  ProjArgs& sa = *reinterpret_cast<ProjArgs*>(lds);   // set-up only: the tiles reuse it
+  stage_args(a, sa);
+  __shared__ OpsTab<NKB> tab;
+  const float acc0 = build_ops<NKB, G2>(sa, B, nc, tab);
+  const float inv = 1.f / sa.scale[j];   // a power of two: exact
+  __syncthreads();
+  float* plane = y + (int64_t)(live ? j : 0) * P;
+  const bool aligned = (P & 3) == 0 && (reinterpret_cast<uintptr_t>(y) & 15) == 0;
+  run_tiles<NKB, G2>(cube, B, P, tab, acc0, lds, [&](int64_t t, const f32x4 (&acc)[RB]) {
+    const int64_t pb = t * TP;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      f32x4 v;
+      int64_t px;
+      if constexpr (G2 == 2) {
+        // this lane: pixel p of rows 4 g + e; send the partner the two rows it writes
+        const float s0 = p == 0 ? acc[rb][2] : acc[rb][0];
+        const float s1 = p == 0 ? acc[rb][3] : acc[rb][1];
+        const float r0 = __shfl_xor(s0, 8, 64), r1 = __shfl_xor(s1, 8, 64);
+        v = p == 0 ? f32x4{acc[rb][0], r0, acc[rb][1], r1} : f32x4{r0, acc[rb][2], r1, acc[rb][3]};
+        px = pb + 2 * (16 * rb + 4 * g) + 4 * p;
+      } else {
+        v = acc[rb];
+        px = pb + 16 * rb + 4 * g;
+      }
+      v *= inv;
+      if (live) {
+        if (aligned && px + 3 < P) {
+          *reinterpret_cast<f32x4*>(plane + px) = v;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (px + e < P) plane[px + e] = v[e];
+        }
+      }
+    }
+  });
+}
+
 // LDS: the wave slices plus 8 dwords that the last row's reads may reach;
 // at least one ProjArgs, which set-up stages there.
 template <int NKB, int G2>
@@ -452,6 +507,16 @@ hipError_t stretch_k(const void* cube, int B, int64_t P, int nc, const ProjArgs&
   return hipGetLastError();
 }
 
+template <int NKB, int G2>
+hipError_t float_k(const void* cube, int B, int64_t P, int nc, const ProjArgs& a, int nblocks, float* y,
+                   hipStream_t s) {
+  const size_t sm = smem<NKB, G2>(B);
+  const void* k = reinterpret_cast<const void*>(&k_float_u16<NKB, G2>);
+  const int nb = grid(k, sm, nblocks, P, B, 16 * row_blocks<NKB>());
+  hipLaunchKernelGGL((k_float_u16<NKB, G2>), dim3(nb), dim3(kBlock), sm, s, cube, B, P, nc, a, y);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 // NKB = ceil(S / 8) K-blocks for S dwords per row (S = B for odd B, else B / 2).
@@ -488,6 +553,14 @@ hipError_t launch_project_stretch_u16(const void* cube, int B, int64_t P, int nc
 #define CVX_S(N, G) stretch_k<N, G>(cube, B, P, nc, a, nblocks, range_dev, images, s)
   CVX_U16_SWITCH(CVX_S)
 #undef CVX_S
+}
+
+hipError_t launch_project_float_u16(const void* cube, int B, int64_t P, int nc, const ProjArgs& a, int nblocks,
+                                    float* y, hipStream_t s) {
+  if (B < 1 || B > kMaxB || nc < 1 || nc > 8) return hipErrorInvalidValue;
+#define CVX_F(N, G) float_k<N, G>(cube, B, P, nc, a, nblocks, y, s)
+  CVX_U16_SWITCH(CVX_F)
+#undef CVX_F
 }
 
 #undef CVX_U16_SWITCH

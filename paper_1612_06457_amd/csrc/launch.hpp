@@ -86,6 +86,38 @@ hipError_t launch_project_stretch_mfma(int dtype, const void* cube, int B, int64
                                        const ProjArgs& a, int nblocks, const float* range_dev,
                                        uint8_t* images, hipStream_t s);
 
+hipError_t launch_project_float_u16(const void* cube, int B, int64_t P, int nc, const ProjArgs& a, int nblocks,
+                                    float* y, hipStream_t s);
+hipError_t launch_project_float_mfma(int dtype, const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
+                                     int nblocks, float* y, hipStream_t s);
+
+// rescaling from FP32 component planes y (nc planes of P floats, nc <= 64)
+constexpr int kSelTargets = 4;   // order statistics wanted per plane by one select
+// blocks per plane for the reductions over m values of each of nc planes
+int stretch_reduce_blocks(int64_t m, int nc, int num_cu);
+// part[(j * nb + blk) * 2 + {0, 1}]: block partial min/max of plane j over
+// all pixels, or over idx[0..n) if idx is non-NULL (an index outside
+// 0..P-1 sets bit 2 of *err and is skipped)
+hipError_t launch_plane_minmax(const float* y, int64_t P, int nc, const int64_t* idx, int64_t n, int nb,
+                               float* part, int32_t* err, hipStream_t s);
+// exact order statistics of ranks[t] (0-based) in every plane: sel
+// (nc x kSelTargets) ends with their order-preserving keys; hist holds
+// 2 x nc x kSelTargets x 256 counters
+hipError_t launch_select(const float* y, int64_t P, int nc, const uint32_t (&ranks)[kSelTargets], int nb,
+                         uint2* sel, uint32_t* hist, hipStream_t s);
+// range ab[2 j + {0, 1}] = (a_j, b_j): mode 1 / 2 fold the nb partials per
+// plane, mode 3 interpolates the order statistics in sel
+hipError_t launch_stretch_finish(int mode, int nc, int nb, const float* part, const uint2* sel, double g_lo,
+                                 double g_hi, double* ab, hipStream_t s);
+hipError_t launch_stretch_planes(const float* y, int64_t P, int nc, const double* ab, int bits, void* out,
+                                 int num_cu, hipStream_t s);
+hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
+hipError_t launch_compose_rgb(const uint8_t* r, const uint8_t* g, const uint8_t* b, int64_t P, uint8_t* rgb,
+                              int num_cu, hipStream_t s);
+// projection to FP32 planes (y[j][p] = w_j^T (x_p - c), n_comp x P)
+hipError_t launch_project_float(int dtype, const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
+                                int nblocks, float* y, hipStream_t s);
+
 // soft-label CVA
 hipError_t launch_soft_first(const float* X, const float* w, int64_t N, int B, int K,
                              int nblocks, double* part, unsigned* ticket, double* first,

@@ -185,6 +185,40 @@ def test_argument_checks_without_a_device():
         assert fitp(classes=ctypes.c_void_p(0x50008)) == L.E_UNSUPPORTED
         assert fitp(pixels=ctypes.c_void_p(0x40004)) == L.E_UNSUPPORTED
         assert fitp() == L.E_DEVICE
+        # float images, rescaling, colour
+        assert lib.cvamx_project_float(ctx, ctypes.byref(good), W.ctypes.data, c.ctypes.data, 2, None,
+                                       None) == L.E_INVALID_ARG
+        assert lib.cvamx_project_float(ctx, ctypes.byref(good), W.ctypes.data, c.ctypes.data, 2,
+                                       ctypes.c_void_p(0x10002), None) == L.E_UNSUPPORTED
+        assert lib.cvamx_project_float(ctx, ctypes.byref(good), W.ctypes.data, c.ctypes.data, 2, aligned,
+                                       None) == L.E_DEVICE
+        y, out, tp = ctypes.c_void_p(0x60000), ctypes.c_void_p(0x70000), ctypes.c_void_p(0x80000)
+
+        def st(y=y, P=256, n=2, mode=1, pct=1.0, train=None, n_train=0, bits=8, out=out):
+            return lib.cvamx_stretch(ctx, y, P, n, mode, pct, train, n_train, bits, out, None, None)
+
+        assert st(y=None) == L.E_INVALID_ARG
+        assert st(out=None) == L.E_INVALID_ARG
+        assert st(P=0) == L.E_INVALID_ARG
+        assert st(n=0) == L.E_INVALID_ARG
+        assert st(n=65) == L.E_INVALID_ARG
+        assert st(mode=0) == L.E_INVALID_ARG
+        assert st(mode=4) == L.E_INVALID_ARG
+        assert st(bits=12) == L.E_INVALID_ARG
+        assert st(mode=2) == L.E_INVALID_ARG                      # no pixel list
+        assert st(mode=2, train=tp, n_train=0) == L.E_INVALID_ARG
+        assert st(mode=3, pct=50.0) == L.E_INVALID_ARG
+        assert st(mode=3, pct=-0.5) == L.E_INVALID_ARG
+        assert st(mode=3, pct=float("nan")) == L.E_INVALID_ARG
+        assert st(y=ctypes.c_void_p(0x60002)) == L.E_UNSUPPORTED
+        assert st(bits=16, out=ctypes.c_void_p(0x70001)) == L.E_UNSUPPORTED
+        assert st(mode=2, train=ctypes.c_void_p(0x80004), n_train=5) == L.E_UNSUPPORTED
+        assert st(mode=2, train=tp, n_train=5) == L.E_DEVICE
+        assert st(mode=3, pct=0.0) == L.E_DEVICE
+        assert st(bits=16, out=ctypes.c_void_p(0x70002)) == L.E_DEVICE
+        assert lib.cvamx_compose_rgb(ctx, y, y, y, 10, None, None) == L.E_INVALID_ARG
+        assert lib.cvamx_compose_rgb(ctx, y, y, y, 0, out, None) == L.E_INVALID_ARG
+        assert lib.cvamx_compose_rgb(ctx, None, y, None, 10, out, None) == L.E_DEVICE
     finally:
         lib.cvamx_destroy(ctx)
     assert lib.cvamx_status_str(L.E_NOT_PD) == b"within-class scatter not positive definite"

@@ -310,6 +310,59 @@ def test_stretch_modes_two_and_three():
     assert abs(a5[0] - (srt[i] + (pos - i) * (srt[i + 1] - srt[i]))) <= 1e-12
 
 
+def test_stretch_sixteen_bits():
+    rng = np.random.default_rng(14)
+    y = rng.normal(0, 2, size=(6000, 2))
+    q16, a, b = oracle.stretch_minmax(y, levels=65535)
+    assert q16.dtype == np.uint16
+    q8, _, _ = oracle.stretch_minmax(y)
+    for j in range(2):
+        assert q16[np.argmin(y[:, j]), j] == 0 and q16[np.argmax(y[:, j]), j] == 65535
+        # 65535 = 255 * 257: the two maps agree within one 8-bit level
+        assert np.max(np.abs(np.rint(q16[:, j] / 257.0) - q8[:, j])) <= 1
+        lo, hi = y[:, j].min(), y[:, j].max()
+        for p in range(0, 6000, 131):
+            v = int(np.floor(65535.0 * (y[p, j] - lo) / (hi - lo) + 0.5))
+            assert q16[p, j] == min(max(v, 0), 65535)
+    # modes 2 and 3 clamp at the 16-bit top as well
+    qt, _, _ = oracle.stretch_training_range(y, y[:50], levels=65535)
+    assert qt.max() == 65535 and qt.min() == 0
+
+
+def test_percentiles_closed_forms():
+    rng = np.random.default_rng(15)
+    # a shuffled arithmetic sequence 0, 1, ..., 100: the p-th percentile is p
+    y = rng.permutation(np.arange(101.0))[:, None]
+    for pct in (0.0, 1.0, 5.0, 12.5):
+        _, a, b = oracle.stretch_percentile(y, pct)
+        assert a[0] == pct and b[0] == 100.0 - pct
+    # the 0-th percentile is the minimum: mode 3 at 0 is mode 1
+    z = rng.normal(size=(997, 3))
+    q0, a0, b0 = oracle.stretch_percentile(z, 0.0)
+    q1, a1, b1 = oracle.stretch_minmax(z)
+    assert (a0 == a1).all() and (b0 == b1).all() and (q0 == q1).all()
+    # 0.01 % of 10001 values sits exactly on the second order statistic
+    w = rng.permutation(np.arange(10001.0) * 0.5)[:, None]
+    _, a, b = oracle.stretch_percentile(w, 0.01)
+    assert a[0] == 0.5 and abs(b[0] - 4999.5) <= 1e-9   # 99.99 / 100 is inexact
+    # between two order statistics: 10 values 0, 10, ..., 90, 5 % -> 0.45
+    v = rng.permutation(np.arange(10) * 10.0)[:, None]
+    _, a, b = oracle.stretch_percentile(v, 5.0)
+    assert abs(a[0] - 4.5) <= 1e-12 and abs(b[0] - 85.5) <= 1e-12
+
+
+def test_compose_rgb_layout():
+    rng = np.random.default_rng(16)
+    r, g = rng.integers(0, 256, (2, 7, 9), dtype=np.uint8)
+    rgb = oracle.compose_rgb(r, g, None)
+    assert rgb.shape == (7, 9, 3)
+    for y in range(7):
+        for x in range(9):
+            assert tuple(rgb[y, x]) == (r[y, x], g[y, x], 0)
+    two = oracle.compose_rgb(g, r, r)          # one image in two channels
+    assert (two[..., 1] == two[..., 2]).all() and (two[..., 0] == g).all()
+
+
 # ----------------------------------------------------------- sign and errors
 
 def test_sign_rule():
