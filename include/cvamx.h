@@ -60,7 +60,8 @@ typedef enum {
   CVAMX_U16 = 0,   /* unsigned 16-bit detector counts */
   CVAMX_F32 = 1,
   CVAMX_BF16 = 2,
-  CVAMX_F16 = 3
+  CVAMX_F16 = 3,
+  CVAMX_U8 = 4     /* 8-bit images: accepted by cvamx_cluster_indices only */
 } cvamx_dtype;
 
 typedef enum {
@@ -221,6 +222,37 @@ int cvamx_stretch(cvamx_ctx* ctx, const float* y, int64_t P, int32_t n_comp,
  * Asynchronous on `stream`. */
 int cvamx_compose_rgb(cvamx_ctx* ctx, const uint8_t* r, const uint8_t* g,
                       const uint8_t* b, int64_t P, uint8_t* rgb, void* stream);
+
+/* ---- numerical assessment ------------------------------------------------ */
+
+/* Cluster-separation indices of labelled points on a set of images (paper
+ * Section 3, Eqs. 1-5).  A point's feature vector X is the values of the
+ * n_feat planes at its pixel; for each class k:
+ *   A_k = mean of X over the class's points (centroid),
+ *   S_k = mean of ||X - A_k||_p over the class's points (Eq. 1),
+ * and for each pair M_ij = ||A_i - A_j||_p (Eq. 2),
+ *   R_ij = (S_i + S_j) / M_ij (Eq. 3, Davies-Bouldin),
+ *   D_ij = (M_ij - S_i - S_j) / max(S_i, S_j) (Eq. 5, Dunn),
+ * with R_ii = D_ii = 0.  scores[0] = (1/K) sum_i max_{j != i} R_ij and
+ * scores[1] = min_{i != j} (M_ij - S_i - S_j) / max_k S_k; with K = 2 they
+ * are the paper's two-cluster values.
+ *   images   device, n_feat x P planar, element type dtype (CVAMX_U8,
+ *            CVAMX_U16, CVAMX_F32, CVAMX_BF16, CVAMX_F16), aligned to it
+ *   pixels   device, N int64 pixel indices (0..P-1), 8-byte aligned
+ *   classes  device, N int8 (-1 = skip, else 0..K-1), 16-byte aligned
+ *   K        2..CVAMX_MAX_CLASSES; every class needs a point
+ *   p        the norm's order, p >= 1 (the paper: usually 2)
+ * Host outputs (each nullable except scores): centroids K x n_feat,
+ * scatter K, dist K x K (M), dbi K x K (R), dunn K x K (D), scores 2.
+ * Sums and distances in FP64 in a fixed order: repeatable bit for bit.
+ * Synchronises `stream`.  A class outside -1..K-1 or a pixel outside the
+ * page: CVAMX_E_INVALID_ARG; an empty class: CVAMX_E_EMPTY_CLASS. */
+int cvamx_cluster_indices(cvamx_ctx* ctx, const void* images, int32_t dtype,
+                          int64_t P, int32_t n_feat, const int64_t* pixels,
+                          const int8_t* classes, int64_t N, int32_t K,
+                          double p, double* centroids, double* scatter,
+                          double* dist, double* dbi, double* dunn,
+                          double* scores, void* stream);
 
 /* ---- soft-label CVA ------------------------------------------------------ */
 

@@ -34,11 +34,12 @@ from .cva import (class_counts, class_index_lists, class_moments, within_scatter
 from .stretch import compose_rgb, stretch_minmax, stretch_training_range, stretch_percentile
 from .pca import pca_fit, pca_project
 from .soft import soft_moments, soft_fit, soft_grad, soft_delta_J
+from .cluster import cluster_indices
 
 __all__ = [
     "class_counts", "class_index_lists", "class_moments", "within_scatter",
     "between_scatter", "total_scatter", "generalized_eig", "sign_rule",
     "cva_fit", "cva_fit_points", "project", "cva_project", "stretch_minmax",
     "stretch_training_range", "stretch_percentile", "compose_rgb", "pca_fit", "pca_project",
-    "soft_moments", "soft_fit", "soft_grad", "soft_delta_J",
+    "soft_moments", "soft_fit", "soft_grad", "soft_delta_J", "cluster_indices",
 ]

@@ -23,7 +23,7 @@ E_DEVICE = -5
 E_NO_MEMORY = -6
 E_NUMERIC = -7
 
-DT_U16, DT_F32, DT_BF16, DT_F16 = 0, 1, 2, 3
+DT_U16, DT_F32, DT_BF16, DT_F16, DT_U8 = 0, 1, 2, 3, 4
 PREC = {"fp32": 0, "bf16x3": 1, "f16x3": 2}
 
 
@@ -58,6 +58,8 @@ EXPORTS = {
     "cvamx_project_float": (ctypes.c_int, [_vp, ctypes.POINTER(Cube), _vp, _vp, _i32, _vp, _vp]),
     "cvamx_stretch": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _f64, _vp, _i64, _i32, _vp, _vp, _vp]),
     "cvamx_compose_rgb": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp]),
+    "cvamx_cluster_indices": (ctypes.c_int, [_vp, _vp, _i32, _i64, _i32, _vp, _vp, _i64, _i32, _f64,
+                                             _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pca_fit": (ctypes.c_int, [_vp, ctypes.POINTER(Cube), _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "pca_project": (ctypes.c_int, [_vp, ctypes.POINTER(Cube), _vp, _vp, _i32, _vp, _vp, _vp]),
     "cva_soft_forward": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _f64,

@@ -234,6 +234,52 @@ def compose_rgb(r: Optional[torch.Tensor], g: Optional[torch.Tensor], b: Optiona
     return rgb
 
 
+@dataclass
+class ClusterIndices:
+    centroids: np.ndarray   # K x n
+    scatter: np.ndarray     # K   (S_k, the mean distance to the centroid)
+    dist: np.ndarray        # K x K (M_ij, centroid distances)
+    dbi_pairs: np.ndarray   # K x K (R_ij)
+    dunn_pairs: np.ndarray  # K x K (D_ij)
+    dbi: float
+    dunn: float
+
+
+_IMG_DTYPES = {torch.uint8: _lib.DT_U8, **_DTYPES}
+
+
+def cluster_indices(images: torch.Tensor, pixels: torch.Tensor, classes: torch.Tensor, K: int,
+                    p: float = 2.0) -> ClusterIndices:
+    """Davies-Bouldin and Dunn indices of labelled points on images
+    (n x ... planes, or one H x W image): pixels int64 N flat indices,
+    classes int8 N (-1 = skip), all on one device."""
+    if images.dtype not in _IMG_DTYPES or not images.is_contiguous():
+        raise ValueError("images must be a contiguous uint8, uint16, float32, bfloat16 or float16 tensor")
+    if images.dim() == 2:
+        images = images.unsqueeze(0)
+    if pixels.dtype != torch.int64 or classes.dtype != torch.int8 or pixels.dim() != 1 \
+            or tuple(classes.shape) != tuple(pixels.shape):
+        raise ValueError("pixels must be int64 N and classes int8 N")
+    for t in (pixels, classes):
+        if t.device != images.device or not t.is_contiguous():
+            raise ValueError("pixels and classes must be contiguous and on the images' device")
+    n = images.shape[0]
+    P = images[0].numel()
+    A = np.empty((K, n))
+    S = np.empty(K)
+    M = np.empty((K, K))
+    R = np.empty((K, K))
+    D = np.empty((K, K))
+    sc = np.empty(2)
+    dev = _dev_index(images)
+    ctx = context(dev)
+    st = lib().cvamx_cluster_indices(ctx, _ptr(images), _IMG_DTYPES[images.dtype], P, n, _ptr(pixels),
+                                     _ptr(classes), int(pixels.numel()), K, float(p), _ptr(A), _ptr(S),
+                                     _ptr(M), _ptr(R), _ptr(D), _ptr(sc), _stream(images.device))
+    check(st, ctx)
+    return ClusterIndices(A, S, M, R, D, float(sc[0]), float(sc[1]))
+
+
 def pca_fit(cube: torch.Tensor, mask: Optional[torch.Tensor] = None, n_comp: int = 3,
             precision: str = "fp32"):
     """Covariance PCA of the page (or of the pixels where mask != 0).

@@ -667,7 +667,7 @@ int cvamx_stretch(cvamx_ctx* ctx, const float* y, int64_t P, int32_t n_comp, int
       HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
       int32_t flag = 0;
       std::memcpy(&flag, ctx->pinned, 4);
-      if (flag & 4) return fail(ctx, CVAMX_E_INVALID_ARG, "a training pixel lies outside 0..P-1");
+      if (flag & 2) return fail(ctx, CVAMX_E_INVALID_ARG, "a training pixel lies outside 0..P-1");
     }
   } else {
     // linear interpolation between the order statistics around the virtual
@@ -722,6 +722,98 @@ int cvamx_compose_rgb(cvamx_ctx* ctx, const uint8_t* r, const uint8_t* g, const 
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "compose launch");
   return 0;
+}
+
+int cvamx_cluster_indices(cvamx_ctx* ctx, const void* images, int32_t dtype, int64_t P, int32_t n_feat,
+                          const int64_t* pixels, const int8_t* classes, int64_t N, int32_t K, double p,
+                          double* centroids, double* scatter, double* dist, double* dbi, double* dunn,
+                          double* scores, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (!images || !pixels || !classes || !scores)
+    return fail(ctx, CVAMX_E_INVALID_ARG, "images, pixels, classes and scores must be non-NULL");
+  if (dtype < CVAMX_U16 || dtype > CVAMX_U8) return fail(ctx, CVAMX_E_UNSUPPORTED, "unknown dtype");
+  if (P < 1 || P >= (int64_t(1) << 31) - 1) return fail(ctx, CVAMX_E_INVALID_ARG, "P must lie in 1..2^31-2");
+  if (n_feat < 1 || n_feat > CVAMX_MAX_BANDS)
+    return fail(ctx, CVAMX_E_INVALID_ARG, "n_feat must lie in 1..CVAMX_MAX_BANDS");
+  if (N < 1 || N >= (int64_t(1) << 31)) return fail(ctx, CVAMX_E_INVALID_ARG, "N must lie in 1..2^31-1");
+  if (K < 2 || K > CVAMX_MAX_CLASSES) return fail(ctx, CVAMX_E_INVALID_ARG, "K must lie in 2..127");
+  if (!(std::isfinite(p) && p >= 1.0)) return fail(ctx, CVAMX_E_INVALID_ARG, "p must be finite and >= 1");
+  const size_t el = dtype == CVAMX_U8 ? 1 : esize(dtype);
+  if ((reinterpret_cast<uintptr_t>(images) & (el - 1)) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "images must be aligned to their element size");
+  if ((reinterpret_cast<uintptr_t>(pixels) & 7u) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "pixels must be 8-byte aligned");
+  if ((reinterpret_cast<uintptr_t>(classes) & 15u) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "classes must be 16-byte aligned");
+  if (int st = check_device(ctx)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int L = cvx::cluster_sum_len(n_feat);
+  const int G = std::max(1, std::min(64, 2 * ctx->num_cu / K));
+  // results: counts, offsets, error flag (FitLayout with one "band" for the
+  // distance sums in the shift slot and the feature sums in the Gram slot)
+  const FitLayout lay(K, 1, L);
+  if (int st = ensure(ctx, B_PART, (size_t)K * G * (L + 1) * 8)) return st;
+  if (int st = ensure(ctx, B_RES, lay.total)) return st;
+  if (int st = ensure_pinned(ctx, lay.total)) return st;
+  char* res = static_cast<char*>(ctx->buf[B_RES]);
+  if (int st = build_index(ctx, classes, pixels, N, P, K, lay, res, s)) return st;
+  prof_begin(ctx, s, "cluster_moments");
+  hipError_t e = cvx::launch_cluster_moments(dtype, images, P, n_feat, (const int32_t*)ctx->buf[B_IDX],
+                                             (const int32_t*)(res + lay.offsets), (const int64_t*)(res + lay.counts),
+                                             K, G, p, (double*)ctx->buf[B_PART], (double*)(res + lay.gram),
+                                             (double*)(res + lay.shift), s);
+  prof_end(ctx, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "cluster moments launch");
+  HIP_TRY(hipMemcpyAsync(ctx->pinned, res, lay.total, hipMemcpyDeviceToHost, s), "result copy");
+  HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+  const char* h = static_cast<const char*>(ctx->pinned);
+  int32_t errflag;
+  std::memcpy(&errflag, h + lay.err, 4);
+  if (errflag & 1) return fail(ctx, CVAMX_E_INVALID_ARG, "a class lies outside -1..K-1");
+  if (errflag & 2) return fail(ctx, CVAMX_E_INVALID_ARG, "a point lies outside the page");
+  std::vector<int64_t> cnt(K);
+  std::memcpy(cnt.data(), h + lay.counts, 8 * (size_t)K);
+  for (int k = 0; k < K; ++k)
+    if (cnt[k] < 1) return fail(ctx, CVAMX_E_EMPTY_CLASS, "class " + std::to_string(k) + " has no point");
+  const double* sums = reinterpret_cast<const double*>(h + lay.gram);
+  const double* dsum = reinterpret_cast<const double*>(h + lay.shift);
+  const int n = n_feat;
+  std::vector<double> A((size_t)K * n), S(K), M((size_t)K * K, 0.0), R((size_t)K * K, 0.0), D((size_t)K * K, 0.0);
+  for (int k = 0; k < K; ++k) {
+    for (int f = 0; f < n; ++f) A[(size_t)k * n + f] = sums[(size_t)k * L + f] / (double)cnt[k];
+    S[k] = dsum[k] / (double)cnt[k];
+  }
+  auto norm = [&](const double* a, const double* b) {
+    double t = 0.0;
+    for (int f = 0; f < n; ++f) {
+      const double d = std::fabs(a[f] - b[f]);
+      t += p == 2.0 ? d * d : (p == 1.0 ? d : std::pow(d, p));
+    }
+    return p == 2.0 ? std::sqrt(t) : (p == 1.0 ? t : std::pow(t, 1.0 / p));
+  };
+  double smax = 0.0, dmin = INFINITY, dbi_sum = 0.0;
+  for (int k = 0; k < K; ++k) smax = std::max(smax, S[k]);
+  for (int i = 0; i < K; ++i) {
+    double rmax = -INFINITY;
+    for (int j = 0; j < K; ++j) {
+      if (i == j) continue;
+      const double m = norm(&A[(size_t)i * n], &A[(size_t)j * n]);
+      M[(size_t)i * K + j] = m;
+      R[(size_t)i * K + j] = (S[i] + S[j]) / m;
+      D[(size_t)i * K + j] = (m - S[i] - S[j]) / std::max(S[i], S[j]);
+      rmax = std::max(rmax, R[(size_t)i * K + j]);
+      dmin = std::min(dmin, m - S[i] - S[j]);
+    }
+    dbi_sum += rmax;
+  }
+  scores[0] = dbi_sum / K;
+  scores[1] = dmin / smax;
+  if (centroids) std::copy(A.begin(), A.end(), centroids);
+  if (scatter) std::copy(S.begin(), S.end(), scatter);
+  if (dist) std::copy(M.begin(), M.end(), dist);
+  if (dbi) std::copy(R.begin(), R.end(), dbi);
+  if (dunn) std::copy(D.begin(), D.end(), dunn);
+  return CVAMX_OK;
 }
 
 int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t n_comp, int32_t prec,

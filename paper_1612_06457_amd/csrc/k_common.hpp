@@ -9,7 +9,7 @@
 
 namespace cvx {
 
-enum { DT_U16 = 0, DT_F32 = 1, DT_BF16 = 2, DT_F16 = 3 };
+enum { DT_U16 = 0, DT_F32 = 1, DT_BF16 = 2, DT_F16 = 3, DT_U8 = 4 };
 
 
 // Element storage types.

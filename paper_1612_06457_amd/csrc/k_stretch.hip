@@ -44,7 +44,7 @@ __device__ __forceinline__ bool first_active() {
 
 // Block (blockIdx.x, plane j = blockIdx.y) partial min/max of plane j over
 // all P pixels, or over the pixels idx[0..n) when idx is non-NULL (an index
-// outside 0..P-1 is skipped and sets bit 2 of *err).
+// outside 0..P-1 is skipped and sets the value 2 in *err).
 // part[(j * gridDim.x + blockIdx.x) * 2 + {0, 1}] = {min, max}.
 __global__ __launch_bounds__(kBlock) void k_plane_minmax(const float* __restrict__ y, int64_t P,
                                                          const int64_t* __restrict__ idx, int64_t n,
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kBlock) void k_plane_minmax(const float* __restrict
       lo = fminf(lo, v);
       hi = fmaxf(hi, v);
     }
-    if (bad) atomicOr(err, 4);
+    if (bad) atomicOr(err, 2);
   } else if ((P & 3) == 0 && (reinterpret_cast<uintptr_t>(y) & 15) == 0) {
     const float4* y4 = reinterpret_cast<const float4*>(yj);
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < P / 4; i += stride) {

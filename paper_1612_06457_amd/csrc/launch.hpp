@@ -36,7 +36,7 @@ hipError_t launch_label_index(const int8_t* labels, int64_t P, int K, int nT,
                               int64_t* counts_out, int32_t* offsets_out, hipStream_t s);
 
 // training points as a list: turn the class-grouped list positions in idx
-// (offsets[K] of them) into pixels; sets bit 2 of *err_flag for a pixel
+// (offsets[K] of them) into pixels; ORs 2 into *err_flag for a pixel
 // outside 0..P-1
 hipError_t launch_points_to_pixels(const int64_t* pixels, int32_t* idx, const int32_t* offsets, int K, int64_t N,
                                    int64_t P, int32_t* err_flag, int num_cu, hipStream_t s);
@@ -97,7 +97,7 @@ constexpr int kSelTargets = 4;   // order statistics wanted per plane by one sel
 int stretch_reduce_blocks(int64_t m, int nc, int num_cu);
 // part[(j * nb + blk) * 2 + {0, 1}]: block partial min/max of plane j over
 // all pixels, or over idx[0..n) if idx is non-NULL (an index outside
-// 0..P-1 sets bit 2 of *err and is skipped)
+// 0..P-1 ORs 2 into *err and is skipped)
 hipError_t launch_plane_minmax(const float* y, int64_t P, int nc, const int64_t* idx, int64_t n, int nb,
                                float* part, int32_t* err, hipStream_t s);
 // exact order statistics of ranks[t] (0-based) in every plane: sel
@@ -117,6 +117,15 @@ hipError_t launch_compose_rgb(const uint8_t* r, const uint8_t* g, const uint8_t*
 // projection to FP32 planes (y[j][p] = w_j^T (x_p - c), n_comp x P)
 hipError_t launch_project_float(int dtype, const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
                                 int nblocks, float* y, hipStream_t s);
+
+// cluster-separation indices: per class k of the class-grouped points,
+// sums[k * L + f] = sum of feature f (L = cluster_sum_len(n)) and
+// dsum[k] = sum of ||X - A_k||_p with A_k = sums[k] / counts[k]; part holds
+// K x G x (L + 1) doubles
+int cluster_sum_len(int n);
+hipError_t launch_cluster_moments(int dtype, const void* img, int64_t P, int n, const int32_t* idx,
+                                  const int32_t* offsets, const int64_t* counts, int K, int G, double p,
+                                  double* part, double* sums, double* dsum, hipStream_t s);
 
 // soft-label CVA
 hipError_t launch_soft_first(const float* X, const float* w, int64_t N, int B, int K,

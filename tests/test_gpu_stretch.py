@@ -1,5 +1,6 @@
 """GPU parity of the float images, the three rescaling modes, the 16-bit
-output and the RGB composite, through the C ABI.
+output, the RGB composite and the cluster-separation indices, through the
+C ABI.
 
 Bars: the float planes within 1e-4 of each component's range of the FP64
 oracle's (as for the fused projection), and mode 1 on them finds the fused
@@ -8,7 +9,9 @@ exact, so the range equals NumPy's percentile of the device's own FP32
 values up to FP64 rounding of the interpolation; the images equal, bit for
 bit, the oracle's quantisation of the device's own values on the device's
 range (both evaluate the definition in FP64), and lie within one level of
-the full FP64 oracle pipeline; the RGB composite is bit-exact.
+the full FP64 oracle pipeline; the RGB composite is bit-exact; the
+Davies-Bouldin and Dunn indices within 1e-12 relative of the FP64 oracle
+(FP64 sums in another order).
 """
 import sys
 
@@ -348,3 +351,96 @@ def test_full_page_percentile_cfg5(dev):
     qs = q.cpu().numpy().reshape(q.shape[0], -1)[:, sample].astype(np.int64)
     q_ref = _quantise(yh[:, sample].T, ab[:, 0], ab[:, 1], 65535)
     assert np.array_equal(qs.T, q_ref)
+
+
+# ------------------------------------------ Davies-Bouldin and Dunn (Sec. 3)
+
+@pytest.mark.parametrize("dt", ["u8", "u16", "f32", "bf16"])
+@pytest.mark.parametrize("p", [2.0, 1.0, 3.0])
+def test_cluster_indices(dev, dt, p):
+    say(f"cluster indices {dt} p={p}")
+    import paper_1612_06457_amd as cx
+    import torch
+    rng = np.random.default_rng(7)
+    n, H, W, K = 3, 61, 47, 4
+    base = rng.uniform(0, 200, (n, H, W))
+    if dt == "u8":
+        img = base.astype(np.uint8)
+    elif dt == "u16":
+        img = (base * 300).astype(np.uint16)
+    elif dt == "f32":
+        img = base.astype(np.float32)
+    else:
+        img = torch.from_numpy(base.astype(np.float32)).to(torch.bfloat16)
+    N = 2000
+    pix = rng.integers(0, H * W, N).astype(np.int64)
+    cls = rng.integers(-1, K, N).astype(np.int8)
+    host = img.float() if dt == "bf16" else img
+    got = cx.cluster_indices(_t(img, dev), _t(pix, dev), _t(cls, dev), K, p=p)
+    ref = oracle.cluster_indices(host.numpy() if dt == "bf16" else host, pix, cls, K, p=p)
+    for name in ("centroids", "scatter", "dist", "dbi_pairs", "dunn_pairs"):
+        a, b = getattr(got, name), ref[name]
+        assert np.max(np.abs(a - b)) <= 1e-12 * max(np.max(np.abs(b)), 1e-300), name
+    assert abs(got.dbi - ref["dbi"]) <= 1e-12 * abs(ref["dbi"])
+    assert abs(got.dunn - ref["dunn"]) <= 1e-12 * abs(ref["dunn"])
+    # bit for bit repeatable
+    again = cx.cluster_indices(_t(img, dev), _t(pix, dev), _t(cls, dev), K, p=p)
+    assert np.array_equal(again.scatter, got.scatter) and again.dbi == got.dbi
+
+
+def test_cluster_indices_closed_form_and_one_image(dev):
+    say("cluster indices: closed form, one H x W image")
+    import paper_1612_06457_amd as cx
+    import torch
+    img = torch.tensor([[0, 2, 10, 12], [99, 99, 99, 99]], dtype=torch.uint8, device=dev)
+    pix = torch.tensor([0, 1, 2, 3, 4], dtype=torch.int64, device=dev)
+    cls = torch.tensor([0, 0, 1, 1, -1], dtype=torch.int8, device=dev)
+    r = cx.cluster_indices(img, pix, cls, 2)
+    assert r.centroids.tolist() == [[1.0], [11.0]] and r.scatter.tolist() == [1.0, 1.0]
+    assert r.dbi == 0.2 and r.dunn == 8.0
+
+
+def test_cluster_indices_on_cva_images(dev):
+    """The paper's assessment: 8-bit CVA components of a page, underwriting
+    against parchment points; many points per class and several blocks."""
+    say("cluster indices on the CVA images of a page")
+    import paper_1612_06457_amd as cx
+    c = make_case(2, scale=0.25)
+    cd = _t(c.cube, dev)
+    fit = cx.cva_fit(cd, _t(c.labels, dev), c.K)
+    q = cx.cva_project(cd, fit.W, fit.mean)
+    flat = c.labels.reshape(-1)
+    pix = np.flatnonzero(flat >= 0).astype(np.int64)
+    cls = flat[pix].astype(np.int8)
+    qh = q.cpu().numpy()
+    got = cx.cluster_indices(q, _t(pix, dev), _t(cls, dev), c.K)
+    ref = oracle.cluster_indices(qh, pix, cls, c.K)
+    assert np.max(np.abs(got.dbi_pairs - ref["dbi_pairs"])) <= 1e-12 * np.max(np.abs(ref["dbi_pairs"]))
+    assert abs(got.dbi - ref["dbi"]) <= 1e-12 * ref["dbi"]
+    # the components separate the classes better than any single raw band
+    raw = np.ascontiguousarray(np.moveaxis(c.cube, -1, 0))
+    best_band = min(oracle.cluster_indices(raw[b:b + 1], pix, cls, c.K)["dbi"] for b in range(raw.shape[0]))
+    say(f"  DBI: CVA images {got.dbi:.4f}, best raw band {best_band:.4f}")
+    assert got.dbi < best_band
+
+
+def test_cluster_indices_errors(dev):
+    say("cluster indices: errors")
+    import paper_1612_06457_amd as cx
+    import torch
+    img = torch.zeros((1, 8, 8), dtype=torch.uint8, device=dev)
+    pix = torch.tensor([0, 1, 2], dtype=torch.int64, device=dev)
+    with pytest.raises(cx.CvamxError) as e:
+        cx.cluster_indices(img, pix, torch.tensor([0, 0, 0], dtype=torch.int8, device=dev), 2)
+    assert e.value.status == -3                                      # empty class
+    with pytest.raises(cx.CvamxError) as e:
+        cx.cluster_indices(img, pix, torch.tensor([0, 1, 5], dtype=torch.int8, device=dev), 2)
+    assert e.value.status == -1                                      # class outside
+    with pytest.raises(cx.CvamxError) as e:
+        cx.cluster_indices(img, torch.tensor([0, 1, 64], dtype=torch.int64, device=dev),
+                           torch.tensor([0, 1, 1], dtype=torch.int8, device=dev), 2)
+    assert e.value.status == -1                                      # pixel outside
+    with pytest.raises(cx.CvamxError):
+        cx.cluster_indices(img, pix, torch.tensor([0, 1, 1], dtype=torch.int8, device=dev), 2, p=0.5)
+    r = cx.cluster_indices(img, pix, torch.tensor([0, 1, 1], dtype=torch.int8, device=dev), 2)
+    assert r.scatter.tolist() == [0.0, 0.0]

@@ -219,6 +219,26 @@ def test_argument_checks_without_a_device():
         assert lib.cvamx_compose_rgb(ctx, y, y, y, 10, None, None) == L.E_INVALID_ARG
         assert lib.cvamx_compose_rgb(ctx, y, y, y, 0, out, None) == L.E_INVALID_ARG
         assert lib.cvamx_compose_rgb(ctx, None, y, None, 10, out, None) == L.E_DEVICE
+        # cluster indices
+        sc = np.empty(2)
+
+        def ci(img=y, dt=L.DT_U8, P=64, n=1, pix=pts, cl=cls, N=10, K=2, p=2.0, scores=sc.ctypes.data):
+            return lib.cvamx_cluster_indices(ctx, img, dt, P, n, pix, cl, N, K, p, None, None, None, None, None,
+                                             scores, None)
+
+        assert ci(img=None) == L.E_INVALID_ARG
+        assert ci(scores=None) == L.E_INVALID_ARG
+        assert ci(dt=9) == L.E_UNSUPPORTED
+        assert ci(P=0) == L.E_INVALID_ARG
+        assert ci(n=0) == L.E_INVALID_ARG
+        assert ci(N=0) == L.E_INVALID_ARG
+        assert ci(K=1) == L.E_INVALID_ARG
+        assert ci(p=0.5) == L.E_INVALID_ARG
+        assert ci(p=float("inf")) == L.E_INVALID_ARG
+        assert ci(dt=L.DT_F32, img=ctypes.c_void_p(0x60002)) == L.E_UNSUPPORTED
+        assert ci(pix=ctypes.c_void_p(0x40004)) == L.E_UNSUPPORTED
+        assert ci(cl=ctypes.c_void_p(0x50008)) == L.E_UNSUPPORTED
+        assert ci(img=ctypes.c_void_p(0x60001)) == L.E_DEVICE          # bytes need no alignment
     finally:
         lib.cvamx_destroy(ctx)
     assert lib.cvamx_status_str(L.E_NOT_PD) == b"within-class scatter not positive definite"

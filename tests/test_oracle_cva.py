@@ -363,6 +363,67 @@ def test_compose_rgb_layout():
     assert (two[..., 1] == two[..., 2]).all() and (two[..., 0] == g).all()
 
 
+# ------------------------------------------------- DB and Dunn indices (Sec. 3)
+
+def test_cluster_indices_two_clusters_closed_form():
+    # {0, 2} and {10, 12}: centroids 1 and 11, scatters 1 and 1, M = 10
+    img = np.array([[0, 2, 10, 12, 99]], dtype=np.uint8)
+    r = oracle.cluster_indices(img, [0, 1, 2, 3, 4], [0, 0, 1, 1, -1], 2)
+    assert r["centroids"].tolist() == [[1.0], [11.0]]
+    assert r["scatter"].tolist() == [1.0, 1.0]
+    assert r["dist"][0, 1] == 10.0 and r["dist"][1, 0] == 10.0
+    assert r["dbi_pairs"][0, 1] == 0.2 and r["dbi"] == 0.2            # (1 + 1) / 10
+    assert r["dunn_pairs"][0, 1] == 8.0 and r["dunn"] == 8.0          # (10 - 1 - 1) / 1
+    assert r["counts"].tolist() == [2, 2]
+
+
+def test_cluster_indices_three_clusters_by_hand():
+    # centroids 0, 10, 30 with scatters 1, 2, 3 (points c - s, c + s)
+    vals = [-1, 1, 8, 12, 27, 33]
+    r = oracle.cluster_indices(np.array([vals], dtype=np.float64), range(6), [0, 0, 1, 1, 2, 2], 3)
+    assert np.allclose(r["scatter"], [1, 2, 3], rtol=0, atol=1e-15)
+    R = r["dbi_pairs"]
+    assert abs(R[0, 1] - 3 / 10) < 1e-15 and abs(R[0, 2] - 4 / 30) < 1e-15 and abs(R[1, 2] - 5 / 20) < 1e-15
+    assert abs(r["dbi"] - (0.3 + 0.3 + 0.25) / 3) < 1e-15
+    assert abs(r["dunn"] - min(10 - 3, 30 - 4, 20 - 5) / 3) < 1e-15
+    assert abs(r["dunn_pairs"][1, 2] - (20 - 5) / 3) < 1e-15
+
+
+def test_cluster_indices_brute_force_norms_and_invariance():
+    rng = np.random.default_rng(21)
+    img = rng.normal(size=(3, 40, 30))
+    pix = rng.choice(1200, 300, replace=False)
+    cls = rng.integers(-1, 4, 300)
+    for p in (1.0, 2.0, 3.0):
+        r = oracle.cluster_indices(img, pix, cls, 4, p=p)
+        flat = img.reshape(3, -1)
+        for k in range(4):
+            pts = [flat[:, q] for q, c in zip(pix, cls) if c == k]
+            A = [sum(v[f] for v in pts) / len(pts) for f in range(3)]
+            S = sum(sum(abs(v[f] - A[f]) ** p for f in range(3)) ** (1 / p) for v in pts) / len(pts)
+            assert abs(r["scatter"][k] - S) <= 1e-12 * S
+        a0, a1 = r["centroids"][0], r["centroids"][1]
+        assert abs(r["dist"][0, 1] - sum(abs(a0 - a1) ** p) ** (1 / p)) <= 1e-12 * r["dist"][0, 1]
+        # scale and shift of every feature leave the ratios unchanged
+        r2 = oracle.cluster_indices(7.0 * img - 3.0, pix, cls, 4, p=p)
+        assert np.allclose(r2["dbi_pairs"], r["dbi_pairs"], rtol=1e-12, atol=0)
+        assert np.allclose(r2["dunn_pairs"], r["dunn_pairs"], rtol=1e-12, atol=1e-12)
+    # p = 1 and p = 2 on two-dimensional points (0, 0), (2, 2): A = (1, 1)
+    img2 = np.array([[0, 2, 5, 5], [0, 2, 9, 9]], dtype=np.float64)
+    assert oracle.cluster_indices(img2, [0, 1, 2, 3], [0, 0, 1, 1], 2, p=1.0)["scatter"][0] == 2.0
+    assert abs(oracle.cluster_indices(img2, [0, 1, 2, 3], [0, 0, 1, 1], 2)["scatter"][0] - np.sqrt(2)) < 1e-15
+
+
+def test_cluster_indices_errors():
+    img = np.zeros((1, 10))
+    with pytest.raises(ValueError):
+        oracle.cluster_indices(img, [0, 1], [0, 2], 2)          # class outside
+    with pytest.raises(ValueError):
+        oracle.cluster_indices(img, [0, 10], [0, 1], 2)         # pixel outside
+    with pytest.raises(ValueError):
+        oracle.cluster_indices(img, [0, 1], [0, 0], 2)          # empty class
+
+
 # ----------------------------------------------------------- sign and errors
 
 def test_sign_rule():
