@@ -223,6 +223,56 @@ int cvamx_stretch(cvamx_ctx* ctx, const float* y, int64_t P, int32_t n_comp,
 int cvamx_compose_rgb(cvamx_ctx* ctx, const uint8_t* r, const uint8_t* g,
                       const uint8_t* b, int64_t P, uint8_t* rgb, void* stream);
 
+/* ---- pages as image stacks, many pages ------------------------------------ */
+
+/* A page's band images as read from one image file per band (paper
+ * Section 2: the multispectral images of a page, 8-bit), band-sequential
+ * (B planes of P pixels), into the band-interleaved page the other calls
+ * read.  uint8 and uint16 bands give a CVAMX_U16 page (values kept),
+ * float32 bands a CVAMX_F32 page.
+ *   bands    device, B x P, in_dtype (CVAMX_U8, CVAMX_U16, CVAMX_F32),
+ *            aligned to its element size (16-byte aligned, P % 4 == 0 for
+ *            full-width loads)
+ *   cube     device, P x B (uint16, or float32 for float bands), 16-byte
+ *            aligned
+ * Asynchronous on `stream`. */
+int cvamx_bands_to_cube(cvamx_ctx* ctx, const void* bands, int32_t in_dtype,
+                        int32_t B, int64_t P, void* cube, void* stream);
+
+/* One page of a batch for cvamx_run_pages.  All pointers are host memory;
+ * page-locked memory (hipHostMalloc) lets its copies overlap the other
+ * pages' work (ordinary memory works, without the overlap). */
+typedef struct {
+  const void* bands;        /* B x height x width band-sequential, in_dtype */
+  const int64_t* pixels;    /* n_points training pixel indices (y * width + x) */
+  const int8_t* classes;    /* n_points classes, -1 = skip */
+  int64_t n_points;
+  void* images;             /* out: n_comp x height x width, uint8 or uint16 */
+  double* W;                /* out: bands x n_comp, or NULL */
+  double* eigvals;          /* out: n_comp, or NULL */
+  double* range;            /* out: 2 * n_comp (a_j, b_j) of the stretch, or NULL */
+  int32_t status;           /* out: CVAMX_OK or this page's error code */
+} cvamx_page;
+
+/* CVA enhancement of many pages of one geometry (paper Section 4: a whole
+ * manuscript, pages re-run with other training points): per page, the
+ * band images to the page (cvamx_bands_to_cube), the fit from its points
+ * (cva_fit_points), the float images (cvamx_project_float) and the
+ * stretch (cvamx_stretch with mode, pct, bits; mode 2 takes the page's
+ * points of any class).  The next page's host-to-device copy and the
+ * previous page's image copy run on their own streams, overlapped with the
+ * current page's kernels and its host eigensolve.  A page whose pointers
+ * or sizes are bad, or whose fit fails (e.g. an empty class), gets that
+ * status and the batch goes on; a device error stops the batch and is
+ * returned.  Device memory: two staging slots of the band images and the
+ * points, one page, its float images and two image slots, freed on return.
+ * Synchronises `stream`. */
+int cvamx_run_pages(cvamx_ctx* ctx, int32_t in_dtype, int32_t bands,
+                    int64_t height, int64_t width, int32_t K, int32_t n_comp,
+                    int32_t prec, double ridge, int32_t mode, double pct,
+                    int32_t bits, cvamx_page* pages, int32_t n_pages,
+                    void* stream);
+
 /* ---- numerical assessment ------------------------------------------------ */
 
 /* Cluster-separation indices of labelled points on a set of images (paper

@@ -5,13 +5,13 @@ The computation lives in libcvamx.so (hand-written HIP kernels plus an FP64
 host finisher behind a C ABI, declared in include/cvamx.h); this package is
 a thin ctypes binding over torch tensors.
 """
-from .api import (ClusterIndices, CvaFit, SoftFit, SoftCVA, cluster_indices, compose_rgb, cva_fit,
-                  cva_fit_points, cva_project, cva_soft_backward, cva_soft_forward, cva_solve_moments, pca_fit, pca_project, profile_enable,
-                  profile_report, project_float, stretch, sym_eig)
+from .api import (ClusterIndices, CvaFit, SoftFit, SoftCVA, bands_to_cube, cluster_indices, compose_rgb,
+                  cva_fit, cva_fit_points, cva_project, cva_soft_backward, cva_soft_forward, cva_solve_moments,
+                  pca_fit, pca_project, profile_enable, profile_report, project_float, run_pages, stretch,
+                  sym_eig)
 from ._lib import CvamxError, LIB_PATH
 
-__all__ = ["ClusterIndices", "CvaFit", "SoftFit", "SoftCVA", "cluster_indices", "compose_rgb", "project_float",
-           "stretch", "cva_fit", "cva_fit_points", "cva_project", "cva_soft_backward",
-           "cva_soft_forward", "cva_solve_moments", "pca_fit", "pca_project", "profile_enable",
-           "profile_report", "sym_eig",
-           "CvamxError", "LIB_PATH"]
+__all__ = ["ClusterIndices", "CvaFit", "SoftFit", "SoftCVA", "bands_to_cube", "cluster_indices", "compose_rgb",
+           "cva_fit", "cva_fit_points", "cva_project", "cva_soft_backward", "cva_soft_forward", "cva_solve_moments",
+           "pca_fit", "pca_project", "profile_enable", "profile_report", "project_float", "run_pages", "stretch",
+           "sym_eig", "CvamxError", "LIB_PATH"]

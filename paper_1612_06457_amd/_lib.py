@@ -40,6 +40,12 @@ class Cube(ctypes.Structure):
                 ("dtype", ctypes.c_int32)]
 
 
+class Page(ctypes.Structure):
+    _fields_ = [("bands", ctypes.c_void_p), ("pixels", ctypes.c_void_p), ("classes", ctypes.c_void_p),
+                ("n_points", ctypes.c_int64), ("images", ctypes.c_void_p), ("W", ctypes.c_void_p),
+                ("eigvals", ctypes.c_void_p), ("range", ctypes.c_void_p), ("status", ctypes.c_int32)]
+
+
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
@@ -58,6 +64,9 @@ EXPORTS = {
     "cvamx_project_float": (ctypes.c_int, [_vp, ctypes.POINTER(Cube), _vp, _vp, _i32, _vp, _vp]),
     "cvamx_stretch": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _f64, _vp, _i64, _i32, _vp, _vp, _vp]),
     "cvamx_compose_rgb": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp]),
+    "cvamx_bands_to_cube": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i64, _vp, _vp]),
+    "cvamx_run_pages": (ctypes.c_int, [_vp, _i32, _i32, _i64, _i64, _i32, _i32, _i32, _f64, _i32, _f64, _i32,
+                                       ctypes.POINTER(Page), _i32, _vp]),
     "cvamx_cluster_indices": (ctypes.c_int, [_vp, _vp, _i32, _i64, _i32, _vp, _vp, _i64, _i32, _f64,
                                              _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pca_fit": (ctypes.c_int, [_vp, ctypes.POINTER(Cube), _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),

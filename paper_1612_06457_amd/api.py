@@ -234,6 +234,75 @@ def compose_rgb(r: Optional[torch.Tensor], g: Optional[torch.Tensor], b: Optiona
     return rgb
 
 
+_BAND_DTYPES = {torch.uint8: _lib.DT_U8, torch.uint16: _lib.DT_U16, torch.float32: _lib.DT_F32}
+
+
+def bands_to_cube(bands: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """A page's band images, band-sequential B x H x W (uint8, uint16 or
+    float32, on the device), as the band-interleaved H x W x B page
+    (uint16 for 8/16-bit bands, float32 for float bands)."""
+    if bands.dtype not in _BAND_DTYPES or bands.dim() != 3 or not bands.is_contiguous():
+        raise ValueError("bands must be a contiguous B x H x W uint8, uint16 or float32 tensor")
+    B, H, W = bands.shape
+    odt = torch.float32 if bands.dtype == torch.float32 else torch.uint16
+    if out is None:
+        out = torch.empty((H, W, B), dtype=odt, device=bands.device)
+    elif out.dtype != odt or tuple(out.shape) != (H, W, B) or not out.is_contiguous() or out.device != bands.device:
+        raise ValueError("out must be a contiguous H x W x B tensor of the page type on the bands' device")
+    dev = _dev_index(bands)
+    ctx = context(dev)
+    st = lib().cvamx_bands_to_cube(ctx, _ptr(bands), _BAND_DTYPES[bands.dtype], B, H * W, _ptr(out),
+                                   _stream(bands.device))
+    check(st, ctx)
+    return out
+
+
+def run_pages(pages, K: int, n_comp: Optional[int] = None, precision: str = "fp32", ridge: float = 0.0,
+              mode: str = "minmax", pct: float = 1.0, bits: int = 8, device: int = 0):
+    """CVA enhancement of many pages of one geometry, copies overlapped with
+    compute.  pages: a list of dicts with host tensors 'bands' (B x H x W
+    uint8 / uint16 / float32; page-locked memory, e.g. pin_memory=True,
+    for the overlap), 'pixels' (int64 N) and 'classes' (int8 N).  Returns
+    one dict per page: 'images' (n_comp x H x W, uint8 or uint16, in
+    page-locked host memory), 'W', 'eigvals', 'range' and 'status' (0 = ok;
+    a page whose fit failed keeps its error code and no images)."""
+    if not pages:
+        raise ValueError("no pages")
+    b0 = pages[0]["bands"]
+    if b0.dtype not in _BAND_DTYPES or b0.dim() != 3:
+        raise ValueError("bands must be B x H x W uint8, uint16 or float32")
+    B, H, W = b0.shape
+    C = min(K - 1, B)
+    n_comp = C if n_comp is None else int(n_comp)
+    odt = torch.uint8 if bits == 8 else torch.uint16
+    arr = (_lib.Page * len(pages))()
+    keep, outs = [], []
+    for i, pg in enumerate(pages):
+        bands, pix, cls = pg["bands"], pg["pixels"], pg["classes"]
+        if bands.dtype != b0.dtype or tuple(bands.shape) != (B, H, W) or bands.device.type != "cpu" \
+                or not bands.is_contiguous():
+            raise ValueError(f"page {i}: bands must be a contiguous host tensor like page 0's")
+        if pix.dtype != torch.int64 or cls.dtype != torch.int8 or pix.dim() != 1 \
+                or tuple(cls.shape) != tuple(pix.shape) or pix.device.type != "cpu" or cls.device.type != "cpu":
+            raise ValueError(f"page {i}: pixels must be host int64 N and classes host int8 N")
+        pix, cls = pix.contiguous(), cls.contiguous()
+        images = torch.empty((n_comp, H, W), dtype=odt, pin_memory=True)
+        o = {"images": images, "W": np.empty((B, n_comp)), "eigvals": np.empty(n_comp),
+             "range": np.empty((n_comp, 2))}
+        arr[i] = _lib.Page(bands.data_ptr(), pix.data_ptr(), cls.data_ptr(), int(pix.numel()), images.data_ptr(),
+                           o["W"].ctypes.data, o["eigvals"].ctypes.data, o["range"].ctypes.data, 0)
+        keep += [bands, pix, cls]
+        outs.append(o)
+    ctx = context(device)
+    st = lib().cvamx_run_pages(ctx, _BAND_DTYPES[b0.dtype], B, H, W, K, n_comp, _lib.PREC[precision],
+                               float(ridge), STRETCH_MODES[mode], float(pct), bits, arr, len(pages),
+                               _stream(torch.device("cuda", device)))
+    check(st, ctx)
+    for i, o in enumerate(outs):
+        o["status"] = int(arr[i].status)
+    return outs
+
+
 @dataclass
 class ClusterIndices:
     centroids: np.ndarray   # K x n

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "ctx_internal.hpp"
 #include "cvamx.h"
 #include "finisher.h"
 #include "launch.hpp"
@@ -339,6 +340,11 @@ int project_common(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, cons
 }
 
 }  // namespace
+
+namespace cvamx {
+int set_error(cvamx_ctx* ctx, int code, const std::string& msg) { return fail(ctx, code, msg); }
+int ctx_device(const cvamx_ctx* ctx) { return ctx ? ctx->device : -1; }
+}  // namespace cvamx
 
 extern "C" {
 
@@ -721,6 +727,28 @@ int cvamx_compose_rgb(cvamx_ctx* ctx, const uint8_t* r, const uint8_t* g, const 
   hipError_t e = cvx::launch_compose_rgb(r, g, b, P, rgb, ctx->num_cu, s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "compose launch");
+  return 0;
+}
+
+int cvamx_bands_to_cube(cvamx_ctx* ctx, const void* bands, int32_t in_dtype, int32_t B, int64_t P, void* cube,
+                        void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (!bands || !cube) return fail(ctx, CVAMX_E_INVALID_ARG, "bands and cube must be non-NULL");
+  if (in_dtype != CVAMX_U8 && in_dtype != CVAMX_U16 && in_dtype != CVAMX_F32)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "band images must be uint8, uint16 or float32");
+  if (B < 1 || B > CVAMX_MAX_BANDS) return fail(ctx, CVAMX_E_INVALID_ARG, "B must lie in 1..CVAMX_MAX_BANDS");
+  if (P < 1 || P >= (int64_t(1) << 31) - 1) return fail(ctx, CVAMX_E_INVALID_ARG, "P must lie in 1..2^31-2");
+  const size_t ein = in_dtype == CVAMX_U8 ? 1 : (in_dtype == CVAMX_U16 ? 2 : 4);
+  if ((reinterpret_cast<uintptr_t>(bands) & (ein - 1)) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "bands must be aligned to their element size");
+  if ((reinterpret_cast<uintptr_t>(cube) & 15u) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "cube must be 16-byte aligned");
+  if (int st = check_device(ctx)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  prof_begin(ctx, s, "bands_to_cube");
+  hipError_t e = cvx::launch_bands_to_cube(in_dtype, bands, B, P, cube, s);
+  prof_end(ctx, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "bands launch");
   return 0;
 }
 

@@ -127,6 +127,10 @@ hipError_t launch_cluster_moments(int dtype, const void* img, int64_t P, int n, 
                                   const int32_t* offsets, const int64_t* counts, int K, int G, double p,
                                   double* part, double* sums, double* dsum, hipStream_t s);
 
+// band-sequential stack (B planes of P; uint8, uint16 or float32) to the
+// band-interleaved page (uint16 for 8/16-bit bands, float32 for float)
+hipError_t launch_bands_to_cube(int in_dtype, const void* bands, int B, int64_t P, void* cube, hipStream_t s);
+
 // soft-label CVA
 hipError_t launch_soft_first(const float* X, const float* w, int64_t N, int B, int K,
                              int nblocks, double* part, unsigned* ticket, double* first,

@@ -1,0 +1,163 @@
+"""GPU tests of the band-sequential import and the many-page pipeline,
+through the C ABI.
+
+Bars: the band-interleaved page equals the transposed stack exactly; every
+page of a batch gives, bit for bit, what the single calls give on that page
+(same kernels, fixed reduction orders), whatever its slot and neighbours;
+its fit matches the FP64 oracle as the single fit does; a page whose fit
+fails reports its error and leaves the other pages intact.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import make_case
+from tests._cases import full_page
+from tests._parity import TOL_LAM, check_images, check_vectors
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1612_06457_amd  # noqa: F401  (raises if the library is missing)
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    import torch
+    if hasattr(a, "to"):
+        return a.contiguous().to(dev)
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+@pytest.mark.parametrize("dt", ["u8", "u16", "f32"])
+@pytest.mark.parametrize("H,W,B", [(37, 53, 33), (64, 64, 23), (16, 16, 64), (1, 1, 1), (100, 256, 7),
+                                   (3, 5, 2)])
+def test_bands_to_cube(dev, dt, H, W, B):
+    say(f"bands to cube {dt} H={H} W={W} B={B}")
+    import paper_1612_06457_amd as cx
+    import torch
+    rng = np.random.default_rng(H * W + B)
+    if dt == "u8":
+        bands = rng.integers(0, 256, (B, H, W), dtype=np.uint8)
+    elif dt == "u16":
+        bands = rng.integers(0, 65536, (B, H, W), dtype=np.uint16)
+    else:
+        bands = rng.normal(size=(B, H, W)).astype(np.float32)
+    want = np.moveaxis(bands, 0, -1)
+    got = cx.bands_to_cube(_t(bands, dev)).cpu().numpy()
+    assert got.dtype == (np.float32 if dt == "f32" else np.uint16)
+    assert np.array_equal(got, want)
+    # band images starting off their 16-byte alignment take the element path
+    tb = _t(bands, dev)
+    big = torch.empty(tb.numel() + 1, dtype=tb.dtype, device=dev)
+    mis = big[1:].view(B, H, W)
+    mis.copy_(tb)
+    assert np.array_equal(cx.bands_to_cube(mis).cpu().numpy(), want)
+
+
+def _page(seed, K=3, drop_class=None):
+    """A small page as 8-bit band images plus its training points."""
+    import torch
+    c = make_case(1, scale=0.25, seed=seed) if seed is not None else make_case(1, scale=0.25)
+    cube8 = (c.cube >> 4).astype(np.uint8)                          # H x W x B, 8-bit values
+    bands = torch.from_numpy(np.ascontiguousarray(np.moveaxis(cube8, -1, 0))).pin_memory()
+    flat = c.labels.reshape(-1)
+    pix = np.flatnonzero(flat >= 0).astype(np.int64)
+    cls = flat[pix].astype(np.int8)
+    rng = np.random.default_rng(seed or 0)
+    order = rng.permutation(pix.size)
+    pix, cls = pix[order], cls[order]
+    if drop_class is not None:
+        cls = cls.copy()
+        cls[cls == drop_class] = -1
+    return {"bands": bands, "pixels": torch.from_numpy(pix), "classes": torch.from_numpy(cls),
+            "cube8": cube8}
+
+
+def _single(cx, dev, pg, K, n_comp, mode, pct, bits):
+    """The same page through the single calls."""
+    cube = cx.bands_to_cube(_t(pg["bands"], dev))
+    fit = cx.cva_fit_points(cube, _t(pg["pixels"], dev), _t(pg["classes"], dev), K, n_comp=n_comp)
+    y = cx.project_float(cube, fit.W, fit.mean)
+    train = None
+    if mode == "training":
+        cls = pg["classes"].numpy()
+        train = _t(pg["pixels"].numpy()[cls >= 0], dev)
+    q, rng = cx.stretch(y, mode, pct=pct, train_pixels=train, bits=bits, return_range=True)
+    return fit, q.cpu().numpy(), rng
+
+
+@pytest.mark.parametrize("mode,pct,bits", [("minmax", 0.0, 8), ("percentile", 1.0, 16), ("training", 0.0, 8)])
+def test_run_pages_matches_single_calls(dev, mode, pct, bits):
+    say(f"run_pages {mode} bits={bits}")
+    import paper_1612_06457_amd as cx
+    K = 3
+    pages = [_page(s) for s in (11, 12, 13, 14, 15)]
+    out = cx.run_pages(pages, K, mode=mode, pct=pct, bits=bits)
+    for i, (pg, o) in enumerate(zip(pages, out)):
+        assert o["status"] == 0, f"page {i}: status {o['status']}"
+        fit, q, rng = _single(cx, dev, pg, K, None, mode, pct, bits)
+        assert np.array_equal(o["W"], fit.W) and np.array_equal(o["eigvals"], fit.eigvals)
+        assert np.array_equal(o["images"].numpy(), q), f"page {i}: images differ from the single calls"
+        assert np.array_equal(o["range"], rng)
+
+
+def test_run_pages_against_oracle_and_failures(dev):
+    say("run_pages: oracle parity, a failing page and a bad page")
+    import paper_1612_06457_amd as cx
+    import torch
+    K = 3
+    pages = [_page(21), _page(22, drop_class=2), _page(23)]
+    bad = dict(_page(24))
+    bad["pixels"] = torch.zeros(0, dtype=torch.int64)
+    bad["classes"] = torch.zeros(0, dtype=torch.int8)
+    pages.append(bad)
+    pages.append(_page(25))
+    out = cx.run_pages(pages, K)
+    assert [o["status"] for o in out] == [0, -3, 0, -1, 0]
+    for i in (0, 2, 4):
+        pg = pages[i]
+        ref = oracle.cva_fit_points(pg["cube8"].astype(np.uint16), pg["pixels"].numpy(), pg["classes"].numpy(), K)
+        assert np.max(np.abs(out[i]["eigvals"] - ref["eigvals"]) / ref["eigvals"]) <= TOL_LAM
+        signs, _ = check_vectors(out[i]["W"], ref["W"], ref["eigvals"])
+        q_ref, _ = oracle.cva_project(pg["cube8"].astype(np.uint16), ref["W"], ref["mean"])
+        check_images(out[i]["images"].numpy(), q_ref, signs)
+
+
+def test_run_pages_full_size(dev):
+    """Four 7216 x 5412 pages of 33 8-bit bands, as the page stacks of the
+    paper's manuscript would arrive: every page equals the single calls."""
+    say("run_pages: four full-size 8-bit pages")
+    import paper_1612_06457_amd as cx
+    import torch
+    c = full_page()
+    cube8 = (c.cube >> 4).astype(np.uint8)
+    bands = torch.from_numpy(np.ascontiguousarray(np.moveaxis(cube8, -1, 0))).pin_memory()
+    del cube8
+    flat = c.labels.reshape(-1)
+    pix = np.flatnonzero(flat >= 0).astype(np.int64)
+    cls = flat[pix].astype(np.int8)
+    pages = []
+    for s in range(4):
+        keep = np.random.default_rng(s).random(pix.size) < 0.9          # other training points per page
+        pages.append({"bands": bands, "pixels": torch.from_numpy(pix[keep].copy()),
+                      "classes": torch.from_numpy(cls[keep].copy())})
+    out = cx.run_pages(pages, c.K)
+    for i, (pg, o) in enumerate(zip(pages, out)):
+        assert o["status"] == 0
+        fit, q, rng = _single(cx, dev, pg, c.K, None, "minmax", 0.0, 8)
+        assert np.array_equal(o["W"], fit.W)
+        assert np.array_equal(o["images"].numpy(), q), f"page {i}"
+        assert np.array_equal(o["range"], rng)

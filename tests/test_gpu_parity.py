@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 from synth import make_case, make_soft_case, to_half_cube
+from tests._cases import full_page
 from tests._parity import (TOL_LAM, TOL_S, TOL_Y, check_images, check_vectors, rel_max)
 
 pytestmark = pytest.mark.gpu
@@ -335,7 +336,7 @@ def test_full_page_cfg5(dev):
     fit parity, every pixel of the 7 projected images, and PCA."""
     say("cfg5 full page 7216x5412x33 u16 K=8")
     import paper_1612_06457_amd as cx
-    c = make_case(5, threads=16)
+    c = full_page()
     say("cfg5 generated")
     ref, got, signs = _fit_parity(c.cube, c.labels, c.K, dev)
     say("cfg5 fit ok", got.eigvals)
@@ -492,7 +493,7 @@ def test_full_page_cfg5_mixed(dev):
     compensated scatter on MFMA, FP64 eigensolve; PCA on all pixels."""
     say("cfg5 full page, bf16x3")
     import paper_1612_06457_amd as cx
-    c = make_case(5, threads=16)
+    c = full_page()
     cube = _t(c.cube, dev)
     ref, got = _mixed_fit_check(cube, c.cube, c.labels, c.K, dev, "bf16x3", BOUND_EXACT)
     say("cfg5 mixed fit ok", got.eigvals)

@@ -20,6 +20,7 @@ import pytest
 
 import oracle
 from synth import make_case, to_half_cube
+from tests._cases import full_page
 from oracle.stretch import _quantise
 from tests._parity import TOL_Y, check_images
 
@@ -325,7 +326,7 @@ def test_full_page_percentile_cfg5(dev):
     16-bit images on sampled pixels against the oracle's map."""
     say("cfg5 full page: float planes, percentile and 16-bit stretch")
     import paper_1612_06457_amd as cx
-    c = make_case(5)
+    c = full_page()
     cd = _t(c.cube, dev)
     fit = cx.cva_fit(cd, _t(c.labels, dev), c.K)
     y = cx.project_float(cd, fit.W, fit.mean)

@@ -239,6 +239,30 @@ def test_argument_checks_without_a_device():
         assert ci(pix=ctypes.c_void_p(0x40004)) == L.E_UNSUPPORTED
         assert ci(cl=ctypes.c_void_p(0x50008)) == L.E_UNSUPPORTED
         assert ci(img=ctypes.c_void_p(0x60001)) == L.E_DEVICE          # bytes need no alignment
+        # band images and page batches
+        cb = ctypes.c_void_p(0x90000)
+        assert lib.cvamx_bands_to_cube(ctx, None, L.DT_U8, 8, 64, cb, None) == L.E_INVALID_ARG
+        assert lib.cvamx_bands_to_cube(ctx, y, L.DT_BF16, 8, 64, cb, None) == L.E_UNSUPPORTED
+        assert lib.cvamx_bands_to_cube(ctx, y, L.DT_U8, 65, 64, cb, None) == L.E_INVALID_ARG
+        assert lib.cvamx_bands_to_cube(ctx, y, L.DT_U8, 8, 0, cb, None) == L.E_INVALID_ARG
+        assert lib.cvamx_bands_to_cube(ctx, ctypes.c_void_p(0x60001), L.DT_U16, 8, 64, cb, None) == L.E_UNSUPPORTED
+        assert lib.cvamx_bands_to_cube(ctx, y, L.DT_U8, 8, 64, ctypes.c_void_p(0x90008), None) == L.E_UNSUPPORTED
+        assert lib.cvamx_bands_to_cube(ctx, ctypes.c_void_p(0x60001), L.DT_U8, 8, 64, cb, None) == L.E_DEVICE
+        pg = (L.Page * 2)()
+
+        def rp(dt=L.DT_U8, B=8, H=16, W=16, K=3, n_comp=2, mode=1, bits=8, pages=pg, n=2):
+            return lib.cvamx_run_pages(ctx, dt, B, H, W, K, n_comp, 0, 0.0, mode, 1.0, bits, pages, n, None)
+
+        assert rp(pages=None) == L.E_INVALID_ARG
+        assert rp(n=0) == L.E_INVALID_ARG
+        assert rp(dt=L.DT_F16) == L.E_UNSUPPORTED
+        assert rp(B=0) == L.E_INVALID_ARG
+        assert rp(H=0) == L.E_INVALID_ARG
+        assert rp(K=1) == L.E_INVALID_ARG
+        assert rp(n_comp=3) == L.E_INVALID_ARG
+        assert rp(mode=5) == L.E_INVALID_ARG
+        assert rp(bits=4) == L.E_INVALID_ARG
+        assert rp() == L.E_DEVICE
     finally:
         lib.cvamx_destroy(ctx)
     assert lib.cvamx_status_str(L.E_NOT_PD) == b"within-class scatter not positive definite"
