@@ -84,6 +84,87 @@ def cpu_baseline(case, min_seconds: float = 10.0):
     return pixbands / per / 1e9, per, threads, sample, per1
 
 
+def fit_last(cx, cube, labels, K):
+    return cx.cva_fit(cube, labels, K)
+
+
+def _timed(torch, fn, reps=5):
+    """Median milliseconds of fn() over reps runs, HIP events on torch's
+    current stream (the one the library launches on)."""
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def extras(cx, torch, case, cube, fit, dev):
+    """Timings of the calls beyond the headline path on the same page:
+    float images, the three rescaling modes, 16-bit output, the RGB
+    composite, the cluster indices, the band-sequential import and the
+    many-page pipeline (host-resident pages, so its rate includes PCIe)."""
+    H, W, B, K = case.H, case.W, case.B, case.K
+    P, C = H * W, K - 1
+    res = {}
+
+    def rec(name, ms, nbytes):
+        res[name] = {"ms": round(ms, 4), "algorithmic_MB": round(nbytes / 1e6, 1),
+                     "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+
+    y = torch.empty((C, H, W), dtype=torch.float32, device=dev)
+    rec("project_float", _timed(torch, lambda: cx.project_float(cube, fit.W, fit.mean, out=y)),
+        P * B * 2 + P * C * 4)
+    q8 = torch.empty((C, H, W), dtype=torch.uint8, device=dev)
+    q16 = torch.empty((C, H, W), dtype=torch.uint16, device=dev)
+    rec("stretch_minmax_8bit", _timed(torch, lambda: cx.stretch(y, "minmax", out=q8)), 2 * P * C * 4 + P * C)
+    flat = case.labels.reshape(-1)
+    train = torch.from_numpy(np.flatnonzero(flat >= 0).astype(np.int64)).to(dev)
+    rec("stretch_training_8bit", _timed(torch, lambda: cx.stretch(y, "training", train_pixels=train, out=q8)),
+        P * C * 4 + P * C + train.numel() * (8 + 4 * C))
+    # four radix passes read every value once each, then the stretch pass
+    rec("stretch_percentile_16bit", _timed(torch, lambda: cx.stretch(y, "percentile", pct=1.0, bits=16, out=q16)),
+        5 * P * C * 4 + P * C * 2)
+    rec("compose_rgb", _timed(torch, lambda: cx.compose_rgb(q8[0], q8[1], q8[2])), 6 * P)
+    cls = torch.from_numpy(flat[flat >= 0].astype(np.int8)).to(dev)
+    rec("cluster_indices_7x8bit", _timed(torch, lambda: cx.cluster_indices(q8, train, cls, K)),
+        train.numel() * (8 + 1 + 2 * C))
+    bands8 = torch.from_numpy(np.ascontiguousarray(np.moveaxis((case.cube >> 4).astype(np.uint8), -1, 0)))
+    b8 = bands8.to(dev)
+    page = torch.empty((H, W, B), dtype=torch.uint16, device=dev)
+    rec("bands_to_cube_8bit", _timed(torch, lambda: cx.bands_to_cube(b8, out=page)), P * B * 3)
+    del b8, page, y, q16
+    # many pages: three host-resident 8-bit pages, batched (copies overlapped)
+    # against one call per page
+    pinned = bands8.pin_memory()
+    del bands8
+    pix = torch.from_numpy(np.flatnonzero(flat >= 0).astype(np.int64))
+    pcls = torch.from_numpy(flat[flat >= 0].astype(np.int8))
+    pages = [{"bands": pinned, "pixels": pix, "classes": pcls} for _ in range(3)]
+    cx.run_pages(pages[:1], K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outp = cx.run_pages(pages, K)
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for pg in pages:
+        cx.run_pages([pg], K)
+    t_single = time.perf_counter() - t0
+    assert all(o["status"] == 0 for o in outp)
+    res["run_pages_3x8bit"] = {
+        "batched_ms_per_page": round(t_batch * 1e3 / 3, 2),
+        "one_call_per_page_ms": round(t_single * 1e3 / 3, 2),
+        "pcie_inclusive_Gpix_band_per_s": round(P * B / (t_batch / 3) / 1e9, 2),
+        "host_to_device_MB_per_page": round(P * B / 1e6, 1),
+        "device_to_host_MB_per_page": round(P * C / 1e6, 1)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +173,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "f16x3"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the timings of the rescaling, colour, assessment and many-page calls")
     ap.add_argument("--copy-gib", type=int, default=0,
                     help="after the timed steps, copy this many GiB device to device (a plain copy of "
                          "known size, to calibrate hardware byte counters against)")
@@ -233,6 +316,8 @@ def main():
         "kernels_ms_per_launch": {k: round(v[1] / max(v[0], 1), 4) for k, v in prof.items()},
         "roofline": roof,
     }
+    if not args.no_extras:
+        out["extras"] = extras(cx, torch, case, cube, fit_last(cx, cube, labels, K), dev)
     if args.copy_gib > 0:
         src = torch.ones(args.copy_gib << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

@@ -266,7 +266,8 @@ typedef struct {
  * status and the batch goes on; a device error stops the batch and is
  * returned.  Device memory: two staging slots of the band images and the
  * points, one page, its float images and two image slots, freed on return.
- * Synchronises `stream`. */
+ * The batch runs on streams of its own after draining `stream`, and
+ * returns when every page is done. */
 int cvamx_run_pages(cvamx_ctx* ctx, int32_t in_dtype, int32_t bands,
                     int64_t height, int64_t width, int32_t K, int32_t n_comp,
                     int32_t prec, double ridge, int32_t mode, double pct,

@@ -45,6 +45,9 @@ struct cvamx_ctx {
   std::vector<hipEvent_t> ev_pool;
   std::vector<Pending> pending;
   std::map<std::string, std::pair<long, double>> prof_acc;
+  // state of the page batches (pipeline.cpp), freed through module_free
+  void* module = nullptr;
+  void (*module_free)(void*) = nullptr;
 };
 
 namespace {
@@ -94,6 +97,13 @@ int ensure_pinned(cvamx_ctx* ctx, size_t bytes) {
   ctx->pinned = p;
   ctx->pinned_cap = std::max<size_t>(bytes, 4096);
   return 0;
+}
+
+// Small results into the context's page-locked staging buffer.  A kernel
+// writes them, not the copy engines, so they never wait behind a large
+// transfer queued on another stream.
+hipError_t to_pinned(cvamx_ctx* ctx, const void* src, size_t bytes, hipStream_t s) {
+  return cvx::launch_copy_out(ctx->pinned, src, (int64_t)bytes, s);
 }
 
 hipEvent_t get_event(cvamx_ctx* ctx) {
@@ -331,8 +341,7 @@ int project_common(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, cons
   if (int st = proj_groups(ctx, cube, W, center, n_comp, images, s)) return st;
   if (range) {
     if (int st = ensure_pinned(ctx, 2 * sizeof(float) * n_comp)) return st;
-    HIP_TRY(hipMemcpyAsync(ctx->pinned, ctx->ab_dev, 2 * sizeof(float) * n_comp, hipMemcpyDeviceToHost, s),
-            "range copy");
+    HIP_TRY(to_pinned(ctx, ctx->ab_dev, 2 * sizeof(float) * n_comp, s), "range copy");
     HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
     std::memcpy(range, ctx->pinned, 2 * sizeof(float) * n_comp);
   }
@@ -344,6 +353,8 @@ int project_common(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, cons
 namespace cvamx {
 int set_error(cvamx_ctx* ctx, int code, const std::string& msg) { return fail(ctx, code, msg); }
 int ctx_device(const cvamx_ctx* ctx) { return ctx ? ctx->device : -1; }
+void** ctx_module_state(cvamx_ctx* ctx) { return &ctx->module; }
+void ctx_set_module_free(cvamx_ctx* ctx, void (*fn)(void*)) { ctx->module_free = fn; }
 }  // namespace cvamx
 
 extern "C" {
@@ -416,6 +427,7 @@ void cvamx_destroy(cvamx_ctx* ctx) {
   if (ctx->device >= 0) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    if (ctx->module && ctx->module_free) ctx->module_free(ctx->module);
     for (int b = 0; b < B_COUNT; ++b)
       if (ctx->buf[b]) (void)hipFree(ctx->buf[b]);
     if (ctx->tickets) (void)hipFree(ctx->tickets);
@@ -452,7 +464,7 @@ static int build_index(cvamx_ctx* ctx, const int8_t* labels, const int64_t* poin
   const int nT = (int)((n + cvx::kLabelTile - 1) / cvx::kLabelTile);
   if (int st = ensure(ctx, B_TILECNT, (size_t)nT * K * 4)) return st;
   if (int st = ensure(ctx, B_IDX, (size_t)n * 4)) return st;
-  HIP_TRY(hipMemsetAsync(res + lay.err, 0, 8, s), "memset");
+  HIP_TRY(cvx::launch_zero_u32(reinterpret_cast<uint32_t*>(res + lay.err), 2, s), "flag clear");
   hipError_t e;
   prof_begin(ctx, s, "label_count");
   e = cvx::launch_label_count(labels, n, K, nT, (int32_t*)ctx->buf[B_TILECNT], (int32_t*)(res + lay.err), s);
@@ -497,7 +509,7 @@ static int fit_from_index(cvamx_ctx* ctx, const cvamx_cube* cube, int32_t K, int
   e = cvx::launch_reduce_part((const double*)ctx->buf[B_PART], K, G, L, (double*)(res + lay.gram), s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
-  HIP_TRY(hipMemcpyAsync(ctx->pinned, res, lay.total, hipMemcpyDeviceToHost, s), "result copy");
+  HIP_TRY(to_pinned(ctx, res, lay.total, s), "result copy");
   HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
 
   const char* h = static_cast<const char*>(ctx->pinned);
@@ -669,7 +681,7 @@ int cvamx_stretch(cvamx_ctx* ctx, const float* y, int64_t P, int32_t n_comp, int
     if (e != hipSuccess) return hip_fail(ctx, e, "min/max launch");
     if (mode == CVAMX_STRETCH_TRAINING) {
       if (int st = ensure_pinned(ctx, 16)) return st;
-      HIP_TRY(hipMemcpyAsync(ctx->pinned, err, 4, hipMemcpyDeviceToHost, s), "flag copy");
+      HIP_TRY(to_pinned(ctx, err, 4, s), "flag copy");
       HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
       int32_t flag = 0;
       std::memcpy(&flag, ctx->pinned, 4);
@@ -709,7 +721,7 @@ int cvamx_stretch(cvamx_ctx* ctx, const float* y, int64_t P, int32_t n_comp, int
   if (e != hipSuccess) return hip_fail(ctx, e, "stretch launch");
   if (range) {
     if (int st = ensure_pinned(ctx, 2 * sizeof(double) * n_comp)) return st;
-    HIP_TRY(hipMemcpyAsync(ctx->pinned, ab, 2 * sizeof(double) * n_comp, hipMemcpyDeviceToHost, s), "range copy");
+    HIP_TRY(to_pinned(ctx, ab, 2 * sizeof(double) * n_comp, s), "range copy");
     HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
     std::memcpy(range, ctx->pinned, 2 * sizeof(double) * n_comp);
   }
@@ -792,7 +804,7 @@ int cvamx_cluster_indices(cvamx_ctx* ctx, const void* images, int32_t dtype, int
                                              (double*)(res + lay.shift), s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "cluster moments launch");
-  HIP_TRY(hipMemcpyAsync(ctx->pinned, res, lay.total, hipMemcpyDeviceToHost, s), "result copy");
+  HIP_TRY(to_pinned(ctx, res, lay.total, s), "result copy");
   HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
   const char* h = static_cast<const char*>(ctx->pinned);
   int32_t errflag;
@@ -880,7 +892,7 @@ int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t
   e = cvx::launch_reduce_part((const double*)ctx->buf[B_PART], 1, nblocks, L, (double*)(res + 8 * B), s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
-  HIP_TRY(hipMemcpyAsync(ctx->pinned, res, res_bytes, hipMemcpyDeviceToHost, s), "result copy");
+  HIP_TRY(to_pinned(ctx, res, res_bytes, s), "result copy");
   HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
   const double* shift = static_cast<const double*>(ctx->pinned);
   std::vector<double> G1;
@@ -951,7 +963,7 @@ int cva_soft_forward(cvamx_ctx* ctx, const float* X, const float* w, int64_t N, 
   e = cvx::launch_reduce_part((const double*)ctx->buf[B_PART], K, G, L, (double*)(res + gram_off), s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
-  HIP_TRY(hipMemcpyAsync(ctx->pinned, res, res_bytes, hipMemcpyDeviceToHost, s), "result copy");
+  HIP_TRY(to_pinned(ctx, res, res_bytes, s), "result copy");
   HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
   const char* h = static_cast<const char*>(ctx->pinned);
   const float* mcf = reinterpret_cast<const float*>(h + mcf_off);

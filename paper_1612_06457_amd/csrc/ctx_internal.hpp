@@ -7,6 +7,10 @@
 namespace cvamx {
 // Store msg as the context's last error and return code.
 int set_error(cvamx_ctx* ctx, int code, const std::string& msg);
-// The context's device (-1: none) and its compute-unit count.
+// The context's device (-1: none).
 int ctx_device(const cvamx_ctx* ctx);
+// Per-context state of a host module (the page batches): a pointer the
+// module owns, freed through fn by cvamx_destroy once the device is idle.
+void** ctx_module_state(cvamx_ctx* ctx);
+void ctx_set_module_free(cvamx_ctx* ctx, void (*fn)(void*));
 }  // namespace cvamx

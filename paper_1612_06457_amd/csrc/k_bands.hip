@@ -73,7 +73,33 @@ __global__ __launch_bounds__(kBlock) void k_bands_to_cube(const Tin* __restrict_
   }
 }
 
+// Small result regions to page-locked host memory, written by the kernel
+// itself (16-byte stores when both ends allow).  A DMA copy would queue
+// behind whatever large transfer the copy engines are busy with (for
+// example the next page's upload), stalling the host's FP64 finish.
+__global__ __launch_bounds__(kBlock) void k_copy_out(unsigned char* __restrict__ dst,
+                                                     const unsigned char* __restrict__ src, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15) == 0) {
+    const int64_t n16 = n / 16;
+    for (int64_t i = i0; i < n16; i += stride)
+      reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
+    for (int64_t i = 16 * n16 + i0; i < n; i += stride) dst[i] = src[i];
+  } else {
+    for (int64_t i = i0; i < n; i += stride) dst[i] = src[i];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_copy_out(void* dst, const void* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t chunks = (n + 16 * kBlock - 1) / (16 * kBlock);
+  const unsigned nb = (unsigned)(chunks < 64 ? chunks : 64);
+  hipLaunchKernelGGL(k_copy_out, dim3(nb), dim3(kBlock), 0, s, (unsigned char*)dst, (const unsigned char*)src, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_bands_to_cube(int in_dtype, const void* bands, int B, int64_t P, void* cube, hipStream_t s) {
   if (B < 1 || B > kMaxB || P < 1) return hipErrorInvalidValue;

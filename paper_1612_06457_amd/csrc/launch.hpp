@@ -131,6 +131,9 @@ hipError_t launch_cluster_moments(int dtype, const void* img, int64_t P, int n, 
 // band-interleaved page (uint16 for 8/16-bit bands, float32 for float)
 hipError_t launch_bands_to_cube(int in_dtype, const void* bands, int B, int64_t P, void* cube, hipStream_t s);
 
+// n bytes from device memory to page-locked host memory, by a kernel
+hipError_t launch_copy_out(void* dst, const void* src, int64_t n, hipStream_t s);
+
 // soft-label CVA
 hipError_t launch_soft_first(const float* X, const float* w, int64_t N, int B, int K,
                              int nblocks, double* part, unsigned* ticket, double* first,
