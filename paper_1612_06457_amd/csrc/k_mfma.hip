@@ -86,6 +86,143 @@ __global__ __launch_bounds__(kBlock) void k_pca_gram_mfma(const void* __restrict
   block_combine<NRB>(accd, B, scale, red, part + (int64_t)blockIdx.x * packed_doubles(B));
 }
 
+// uint16 pages: exact fp16 operands built with bit operations.  With
+// x = 1024 h + l (h: 6 bits, l: 10 bits) and the integer shift
+// c = 1024 c_h + c_l, v = (x - c) / 1024 = (h - c_h) + (l - c_l) / 1024:
+// the fp16 with bits 0x6400 | h is 1024 + h and the one with bits
+// 0x3c00 | l is 1 + l / 1024, so one AND-OR and one packed fp16 add give
+// each term exactly, two pixels per dword.  Every product of two terms is
+// exact in FP32 (at most 22 significant bits); the Gram of v is summed as
+// H H + H L + L H + L L on v_mfma_f32_16x16x32_f16 and unscaled by 2^20 in
+// FP64.  The ones column holds 1 in the L term.  Rows that hold no pixel
+// (the page's end, the mask) are zeroed by a per-pixel mask, computed only
+// for tiles that need it.
+struct U16Masks {
+  uint32_t lo, hi, exp_l, exp_h;   // 0x03ff03ff, 0x003f003f, 0x3c003c00, 0x64006400
+};
+__device__ __forceinline__ U16Masks make_u16_masks() {
+  U16Masks m{0x03ff03ffu, 0x003f003fu, 0x3c003c00u, 0x64006400u};
+  asm volatile("" : "+v"(m.lo), "+v"(m.hi), "+v"(m.exp_l), "+v"(m.exp_h));   // registers: VOP3 takes no literal
+  return m;
+}
+
+__device__ __forceinline__ uint32_t pk_add_f16(uint32_t a, uint32_t b) {
+  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(h2, a) + __builtin_bit_cast(h2, b));
+}
+
+template <int NRB>
+__global__ __launch_bounds__(kBlock) void k_pca_gram_u16(const void* __restrict__ cube, int B, int64_t P,
+                                                         const uint8_t* __restrict__ mask,
+                                                         double* __restrict__ part,
+                                                         double* __restrict__ shift_out) {
+  constexpr int Q = 4 * NRB < kMaxQ ? 4 * NRB : kMaxQ;   // chunks per lane: S <= 16 NRB - 1 dwords
+  extern __shared__ __align__(16) uint32_t lds[];
+  __shared__ float cs[kMaxB];
+  __shared__ uint8_t vrow[kWaves][128];
+  const int S = Geo<DT_U16>::S(B), g2 = Geo<DT_U16>::g2(B);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, grp = lane >> 4;
+  uint32_t* my = lds + w * 64 * S;
+  double* red = reinterpret_cast<double*>(lds);
+  const uint16_t* cx = reinterpret_cast<const uint16_t*>(cube);
+
+  // shift: integer mean of 64 pixels spread evenly over the page, fixed order
+  for (int b = threadIdx.x; b < B; b += kBlock) {
+    float x[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) x[i] = (float)cx[((int64_t)i * P / 64) * B + b];
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < 64; ++i) s += x[i];
+    const float c = rintf(s / 64.f);
+    cs[b] = c;
+    if (blockIdx.x == 0) shift_out[b] = (double)c;
+  }
+  __syncthreads();
+
+  // per row block: this lane's band, its load column, the negated shift terms
+  // and the masks that keep real bands and put 1 in the ones column
+  int bcol[NRB];
+  uint32_t nh[NRB], nl[NRB], keep[NRB], ones[NRB];
+#pragma unroll
+  for (int rb = 0; rb < NRB; ++rb) {
+    const int band = 16 * rb + col;
+    bcol[rb] = band < B ? band : B - 1;
+    const uint32_t c = band < B ? (uint32_t)cs[band] : 0u;
+    const uint32_t h = __builtin_bit_cast(uint16_t, (_Float16)(-(1024.f + (float)(c >> 10))));
+    const uint32_t l = __builtin_bit_cast(uint16_t, (_Float16)(-(1.f + (float)(c & 1023u) / 1024.f)));
+    nh[rb] = h | (h << 16);
+    nl[rb] = l | (l << 16);
+    keep[rb] = band < B ? 0xffffffffu : 0u;
+    ones[rb] = band == B ? 0x3c003c00u : 0u;
+  }
+  const U16Masks mk = make_u16_masks();
+
+  constexpr int NP = npairs(NRB);
+  f32x4 acc[NP];
+  double accd[NP][4];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      acc[p][e] = 0.f;
+      accd[p][e] = 0.0;
+    }
+  const int tp = 64 * g2;
+  const int64_t nt = (P + tp - 1) / tp;
+  const int64_t total_bytes = P * B * 2;
+  const unsigned char* base = reinterpret_cast<const unsigned char*>(cube);
+  for_each_tile<Q>(base, total_bytes, nt, S, my, [&](int64_t t) {
+    const int64_t pix0 = t * tp;
+    const bool full = pix0 + tp <= P && mask == nullptr;
+    if (!full) {
+      for (int r = lane; r < tp; r += 64) {
+        const int64_t p = pix0 + r;
+        vrow[w][r] = (p < P && (mask == nullptr || mask[p] != 0)) ? 1 : 0;
+      }
+      wave_lds_sync();
+    }
+    const uint16_t* tile = reinterpret_cast<const uint16_t*>(my);
+    for (int k0 = 0; k0 < tp; k0 += 32) {
+      f16x8 Hv[NRB], Lv[NRB];
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb) {
+        u32x4 H, L;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = k0 + 8 * grp + 2 * u;
+          const uint32_t d = (uint32_t)tile[r * B + bcol[rb]] | ((uint32_t)tile[(r + 1) * B + bcol[rb]] << 16);
+          uint32_t m = keep[rb], on = ones[rb];
+          if (!full) {
+            const uint32_t rm = (vrow[w][r] ? 0x0000ffffu : 0u) | (vrow[w][r + 1] ? 0xffff0000u : 0u);
+            m &= rm;
+            on &= rm;
+          }
+          H[u] = pk_add_f16(((d >> 10) & mk.hi) | mk.exp_h, nh[rb]) & m;
+          L[u] = (pk_add_f16((d & mk.lo) | mk.exp_l, nl[rb]) & m) | on;
+        }
+        Hv[rb] = __builtin_bit_cast(f16x8, H);
+        Lv[rb] = __builtin_bit_cast(f16x8, L);
+      }
+      int p = 0;
+#pragma unroll
+      for (int ri = 0; ri < NRB; ++ri) {
+#pragma unroll
+        for (int rj = ri; rj < NRB; ++rj, ++p) {
+          acc[p] = SplitT<1>::mma(Lv[ri], Lv[rj], acc[p]);   // smallest terms first
+          acc[p] = SplitT<1>::mma(Hv[ri], Lv[rj], acc[p]);
+          acc[p] = SplitT<1>::mma(Lv[ri], Hv[rj], acc[p]);
+          acc[p] = SplitT<1>::mma(Hv[ri], Hv[rj], acc[p]);
+        }
+      }
+    }
+    fold<NRB>(acc, accd);
+  });
+  __syncthreads();
+  block_combine<NRB>(accd, B, 1.f / 1024.f, red, part + (int64_t)blockIdx.x * packed_doubles(B));
+}
+
 template <int DT, int SPLIT>
 hipError_t pca_launch_dt(const void* cube, int B, int64_t P, const uint8_t* mask, int nblocks, double* part,
                          double* shift_out, hipStream_t s) {
@@ -109,11 +246,34 @@ hipError_t pca_launch_dt(const void* cube, int B, int64_t P, const uint8_t* mask
   return hipGetLastError();
 }
 
+hipError_t pca_launch_u16(const void* cube, int B, int64_t P, const uint8_t* mask, int nblocks, double* part,
+                          double* shift_out, hipStream_t s) {
+  const int S = Geo<DT_U16>::S(B);
+  const size_t sm = std::max((size_t)kWaves * 64 * S * 4, packed_doubles(B) * 8);
+  switch (nrb_for(B)) {
+    case 2:
+      hipLaunchKernelGGL((k_pca_gram_u16<2>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, mask, part,
+                         shift_out);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_pca_gram_u16<3>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, mask, part,
+                         shift_out);
+      break;
+    default:
+      hipLaunchKernelGGL((k_pca_gram_u16<5>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, mask, part,
+                         shift_out);
+      break;
+  }
+  return hipGetLastError();
+}
+
 template <int SPLIT>
 hipError_t pca_launch(int dtype, const void* cube, int B, int64_t P, const uint8_t* mask, int nblocks,
                       double* part, double* shift_out, hipStream_t s) {
   switch (dtype) {
-    case DT_U16: return pca_launch_dt<DT_U16, SPLIT>(cube, B, P, mask, nblocks, part, shift_out, s);
+    // uint16 pages: the exact bit-built operands whatever split was asked
+    // (every product is exact either way)
+    case DT_U16: return pca_launch_u16(cube, B, P, mask, nblocks, part, shift_out, s);
     case DT_F32: return pca_launch_dt<DT_F32, SPLIT>(cube, B, P, mask, nblocks, part, shift_out, s);
     case DT_BF16: return pca_launch_dt<DT_BF16, SPLIT>(cube, B, P, mask, nblocks, part, shift_out, s);
     case DT_F16: return pca_launch_dt<DT_F16, SPLIT>(cube, B, P, mask, nblocks, part, shift_out, s);
