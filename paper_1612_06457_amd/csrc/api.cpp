@@ -33,7 +33,7 @@ struct cvamx_ctx {
   size_t cap[B_COUNT] = {};
   void* pinned = nullptr;
   size_t pinned_cap = 0;
-  unsigned* tickets = nullptr;   // [0] projection range, [1] soft first moments
+  unsigned* tickets = nullptr;   // [0] projection range
   float* range_dev = nullptr;    // 16 floats: scale[8], offset[8] of the current group
   float* ab_dev = nullptr;       // 2 * CVAMX_MAX_BANDS floats: (min, max) per component
   // kernel timing (cvamx_profile_enable)
@@ -939,22 +939,31 @@ int cva_soft_forward(cvamx_ctx* ctx, const float* X, const float* w, int64_t N, 
   hipStream_t s = (hipStream_t)stream;
   const int BP = cvx::padded_bp(B), KP = (K + 3) & ~3;
   const int L = cvx::tri_blocks(B) * 16;
-  const int nb1 = (int)std::max<int64_t>(1, std::min<int64_t>(2 * ctx->num_cu, (N + cvx::kChunk - 1) / cvx::kChunk));
-  const int G = std::max(1, std::min(128, 1024 / K));
+  const int64_t nch = (N + cvx::kChunk - 1) / cvx::kChunk;
+  const int nb1 = (int)std::max<int64_t>(1, std::min<int64_t>(2 * ctx->num_cu, nch));
+  // pass 2: about two blocks per CU over all class groups of four
+  const int groups = (K + cvx::kWaves - 1) / cvx::kWaves;
+  const int G = (int)std::max<int64_t>(1, std::min<int64_t>(2 * ctx->num_cu / groups, nch));
   const size_t first_bytes = 8 * (size_t)K * (B + 1);
   const size_t mcf_off = first_bytes;
   const size_t gram_off = (mcf_off + 4 * (size_t)K * B + 7) & ~size_t(7);
   const size_t res_bytes = gram_off + 8 * (size_t)K * L;
-  if (int st = ensure(ctx, B_FIRST, (size_t)nb1 * KP * BP * 8)) return st;
+  // pass-1 scratch: block partials, then their reduction
+  const size_t fp_off = (size_t)nb1 * KP * BP * 8;
+  if (int st = ensure(ctx, B_FIRST, fp_off + (size_t)KP * BP * 8)) return st;
   if (int st = ensure(ctx, B_PART, (size_t)K * G * L * 8)) return st;
   if (int st = ensure(ctx, B_RES, res_bytes)) return st;
   if (int st = ensure_pinned(ctx, res_bytes)) return st;
   char* res = static_cast<char*>(ctx->buf[B_RES]);
+  char* f1 = static_cast<char*>(ctx->buf[B_FIRST]);
   prof_begin(ctx, s, "soft_first");
-  hipError_t e = cvx::launch_soft_first(X, w, N, B, K, nb1, (double*)ctx->buf[B_FIRST], ctx->tickets + 1,
-                                        (double*)res, (float*)(res + mcf_off), s);
+  hipError_t e = cvx::launch_soft_first(X, w, N, B, K, nb1, (double*)f1, s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "soft first launch");
+  e = cvx::launch_reduce_part((const double*)f1, 1, nb1, KP * BP, (double*)(f1 + fp_off), s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
+  e = cvx::launch_soft_means(B, K, (const double*)(f1 + fp_off), (double*)res, (float*)(res + mcf_off), s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "class means launch");
   prof_begin(ctx, s, "soft_scatter");
   e = cvx::launch_soft_scatter(X, w, N, B, K, G, (const float*)(res + mcf_off), (double*)ctx->buf[B_PART], s);
   prof_end(ctx, s);

@@ -3,20 +3,22 @@
 // the paper's CVA (Section 2, canonical variates paragraph).
 //
 // Forward, two passes over X:
-//   1. n_c = sum_p w_pc and t_c = sum_p w_pc x_p (register-tiled w^T [X, 1]);
-//      the last block combines the block partials in a fixed order and
-//      stores the class means m_c = t_c / n_c;
+//   1. n_c = sum_p w_pc and t_c = sum_p w_pc x_p (register-tiled w^T [X, 1])
+//      into block partials; the partials are combined by the fixed-order
+//      reduction, and a one-block kernel stores the class means
+//      m_c = t_c / n_c;
 //   2. per class, the weighted augmented Gram of [x - m_c, 1]: sum w d d^T,
-//      sum w d and sum w (d = x - float(m_c)); the host removes the tiny
-//      offset between float(m_c) and m_c exactly.
+//      sum w d and sum w (d = x - float(m_c)) on the matrix cores (see
+//      k_soft_scatter_mfma); the host removes the tiny offset between
+//      float(m_c) and m_c exactly.
 // Both passes stream chunks of kChunk rows of X and of w through a block-wide
 // prefetching driver: the next chunk's 16-byte loads are in flight while the
-// current chunk is accumulated (pass 1); pass 2 is bound by its register
-// tiles' LDS reads and stages rows directly.
+// current chunk is accumulated.
 // Backward: per pixel, u = x - m, z_j = w_j^T u for the C canonical
 // vectors, and dJ/dw_pc = sum_j z_j^2 - sum_j (1 + lambda_j)(z_j - d_jc)^2
 // with d_jc = w_j^T (m_c - m).
 #include "k_gram.hpp"
+#include "k_split.hpp"
 #include "k_tile.hpp"
 #include "launch.hpp"
 
@@ -74,9 +76,7 @@ __device__ __forceinline__ void for_each_chunk(const float* __restrict__ X, cons
 }
 
 __global__ __launch_bounds__(kBlock) void k_soft_first(const float* __restrict__ X, const float* __restrict__ W,
-                                                       int64_t N, int B, int K, double* __restrict__ part,
-                                                       unsigned* __restrict__ ticket, double* __restrict__ first,
-                                                       float* __restrict__ mc_f) {
+                                                       int64_t N, int B, int K, double* __restrict__ part) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int BP = (B + 1 + 3) & ~3, KP = (K + 3) & ~3;
   float* xs = reinterpret_cast<float*>(smem_raw);                 // kChunk x BP: [x, 1]
@@ -84,7 +84,6 @@ __global__ __launch_bounds__(kBlock) void k_soft_first(const float* __restrict__
   uint32_t* xr = reinterpret_cast<uint32_t*>(ws + kChunk * KP);    // raw rows of X
   uint32_t* wr = xr + kChunk * B;                                  // raw rows of w
   double* red = reinterpret_cast<double*>(smem_raw);
-  __shared__ bool am_last;
   const int nbi = KP / 4, nbj = BP / 4, nblk = nbi * nbj;
   const int nslice = kBlock / nblk;
   const int blk = threadIdx.x % nblk, slice = threadIdx.x / nblk;
@@ -132,123 +131,141 @@ __global__ __launch_bounds__(kBlock) void k_soft_first(const float* __restrict__
     const int c = 4 * (bk / nbj) + e / 4, col = 4 * (bk % nbj) + e % 4;
     mine[c * BP + col] = s;
   }
-  __threadfence();   // every writer publishes its part before the ticket
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    am_last = (atomicAdd(ticket, 1u) == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (am_last) {
-    __threadfence();
-    for (int t = threadIdx.x; t < K * (B + 1); t += kBlock) {
-      const int c = t / (B + 1), col = t % (B + 1);
-      double s = 0.0;
-      for (unsigned bk = 0; bk < gridDim.x; ++bk)
-        s += __builtin_nontemporal_load(part + (int64_t)bk * L + c * BP + col);
-      first[t] = s;
-    }
-    __threadfence_block();
-    __syncthreads();
-    for (int t = threadIdx.x; t < K * B; t += kBlock) {
-      const int c = t / B, b = t % B;
-      const double n = first[c * (B + 1) + B];
-      mc_f[t] = (n != 0.0) ? (float)(first[c * (B + 1) + b] / n) : 0.f;
-    }
-    if (threadIdx.x == 0) *ticket = 0u;
-  }
 }
 
-// Pass 2, grid (G, K): block (g, c) takes chunks g, g + G, ... for class
-// c.  Bound by the LDS reads of the register tiles rather than by memory, so
-// it keeps a small LDS footprint (four blocks per CU) and stages rows
-// directly instead of through the prefetching driver.
-// Stage rows [r0, r0 + rows) of a row-major N x L float matrix into LDS
-// (kChunk x ld, zero-filled beyond `rows` and beyond L).
-__device__ __forceinline__ void stage_rows(const float* __restrict__ src, int L, int ld, int64_t r0,
-                                           int rows, float* __restrict__ dst) {
-  const int per = kChunk * L;
-  const int nel = rows * L;
-  const float* s = src + r0 * L;
-  const int rstep = kBlock / L, bstep = kBlock % L;
-  int r = threadIdx.x / L, b = threadIdx.x % L;
-  for (int e = threadIdx.x; e < per; e += kBlock) {
-    dst[r * ld + b] = (e < nel) ? s[e] : 0.f;
-    r += rstep;
-    b += bstep;
-    if (b >= L) {
-      b -= L;
-      ++r;
-    }
-  }
-  for (int e = threadIdx.x; e < kChunk * (ld - L); e += kBlock) {
-    const int rr = e / (ld - L), cc = L + e % (ld - L);
-    dst[rr * ld + cc] = 0.f;
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_soft_scatter(const float* __restrict__ X,
-                                                         const float* __restrict__ W, int64_t N,
-                                                         int B, int K, int G,
-                                                         const float* __restrict__ mc_f,
-                                                         double* __restrict__ part) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+// One block: from the reduced first moments (KP x BP, packed by class), the
+// moments n_c, t_c per class (first[c][0..B]) and the class means in FP32.
+__global__ __launch_bounds__(kBlock) void k_soft_means(int B, int K, const double* __restrict__ fp,
+                                                       double* __restrict__ first, float* __restrict__ mc_f) {
   const int BP = (B + 1 + 3) & ~3;
-  float* ds = reinterpret_cast<float*>(smem_raw);   // kChunk x BP: [x - m_c, 1]
-  float* as = ds + kChunk * BP;                      // kChunk x BP: w_pc * ds
-  double* red = reinterpret_cast<double*>(smem_raw);
-  __shared__ float mcs[kMaxB];
-  __shared__ float wrow[kChunk];
-  const int c = blockIdx.y, g = blockIdx.x;
-  for (int b = threadIdx.x; b < B; b += kBlock) mcs[b] = mc_f[c * B + b];
-  const int nb = BP / 4, nblk = nb * (nb + 1) / 2, nslice = kBlock / nblk;
-  const int blk = threadIdx.x % nblk, slice = threadIdx.x / nblk;
-  int bi = 0, bj = 0;
-  const bool active = slice < nslice && tri_tile(blk, nb, bi, bj);
-  float acc[16];
-  double accd[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    acc[e] = 0.f;
-    accd[e] = 0.0;
+  for (int t = threadIdx.x; t < K * (B + 1); t += kBlock) first[t] = fp[(t / (B + 1)) * BP + t % (B + 1)];
+  for (int t = threadIdx.x; t < K * B; t += kBlock) {
+    const int c = t / B, b = t % B;
+    const double n = fp[c * BP + B];
+    mc_f[t] = (n != 0.0) ? (float)(fp[c * BP + b] / n) : 0.f;
   }
-  __syncthreads();
-  const int64_t nch = (N + kChunk - 1) / kChunk;
-  for (int64_t ch = g; ch < nch; ch += G) {
-    const int64_t r0 = ch * kChunk;
-    const int rows = (N - r0 < kChunk) ? (int)(N - r0) : kChunk;
-    if (threadIdx.x < kChunk)
-      wrow[threadIdx.x] = (threadIdx.x < rows) ? W[(r0 + threadIdx.x) * K + c] : 0.f;
-    stage_rows(X, B, BP, r0, rows, ds);
-    __syncthreads();
-    for (int e = threadIdx.x; e < kChunk * BP; e += kBlock) {
-      const int r = e / BP, col = e % BP;
-      float d = 0.f;
-      if (r < rows) {
-        if (col < B) d = ds[e] - mcs[col];
-        else if (col == B) d = 1.f;
+}
+
+// Pass 2 on the matrix cores, grid (G, ceil(K / 4)): block (g, q) takes
+// chunks g, g + G, ... of X and w (through the prefetching driver) and its
+// wave v the class c = 4 q + v.  The weighted Gram of d = [x - m_c, 1] is
+// sum_p a_p d_p^T with a = w_pc d.  Each FP32 operand is split into three
+// bf16 terms, v = h + m + l with h = bf16(v), m = bf16(v - h),
+// l = bf16(v - h - m), which is exact (bf16 has FP32's exponent range, so
+// no scaling is needed and no band's values fall out of range), and the
+// products h h + h m + m h + m m + h l + l h accumulate in FP32 on
+// v_mfma_f32_16x16x32_bf16; the dropped terms are below 2^-26 of |a d|.
+// Every product is exact, so the result carries the accuracy of FP32
+// accumulation; the FP32 tiles fold into FP64 after every chunk.
+// Operand layout as in k_split.hpp: lane l holds pixel 8 (l / 16) + t, band
+// 16 r + l % 16.  Rows past N have zero weights (the partial chunk is
+// zero-filled), so they add nothing.  Each wave writes its class's partial
+// in the packed layout of the fixed-order reduction.
+__device__ __forceinline__ void split3_bf16(float v, __bf16& h, __bf16& m, __bf16& l) {
+  h = (__bf16)v;
+  const float r = v - (float)h;
+  m = (__bf16)r;
+  l = (__bf16)(r - (float)m);
+}
+
+template <int NRB, int QX, int QW>
+__global__ __launch_bounds__(kBlock) void k_soft_scatter_mfma(const float* __restrict__ X,
+                                                              const float* __restrict__ W, int64_t N, int B, int K,
+                                                              const float* __restrict__ mc_f,
+                                                              double* __restrict__ part) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  uint32_t* xr = lds;                 // kChunk x B raw rows of X
+  uint32_t* wr = lds + kChunk * B;    // kChunk x K raw rows of w
+  const int G = gridDim.x, g = blockIdx.x;
+  const int v = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, grp = lane >> 4;
+  const int c = blockIdx.y * kWaves + v;
+  const bool live = c < K;
+  using ST = SplitT<0>;
+  int bcol[NRB];
+  float mrb[NRB], onev[NRB];
+  bool real[NRB];
+#pragma unroll
+  for (int rb = 0; rb < NRB; ++rb) {
+    const int band = 16 * rb + col;
+    real[rb] = band < B;
+    bcol[rb] = band < B ? band : 0;
+    mrb[rb] = (live && band < B) ? mc_f[c * B + band] : 0.f;
+    onev[rb] = band == B ? 1.f : 0.f;
+  }
+  constexpr int NP = npairs(NRB);
+  f32x4 acc[NP];
+  double accd[NP][4];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      acc[p][e] = 0.f;
+      accd[p][e] = 0.0;
+    }
+  const float* xf = reinterpret_cast<const float*>(xr);
+  const float* wf = reinterpret_cast<const float*>(wr);
+  auto body = [&](int64_t, int) {
+    if (!live) return;
+    for (int k0 = 0; k0 < kChunk; k0 += 32) {
+      float wv[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) wv[t] = wf[(k0 + 8 * grp + t) * K + c];
+      bf16x8 ah[NRB], am[NRB], al[NRB], dh[NRB], dm[NRB], dl[NRB];
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int r = k0 + 8 * grp + t;
+          const float d = real[rb] ? xf[r * B + bcol[rb]] - mrb[rb] : onev[rb];
+          const float a = wv[t] * d;
+          __bf16 h, m, l;
+          split3_bf16(d, h, m, l);
+          dh[rb][t] = h;
+          dm[rb][t] = m;
+          dl[rb][t] = l;
+          split3_bf16(a, h, m, l);
+          ah[rb][t] = h;
+          am[rb][t] = m;
+          al[rb][t] = l;
+        }
       }
-      ds[e] = d;
-      as[e] = wrow[r] * d;
-    }
-    __syncthreads();
-    if (active) tile_acc(as, BP, ds, BP, bi, bj, slice, kChunk, nslice, acc);
-    __syncthreads();
+      int p = 0;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      accd[e] += (double)acc[e];
-      acc[e] = 0.f;
+      for (int ri = 0; ri < NRB; ++ri) {
+#pragma unroll
+        for (int rj = ri; rj < NRB; ++rj, ++p) {
+          acc[p] = ST::mma(al[ri], dh[rj], acc[p]);   // smallest terms first
+          acc[p] = ST::mma(ah[ri], dl[rj], acc[p]);
+          acc[p] = ST::mma(am[ri], dm[rj], acc[p]);
+          acc[p] = ST::mma(am[ri], dh[rj], acc[p]);
+          acc[p] = ST::mma(ah[ri], dm[rj], acc[p]);
+          acc[p] = ST::mma(ah[ri], dh[rj], acc[p]);
+        }
+      }
     }
-  }
-  __syncthreads();
-  if (active)
-    for (int e = 0; e < 16; ++e) red[(slice * nblk + blk) * 16 + e] = accd[e];
-  __syncthreads();
-  double* out = part + ((int64_t)c * G + g) * nblk * 16;
-  for (int t = threadIdx.x; t < nblk * 16; t += kBlock) {
-    double s = 0.0;
-    for (int sl = 0; sl < nslice; ++sl) s += red[sl * nblk * 16 + t];
-    out[t] = s;
+    fold<NRB>(acc, accd);
+  };
+  for_each_chunk<QX, QW>(X, W, N, B, K, g, G, xr, wr, body);
+  if (!live) return;
+  const int BP = (B + 1 + 3) & ~3, nb = BP / 4, L = nb * (nb + 1) / 2 * 16;
+  double* out = part + ((int64_t)c * G + g) * L;
+  int p = 0;
+#pragma unroll
+  for (int ri = 0; ri < NRB; ++ri) {
+#pragma unroll
+    for (int rj = ri; rj < NRB; ++rj, ++p) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int I = 16 * ri + 4 * grp + e, J = 16 * rj + col;
+        // every packed entry (4 x 4 tiles bi <= bj of the padded matrix) once
+        if ((I >> 2) <= (J >> 2) && I < BP && J < BP) {
+          const int bi = I >> 2, bj = J >> 2;
+          const int tix = bi * nb - bi * (bi - 1) / 2 + (bj - bi);
+          out[tix * 16 + (I & 3) * 4 + (J & 3)] = accd[p][e];
+        }
+      }
+    }
   }
 }
 
@@ -301,32 +318,43 @@ size_t first_smem(int B, int K) {
   return a > r ? a : r;
 }
 
-size_t scatter_smem(int B, int K) {
-  (void)K;
-  const int BP = padded_bp(B);
-  const size_t a = (size_t)2 * kChunk * BP * sizeof(float);
-  const int nblk = tri_blocks(B);
-  const size_t r = (size_t)(kBlock / nblk) * nblk * 16 * sizeof(double);
-  return a > r ? a : r;
+size_t scatter_smem(int B, int K) { return (size_t)kChunk * (B + K) * sizeof(float); }
+
+template <int NRB>
+hipError_t scatter_nrb(const float* X, const float* w, int64_t N, int B, int K, int G, const float* mc_f,
+                       double* part, hipStream_t s) {
+  const dim3 grid(G, (K + kWaves - 1) / kWaves);
+  if (B <= 40 && K <= 8)
+    hipLaunchKernelGGL((k_soft_scatter_mfma<NRB, 5, 1>), grid, dim3(kBlock), scatter_smem(B, K), s, X, w, N, B, K,
+                       mc_f, part);
+  else
+    hipLaunchKernelGGL((k_soft_scatter_mfma<NRB, 8, 4>), grid, dim3(kBlock), scatter_smem(B, K), s, X, w, N, B, K,
+                       mc_f, part);
+  return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_soft_first(const float* X, const float* w, int64_t N, int B, int K, int nblocks,
-                             double* part, unsigned* ticket, double* first, float* mc_f,
-                             hipStream_t s) {
+                             double* part, hipStream_t s) {
   if (B < 1 || B > kMaxB || K < 1 || K > 32 || nblocks < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_soft_first, dim3(nblocks), dim3(kBlock), first_smem(B, K), s, X, w, N, B, K, part, ticket,
-                     first, mc_f);
+  hipLaunchKernelGGL(k_soft_first, dim3(nblocks), dim3(kBlock), first_smem(B, K), s, X, w, N, B, K, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_soft_means(int B, int K, const double* fp, double* first, float* mc_f, hipStream_t s) {
+  hipLaunchKernelGGL(k_soft_means, dim3(1), dim3(kBlock), 0, s, B, K, fp, first, mc_f);
   return hipGetLastError();
 }
 
 hipError_t launch_soft_scatter(const float* X, const float* w, int64_t N, int B, int K, int G,
                                const float* mc_f, double* part, hipStream_t s) {
   if (B < 1 || B > kMaxB || K < 1 || K > 32 || G < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_soft_scatter, dim3(G, K), dim3(kBlock), scatter_smem(B, K), s, X, w, N, B, K, G, mc_f,
-                     part);
-  return hipGetLastError();
+  switch (nrb_for(B)) {
+    case 2: return scatter_nrb<2>(X, w, N, B, K, G, mc_f, part, s);
+    case 3: return scatter_nrb<3>(X, w, N, B, K, G, mc_f, part, s);
+    default: return scatter_nrb<5>(X, w, N, B, K, G, mc_f, part, s);
+  }
 }
 
 hipError_t launch_soft_backward(const float* X, int64_t N, int B, int K, const SoftBwdArgs& a,

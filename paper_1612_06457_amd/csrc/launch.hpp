@@ -135,11 +135,15 @@ hipError_t launch_bands_to_cube(int in_dtype, const void* bands, int B, int64_t 
 hipError_t launch_copy_out(void* dst, const void* src, int64_t n, hipStream_t s);
 
 // soft-label CVA
-hipError_t launch_soft_first(const float* X, const float* w, int64_t N, int B, int K,
-                             int nblocks, double* part, unsigned* ticket, double* first,
-                             float* mc_f, hipStream_t s);
-hipError_t launch_soft_scatter(const float* X, const float* w, int64_t N, int B, int K,
-                               int G, const float* mc_f, double* part, hipStream_t s);
+// pass 1: block partials of w^T [X, 1] (KP x BP each)
+hipError_t launch_soft_first(const float* X, const float* w, int64_t N, int B, int K, int nblocks,
+                             double* part, hipStream_t s);
+// from the reduced first moments fp (KP x BP): first[c][0..B] and the class
+// means in FP32
+hipError_t launch_soft_means(int B, int K, const double* fp, double* first, float* mc_f, hipStream_t s);
+// pass 2: per-class weighted Gram partials part[(c * G + g) * L + t]
+hipError_t launch_soft_scatter(const float* X, const float* w, int64_t N, int B, int K, int G,
+                               const float* mc_f, double* part, hipStream_t s);
 hipError_t launch_soft_backward(const float* X, int64_t N, int B, int K, const SoftBwdArgs& a,
                                 bool accumulate, int nblocks, float* dw, hipStream_t s);
 

@@ -328,6 +328,38 @@ def test_soft_label_autograd(dev):
     assert abs(float(J) - fit.J) <= 1e-12 * fit.J
 
 
+@pytest.mark.parametrize("N,B,K,xs,ws,neg", [
+    (1000, 23, 5, 1.0, 1.0, False), (100, 7, 3, 1.0, 1.0, False), (5000, 64, 32, 1.0, 1.0, False),
+    (3000, 1, 2, 1.0, 1.0, False), (4000, 33, 8, 1e5, 1e3, False), (4000, 33, 8, 1e-4, 1e-3, False),
+    (6000, 16, 4, 1.0, 1.0, True)])
+def test_soft_label_shapes_and_scales(dev, N, B, K, xs, ws, neg):
+    """Ragged and short row counts, every row-block count, class groups that
+    leave waves idle, values far outside the fp16 range either way, and
+    weights of both signs: J, eigenvalues, class means, and W^T S_w W = I
+    against the oracle's S_w."""
+    say(f"soft-label N={N} B={B} K={K} x*{xs} w*{ws} neg={neg}")
+    import paper_1612_06457_amd as cx
+    rng = np.random.default_rng(N + B + K)
+    mu = rng.uniform(800, 3500, (K, B))
+    cls = np.arange(N) % K
+    X = (mu[cls] + rng.normal(0, 60, (N, B))) * xs
+    w = rng.dirichlet(np.full(K, 0.5), N)
+    w = 0.5 * w + 0.5 * np.eye(K)[cls]
+    if neg:
+        flip = rng.random(N) < 0.1
+        w[flip] -= 0.05
+    w = w * ws
+    X, w = X.astype(np.float32), w.astype(np.float32)
+    ref = oracle.soft_fit(X, w)
+    fit = cx.cva_soft_forward(_t(X, dev), _t(w, dev))
+    assert abs(fit.J - ref["J"]) <= TOL_LAM * ref["J"]
+    assert np.max(np.abs(fit.eigvals - ref["eigvals"]) / ref["eigvals"]) <= TOL_LAM
+    assert rel_max(fit.class_means, ref["class_means"]) <= 1e-6
+    check_vectors(fit.W, ref["W"], ref["eigvals"])
+    G = fit.W.T @ ref["Sw"] @ fit.W
+    assert np.max(np.abs(G - np.eye(G.shape[0]))) <= 1e-5
+
+
 # ------------------------------------------------------------ full sizes
 
 @pytest.mark.timeout(900)
