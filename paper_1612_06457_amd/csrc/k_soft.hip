@@ -149,23 +149,17 @@ __global__ __launch_bounds__(kBlock) void k_soft_means(int B, int K, const doubl
 // Pass 2 on the matrix cores, grid (G, ceil(K / 4)): block (g, q) takes
 // chunks g, g + G, ... of X and w (through the prefetching driver) and its
 // wave v the class c = 4 q + v.  The weighted Gram of d = [x - m_c, 1] is
-// sum_p a_p d_p^T with a = w_pc d.  Each FP32 operand is split into three
-// bf16 terms, v = h + m + l with h = bf16(v), m = bf16(v - h),
-// l = bf16(v - h - m), which is exact (bf16 has FP32's exponent range, so
-// no scaling is needed and no band's values fall out of range), and the
-// products h h + h m + m h + m m + h l + l h accumulate in FP32 on
-// v_mfma_f32_16x16x32_bf16; the dropped terms are below 2^-26 of |a d|.
-// Every product is exact, so the result carries the accuracy of FP32
-// accumulation; the FP32 tiles fold into FP64 after every chunk.
-// Operand layout as in k_split.hpp: lane l holds pixel 8 (l / 16) + t, band
-// 16 r + l % 16.  Rows past N have zero weights (the partial chunk is
-// zero-filled), so they add nothing.  Each wave writes its class's partial
-// in the packed layout of the fixed-order reduction.
-__device__ __forceinline__ void split3_bf16(float v, __bf16& h, __bf16& m, __bf16& l) {
-  h = (__bf16)v;
-  const float r = v - (float)h;
-  m = (__bf16)r;
-  l = (__bf16)(r - (float)m);
+// sum_p a_p d_p^T with a = w_pc d, accumulated with the FP32 matrix
+// instruction v_mfma_f32_16x16x4_f32: FP32 operands, FP32 products and
+// accumulation, so the arithmetic is that of the plain FP32 path; the FP32
+// tiles fold into FP64 after every chunk.  Operand layout: lane l holds
+// pixel k0 + l / 16 and band 16 r + l % 16 of both operands (A[i][k] and
+// B[k][j]); the output tile as for the other MFMA shapes (rows
+// 4 (l / 16) + e, column l % 16).  Rows past N have zero weights (the partial
+// chunk is zero-filled), so they add nothing.  Each wave writes its class's
+// partial in the packed layout of the fixed-order reduction.
+__device__ __forceinline__ f32x4 mma_f32(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
 template <int NRB, int QX, int QW>
@@ -181,7 +175,6 @@ __global__ __launch_bounds__(kBlock) void k_soft_scatter_mfma(const float* __res
   const int col = lane & 15, grp = lane >> 4;
   const int c = blockIdx.y * kWaves + v;
   const bool live = c < K;
-  using ST = SplitT<0>;
   int bcol[NRB];
   float mrb[NRB], onev[NRB];
   bool real[NRB];
@@ -207,42 +200,21 @@ __global__ __launch_bounds__(kBlock) void k_soft_scatter_mfma(const float* __res
   const float* wf = reinterpret_cast<const float*>(wr);
   auto body = [&](int64_t, int) {
     if (!live) return;
-    for (int k0 = 0; k0 < kChunk; k0 += 32) {
-      float wv[8];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) wv[t] = wf[(k0 + 8 * grp + t) * K + c];
-      bf16x8 ah[NRB], am[NRB], al[NRB], dh[NRB], dm[NRB], dl[NRB];
+#pragma unroll 4
+    for (int k0 = 0; k0 < kChunk; k0 += 4) {
+      const int r = k0 + grp;
+      const float wv = wf[r * K + c];
+      float a[NRB], d[NRB];
 #pragma unroll
       for (int rb = 0; rb < NRB; ++rb) {
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int r = k0 + 8 * grp + t;
-          const float d = real[rb] ? xf[r * B + bcol[rb]] - mrb[rb] : onev[rb];
-          const float a = wv[t] * d;
-          __bf16 h, m, l;
-          split3_bf16(d, h, m, l);
-          dh[rb][t] = h;
-          dm[rb][t] = m;
-          dl[rb][t] = l;
-          split3_bf16(a, h, m, l);
-          ah[rb][t] = h;
-          am[rb][t] = m;
-          al[rb][t] = l;
-        }
+        d[rb] = real[rb] ? xf[r * B + bcol[rb]] - mrb[rb] : onev[rb];
+        a[rb] = wv * d[rb];
       }
       int p = 0;
 #pragma unroll
-      for (int ri = 0; ri < NRB; ++ri) {
+      for (int ri = 0; ri < NRB; ++ri)
 #pragma unroll
-        for (int rj = ri; rj < NRB; ++rj, ++p) {
-          acc[p] = ST::mma(al[ri], dh[rj], acc[p]);   // smallest terms first
-          acc[p] = ST::mma(ah[ri], dl[rj], acc[p]);
-          acc[p] = ST::mma(am[ri], dm[rj], acc[p]);
-          acc[p] = ST::mma(am[ri], dh[rj], acc[p]);
-          acc[p] = ST::mma(ah[ri], dm[rj], acc[p]);
-          acc[p] = ST::mma(ah[ri], dh[rj], acc[p]);
-        }
-      }
+        for (int rj = ri; rj < NRB; ++rj, ++p) acc[p] = mma_f32(a[ri], d[rj], acc[p]);
     }
     fold<NRB>(acc, accd);
   };
