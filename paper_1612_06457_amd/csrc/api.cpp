@@ -309,8 +309,8 @@ int proj_groups(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const d
     prof_end(ctx, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "project range launch");
     prof_begin(ctx, s, kStretchName[nc]);
-    e = cvx::launch_project_stretch(cube->dtype, cube->data, B, P, nc, nc, a, nblocks,
-                                    ctx->range_dev, images + (int64_t)g0 * P, s);
+    e = cvx::launch_project_stretch(cube->dtype, cube->data, B, P, nc, a, nblocks, ctx->range_dev,
+                                    images + (int64_t)g0 * P, s);
     prof_end(ctx, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "project stretch launch");
   }

@@ -33,10 +33,8 @@ hipError_t launch_project_range(int dtype, const void* cube, int B, int64_t P, i
   return project_range_generic(dtype, nc, cube, B, P, a, nblocks, part, ticket, range_dev, ab_dev, s);
 }
 
-hipError_t launch_project_stretch(int dtype, const void* cube, int B, int64_t P, int nc, int nvalid,
-                                  const ProjArgs& a, int nblocks, const float* range_dev,
-                                  uint8_t* images, hipStream_t s) {
-  (void)nvalid;
+hipError_t launch_project_stretch(int dtype, const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
+                                  int nblocks, const float* range_dev, uint8_t* images, hipStream_t s) {
   if (dtype == DT_U16) return launch_project_stretch_u16(cube, B, P, nc, a, nblocks, range_dev, images, s);
   if (dtype != DT_F32)
     return launch_project_stretch_mfma(dtype, cube, B, P, nc, a, nblocks, range_dev, images, s);

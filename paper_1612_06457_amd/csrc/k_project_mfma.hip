@@ -1,6 +1,7 @@
-// Fused centre-project-stretch on the matrix cores, for 16-bit pages
+// Fused centre-project-stretch on the matrix cores, for bf16 and fp16 pages
 // (paper Section 2: the regression coefficients multiply every band of the
 // whole page; each float image is rescaled to 0..255 on its page range).
+// uint16 pages take k_project_u16.hip.
 //
 // The projection Y = (X - c) W is a dense contraction over the bands
 // (K = B, N = components).  On gfx950 with packed FP32 off, the VALU form
@@ -10,8 +11,8 @@
 //
 //   A (16 pixels x 32 bands): lane l holds pixel l % 16, bands
 //       32 kb + 8 (l / 16) + t, t = 0..7, as (x - c) split exactly into
-//       bf16 hi + lo (x - c is an integer below 2^16 for uint16 pages, and
-//       a value of at most 16 significant bits for bf16 pages);
+//       bf16 hi + lo (x - c has at most 16 significant bits for bf16 pages,
+//       with c of the page's type);
 //   B (32 bands x 16 components): W split into three bf16 terms
 //       w1 + w2 + w3 (24 significant bits), held in registers for the
 //       whole kernel;
@@ -21,13 +22,14 @@
 // below 2^-24 of the term) accumulate in FP32, like the VALU path.  fp16
 // pages use a third term for x - c.
 //
-// The page is streamed in wave tiles exactly as in the VALU kernels
-// (coalesced 16-byte loads of 64 lane groups into the wave's LDS slice);
-// each lane then reads its pixel's 8 bands per 32-band block from LDS.
+// The page is streamed in wave tiles by the prefetching driver of
+// k_tile.hpp (coalesced 16-byte loads of 64 lane groups, the next tile's
+// loads in flight while the current one is computed); each lane then reads
+// its pixel's 8 bands per 32-band block from the wave's LDS slice.
 // Pass 1 keeps per-lane min/max for its component and the last block folds
 // the block partials; pass 2 quantises q = floor(y s + o), clamped, and
 // writes 4 consecutive pixels of one component plane per lane.
-#include "k_common.hpp"
+#include "k_tile.hpp"
 #include "launch.hpp"
 
 namespace cvx {
@@ -47,52 +49,10 @@ struct PG {
   static __device__ __host__ constexpr int S(int B) { return (B & 1) ? B : B / 2; }
 };
 
-// Issue and store one wave tile (64 lane groups, 256 S bytes) to LDS.
-__device__ __forceinline__ void fetch_tile(const unsigned char* __restrict__ base, int64_t total_bytes,
-                                           int64_t t, int S, uint32_t* __restrict__ my, int lane) {
-  const int64_t tb = t * 256 * (int64_t)S;
-  const int nchunk = 16 * S;
-  uint4 r[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    if (64 * q < nchunk) {
-      const int j = lane + 64 * q;
-      if (j < nchunk) {
-        const int64_t ob = tb + 16 * (int64_t)j;
-        if (ob + 16 <= total_bytes) {
-          r[q] = *reinterpret_cast<const uint4*>(base + ob);
-        } else {
-          uint16_t h[8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e)
-            h[e] = (ob + 2 * e + 2 <= total_bytes) ? *reinterpret_cast<const uint16_t*>(base + ob + 2 * e) : 0;
-          r[q].x = h[0] | ((uint32_t)h[1] << 16);
-          r[q].y = h[2] | ((uint32_t)h[3] << 16);
-          r[q].z = h[4] | ((uint32_t)h[5] << 16);
-          r[q].w = h[6] | ((uint32_t)h[7] << 16);
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    if (64 * q < nchunk) {
-      const int j = lane + 64 * q;
-      if (j < nchunk) *reinterpret_cast<uint4*>(my + 4 * j) = r[q];
-    }
-  }
-}
-
 // x - c for element e of the tile (16-bit storage), as an exact float.
 template <int DT>
 __device__ __forceinline__ float centred(const uint16_t* __restrict__ tile, int e, float c) {
-  const uint16_t v = tile[e];
-  if constexpr (DT == DT_U16) {
-    // 2^23 + x built bit-wise; c holds 2^23 + (integer centre)
-    return __uint_as_float((uint32_t)v | 0x4b000000u) - c;
-  } else {
-    return to_float<DT>(v) - c;
-  }
+  return to_float<DT>(tile[e]) - c;
 }
 
 // Per-lane constant operands and centres for NKB 32-band blocks.
@@ -179,9 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_range_mfma(const void* __restrict__ 
   load_ops<DT, NKB>(a, B, nc, o);
   float mn = __builtin_inff(), mx = -__builtin_inff();
   const int g = lane >> 4;
-  for (int64_t t = (int64_t)blockIdx.x * kWaves + w; t < nt; t += (int64_t)gridDim.x * kWaves) {
-    fetch_tile(base, total_bytes, t, S, my, lane);
-    wave_lds_sync();
+  for_each_tile<8 * NKB>(base, total_bytes, nt, S, my, [&](int64_t t) {
     const int64_t pix0 = t * tp;
     for (int p0 = 0; p0 < tp; p0 += 16) {
       const f32x4 y = project16<DT, NKB>(tile, p0, B, o);
@@ -193,8 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_range_mfma(const void* __restrict__ 
         }
       }
     }
-    wave_lds_sync();
-  }
+  });
   // lanes with the same component (l % 16) hold disjoint pixels
   mn = fminf(mn, __shfl_xor(mn, 16, 64));
   mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
@@ -286,9 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_stretch_mfma(const void* __restrict_
   const float of = active ? range_dev[8 + j] : 0.f;
   uint8_t* plane = images + (int64_t)(active ? j : 0) * P;
   const bool aligned4 = (P & 3) == 0 && (reinterpret_cast<uintptr_t>(images) & 3) == 0;
-  for (int64_t t = (int64_t)blockIdx.x * kWaves + w; t < nt; t += (int64_t)gridDim.x * kWaves) {
-    fetch_tile(base, total_bytes, t, S, my, lane);
-    wave_lds_sync();
+  for_each_tile<8 * NKB>(base, total_bytes, nt, S, my, [&](int64_t t) {
     const int64_t pix0 = t * tp;
     for (int p0 = 0; p0 < tp; p0 += 16) {
       const f32x4 y = project16<DT, NKB>(tile, p0, B, o);
@@ -305,8 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_stretch_mfma(const void* __restrict_
         }
       }
     }
-    wave_lds_sync();
-  }
+  });
 }
 
 // The FP32 component planes: lane (g, j) stores the 4 consecutive pixels it
@@ -329,9 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_float_mfma(const void* __restrict__ 
   const bool active = j < nc;
   float* plane = y + (int64_t)(active ? j : 0) * P;
   const bool aligned = (P & 3) == 0 && (reinterpret_cast<uintptr_t>(y) & 15) == 0;
-  for (int64_t t = (int64_t)blockIdx.x * kWaves + w; t < nt; t += (int64_t)gridDim.x * kWaves) {
-    fetch_tile(base, total_bytes, t, S, my, lane);
-    wave_lds_sync();
+  for_each_tile<8 * NKB>(base, total_bytes, nt, S, my, [&](int64_t t) {
     const int64_t pix0 = t * tp;
     for (int p0 = 0; p0 < tp; p0 += 16) {
       const f32x4 v = project16<DT, NKB>(tile, p0, B, o);
@@ -346,8 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_float_mfma(const void* __restrict__ 
         }
       }
     }
-    wave_lds_sync();
-  }
+  });
 }
 
 size_t smem(int B) { return (size_t)kWaves * 64 * ((B & 1) ? B : B / 2) * 4; }
@@ -393,7 +344,6 @@ hipError_t launch_project_range_mfma(int dtype, const void* cube, int B, int64_t
                                      hipStream_t s) {
   const int nkb = (B + 31) / 32;
   switch (dtype) {
-    case DT_U16: return range_dt<DT_U16>(nkb, cube, B, P, nc, a, nblocks, part, ticket, range_dev, ab_dev, s);
     case DT_BF16: return range_dt<DT_BF16>(nkb, cube, B, P, nc, a, nblocks, part, ticket, range_dev, ab_dev, s);
     case DT_F16: return range_dt<DT_F16>(nkb, cube, B, P, nc, a, nblocks, part, ticket, range_dev, ab_dev, s);
   }
@@ -404,7 +354,6 @@ hipError_t launch_project_stretch_mfma(int dtype, const void* cube, int B, int64
                                        int nblocks, const float* range_dev, uint8_t* images, hipStream_t s) {
   const int nkb = (B + 31) / 32;
   switch (dtype) {
-    case DT_U16: return stretch_dt<DT_U16>(nkb, cube, B, P, nc, a, nblocks, range_dev, images, s);
     case DT_BF16: return stretch_dt<DT_BF16>(nkb, cube, B, P, nc, a, nblocks, range_dev, images, s);
     case DT_F16: return stretch_dt<DT_F16>(nkb, cube, B, P, nc, a, nblocks, range_dev, images, s);
   }

@@ -132,52 +132,4 @@ __device__ __forceinline__ void for_each_tile(const unsigned char* __restrict__ 
   for_each_tile_n<Q, 64>(base, total_bytes, nt, 256 * S, my, compute);
 }
 
-// As for_each_tile, with two tiles in flight per wave: tiles t and
-// t + stride sit in two register buffers, and each one is refilled with the
-// tile two strides on as soon as it has been stored to LDS.  Both refills
-// are unconditional (clamped), for the same reason as above.
-template <int Q, typename Compute>
-__device__ __forceinline__ void for_each_tile2(const unsigned char* __restrict__ base, int64_t total_bytes,
-                                               int64_t nt, int S, uint32_t* __restrict__ my, Compute compute) {
-  const int tile_bytes = 256 * S;
-  const int tid = threadIdx.x & 63;
-  const int64_t stride = (int64_t)gridDim.x * kWaves;
-  int64_t t = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-  const int64_t nfull = total_bytes / tile_bytes;
-  if (nfull == 0) {
-    for (; t < nt; t += stride) {
-      copy_partial_tile<64>(base, total_bytes, t, tile_bytes, tid, my);
-      wave_lds_sync();
-      compute(t);
-      wave_lds_sync();
-    }
-    return;
-  }
-  // a whole tile to read next: x itself, else the current tile, else the last whole one
-  auto next = [&](int64_t x, int64_t cur) { return x < nfull ? x : (cur < nfull ? cur : nfull - 1); };
-  u32x4 r0[Q], r1[Q];
-  load_tile<Q, 64>(base, next(t, t), tile_bytes, tid, r0);
-  load_tile<Q, 64>(base, next(t + stride, t), tile_bytes, tid, r1);
-  for (; t < nt; t += 2 * stride) {
-    if (t < nfull) store_tile<Q, 64>(my, tile_bytes, tid, r0);
-    else copy_partial_tile<64>(base, total_bytes, t, tile_bytes, tid, my);
-    wave_lds_sync();
-    load_tile<Q, 64>(base, next(t + 2 * stride, t), tile_bytes, tid, r0);
-    __builtin_amdgcn_sched_barrier(0);
-    compute(t);
-    wave_lds_sync();
-    const int64_t t1 = t + stride;
-    const bool has1 = t1 < nt;
-    if (has1) {
-      if (t1 < nfull) store_tile<Q, 64>(my, tile_bytes, tid, r1);
-      else copy_partial_tile<64>(base, total_bytes, t1, tile_bytes, tid, my);
-    }
-    wave_lds_sync();
-    load_tile<Q, 64>(base, next(t1 + 2 * stride, has1 ? t1 : t), tile_bytes, tid, r1);
-    __builtin_amdgcn_sched_barrier(0);
-    if (has1) compute(t1);
-    wave_lds_sync();
-  }
-}
-
 }  // namespace cvx

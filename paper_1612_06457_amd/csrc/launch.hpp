@@ -67,9 +67,8 @@ hipError_t launch_project_range(int dtype, const void* cube, int B, int64_t P, i
                                 const ProjArgs& a, int nblocks, float* part,
                                 unsigned* ticket, float* range_dev, float* ab_dev,
                                 hipStream_t s);
-hipError_t launch_project_stretch(int dtype, const void* cube, int B, int64_t P, int nc,
-                                  int nvalid, const ProjArgs& a, int nblocks,
-                                  const float* range_dev, uint8_t* images, hipStream_t s);
+hipError_t launch_project_stretch(int dtype, const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
+                                  int nblocks, const float* range_dev, uint8_t* images, hipStream_t s);
 
 // matrix-core projection (same contract as above): uint16 pages, and
 // bf16 / fp16 pages
