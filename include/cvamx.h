@@ -142,6 +142,18 @@ int cva_project(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W,
                 const double* center, int32_t n_comp, uint8_t* images,
                 float* range, void* stream);
 
+/* cva_fit followed by cva_project with the fitted (W, mean), in one call:
+ * the projection is launched straight after the host's FP64 finish, with
+ * no return to the caller in between.  Arguments as for the two calls
+ * (W, eigvals, mean, counts required; images device n_comp x height x
+ * width uint8; range host 2*n_comp float or NULL).  Synchronises `stream`
+ * for the fit; the projection is asynchronous unless range is non-NULL. */
+int cva_fit_project(cvamx_ctx* ctx, const cvamx_cube* cube,
+                    const int8_t* labels, int32_t K, int32_t prec,
+                    double ridge, int32_t n_comp, double* W,
+                    double* eigvals, double* mean, int64_t* counts,
+                    uint8_t* images, float* range, void* stream);
+
 /* ---- PCA ---------------------------------------------------------------- */
 
 /* Covariance PCA of the page (paper Section 2, PCA paragraph: centre,

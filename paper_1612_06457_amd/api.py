@@ -61,9 +61,9 @@ class CvaFit:
     eigvals: np.ndarray      # n_comp
     mean: np.ndarray         # B
     counts: np.ndarray       # K (int64)
-    class_means: np.ndarray  # K x B
-    Sw: np.ndarray           # B x B
-    Sb: np.ndarray           # B x B
+    class_means: Optional[np.ndarray]  # K x B
+    Sw: Optional[np.ndarray]           # B x B
+    Sb: Optional[np.ndarray]           # B x B
 
 
 def cva_fit(cube: torch.Tensor, labels: torch.Tensor, K: int, precision: str = "fp32",
@@ -121,6 +121,40 @@ def cva_fit_points(cube: torch.Tensor, pixels: torch.Tensor, classes: torch.Tens
                               _ptr(counts), _ptr(cm), _ptr(Sw), _ptr(Sb), _stream(cube.device))
     check(st, ctx)
     return CvaFit(W, lam, mean, counts, cm, Sw, Sb)
+
+
+def cva_fit_project(cube: torch.Tensor, labels: torch.Tensor, K: int, precision: str = "fp32",
+                    ridge: float = 0.0, n_comp: Optional[int] = None, out: Optional[torch.Tensor] = None,
+                    return_range: bool = False):
+    """cva_fit then cva_project with the fitted vectors, in one library call
+    (no return to Python between the fit's host finish and the projection).
+    Returns (images, fit) or (images, fit, range); fit carries W, eigvals,
+    mean and counts (class_means, Sw, Sb are None)."""
+    c = _cube(cube)
+    if labels.dtype != torch.int8 or tuple(labels.shape) != tuple(cube.shape[:2]):
+        raise ValueError("labels must be int8 with the page's H x W shape")
+    if labels.device != cube.device or not labels.is_contiguous():
+        raise ValueError("labels must be contiguous and on the cube's device")
+    B = c.bands
+    n_comp = min(K - 1, B) if n_comp is None else int(n_comp)
+    H, Wd = cube.shape[0], cube.shape[1]
+    if out is None:
+        out = torch.empty((n_comp, H, Wd), dtype=torch.uint8, device=cube.device)
+    elif out.dtype != torch.uint8 or tuple(out.shape) != (n_comp, H, Wd) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous uint8 n_comp x H x W tensor")
+    W = np.empty((B, n_comp))
+    lam = np.empty(n_comp)
+    mean = np.empty(B)
+    counts = np.empty(K, dtype=np.int64)
+    rng = np.empty((n_comp, 2), dtype=np.float32) if return_range else None
+    dev = _dev_index(cube)
+    ctx = context(dev)
+    st = lib().cva_fit_project(ctx, ctypes.byref(c), _ptr(labels), K, _lib.PREC[precision], float(ridge), n_comp,
+                               _ptr(W), _ptr(lam), _ptr(mean), _ptr(counts), _ptr(out), _ptr(rng),
+                               _stream(cube.device))
+    check(st, ctx)
+    fit = CvaFit(W, lam, mean, counts, None, None, None)
+    return (out, fit, rng) if return_range else (out, fit)
 
 
 def cva_project(cube: torch.Tensor, W, center, out: Optional[torch.Tensor] = None,

@@ -581,6 +581,17 @@ int cva_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels, int32_
                         G, L, s);
 }
 
+int cva_fit_project(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels, int32_t K, int32_t prec,
+                    double ridge, int32_t n_comp, double* W, double* eigvals, double* mean, int64_t* counts,
+                    uint8_t* images, float* range, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (!images) return fail(ctx, CVAMX_E_INVALID_ARG, "images must be non-NULL");
+  if (int st = cva_fit(ctx, cube, labels, K, prec, ridge, n_comp, W, eigvals, mean, counts, nullptr, nullptr,
+                       nullptr, stream))
+    return st;
+  return project_common(ctx, cube, W, mean, n_comp, images, range, stream);
+}
+
 int cva_fit_points(cvamx_ctx* ctx, const cvamx_cube* cube, const int64_t* pixels, const int8_t* classes,
                    int64_t N, int32_t K, int32_t prec, double ridge, int32_t n_comp, double* W, double* eigvals,
                    double* mean, int64_t* counts, double* class_means, double* Sw, double* Sb, void* stream) {

@@ -120,6 +120,21 @@ def test_shapes_and_ragged_tails(dev, H, W, B, K):
     _project_parity(cube, ref["W"], ref["mean"], dev)
 
 
+def test_fit_project_in_one_call(dev):
+    say("cva_fit_project equals cva_fit then cva_project")
+    import paper_1612_06457_amd as cx
+    c = make_case(1, scale=0.5)
+    cube, labels = _t(c.cube, dev), _t(c.labels, dev)
+    q1, fit1, r1 = cx.cva_fit_project(cube, labels, c.K, return_range=True)
+    fit0 = cx.cva_fit(cube, labels, c.K)
+    q0, r0 = cx.cva_project(cube, fit0.W, fit0.mean, return_range=True)
+    assert np.array_equal(fit1.W, fit0.W) and np.array_equal(fit1.eigvals, fit0.eigvals)
+    assert np.array_equal(fit1.counts, fit0.counts) and np.array_equal(fit1.mean, fit0.mean)
+    assert np.array_equal(q1.cpu().numpy(), q0.cpu().numpy()) and np.array_equal(r1, r0)
+    q2, _ = cx.cva_fit_project(cube, labels, c.K, n_comp=1)
+    assert np.array_equal(q2.cpu().numpy()[0], q0.cpu().numpy()[0])
+
+
 def test_single_pixel_class(dev):
     say("class with one training pixel")
     c = make_case(1, scale=0.25)

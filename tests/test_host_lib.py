@@ -155,6 +155,12 @@ def test_argument_checks_without_a_device():
         W[0, 0] = 0
         assert lib.cva_project(ctx, ctypes.byref(good), W.ctypes.data, c.ctypes.data, 2, aligned,
                                None, None) == L.E_DEVICE
+        assert lib.cva_fit_project(ctx, ctypes.byref(good), lab, 3, 0, 0.0, 2, buf, buf, buf, i64, None, None,
+                                   None) == L.E_INVALID_ARG
+        assert lib.cva_fit_project(ctx, ctypes.byref(good), lab, 3, 0, 0.0, 3, buf, buf, buf, i64, aligned, None,
+                                   None) == L.E_INVALID_ARG
+        assert lib.cva_fit_project(ctx, ctypes.byref(good), lab, 3, 0, 0.0, 2, buf, buf, buf, i64, aligned, None,
+                                   None) == L.E_DEVICE
         # pca
         assert lib.pca_fit(ctx, ctypes.byref(good), None, 9, 0, buf, buf, buf, None, None) == L.E_INVALID_ARG
         assert lib.pca_fit(ctx, ctypes.byref(good), None, 3, 0, buf, buf, buf, None, None) == L.E_DEVICE
