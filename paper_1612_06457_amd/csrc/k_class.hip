@@ -87,6 +87,12 @@ __device__ __forceinline__ float staged(const u32x2* __restrict__ stg, int NQ, i
   }
 }
 
+// The raw 16-bit element b of staged row r.
+__device__ __forceinline__ uint32_t staged_u16(const u32x2* __restrict__ stg, int NQ, int r, int ro, int b) {
+  const unsigned char* row = reinterpret_cast<const unsigned char*>(stg + r * NQ) + ro;
+  return *reinterpret_cast<const uint16_t*>(row + 2 * b);
+}
+
 template <int DT>
 __device__ __forceinline__ float round_elem(float c) {
   return round_shift<DT>(c);
@@ -271,6 +277,71 @@ __global__ __launch_bounds__(kBlock) void k_class_split(const void* __restrict__
   block_combine<NRB>(accd, B, scale, red, part + ((int64_t)k * G + g) * (nb * (nb + 1) / 2 * 16));
 }
 
+// uint16 pages: the Gram of (x - c_k) / 1024 on the fp16 matrix units with
+// operands built exactly by bit operations (U16Lane, k_split.hpp), summed as
+// HH + HL + LH + LL and unscaled by 2^20 in FP64.  Same gather, shift and
+// output layout as k_class_split; every product is exact.
+template <int NRB, int UM>
+__global__ __launch_bounds__(kBlock) void k_class_u16(const void* __restrict__ cube, int B, int64_t P,
+                                                      const int32_t* __restrict__ idx,
+                                                      const int32_t* __restrict__ offsets, int G,
+                                                      double* __restrict__ part, double* __restrict__ shift_out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ float cs[kMaxB];
+  const int k = blockIdx.y, g = blockIdx.x;
+  const int NQ = words_per_row(B * 2);
+  u32x2* stg = reinterpret_cast<u32x2*>(smem);
+  double* red = reinterpret_cast<double*>(smem);
+  const int off = offsets[k];
+  const int n = offsets[k + 1] - off;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, grp = lane >> 4;
+  constexpr int NP = npairs(NRB);
+  f32x4 acc[NP];
+  double accd[NP][4];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      acc[p][e] = 0.f;
+      accd[p][e] = 0.0;
+    }
+  if (n > 0) {
+    const U16Masks mk = make_u16_masks();
+    class_rows<DT_U16, UM>(cube, B, P, idx, off, n, G, part, stg, cs, shift_out,
+                           [&](const int* __restrict__ rp, const int* __restrict__ ro) {
+      U16Lane<NRB> ln;   // the class shift is in cs from the first chunk on
+      ln.init(B, cs, col);
+      // wave w takes rows 32 w .. 32 w + 31 of the chunk
+      const int k0 = 32 * w;
+      f16x8 Hv[NRB], Lv[NRB];
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb) {
+        u32x4 H, L;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = k0 + 8 * grp + 2 * u;
+          const uint32_t d = staged_u16(stg, NQ, r, ro[r], ln.bcol[rb]) |
+                             (staged_u16(stg, NQ, r + 1, ro[r + 1], ln.bcol[rb]) << 16);
+          const uint32_t rm = (rp[r] >= 0 ? 0x0000ffffu : 0u) | (rp[r + 1] >= 0 ? 0xffff0000u : 0u);
+          uint32_t h, l;
+          ln.terms(d, rb, rm, mk, h, l);
+          H[u] = h;
+          L[u] = l;
+        }
+        Hv[rb] = __builtin_bit_cast(f16x8, H);
+        Lv[rb] = __builtin_bit_cast(f16x8, L);
+      }
+      u16_tile_products<NRB>(Hv, Lv, acc);
+      fold<NRB>(acc, accd);
+      __syncthreads();
+    });
+  }
+  __syncthreads();
+  const int nb = (B + 4) / 4;
+  block_combine<NRB>(accd, B, 1.f / 1024.f, red, part + ((int64_t)k * G + g) * (nb * (nb + 1) / 2 * 16));
+}
+
 // Loads per thread per chunk: ceil(kChunk NQ / kBlock), rounded up to an instantiated bound.
 int um_for(int dtype, int B) {
   const int nq = words_per_row(B * (dtype == DT_F32 ? 4 : 2));
@@ -332,12 +403,38 @@ hipError_t split_dt(int um, const void* cube, int B, int64_t P, const int32_t* i
   }
 }
 
+template <int NRB>
+hipError_t u16_nrb(int um, const void* cube, int B, int64_t P, const int32_t* idx, const int32_t* offsets, int K,
+                   int G, double* part, double* shift_out, hipStream_t s) {
+  const dim3 grid(G, K);
+  const size_t sm = split_smem(DT_U16, B);
+#define CVX_C(U)                                                                                              \
+  case U:                                                                                                     \
+    hipLaunchKernelGGL((k_class_u16<NRB, U>), grid, dim3(kBlock), sm, s, cube, B, P, idx, offsets, G, part,   \
+                       shift_out);                                                                            \
+    break;
+  switch (um) { CVX_C(3) CVX_C(5) CVX_C(9) CVX_C(17) default: return hipErrorInvalidValue; }
+#undef CVX_C
+  return hipGetLastError();
+}
+
+hipError_t u16_launch(const void* cube, int B, int64_t P, const int32_t* idx, const int32_t* offsets, int K, int G,
+                      double* part, double* shift_out, hipStream_t s) {
+  const int um = um_for(DT_U16, B);
+  switch (nrb_for(B)) {
+    case 2: return u16_nrb<2>(um, cube, B, P, idx, offsets, K, G, part, shift_out, s);
+    case 3: return u16_nrb<3>(um, cube, B, P, idx, offsets, K, G, part, shift_out, s);
+    default: return u16_nrb<5>(um, cube, B, P, idx, offsets, K, G, part, shift_out, s);
+  }
+}
+
 template <int SPLIT>
 hipError_t split_launch(int dtype, const void* cube, int B, int64_t P, const int32_t* idx, const int32_t* offsets,
                         int K, int G, double* part, double* shift_out, hipStream_t s) {
   const int um = um_for(dtype, B);
   switch (dtype) {
-    case DT_U16: return split_dt<DT_U16, SPLIT>(um, cube, B, P, idx, offsets, K, G, part, shift_out, s);
+    // uint16 pages: the exact bit-built operands whatever split was asked
+    case DT_U16: return u16_launch(cube, B, P, idx, offsets, K, G, part, shift_out, s);
     case DT_F32: return split_dt<DT_F32, SPLIT>(um, cube, B, P, idx, offsets, K, G, part, shift_out, s);
     case DT_BF16: return split_dt<DT_BF16, SPLIT>(um, cube, B, P, idx, offsets, K, G, part, shift_out, s);
     case DT_F16: return split_dt<DT_F16, SPLIT>(um, cube, B, P, idx, offsets, K, G, part, shift_out, s);

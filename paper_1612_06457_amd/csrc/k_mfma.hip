@@ -97,20 +97,6 @@ __global__ __launch_bounds__(kBlock) void k_pca_gram_mfma(const void* __restrict
 // FP64.  The ones column holds 1 in the L term.  Rows that hold no pixel
 // (the page's end, the mask) are zeroed by a per-pixel mask, computed only
 // for tiles that need it.
-struct U16Masks {
-  uint32_t lo, hi, exp_l, exp_h;   // 0x03ff03ff, 0x003f003f, 0x3c003c00, 0x64006400
-};
-__device__ __forceinline__ U16Masks make_u16_masks() {
-  U16Masks m{0x03ff03ffu, 0x003f003fu, 0x3c003c00u, 0x64006400u};
-  asm volatile("" : "+v"(m.lo), "+v"(m.hi), "+v"(m.exp_l), "+v"(m.exp_h));   // registers: VOP3 takes no literal
-  return m;
-}
-
-__device__ __forceinline__ uint32_t pk_add_f16(uint32_t a, uint32_t b) {
-  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(h2, a) + __builtin_bit_cast(h2, b));
-}
-
 template <int NRB>
 __global__ __launch_bounds__(kBlock) void k_pca_gram_u16(const void* __restrict__ cube, int B, int64_t P,
                                                          const uint8_t* __restrict__ mask,
@@ -143,20 +129,8 @@ __global__ __launch_bounds__(kBlock) void k_pca_gram_u16(const void* __restrict_
 
   // per row block: this lane's band, its load column, the negated shift terms
   // and the masks that keep real bands and put 1 in the ones column
-  int bcol[NRB];
-  uint32_t nh[NRB], nl[NRB], keep[NRB], ones[NRB];
-#pragma unroll
-  for (int rb = 0; rb < NRB; ++rb) {
-    const int band = 16 * rb + col;
-    bcol[rb] = band < B ? band : B - 1;
-    const uint32_t c = band < B ? (uint32_t)cs[band] : 0u;
-    const uint32_t h = __builtin_bit_cast(uint16_t, (_Float16)(-(1024.f + (float)(c >> 10))));
-    const uint32_t l = __builtin_bit_cast(uint16_t, (_Float16)(-(1.f + (float)(c & 1023u) / 1024.f)));
-    nh[rb] = h | (h << 16);
-    nl[rb] = l | (l << 16);
-    keep[rb] = band < B ? 0xffffffffu : 0u;
-    ones[rb] = band == B ? 0x3c003c00u : 0u;
-  }
+  U16Lane<NRB> ln;
+  ln.init(B, cs, col);
   const U16Masks mk = make_u16_masks();
 
   constexpr int NP = npairs(NRB);
@@ -192,30 +166,18 @@ __global__ __launch_bounds__(kBlock) void k_pca_gram_u16(const void* __restrict_
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int r = k0 + 8 * grp + 2 * u;
-          const uint32_t d = (uint32_t)tile[r * B + bcol[rb]] | ((uint32_t)tile[(r + 1) * B + bcol[rb]] << 16);
-          uint32_t m = keep[rb], on = ones[rb];
-          if (!full) {
-            const uint32_t rm = (vrow[w][r] ? 0x0000ffffu : 0u) | (vrow[w][r + 1] ? 0xffff0000u : 0u);
-            m &= rm;
-            on &= rm;
-          }
-          H[u] = pk_add_f16(((d >> 10) & mk.hi) | mk.exp_h, nh[rb]) & m;
-          L[u] = (pk_add_f16((d & mk.lo) | mk.exp_l, nl[rb]) & m) | on;
+          const uint32_t d = (uint32_t)tile[r * B + ln.bcol[rb]] | ((uint32_t)tile[(r + 1) * B + ln.bcol[rb]] << 16);
+          uint32_t rm = 0xffffffffu;
+          if (!full) rm = (vrow[w][r] ? 0x0000ffffu : 0u) | (vrow[w][r + 1] ? 0xffff0000u : 0u);
+          uint32_t h, l;
+          ln.terms(d, rb, rm, mk, h, l);
+          H[u] = h;
+          L[u] = l;
         }
         Hv[rb] = __builtin_bit_cast(f16x8, H);
         Lv[rb] = __builtin_bit_cast(f16x8, L);
       }
-      int p = 0;
-#pragma unroll
-      for (int ri = 0; ri < NRB; ++ri) {
-#pragma unroll
-        for (int rj = ri; rj < NRB; ++rj, ++p) {
-          acc[p] = SplitT<1>::mma(Lv[ri], Lv[rj], acc[p]);   // smallest terms first
-          acc[p] = SplitT<1>::mma(Hv[ri], Lv[rj], acc[p]);
-          acc[p] = SplitT<1>::mma(Lv[ri], Hv[rj], acc[p]);
-          acc[p] = SplitT<1>::mma(Hv[ri], Hv[rj], acc[p]);
-        }
-      }
+      u16_tile_products<NRB>(Hv, Lv, acc);
     }
     fold<NRB>(acc, accd);
   });

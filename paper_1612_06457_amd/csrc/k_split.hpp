@@ -151,6 +151,76 @@ __device__ __forceinline__ void block_combine(const double (&accd)[npairs(NRB)][
   for (int t = threadIdx.x; t < L; t += kBlock) out[t] = red[t];
 }
 
+// Exact fp16 operands of uint16 values x about an integer shift
+// c = 1024 c_h + c_l, two pixels per dword: with x = 1024 h + l,
+// (x - c) / 1024 = (h - c_h) + (l - c_l) / 1024, where the fp16 with bits
+// 0x6400 | h is 1024 + h and the one with bits 0x3c00 | l is 1 + l / 1024,
+// so an AND-OR and one packed fp16 add give each term exactly.  Every
+// product of two terms is exact in FP32 (at most 22 significant bits).  The
+// bit masks sit in registers: VOP3 encodings on gfx9 take no literal.
+struct U16Masks {
+  uint32_t lo, hi, exp_l, exp_h;   // 0x03ff03ff, 0x003f003f, 0x3c003c00, 0x64006400
+};
+__device__ __forceinline__ U16Masks make_u16_masks() {
+  U16Masks m{0x03ff03ffu, 0x003f003fu, 0x3c003c00u, 0x64006400u};
+  asm volatile("" : "+v"(m.lo), "+v"(m.hi), "+v"(m.exp_l), "+v"(m.exp_h));
+  return m;
+}
+
+__device__ __forceinline__ uint32_t pk_add_f16(uint32_t a, uint32_t b) {
+  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(h2, a) + __builtin_bit_cast(h2, b));
+}
+
+// Per lane and 16-band row block: the lane's band (16 rb + col), the column
+// it loads (clamped to a real band), the negated shift terms, and the masks
+// that keep real bands and put 1 in the ones column (band B).
+template <int NRB>
+struct U16Lane {
+  int bcol[NRB];
+  uint32_t nh[NRB], nl[NRB], keep[NRB], ones[NRB];
+  __device__ __forceinline__ void init(int B, const float* __restrict__ cs, int col) {
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) {
+      const int band = 16 * rb + col;
+      bcol[rb] = band < B ? band : B - 1;
+      const uint32_t c = band < B ? (uint32_t)cs[band] : 0u;
+      const uint32_t h = __builtin_bit_cast(uint16_t, (_Float16)(-(1024.f + (float)(c >> 10))));
+      const uint32_t l = __builtin_bit_cast(uint16_t, (_Float16)(-(1.f + (float)(c & 1023u) / 1024.f)));
+      nh[rb] = h | (h << 16);
+      nl[rb] = l | (l << 16);
+      keep[rb] = band < B ? 0xffffffffu : 0u;
+      ones[rb] = band == B ? 0x3c003c00u : 0u;
+    }
+  }
+  // The H and L terms of the dword d (two pixels of this lane's band);
+  // rowmask zeroes the halves of pixels that are not there.
+  __device__ __forceinline__ void terms(uint32_t d, int rb, uint32_t rowmask, const U16Masks& mk, uint32_t& H,
+                                        uint32_t& L) const {
+    const uint32_t m = keep[rb] & rowmask, on = ones[rb] & rowmask;
+    H = pk_add_f16(((d >> 10) & mk.hi) | mk.exp_h, nh[rb]) & m;
+    L = (pk_add_f16((d & mk.lo) | mk.exp_l, nl[rb]) & m) | on;
+  }
+};
+
+// Accumulate the 16 x 16 tile pairs of the Gram of v = H + L (per row block
+// rb: Hv[rb], Lv[rb] in the k_split layout) on the fp16 matrix units.
+template <int NRB>
+__device__ __forceinline__ void u16_tile_products(const f16x8 (&Hv)[NRB], const f16x8 (&Lv)[NRB],
+                                                  f32x4 (&acc)[npairs(NRB)]) {
+  int p = 0;
+#pragma unroll
+  for (int ri = 0; ri < NRB; ++ri) {
+#pragma unroll
+    for (int rj = ri; rj < NRB; ++rj, ++p) {
+      acc[p] = SplitT<1>::mma(Lv[ri], Lv[rj], acc[p]);   // smallest terms first
+      acc[p] = SplitT<1>::mma(Hv[ri], Lv[rj], acc[p]);
+      acc[p] = SplitT<1>::mma(Lv[ri], Hv[rj], acc[p]);
+      acc[p] = SplitT<1>::mma(Hv[ri], Hv[rj], acc[p]);
+    }
+  }
+}
+
 // power-of-two prescale keeping split values inside the fp16 range with
 // room for the tail (bf16 has the range of fp32; the scale is exact either way)
 inline float prescale(int dtype, int split) {
