@@ -85,7 +85,13 @@ typedef struct {
 
 /* Create a context on HIP device `device` (>= 0).  device = -1 makes a
  * context without a GPU: argument checking and the host-only calls work,
- * every compute call returns CVAMX_E_DEVICE.  *out receives the context. */
+ * every compute call returns CVAMX_E_DEVICE.  *out receives the context.
+ * Launch shapes can be set for measurement from the environment when the
+ * context is made: CVAMX_PROJ_BLOCKS (blocks of the page-streaming
+ * projection passes; default 8 per compute unit) and CVAMX_GRAM_BLOCKS
+ * (blocks of the PCA Gram pass).  The images and ranges do not depend on
+ * them; the PCA covariance may change in its last bits (another summation
+ * order). */
 int cvamx_create(cvamx_ctx** out, int device);
 void cvamx_destroy(cvamx_ctx* ctx);
 const char* cvamx_status_str(int status);
