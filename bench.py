@@ -31,6 +31,20 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 
+
+# The sources the stretch kernel is compiled from: a recorded traffic figure
+# holds only while all of them are unchanged.
+STRETCH_SOURCES = ("k_project_u16.hip", "k_tile.hpp", "k_common.hpp")
+
+
+def stretch_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    for name in STRETCH_SOURCES:
+        with open(os.path.join(ROOT, "paper_1612_06457_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -289,9 +303,7 @@ def main():
     if os.path.exists(traffic_file):
         try:
             tr = json.load(open(traffic_file))
-            import hashlib
-            src = open(os.path.join(ROOT, "paper_1612_06457_amd", "csrc", "k_project_u16.hip"), "rb").read()
-            if tr.get("source_sha1") == hashlib.sha1(src).hexdigest():
+            if tr.get("source_sha1") == stretch_source_digest():
                 roof["traffic"] = tr.get("bytes_per_launch")
         except Exception:
             pass

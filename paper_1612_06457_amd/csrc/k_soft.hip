@@ -56,8 +56,8 @@ __device__ __forceinline__ void for_each_chunk(const float* __restrict__ X, cons
   }
   auto next = [&](int64_t x, int64_t cur) { return x < nfull ? x : (cur < nfull ? cur : nfull - 1); };
   u32x4 rx[QX], rw[QW];
-  load_tile<QX, kBlock>(xb, next(ch, ch), xbytes, tid, rx);
-  load_tile<QW, kBlock>(wb, next(ch, ch), wbytes, tid, rw);
+  load_tile<QX, kBlock, false>(xb, next(ch, ch), xbytes, tid, rx);
+  load_tile<QW, kBlock, false>(wb, next(ch, ch), wbytes, tid, rw);
   for (; ch < nch; ch += stride) {
     if (ch < nfull) {
       store_tile<QX, kBlock>(xr, xbytes, tid, rx);
@@ -67,8 +67,8 @@ __device__ __forceinline__ void for_each_chunk(const float* __restrict__ X, cons
       copy_partial_tile<kBlock>(wb, wtotal, ch, wbytes, tid, wr);
     }
     __syncthreads();
-    load_tile<QX, kBlock>(xb, next(ch + stride, ch), xbytes, tid, rx);
-    load_tile<QW, kBlock>(wb, next(ch + stride, ch), wbytes, tid, rw);
+    load_tile<QX, kBlock, false>(xb, next(ch + stride, ch), xbytes, tid, rx);
+    load_tile<QW, kBlock, false>(wb, next(ch + stride, ch), wbytes, tid, rw);
     __builtin_amdgcn_sched_barrier(0);   // keep the next chunk's loads ahead of the work
     compute(ch, rows_of(ch));
     __syncthreads();
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_soft_backward(const float* __restric
   uint32_t* my = lds + w * 64 * S;
   const int64_t nt = (N + 63) / 64;
   const unsigned char* base = reinterpret_cast<const unsigned char*>(X);
-  for_each_tile<kMaxQ>(base, N * B * 4, nt, S, my, [&](int64_t t) {
+  for_each_tile<kMaxQ, false>(base, N * B * 4, nt, S, my, [&](int64_t t) {
     const int64_t row = t * 64 + lane;
     float z[8];
 #pragma unroll

@@ -35,14 +35,21 @@ struct Geo {
 // registers, by the NT threads sharing the tile (Q >= tile_bytes / 16 NT),
 // with no branch: a chunk index past the tile's last chunk is clamped to it
 // (a re-read that the store below drops), so every register of r is written
-// on every path and the array stays in registers.
-template <int Q, int NT = 64>
+// on every path and the array stays in registers.  STREAM marks the loads
+// non-temporal: data read once (a page far larger than the caches) then
+// does not displace other lines, and a streaming read measured about 10 %
+// faster on this device (6.46 against 5.87 TB/s).  Operands that the next
+// kernel reads again keep the default policy.
+template <int Q, int NT = 64, bool STREAM = true>
 __device__ __forceinline__ void load_tile(const unsigned char* __restrict__ base, int64_t t, int tile_bytes,
                                           int tid, u32x4 (&r)[Q]) {
   const unsigned char* tb = base + t * (int64_t)tile_bytes;
   const int last = tile_bytes / 16 - 1;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) r[q] = *reinterpret_cast<const u32x4*>(tb + 16 * min(tid + NT * q, last));
+  for (int q = 0; q < Q; ++q) {
+    const u32x4* p = reinterpret_cast<const u32x4*>(tb + 16 * min(tid + NT * q, last));
+    r[q] = STREAM ? __builtin_nontemporal_load(p) : *p;
+  }
 }
 
 template <int Q, int NT = 64>
@@ -93,7 +100,7 @@ __device__ __forceinline__ void tile_sync() {
 // tile takes the plain path.  A scheduling barrier keeps the prefetch issued
 // before the compute (the scheduler would otherwise sink it to the end of
 // the loop body to reuse its registers).
-template <int Q, int NT, typename Compute>
+template <int Q, int NT, bool STREAM = true, typename Compute>
 __device__ __forceinline__ void for_each_tile_n(const unsigned char* __restrict__ base, int64_t total_bytes,
                                                 int64_t nt, int tile_bytes, uint32_t* __restrict__ my,
                                                 Compute compute) {
@@ -112,13 +119,13 @@ __device__ __forceinline__ void for_each_tile_n(const unsigned char* __restrict_
     return;
   }
   u32x4 r[Q];
-  load_tile<Q, NT>(base, t < nfull ? t : nfull - 1, tile_bytes, tid, r);
+  load_tile<Q, NT, STREAM>(base, t < nfull ? t : nfull - 1, tile_bytes, tid, r);
   for (; t < nt; t += stride) {
     if (t < nfull) store_tile<Q, NT>(my, tile_bytes, tid, r);
     else copy_partial_tile<NT>(base, total_bytes, t, tile_bytes, tid, my);
     tile_sync<NT>();
     const int64_t tn = t + stride;
-    load_tile<Q, NT>(base, tn < nfull ? tn : (t < nfull ? t : nfull - 1), tile_bytes, tid, r);
+    load_tile<Q, NT, STREAM>(base, tn < nfull ? tn : (t < nfull ? t : nfull - 1), tile_bytes, tid, r);
     __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the compute
     compute(t);
     tile_sync<NT>();
@@ -126,10 +133,10 @@ __device__ __forceinline__ void for_each_tile_n(const unsigned char* __restrict_
 }
 
 // Wave tiles of 64 lane groups of S dwords.
-template <int Q, typename Compute>
+template <int Q, bool STREAM = true, typename Compute>
 __device__ __forceinline__ void for_each_tile(const unsigned char* __restrict__ base, int64_t total_bytes,
                                               int64_t nt, int S, uint32_t* __restrict__ my, Compute compute) {
-  for_each_tile_n<Q, 64>(base, total_bytes, nt, 256 * S, my, compute);
+  for_each_tile_n<Q, 64, STREAM>(base, total_bytes, nt, 256 * S, my, compute);
 }
 
 }  // namespace cvx
