@@ -134,6 +134,23 @@ int cva_fit_points(cvamx_ctx* ctx, const cvamx_cube* cube, const int64_t* pixels
                    double* mean, int64_t* counts, double* class_means,
                    double* Sw, double* Sb, void* stream);
 
+/* The training pixels of each class, as the fits gather them (paper
+ * Section 2: the analyst's set of points per class): the positions of the
+ * entries equal to k, in increasing order, for k = 0..K-1, one class after
+ * the other.
+ *   labels   device, n int8 (-1 = no class, or 0..K-1), 16-byte aligned
+ *   n        1..2^31-1
+ *   K        1..CVAMX_MAX_CLASSES
+ *   idx      device, int32, room for n entries, 4-byte aligned: receives
+ *            the positions of class k at idx[offsets[k] .. offsets[k+1])
+ *   counts   host, K int64: entries per class
+ *   offsets  host, K + 1 int32: offsets[0] = 0, offsets[K] = labelled total
+ * A label outside -1..K-1 gives CVAMX_E_INVALID_ARG (idx then undefined).
+ * Synchronises `stream`. */
+int cvamx_label_index(cvamx_ctx* ctx, const int8_t* labels, int64_t n,
+                      int32_t K, int32_t* idx, int64_t* counts,
+                      int32_t* offsets, void* stream);
+
 /* Project every pixel onto n_comp vectors and stretch each component to
  * 8 bits by its page-wide min and max (paper Section 2, regression
  * coefficients multiplied with the whole page; first rescale mode).

@@ -123,6 +123,26 @@ def cva_fit_points(cube: torch.Tensor, pixels: torch.Tensor, classes: torch.Tens
     return CvaFit(W, lam, mean, counts, cm, Sw, Sb)
 
 
+def label_index(labels: torch.Tensor, K: int):
+    """The training pixels of each class, as the fits gather them: returns
+    (idx, counts, offsets) with idx an int32 device tensor holding, for
+    k = 0..K-1 in turn, the flat positions of the entries equal to k in
+    increasing order (class k at idx[offsets[k]:offsets[k + 1]]), counts
+    int64 K and offsets int32 K + 1 (NumPy).  labels: int8, any shape,
+    contiguous, on a GPU (-1 = no class)."""
+    if labels.dtype != torch.int8 or not labels.is_contiguous() or labels.device.type != "cuda":
+        raise ValueError("labels must be a contiguous int8 tensor on the GPU")
+    n = int(labels.numel())
+    idx = torch.empty(max(n, 1), dtype=torch.int32, device=labels.device)
+    counts = np.empty(K, dtype=np.int64)
+    offsets = np.empty(K + 1, dtype=np.int32)
+    ctx = context(_dev_index(labels))
+    st = lib().cvamx_label_index(ctx, _ptr(labels), n, int(K), _ptr(idx), _ptr(counts), _ptr(offsets),
+                                 _stream(labels.device))
+    check(st, ctx)
+    return idx[: int(offsets[K])], counts, offsets
+
+
 def cva_fit_project(cube: torch.Tensor, labels: torch.Tensor, K: int, precision: str = "fp32",
                     ridge: float = 0.0, n_comp: Optional[int] = None, out: Optional[torch.Tensor] = None,
                     return_range: bool = False):

@@ -461,17 +461,23 @@ static int check_fit_args(cvamx_ctx* ctx, const cvamx_cube* cube, int32_t K, int
 // region; returns the number of label entries scanned.
 static int build_index(cvamx_ctx* ctx, const int8_t* labels, const int64_t* points, int64_t n, int64_t P, int K,
                 const FitLayout& lay, char* res, hipStream_t s) {
-  const int nT = (int)((n + cvx::kLabelTile - 1) / cvx::kLabelTile);
-  if (int st = ensure(ctx, B_TILECNT, (size_t)nT * K * 4)) return st;
+  const int nW = (int)((n + cvx::kLabelWave - 1) / cvx::kLabelWave);
+  if (int st = ensure(ctx, B_TILECNT, ((size_t)nW + 1) * K * 4)) return st;
+  int32_t* wave_counts = (int32_t*)ctx->buf[B_TILECNT];
+  int32_t* class_total = wave_counts + (size_t)nW * K;
   if (int st = ensure(ctx, B_IDX, (size_t)n * 4)) return st;
   HIP_TRY(cvx::launch_zero_u32(reinterpret_cast<uint32_t*>(res + lay.err), 2, s), "flag clear");
   hipError_t e;
   prof_begin(ctx, s, "label_count");
-  e = cvx::launch_label_count(labels, n, K, nT, (int32_t*)ctx->buf[B_TILECNT], (int32_t*)(res + lay.err), s);
+  e = cvx::launch_label_count(labels, n, K, nW, wave_counts, (int32_t*)(res + lay.err), s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "label count launch");
+  prof_begin(ctx, s, "label_scan");
+  e = cvx::launch_label_scan(wave_counts, nW, K, class_total, s);
+  prof_end(ctx, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "label scan launch");
   prof_begin(ctx, s, "label_index");
-  e = cvx::launch_label_index(labels, n, K, nT, (const int32_t*)ctx->buf[B_TILECNT], (int32_t*)ctx->buf[B_IDX],
+  e = cvx::launch_label_index(labels, n, K, nW, wave_counts, class_total, (int32_t*)ctx->buf[B_IDX],
                               (int64_t*)(res + lay.counts), (int32_t*)(res + lay.offsets), s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "label index launch");
@@ -612,6 +618,38 @@ int cva_fit_points(cvamx_ctx* ctx, const cvamx_cube* cube, const int64_t* pixels
   if (int st = build_index(ctx, classes, pixels, N, P, K, lay, res, s)) return st;
   return fit_from_index(ctx, cube, K, prec, ridge, n_comp, W, eigvals, mean, counts, class_means, Sw, Sb, lay, res,
                         G, L, s);
+}
+
+int cvamx_label_index(cvamx_ctx* ctx, const int8_t* labels, int64_t n, int32_t K, int32_t* idx, int64_t* counts,
+                      int32_t* offsets, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (!labels || !idx || !counts || !offsets)
+    return fail(ctx, CVAMX_E_INVALID_ARG, "labels, idx, counts and offsets must be non-NULL");
+  if (n < 1 || n >= (int64_t(1) << 31)) return fail(ctx, CVAMX_E_INVALID_ARG, "n must lie in 1..2^31-1");
+  if (K < 1 || K > CVAMX_MAX_CLASSES) return fail(ctx, CVAMX_E_INVALID_ARG, "K must lie in 1..127");
+  if ((reinterpret_cast<uintptr_t>(labels) & 15u) != 0 || (reinterpret_cast<uintptr_t>(idx) & 3u) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "labels must be 16-byte aligned and idx 4-byte aligned");
+  if (int st = check_device(ctx)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const FitLayout lay(K, 1, 0);
+  if (int st = ensure(ctx, B_RES, lay.total)) return st;
+  if (int st = ensure_pinned(ctx, lay.total)) return st;
+  char* res = static_cast<char*>(ctx->buf[B_RES]);
+  if (int st = build_index(ctx, labels, nullptr, n, n, K, lay, res, s)) return st;
+  HIP_TRY(to_pinned(ctx, res, lay.total, s), "result copy");
+  HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+  const char* h = static_cast<const char*>(ctx->pinned);
+  int32_t errflag;
+  std::memcpy(&errflag, h + lay.err, 4);
+  if (errflag & 1) return fail(ctx, CVAMX_E_INVALID_ARG, "a label lies outside -1..K-1");
+  std::memcpy(counts, h + lay.counts, 8 * (size_t)K);
+  std::memcpy(offsets, h + lay.offsets, 4 * (size_t)(K + 1));
+  const int64_t total = offsets[K];
+  if (total > 0) {
+    HIP_TRY(hipMemcpyAsync(idx, ctx->buf[B_IDX], (size_t)total * 4, hipMemcpyDeviceToDevice, s), "index copy");
+    HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+  }
+  return CVAMX_OK;
 }
 
 int cva_project(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const double* center,

@@ -3,21 +3,23 @@
 // points per class).  Integer only, so the result is exact and independent
 // of scheduling.
 //
-// Both kernels read the int8 label map in 16-byte chunks: a wave step covers
-// 64 chunks = 1024 consecutive pixels, lane l holding pixels 16 l .. 16 l + 15.
-// Steps are loaded four at a time (4 KiB per wave) with the next four in
-// flight while the current ones are processed; the loads are unconditional
-// (clamped to the wave's last whole group), and only the ragged end of a
-// wave's range takes the byte-wise path.
-// Counting adds each labelled pixel into LDS class counters.  For the index
-// list, the labelled pixels of a step (a few percent of the page) are first
-// compacted, in raster order, into a small per-wave LDS list; ranks within a
-// class then come from one ballot per distinct class over that list.
-//   k_label_count:  per-tile class counts (tile = 64 Ki pixels per block);
-//   k_label_index:  every block derives its output offsets from the counts
-//                   of the tiles before it; each wave walks its quarter of
-//                   the tile with wave-private running offsets, so the main
-//                   loop has no block barrier.
+// The label map is cut into wave tiles of kLabelWave entries (four wave
+// steps).  A wave step covers 64 chunks of 16 bytes = 1024 consecutive
+// entries, lane l holding entries 16 l .. 16 l + 15; a tile's four steps are
+// loaded at once, and only the ragged end of the map takes the byte-wise
+// path.  Small tiles give many waves, which is what these latency-bound
+// passes need (the training pixels are a few percent of the page, scattered
+// over it, so every step holds several classes).
+//   k_label_count: class counts per wave tile, class-major (K x nW), with
+//                  LDS counters private to the wave;
+//   k_label_scan:  one block per class turns its row of counts into
+//                  exclusive offsets within the class, and the class total;
+//   k_label_index: each wave starts from its offsets (class base + its
+//                  offset within the class), compacts the valid labelled
+//                  entries of a step, in raster order, into a per-wave LDS
+//                  list, and writes them with one ballot per distinct class
+//                  of the list, the running offsets held in registers
+//                  spread over the lanes (lane l: classes l and 64 + l).
 #include "k_tile.hpp"
 #include "launch.hpp"
 
@@ -25,7 +27,6 @@ namespace cvx {
 
 namespace {
 
-constexpr int kSub = kLabelTile / kWaves;   // pixels per wave in a tile
 constexpr int kStep = 64 * 16;              // pixels per wave step
 constexpr int kGroup = 4 * kStep;           // pixels per group of four steps
 
@@ -77,21 +78,22 @@ __device__ __forceinline__ void for_each_step(const int8_t* __restrict__ labels,
   for (int64_t st = s0 + kGroup * ng; st < s1; st += kStep) step(load_chunk(labels, st + 16 * lane, s1), st);
 }
 
-// Bit i of the result is set when byte i (of the 16) is >= 0 (labelled).
-// Sets `bad` when a negative byte is not -1.
-__device__ __forceinline__ uint32_t labelled_mask(u32x4 c, bool& bad) {
-  const uint32_t d[4] = {c[0], c[1], c[2], c[3]};
+// Bit i of the result is set when byte i (of the 16) is a class in 0..K-1.
+// Sets `bad` for a byte outside -1..K-1.
+__device__ __forceinline__ uint32_t valid_mask(u32x4 c, int K, bool& bad) {
+  const uint32_t below = (uint32_t)(128 - K) * 0x01010101u;   // byte b < K <=> b + 128 - K < 128
   uint32_t m = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const uint32_t x = d[q];
+    const uint32_t x = c[q];
     const uint32_t neg = x & 0x80808080u;
     const uint32_t y = ~x;                                            // -1 bytes -> 0
     const uint32_t nz = ((y & 0x7f7f7f7fu) + 0x7f7f7f7fu) | y;       // high bit: byte of y != 0
-    if (nz & neg & 0x80808080u) bad = true;                           // negative but not -1
-    const uint32_t pos = (~x) & 0x80808080u;                          // high bit: byte >= 0
-    m |= ((pos >> 7) & 1u) << (4 * q) | ((pos >> 15) & 1u) << (4 * q + 1) |
-         ((pos >> 23) & 1u) << (4 * q + 2) | ((pos >> 31) & 1u) << (4 * q + 3);
+    const uint32_t lt = ~((x & 0x7f7f7f7fu) + below) & 0x80808080u;  // high bit: low 7 bits < K
+    const uint32_t ok = ~neg & lt;                                    // high bit: 0 <= byte < K
+    if ((nz & neg) | (~neg & ~lt & 0x80808080u)) bad = true;         // negative but not -1, or >= K
+    m |= ((ok >> 7) & 1u) << (4 * q) | ((ok >> 15) & 1u) << (4 * q + 1) |
+         ((ok >> 23) & 1u) << (4 * q + 2) | ((ok >> 31) & 1u) << (4 * q + 3);
   }
   return m;
 }
@@ -116,132 +118,174 @@ __device__ __forceinline__ int lane_prefix(int c, int& total) {
   return pre;
 }
 
-// Add the labelled pixels of a chunk into the LDS class counters cnt[].
-__device__ __forceinline__ void count_chunk(u32x4 c, int K, int* __restrict__ cnt, bool& bad) {
-  uint32_t m = labelled_mask(c, bad);
-  while (m) {
-    const int i = __ffs(m) - 1;
-    m &= m - 1;
-    const int v = byte_at(c, i);
-    if (v < K) atomicAdd(&cnt[v], 1);
-    else bad = true;
+// Per-class values held across the wave's lanes: lane l keeps class l in
+// lo and class 64 + l in hi (K <= 127).  v is uniform.  get() reads both
+// registers of the owning lane and selects on the scalar side, so its result
+// does not depend on which lanes are active; still, call it where the whole
+// wave is.
+struct LaneClasses {
+  int lo = 0, hi = 0;
+  __device__ __forceinline__ int get(int v) const {
+    const int l = __builtin_amdgcn_readlane(lo, v & 63);
+    const int h = __builtin_amdgcn_readlane(hi, v & 63);
+    return v < 64 ? l : h;
   }
+  __device__ __forceinline__ void add(int v, int n) {
+    if (__lane_id() == (v & 63)) {
+      if (v < 64) lo += n;
+      else hi += n;
+    }
+  }
+};
+
+// Inclusive prefix sum over the wave's lanes.
+__device__ __forceinline__ int wave_inclusive(int x) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
 }
 
-// Compact the labelled pixels of one wave step into list[] (raster order):
-// list entries are (pixel offset within the step) | (class << 16).
-// Returns the number of entries (uniform).
-__device__ __forceinline__ int compact_step(u32x4 c, int K, uint32_t* __restrict__ list, bool& bad) {
+__global__ __launch_bounds__(kBlock) void k_label_count(const int8_t* __restrict__ labels, int64_t P, int K,
+                                                        int nW, int32_t* __restrict__ wave_counts,
+                                                        int32_t* __restrict__ err) {
+  __shared__ int cnt[kWaves][128];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wv = blockIdx.x * kWaves + w;
+  int* my = cnt[w];
+  my[lane] = 0;
+  my[64 + lane] = 0;
+  wave_lds_sync();
+  if (wv >= nW) return;
+  const int64_t s0 = (int64_t)wv * kLabelWave;
+  const int64_t s1 = (s0 + kLabelWave < P) ? s0 + kLabelWave : P;
+  bool bad = false;
+  for_each_step(labels, s0, s1, [&](u32x4 cur, int64_t) {
+    uint32_t m = valid_mask(cur, K, bad);
+    while (m) {
+      const int i = __ffs(m) - 1;
+      m &= m - 1;
+      atomicAdd(&my[byte_at(cur, i)], 1);
+    }
+  });
+  if (bad) atomicOr(err, 1);
+  wave_lds_sync();
+  for (int k = lane; k < K; k += 64) wave_counts[(int64_t)k * nW + wv] = my[k];
+}
+
+// Block k: row k of the K x nW counts becomes exclusive offsets within the
+// class (in place), and class_total[k] its sum.  Chunks of kScanThreads x
+// kPer entries (one chunk covers a page of 67 M entries): each thread loads
+// kPer consecutive ones, all in flight together, and the block scans the
+// thread sums.
+constexpr int kPer = 16;
+constexpr int kScanThreads = 1024;
+constexpr int kScanWaves = kScanThreads / 64;
+__global__ __launch_bounds__(kScanThreads) void k_label_scan(int32_t* __restrict__ wave_counts, int nW,
+                                                             int32_t* __restrict__ class_total) {
+  __shared__ int wsum[kScanWaves];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int32_t* row = wave_counts + (int64_t)blockIdx.x * nW;
+  int carry = 0;
+  for (int c0 = 0; c0 < nW; c0 += kScanThreads * kPer) {
+    const int j0 = c0 + (int)threadIdx.x * kPer;
+    int v[kPer];
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) v[e] = (j0 + e < nW) ? row[j0 + e] : 0;
+    int sum = 0;
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) sum += v[e];
+    const int inc = wave_inclusive(sum);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int base = carry, tot = 0;
+#pragma unroll
+    for (int ww = 0; ww < kScanWaves; ++ww) {
+      base += (ww < w) ? wsum[ww] : 0;
+      tot += wsum[ww];
+    }
+    __syncthreads();
+    int run = base + inc - sum;
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      if (j0 + e < nW) row[j0 + e] = run;
+      run += v[e];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) class_total[blockIdx.x] = carry;
+}
+
+// Compact the valid labelled entries of one wave step into list[] (raster
+// order): entries are (offset within the step) | (class << 16).  Returns
+// their number (uniform).
+__device__ __forceinline__ int compact_step(u32x4 c, int K, uint32_t* __restrict__ list) {
   const int lane = __lane_id();
-  uint32_t m = labelled_mask(c, bad);
+  bool bad = false;   // reported by the count kernel
+  uint32_t m = valid_mask(c, K, bad);
   int total;
   int pos = lane_prefix(__popc(m), total);
   while (m) {
     const int i = __ffs(m) - 1;
     m &= m - 1;
-    const int v = byte_at(c, i);
-    if (v >= K) bad = true;
-    list[pos++] = (uint32_t)(16 * lane + i) | ((uint32_t)(v < K ? v : 0) << 16);
+    list[pos++] = (uint32_t)(16 * lane + i) | ((uint32_t)byte_at(c, i) << 16);
   }
   return total;
 }
 
-__global__ __launch_bounds__(kBlock) void k_label_count(const int8_t* __restrict__ labels, int64_t P,
-                                                        int K, int32_t* __restrict__ tile_counts,
-                                                        int32_t* __restrict__ err) {
-  __shared__ int cnt[128];
-  for (int i = threadIdx.x; i < 128; i += kBlock) cnt[i] = 0;
-  __syncthreads();
-  const int w = threadIdx.x >> 6;
-  const int64_t s0 = (int64_t)blockIdx.x * kLabelTile + (int64_t)w * kSub;
-  const int64_t s1 = (s0 + kSub < P) ? s0 + kSub : P;
-  bool bad = false;
-  for_each_step(labels, s0, s1, [&](u32x4 cur, int64_t) { count_chunk(cur, K, cnt, bad); });
-  if (bad) atomicOr(err, 1);
-  __syncthreads();
-  for (int i = threadIdx.x; i < K; i += kBlock) tile_counts[(int64_t)blockIdx.x * K + i] = cnt[i];
-}
-
-__global__ __launch_bounds__(kBlock) void k_label_index(const int8_t* __restrict__ labels, int64_t P,
-                                                        int K, int nT,
-                                                        const int32_t* __restrict__ tile_counts,
+__global__ __launch_bounds__(kBlock) void k_label_index(const int8_t* __restrict__ labels, int64_t P, int K,
+                                                        int nW, const int32_t* __restrict__ wave_off,
+                                                        const int32_t* __restrict__ class_total,
                                                         int32_t* __restrict__ idx,
                                                         int64_t* __restrict__ counts_out,
                                                         int32_t* __restrict__ offsets_out) {
-  __shared__ int before[128], total[128];
-  __shared__ int wcnt[kWaves][128];
-  __shared__ int run[kWaves][128];
   __shared__ uint32_t lists[kWaves][kStep];
-  for (int i = threadIdx.x; i < 128; i += kBlock) {
-    before[i] = 0;
-    total[i] = 0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) wcnt[w][i] = 0;
-  }
-  __syncthreads();
-  const int t = blockIdx.x;
-  {
-    // thread i < m sums the entries i, i + m, ... of the nT x K counts, all
-    // of class i % K (m a multiple of K), then adds its two sums into LDS
-    const int m = K * (kBlock / K);
-    if ((int)threadIdx.x < m) {
-      const int k = threadIdx.x % K;
-      int tot = 0, bef = 0;
-      for (int i = threadIdx.x; i < nT * K; i += m) {
-        const int c = tile_counts[i];
-        tot += c;
-        bef += (i / K < t) ? c : 0;
-      }
-      if (tot) atomicAdd(&total[k], tot);
-      if (bef) atomicAdd(&before[k], bef);
-    }
-  }
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  uint32_t* list = lists[w];
-  const int64_t s0 = (int64_t)t * kLabelTile + (int64_t)w * kSub;
-  const int64_t s1 = (s0 + kSub < P) ? s0 + kSub : P;
-  bool bad = false;
-  // per-wave class counts of this wave's quarter of the tile
-  for_each_step(labels, s0, s1, [&](u32x4 cur, int64_t) { count_chunk(cur, K, wcnt[w], bad); });
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int off = 0;
-    for (int k = 0; k < K; ++k) {
-      const int tk = total[k];
-      int b = off + before[k];
-      for (int ww = 0; ww < kWaves; ++ww) {
-        run[ww][k] = b;
-        b += wcnt[ww][k];
-      }
-      if (t == 0) {
-        counts_out[k] = tk;
-        offsets_out[k] = off;
-      }
-      off += tk;
+  const int wv = blockIdx.x * kWaves + w;
+  // class bases (exclusive prefix of the totals), classes lane and 64 + lane
+  const int t_lo = lane < K ? class_total[lane] : 0;
+  const int t_hi = 64 + lane < K ? class_total[64 + lane] : 0;
+  const int inc_lo = wave_inclusive(t_lo);
+  const int sum_lo = __shfl(inc_lo, 63, 64);
+  const int inc_hi = wave_inclusive(t_hi);
+  const int base_lo = inc_lo - t_lo, base_hi = sum_lo + inc_hi - t_hi;
+  if (blockIdx.x == 0 && w == 0) {
+    if (lane < K) {
+      counts_out[lane] = t_lo;
+      offsets_out[lane] = base_lo;
     }
-    if (t == 0) offsets_out[K] = off;
+    if (64 + lane < K) {
+      counts_out[64 + lane] = t_hi;
+      offsets_out[64 + lane] = base_hi;
+    }
+    if (lane == 63) offsets_out[K] = sum_lo + inc_hi;
   }
-  __syncthreads();
-  // write indices in raster order with wave-private running offsets
+  if (wv >= nW) return;
+  LaneClasses at;
+  at.lo = lane < K ? base_lo + wave_off[(int64_t)lane * nW + wv] : 0;
+  at.hi = 64 + lane < K ? base_hi + wave_off[(int64_t)(64 + lane) * nW + wv] : 0;
+  uint32_t* list = lists[w];
+  const int64_t s0 = (int64_t)wv * kLabelWave;
+  const int64_t s1 = (s0 + kLabelWave < P) ? s0 + kLabelWave : P;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for_each_step(labels, s0, s1, [&](u32x4 cur, int64_t st) {
-    const int n = compact_step(cur, K, list, bad);
+    const int n = compact_step(cur, K, list);
     if (n == 0) return;
     wave_lds_sync();
     for (int b0 = 0; b0 < n; b0 += 64) {
       const int i = b0 + lane;
       const uint32_t e = (i < n) ? list[i] : 0u;
       const int k = (i < n) ? (int)(e >> 16) : -1;
-      const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-      uint64_t pending = __ballot(k >= 0);
-      while (pending) {
+      for (uint64_t pending = __ballot(k >= 0); pending;) {
         const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int kk = __shfl(k, leader, 64);
+        const int kk = __builtin_amdgcn_readlane(k, leader);
         const uint64_t mk = __ballot(k == kk);
-        const int base = run[w][kk];
+        const int base = at.get(kk);
         if (k == kk) idx[base + __popcll(mk & lt)] = (int32_t)(st + (e & 0xffffu));
-        wave_lds_sync();
-        if (lane == leader) run[w][kk] = base + __popcll(mk);
-        wave_lds_sync();
+        at.add(kk, __popcll(mk));
         pending &= ~mk;
       }
     }
@@ -277,18 +321,23 @@ hipError_t launch_points_to_pixels(const int64_t* pixels, int32_t* idx, const in
   return hipGetLastError();
 }
 
-hipError_t launch_label_count(const int8_t* labels, int64_t P, int K, int nT,
-                              int32_t* tile_counts, int32_t* err_flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_label_count, dim3(nT), dim3(kBlock), 0, s, labels, P, K, tile_counts,
-                     err_flag);
+hipError_t launch_label_count(const int8_t* labels, int64_t P, int K, int nW, int32_t* wave_counts,
+                              int32_t* err_flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_label_count, dim3((nW + kWaves - 1) / kWaves), dim3(kBlock), 0, s, labels, P, K, nW,
+                     wave_counts, err_flag);
   return hipGetLastError();
 }
 
-hipError_t launch_label_index(const int8_t* labels, int64_t P, int K, int nT,
-                              const int32_t* tile_counts, int32_t* idx, int64_t* counts_out,
-                              int32_t* offsets_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_label_index, dim3(nT), dim3(kBlock), 0, s, labels, P, K, nT, tile_counts,
-                     idx, counts_out, offsets_out);
+hipError_t launch_label_scan(int32_t* wave_counts, int nW, int K, int32_t* class_total, hipStream_t s) {
+  hipLaunchKernelGGL(k_label_scan, dim3(K), dim3(kScanThreads), 0, s, wave_counts, nW, class_total);
+  return hipGetLastError();
+}
+
+hipError_t launch_label_index(const int8_t* labels, int64_t P, int K, int nW, const int32_t* wave_off,
+                              const int32_t* class_total, int32_t* idx, int64_t* counts_out, int32_t* offsets_out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_label_index, dim3((nW + kWaves - 1) / kWaves), dim3(kBlock), 0, s, labels, P, K, nW,
+                     wave_off, class_total, idx, counts_out, offsets_out);
   return hipGetLastError();
 }
 

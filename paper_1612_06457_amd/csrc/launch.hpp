@@ -5,7 +5,7 @@
 
 namespace cvx {
 
-constexpr int kLabelTile = 65536;   // label pixels per block in the label kernels
+constexpr int kLabelWave = 4096;   // label entries per wave tile in the label kernels
 constexpr int kBlock = 256;         // threads per block in every kernel
 constexpr int kWaves = kBlock / 64; // waves per block
 constexpr int kChunk = 128;         // rows staged per chunk in the scatter kernels
@@ -29,11 +29,17 @@ struct SoftBwdArgs {
 };
 
 // label bookkeeping
-hipError_t launch_label_count(const int8_t* labels, int64_t P, int K, int nT,
-                              int32_t* tile_counts, int32_t* err_flag, hipStream_t s);
-hipError_t launch_label_index(const int8_t* labels, int64_t P, int K, int nT,
-                              const int32_t* tile_counts, int32_t* idx,
-                              int64_t* counts_out, int32_t* offsets_out, hipStream_t s);
+// label bookkeeping over nW = ceil(P / kLabelWave) wave tiles:
+// wave_counts is K x nW (class-major); the count kernel writes the counts,
+// the scan kernel turns each class row into exclusive offsets within the
+// class (in place) and writes the K class totals, the index kernel writes
+// the class-grouped list and the counts and offsets
+hipError_t launch_label_count(const int8_t* labels, int64_t P, int K, int nW, int32_t* wave_counts,
+                              int32_t* err_flag, hipStream_t s);
+hipError_t launch_label_scan(int32_t* wave_counts, int nW, int K, int32_t* class_total, hipStream_t s);
+hipError_t launch_label_index(const int8_t* labels, int64_t P, int K, int nW, const int32_t* wave_off,
+                              const int32_t* class_total, int32_t* idx, int64_t* counts_out, int32_t* offsets_out,
+                              hipStream_t s);
 
 // training points as a list: turn the class-grouped list positions in idx
 // (offsets[K] of them) into pixels; ORs 2 into *err_flag for a pixel

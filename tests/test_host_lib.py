@@ -245,6 +245,25 @@ def test_argument_checks_without_a_device():
         assert ci(pix=ctypes.c_void_p(0x40004)) == L.E_UNSUPPORTED
         assert ci(cl=ctypes.c_void_p(0x50008)) == L.E_UNSUPPORTED
         assert ci(img=ctypes.c_void_p(0x60001)) == L.E_DEVICE          # bytes need no alignment
+        # class index lists
+        off = (ctypes.c_int32 * 129)()
+        ix = ctypes.c_void_p(0xa0000)
+
+        def li(labels=lab, n=100, K=3, idx=ix, counts=i64, offsets=off):
+            return lib.cvamx_label_index(ctx, labels, n, K, idx, counts, offsets, None)
+
+        assert li(labels=None) == L.E_INVALID_ARG
+        assert li(idx=None) == L.E_INVALID_ARG
+        assert li(counts=None) == L.E_INVALID_ARG
+        assert li(offsets=None) == L.E_INVALID_ARG
+        assert li(n=0) == L.E_INVALID_ARG
+        assert li(n=1 << 31) == L.E_INVALID_ARG
+        assert li(K=0) == L.E_INVALID_ARG
+        assert li(K=128) == L.E_INVALID_ARG
+        assert li(labels=ctypes.c_void_p(0x20008)) == L.E_UNSUPPORTED
+        assert li(idx=ctypes.c_void_p(0xa0002)) == L.E_UNSUPPORTED
+        assert li(K=1) == L.E_DEVICE
+        assert li(K=127) == L.E_DEVICE
         # band images and page batches
         cb = ctypes.c_void_p(0x90000)
         assert lib.cvamx_bands_to_cube(ctx, None, L.DT_U8, 8, 64, cb, None) == L.E_INVALID_ARG
