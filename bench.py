@@ -11,6 +11,8 @@ step is one pass of the whole hot path over that page:
 
 The headline value is CVA fit + project throughput in Gpix*band/s
 (page pixels x bands / t_fit+project); ms_per_step is the whole step.
+`vs_plain_fp32` times the same calls on the plain FP32 vector-ALU kernels
+and with the bf16x3 split, beside the default path.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
 """
@@ -116,6 +118,40 @@ def _timed(torch, fn, reps=5):
         torch.cuda.synchronize()
         ts.append(a.elapsed_time(b))
     return float(np.median(ts))
+
+
+def vs_plain(cx, torch, cube, labels, K, img, pimg, fit_proj_bytes, per, mean_fp, P, B):
+    """The headline call and the PCA calls on the plain FP32 reference path
+    (the FP32 vector-ALU kernels for the class moments, the covariance and
+    the projections), and the headline call with the bf16x3 split asked
+    for, beside the default path; all three meet the same FP32 tolerances
+    against the oracle (the GPU tests check each).  The soft-label passes
+    have one path, FP32 products on the FP32 matrix instruction."""
+    reps = 10
+    t_mixed = _timed(torch, lambda: cx.cva_fit_project(cube, labels, K, precision="bf16x3", out=img), reps)
+    cx.set_plain_fp32(True)
+    try:
+        t_plain = _timed(torch, lambda: cx.cva_fit_project(cube, labels, K, precision="fp32", out=img), reps)
+        V, _, mean, _ = cx.pca_fit(cube, n_comp=3)
+        t_pfit = _timed(torch, lambda: cx.pca_fit(cube, n_comp=3))
+        t_pproj = _timed(torch, lambda: cx.pca_project(cube, V, mean, out=pimg))
+    finally:
+        cx.set_plain_fp32(False)
+
+    def rate(ms):
+        return {"ms": round(ms, 4), "Gpix_band_per_s": round(P * B / (ms * 1e-3) / 1e9, 1),
+                "frac_of_8TBps": round(fit_proj_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    return {
+        "cva_fit_project": {"default": rate(mean_fp), "plain_fp32": rate(t_plain), "bf16x3": rate(t_mixed),
+                            "speedup_default_vs_plain": round(t_plain / mean_fp, 3),
+                            "speedup_bf16x3_vs_plain": round(t_plain / t_mixed, 3)},
+        "pca_fit": {"default_ms": round(per["pca_fit"], 4), "plain_fp32_ms": round(t_pfit, 4),
+                    "speedup": round(t_pfit / per["pca_fit"], 3)},
+        "pca_project": {"default_ms": round(per["pca_project"], 4), "plain_fp32_ms": round(t_pproj, 4),
+                        "speedup": round(t_pproj / per["pca_project"], 3)},
+        "soft_fwd_bwd_ms": round(per["soft_fwd"] + per["soft_bwd"], 4),
+    }
 
 
 def extras(cx, torch, case, cube, fit, dev, labels=None):
@@ -331,6 +367,7 @@ def main():
         "kernels_ms_per_launch": {k: round(v[1] / max(v[0], 1), 4) for k, v in prof.items()},
         "roofline": roof,
     }
+    out["vs_plain_fp32"] = vs_plain(cx, torch, cube, labels, K, img, pimg, fit_proj_bytes, per, mean_fp, P, B)
     if not args.no_extras:
         out["extras"] = extras(cx, torch, case, cube, fit_last(cx, cube, labels, K), dev, labels)
     if args.copy_gib > 0:

@@ -370,6 +370,19 @@ int cva_soft_backward(cvamx_ctx* ctx, const float* X, const double* W,
                       const double* class_means, int64_t N, int32_t B,
                       int32_t K, double dJ, float* dw, void* stream);
 
+/* ---- plain FP32 reference path ------------------------------------------ */
+
+/* With enable = 1, every FP32 request on this context runs the plain FP32
+ * vector-ALU kernels whatever the page type: the class moments of the fits
+ * and the PCA covariance (prec CVAMX_PREC_FP32), and all projections
+ * (cva_project, pca_project, cva_fit_project, cvamx_project_float).  By
+ * default uint16 pages take the matrix cores with exactly split operands
+ * and bf16 / fp16 pages take them for the projections; the plain path is
+ * the reference those paths are measured against (same FP32 accumulation,
+ * so the same tolerances hold).  0 restores the default.  Host-only: never
+ * fails for a valid context. */
+int cvamx_set_plain_fp32(cvamx_ctx* ctx, int enable);
+
 /* ---- kernel timing ------------------------------------------------------ */
 
 /* Enable (1) or disable (0) per-kernel timing on this context: every kernel

@@ -80,6 +80,7 @@ EXPORTS = {
                                          _f64, _vp, _vp]),
     "cva_solve_moments": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _f64, _i32, _vp, _vp, _vp]),
     "cvamx_sym_eig": (ctypes.c_int, [_i32, _vp, _vp, _vp]),
+    "cvamx_set_plain_fp32": (ctypes.c_int, [_vp, ctypes.c_int]),
     "cvamx_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "cvamx_profile_report": (ctypes.c_int64, [_vp, ctypes.c_char_p, ctypes.c_int64]),
 }

@@ -533,6 +533,14 @@ def sym_eig(A):
 
 # ------------------------------------------------------------ kernel timing
 
+def set_plain_fp32(enable: bool = True, device: int = 0) -> None:
+    """Run every FP32 request on `device` on the plain FP32 vector-ALU kernels
+    (fit moments, PCA covariance, projections) instead of the matrix-core
+    paths; False restores the default.  The reference for the speed-ups."""
+    ctx = context(device)
+    check(lib().cvamx_set_plain_fp32(ctx, 1 if enable else 0), ctx)
+
+
 def profile_enable(enable: bool = True, device: int = 0) -> None:
     """Bracket every kernel the library launches on `device` with HIP events
     (on the stream it is launched on); clears earlier totals."""

@@ -27,6 +27,7 @@ struct cvamx_ctx {
   int device = -1;
   int num_cu = 256;
   int proj_blocks = 0;   // 0 = automatic
+  bool plain = false;    // FP32 requests on the plain vector-ALU kernels
   int gram_blocks = 0;
   std::string err;
   void* buf[B_COUNT] = {};
@@ -248,7 +249,7 @@ int proj_nblocks(cvamx_ctx* ctx, const cvamx_cube* cube) {
 
 // The kernel arguments of components g0 .. g0 + nc - 1.
 void make_proj_args(const cvamx_cube* cube, const double* W, const double* center, int n_comp, int g0, int nc,
-                    cvx::ProjArgs& a) {
+                    bool plain, cvx::ProjArgs& a) {
   const int B = (int)cube->bands;
   std::memset(&a, 0, sizeof(a));
   std::vector<double> c(B);
@@ -271,9 +272,11 @@ void make_proj_args(const cvamx_cube* cube, const double* W, const double* cente
       const double wv = W[(size_t)b * n_comp + g0 + j];
       a.w[b * nc + j] = (float)wv;
       off += wv * (c[b] - center[b]);
-      // uint16 pages: the kernels multiply 1024 + (x mod 1024) rather than
-      // its centred value, so the constant 1024 + (c mod 1024) comes off here
-      if (cube->dtype == CVAMX_U16) off -= (double)a.w[b * nc + j] * (1024.0 + std::fmod(c[b], 1024.0));
+      // uint16 pages on the matrix cores: the kernels multiply 1024 + (x mod
+      // 1024) rather than its centred value, so the constant 1024 + (c mod
+      // 1024) comes off here (the plain kernels use x - c itself)
+      if (cube->dtype == CVAMX_U16 && !plain)
+        off -= (double)a.w[b * nc + j] * (1024.0 + std::fmod(c[b], 1024.0));
     }
     a.off[j] = (float)off;
     // a power of two that brings the largest |W[b][j]| into [16, 32)
@@ -295,7 +298,7 @@ int proj_groups(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const d
   for (int g0 = 0; g0 < n_comp; g0 += 8) {
     const int nc = std::min(8, n_comp - g0);   // the kernels are instantiated for 1..8 components
     cvx::ProjArgs a;
-    make_proj_args(cube, W, center, n_comp, g0, nc, a);
+    make_proj_args(cube, W, center, n_comp, g0, nc, ctx->plain, a);
     static const char* kRangeName[9] = {"", "project_range_nc1", "project_range_nc2", "project_range_nc3",
                                         "project_range_nc4", "project_range_nc5", "project_range_nc6",
                                         "project_range_nc7", "project_range_nc8"};
@@ -303,13 +306,13 @@ int proj_groups(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const d
                                           "project_stretch_nc4", "project_stretch_nc5", "project_stretch_nc6",
                                           "project_stretch_nc7", "project_stretch_nc8"};
     prof_begin(ctx, s, kRangeName[nc]);
-    hipError_t e = cvx::launch_project_range(cube->dtype, cube->data, B, P, nc, a, nblocks,
+    hipError_t e = cvx::launch_project_range(cube->dtype, ctx->plain, cube->data, B, P, nc, a, nblocks,
                                              (float*)ctx->buf[B_PROJPART], ctx->tickets,
                                              ctx->range_dev, ctx->ab_dev + 2 * g0, s);
     prof_end(ctx, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "project range launch");
     prof_begin(ctx, s, kStretchName[nc]);
-    e = cvx::launch_project_stretch(cube->dtype, cube->data, B, P, nc, a, nblocks, ctx->range_dev,
+    e = cvx::launch_project_stretch(cube->dtype, ctx->plain, cube->data, B, P, nc, a, nblocks, ctx->range_dev,
                                     images + (int64_t)g0 * P, s);
     prof_end(ctx, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "project stretch launch");
@@ -498,7 +501,7 @@ static int fit_from_index(cvamx_ctx* ctx, const cvamx_cube* cube, int32_t K, int
   const int B = (int)cube->bands;
   const int64_t P = cube->height * cube->width;
   hipError_t e;
-  if (prec == CVAMX_PREC_FP32 && !split_is_exact(cube->dtype)) {
+  if (prec == CVAMX_PREC_FP32 && (ctx->plain || !split_is_exact(cube->dtype))) {
     prof_begin(ctx, s, "class_moments");
     e = cvx::launch_class_moments(cube->dtype, cube->data, B, P, (const int32_t*)ctx->buf[B_IDX],
                                   (const int32_t*)(res + lay.offsets), K, G, (double*)ctx->buf[B_PART],
@@ -675,9 +678,10 @@ int cvamx_project_float(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W,
   for (int g0 = 0; g0 < n_comp; g0 += 8) {
     const int nc = std::min(8, n_comp - g0);
     cvx::ProjArgs a;
-    make_proj_args(cube, W, center, n_comp, g0, nc, a);
+    make_proj_args(cube, W, center, n_comp, g0, nc, ctx->plain, a);
     prof_begin(ctx, s, "project_float");
-    hipError_t e = cvx::launch_project_float(cube->dtype, cube->data, B, P, nc, a, nblocks, y + (int64_t)g0 * P, s);
+    hipError_t e = cvx::launch_project_float(cube->dtype, ctx->plain, cube->data, B, P, nc, a, nblocks,
+                                             y + (int64_t)g0 * P, s);
     prof_end(ctx, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "project float launch");
   }
@@ -926,7 +930,7 @@ int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t
   if (int st = ensure_pinned(ctx, res_bytes)) return st;
   char* res = static_cast<char*>(ctx->buf[B_RES]);
   hipError_t e;
-  if (prec == CVAMX_PREC_FP32 && !split_is_exact(cube->dtype)) {
+  if (prec == CVAMX_PREC_FP32 && (ctx->plain || !split_is_exact(cube->dtype))) {
     prof_begin(ctx, s, "pca_gram");
     e = cvx::launch_pca_gram(cube->dtype, cube->data, B, P, mask, nblocks, (double*)ctx->buf[B_PART],
                              (double*)res, s);
@@ -1090,6 +1094,12 @@ int cva_soft_backward(cvamx_ctx* ctx, const float* X, const double* W, const dou
     prof_end(ctx, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "soft backward launch");
   }
+  return CVAMX_OK;
+}
+
+int cvamx_set_plain_fp32(cvamx_ctx* ctx, int enable) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  ctx->plain = enable != 0;
   return CVAMX_OK;
 }
 

@@ -1,51 +1,69 @@
-// Projection passes on the VALU (float32 pages), and the dispatchers: uint16
-// pages go to k_project_u16.hip, bf16 / fp16 pages to k_project_mfma.hip.
+// Projection passes on the VALU (float32 pages, and every page type on the
+// plain FP32 reference path), and the dispatchers: otherwise uint16 pages go
+// to k_project_u16.hip, bf16 / fp16 pages to k_project_mfma.hip.
 #include "k_project.hpp"
 
 namespace cvx {
 
+// The VALU passes for any element type: the path of float32 pages, and the
+// plain FP32 reference path of the others.
+#define CVX_GENERIC(CALL)                       \
+  switch (dtype) {                              \
+    case DT_U16: return CALL(DT_U16);           \
+    case DT_F32: return CALL(DT_F32);           \
+    case DT_BF16: return CALL(DT_BF16);         \
+    case DT_F16: return CALL(DT_F16);           \
+    default: return hipErrorInvalidValue;       \
+  }
+
 hipError_t project_range_generic(int dtype, int nc, const void* cube, int B, int64_t P, const ProjArgs& a,
                                  int nblocks, float* part, unsigned* ticket, float* range_dev, float* ab_dev,
                                  hipStream_t s) {
-  if (dtype != DT_F32) return hipErrorInvalidValue;
-  return proj::range_nc<DT_F32>(nc, cube, B, P, a, nblocks, part, ticket, range_dev, ab_dev, s);
+#define CVX_C(D) proj::range_nc<D>(nc, cube, B, P, a, nblocks, part, ticket, range_dev, ab_dev, s)
+  CVX_GENERIC(CVX_C)
+#undef CVX_C
 }
 
 hipError_t project_stretch_generic(int dtype, int nc, const void* cube, int B, int64_t P, const ProjArgs& a,
                                    int nblocks, const float* range_dev, uint8_t* images, hipStream_t s) {
-  if (dtype != DT_F32) return hipErrorInvalidValue;
-  return proj::stretch_nc<DT_F32>(nc, cube, B, P, a, nblocks, range_dev, images, s);
+#define CVX_C(D) proj::stretch_nc<D>(nc, cube, B, P, a, nblocks, range_dev, images, s)
+  CVX_GENERIC(CVX_C)
+#undef CVX_C
 }
 
 hipError_t project_float_generic(int dtype, int nc, const void* cube, int B, int64_t P, const ProjArgs& a,
                                  int nblocks, float* y, hipStream_t s) {
-  if (dtype != DT_F32) return hipErrorInvalidValue;
-  return proj::float_nc<DT_F32>(nc, cube, B, P, a, nblocks, y, s);
+#define CVX_C(D) proj::float_nc<D>(nc, cube, B, P, a, nblocks, y, s)
+  CVX_GENERIC(CVX_C)
+#undef CVX_C
 }
 
-hipError_t launch_project_range(int dtype, const void* cube, int B, int64_t P, int nc,
+#undef CVX_GENERIC
+
+hipError_t launch_project_range(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
                                 const ProjArgs& a, int nblocks, float* part, unsigned* ticket,
                                 float* range_dev, float* ab_dev, hipStream_t s) {
+  if (plain || dtype == DT_F32)
+    return project_range_generic(dtype, nc, cube, B, P, a, nblocks, part, ticket, range_dev, ab_dev, s);
   if (dtype == DT_U16)
     return launch_project_range_u16(cube, B, P, nc, a, nblocks, part, ticket, range_dev, ab_dev, s);
-  if (dtype != DT_F32)
-    return launch_project_range_mfma(dtype, cube, B, P, nc, a, nblocks, part, ticket, range_dev, ab_dev, s);
-  return project_range_generic(dtype, nc, cube, B, P, a, nblocks, part, ticket, range_dev, ab_dev, s);
+  return launch_project_range_mfma(dtype, cube, B, P, nc, a, nblocks, part, ticket, range_dev, ab_dev, s);
 }
 
-hipError_t launch_project_stretch(int dtype, const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
-                                  int nblocks, const float* range_dev, uint8_t* images, hipStream_t s) {
+hipError_t launch_project_stretch(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
+                                  const ProjArgs& a, int nblocks, const float* range_dev, uint8_t* images,
+                                  hipStream_t s) {
+  if (plain || dtype == DT_F32)
+    return project_stretch_generic(dtype, nc, cube, B, P, a, nblocks, range_dev, images, s);
   if (dtype == DT_U16) return launch_project_stretch_u16(cube, B, P, nc, a, nblocks, range_dev, images, s);
-  if (dtype != DT_F32)
-    return launch_project_stretch_mfma(dtype, cube, B, P, nc, a, nblocks, range_dev, images, s);
-  return project_stretch_generic(dtype, nc, cube, B, P, a, nblocks, range_dev, images, s);
+  return launch_project_stretch_mfma(dtype, cube, B, P, nc, a, nblocks, range_dev, images, s);
 }
 
-hipError_t launch_project_float(int dtype, const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
-                                int nblocks, float* y, hipStream_t s) {
+hipError_t launch_project_float(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
+                                const ProjArgs& a, int nblocks, float* y, hipStream_t s) {
+  if (plain || dtype == DT_F32) return project_float_generic(dtype, nc, cube, B, P, a, nblocks, y, s);
   if (dtype == DT_U16) return launch_project_float_u16(cube, B, P, nc, a, nblocks, y, s);
-  if (dtype != DT_F32) return launch_project_float_mfma(dtype, cube, B, P, nc, a, nblocks, y, s);
-  return project_float_generic(dtype, nc, cube, B, P, a, nblocks, y, s);
+  return launch_project_float_mfma(dtype, cube, B, P, nc, a, nblocks, y, s);
 }
 
 }  // namespace cvx

@@ -68,13 +68,15 @@ hipError_t launch_pca_gram_mfma(int dtype, int split, const void* cube, int B, i
 hipError_t launch_reduce_part(const double* part, int nsets, int G, int L, double* out,
                               hipStream_t s);
 
-// projection, pass 1 (range) and pass 2 (stretch to uint8)
-hipError_t launch_project_range(int dtype, const void* cube, int B, int64_t P, int nc,
+// projection, pass 1 (range) and pass 2 (stretch to uint8); plain = the
+// FP32 vector-ALU kernels whatever the page type (else float32 pages only)
+hipError_t launch_project_range(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
                                 const ProjArgs& a, int nblocks, float* part,
                                 unsigned* ticket, float* range_dev, float* ab_dev,
                                 hipStream_t s);
-hipError_t launch_project_stretch(int dtype, const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
-                                  int nblocks, const float* range_dev, uint8_t* images, hipStream_t s);
+hipError_t launch_project_stretch(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
+                                  const ProjArgs& a, int nblocks, const float* range_dev, uint8_t* images,
+                                  hipStream_t s);
 
 // matrix-core projection (same contract as above): uint16 pages, and
 // bf16 / fp16 pages
@@ -120,8 +122,8 @@ hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_compose_rgb(const uint8_t* r, const uint8_t* g, const uint8_t* b, int64_t P, uint8_t* rgb,
                               int num_cu, hipStream_t s);
 // projection to FP32 planes (y[j][p] = w_j^T (x_p - c), n_comp x P)
-hipError_t launch_project_float(int dtype, const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
-                                int nblocks, float* y, hipStream_t s);
+hipError_t launch_project_float(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
+                                const ProjArgs& a, int nblocks, float* y, hipStream_t s);
 
 // cluster-separation indices: per class k of the class-grouped points,
 // sums[k * L + f] = sum of feature f (L = cluster_sum_len(n)) and

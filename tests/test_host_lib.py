@@ -245,6 +245,10 @@ def test_argument_checks_without_a_device():
         assert ci(pix=ctypes.c_void_p(0x40004)) == L.E_UNSUPPORTED
         assert ci(cl=ctypes.c_void_p(0x50008)) == L.E_UNSUPPORTED
         assert ci(img=ctypes.c_void_p(0x60001)) == L.E_DEVICE          # bytes need no alignment
+        # the plain FP32 switch is host-only
+        assert lib.cvamx_set_plain_fp32(None, 1) == L.E_INVALID_ARG
+        assert lib.cvamx_set_plain_fp32(ctx, 1) == L.OK
+        assert lib.cvamx_set_plain_fp32(ctx, 0) == L.OK
         # class index lists
         off = (ctypes.c_int32 * 129)()
         ix = ctypes.c_void_p(0xa0000)
