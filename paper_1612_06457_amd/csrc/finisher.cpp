@@ -23,6 +23,10 @@
 
 namespace cvamx {
 
+// The O(n^3) loops of the eigensolver are built twice, for AVX2 + FMA
+// processors and for the baseline, and the loader picks one at run time.
+#define CVX_HOST_SIMD __attribute__((target_clones("arch=haswell", "default")))
+
 int cholesky_lower(int n, const double* A, double* L) {
   std::fill(L, L + (size_t)n * n, 0.0);
   for (int j = 0; j < n; ++j) {
@@ -46,7 +50,7 @@ int cholesky_lower(int n, const double* A, double* L) {
 // Householder reduction of the full symmetric matrix T (in place) to
 // tridiagonal form, accumulating the reflectors into Q so that the input
 // equals Q T Q^T.
-static void tridiagonalize(int n, double* T, double* Q) {
+CVX_HOST_SIMD static void tridiagonalize(int n, double* T, double* Q) {
   std::vector<double> v(n), p(n), w(n);
   for (int k = 0; k + 2 < n; ++k) {
     double xx = 0.0;
@@ -88,10 +92,20 @@ static void tridiagonalize(int n, double* T, double* Q) {
   }
 }
 
+// sqrt(x^2 + z^2): the plain formula where the squares can neither
+// overflow nor lose precision to underflow, std::hypot otherwise.
+static inline double norm2(double x, double z) {
+  const double ax = std::fabs(x), az = std::fabs(z);
+  const double big = ax > az ? ax : az;
+  if (big > 1e-150 && big < 1e150) return std::sqrt(x * x + z * z);
+  return std::hypot(x, z);
+}
+
 // Implicit symmetric QR steps with a Wilkinson shift on the tridiagonal T
 // (stored dense), deflating negligible off-diagonal entries, with the
-// rotations accumulated into Q.
-static int tridiagonal_qr(int n, double* T, double* Q) {
+// rotations accumulated into Zt = Q^T (row i of Zt is column i of Q, so a
+// rotation of two columns of Q touches two contiguous rows).
+CVX_HOST_SIMD static int tridiagonal_qr(int n, double* T, double* Zt) {
   const int maxit = 60 * n + 100;
   int it = 0;
   int m = n - 1;
@@ -110,12 +124,12 @@ static int tridiagonal_qr(int n, double* T, double* Q) {
     if (++it > maxit) return CVAMX_E_NUMERIC;
     const double a = at(m - 1, m - 1), b = at(m, m - 1), c = at(m, m);
     const double d = 0.5 * (a - c);
-    const double den = d + std::copysign(std::hypot(d, b), d);
+    const double den = d + std::copysign(norm2(d, b), d);
     const double mu = (den != 0.0) ? c - b * b / den : c - std::fabs(b);
     double x = at(l, l) - mu;
     double z = at(l + 1, l);
     for (int k = l; k < m; ++k) {
-      const double r = std::hypot(x, z);
+      const double r = norm2(x, z);
       const double cs = (r == 0.0) ? 1.0 : x / r;
       const double sn = (r == 0.0) ? 0.0 : -z / r;
       const int lo = std::max(l, k - 1), hi = std::min(m, k + 2);
@@ -129,10 +143,12 @@ static int tridiagonal_qr(int n, double* T, double* Q) {
         at(i, k) = cs * t1 - sn * t2;
         at(i, k + 1) = sn * t1 + cs * t2;
       }
+      double* __restrict__ z1 = Zt + (size_t)k * n;
+      double* __restrict__ z2 = z1 + n;
       for (int i = 0; i < n; ++i) {
-        const double q1 = Q[(size_t)i * n + k], q2 = Q[(size_t)i * n + k + 1];
-        Q[(size_t)i * n + k] = cs * q1 - sn * q2;
-        Q[(size_t)i * n + k + 1] = sn * q1 + cs * q2;
+        const double q1 = z1[i], q2 = z2[i];
+        z1[i] = cs * q1 - sn * q2;
+        z2[i] = sn * q1 + cs * q2;
       }
       if (k + 1 < m) {
         x = at(k + 1, k);
@@ -152,7 +168,10 @@ int sym_eig_desc(int n, const double* A, double* w, double* V) {
     }
   for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
   if (n > 2) tridiagonalize(n, T.data(), Q.data());
-  const int st = tridiagonal_qr(n, T.data(), Q.data());
+  std::vector<double> Zt((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Zt[(size_t)j * n + i] = Q[(size_t)i * n + j];
+  const int st = tridiagonal_qr(n, T.data(), Zt.data());
   if (st != 0) return st;
   std::vector<int> ord(n);
   std::iota(ord.begin(), ord.end(), 0);
@@ -161,7 +180,7 @@ int sym_eig_desc(int n, const double* A, double* w, double* V) {
   });
   for (int j = 0; j < n; ++j) {
     w[j] = T[(size_t)ord[j] * n + ord[j]];
-    for (int i = 0; i < n; ++i) V[(size_t)i * n + j] = Q[(size_t)i * n + ord[j]];
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + j] = Zt[(size_t)ord[j] * n + i];
   }
   return 0;
 }
