@@ -465,18 +465,17 @@ static int check_fit_args(cvamx_ctx* ctx, const cvamx_cube* cube, int32_t K, int
 static int build_index(cvamx_ctx* ctx, const int8_t* labels, const int64_t* points, int64_t n, int64_t P, int K,
                 const FitLayout& lay, char* res, hipStream_t s) {
   const int nW = (int)((n + cvx::kLabelWave - 1) / cvx::kLabelWave);
-  if (int st = ensure(ctx, B_TILECNT, ((size_t)nW + 1) * K * 4)) return st;
+  if (int st = ensure(ctx, B_TILECNT, ((size_t)nW + 1) * (K + 1) * 4)) return st;
   int32_t* wave_counts = (int32_t*)ctx->buf[B_TILECNT];
-  int32_t* class_total = wave_counts + (size_t)nW * K;
+  int32_t* class_total = wave_counts + (size_t)nW * (K + 1);
   if (int st = ensure(ctx, B_IDX, (size_t)n * 4)) return st;
-  HIP_TRY(cvx::launch_zero_u32(reinterpret_cast<uint32_t*>(res + lay.err), 2, s), "flag clear");
   hipError_t e;
   prof_begin(ctx, s, "label_count");
-  e = cvx::launch_label_count(labels, n, K, nW, wave_counts, (int32_t*)(res + lay.err), s);
+  e = cvx::launch_label_count(labels, n, K, nW, wave_counts, s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "label count launch");
   prof_begin(ctx, s, "label_scan");
-  e = cvx::launch_label_scan(wave_counts, nW, K, class_total, s);
+  e = cvx::launch_label_scan(wave_counts, nW, K, class_total, (int32_t*)(res + lay.err), s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "label scan launch");
   prof_begin(ctx, s, "label_index");
@@ -514,14 +513,16 @@ static int fit_from_index(cvamx_ctx* ctx, const cvamx_cube* cube, int32_t K, int
   }
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "class moments launch");
+  // the Gram reduction writes into page-locked memory and brings the
+  // results header (counts, offsets, flags, shifts) along
   prof_begin(ctx, s, "reduce_partials");
-  e = cvx::launch_reduce_part((const double*)ctx->buf[B_PART], K, G, L, (double*)(res + lay.gram), s);
+  char* h = static_cast<char*>(ctx->pinned);
+  e = cvx::launch_reduce_part_out((const double*)ctx->buf[B_PART], K, G, L, (double*)(h + lay.gram), res, h,
+                                  (int64_t)lay.gram, s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
-  HIP_TRY(to_pinned(ctx, res, lay.total, s), "result copy");
   HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
 
-  const char* h = static_cast<const char*>(ctx->pinned);
   int32_t errflag;
   std::memcpy(&errflag, h + lay.err, 4);
   if (errflag & 1) return fail(ctx, CVAMX_E_INVALID_ARG, "a label lies outside -1..K-1");
@@ -942,10 +943,11 @@ int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "pca gram launch");
   prof_begin(ctx, s, "reduce_partials");
-  e = cvx::launch_reduce_part((const double*)ctx->buf[B_PART], 1, nblocks, L, (double*)(res + 8 * B), s);
+  e = cvx::launch_reduce_part_out((const double*)ctx->buf[B_PART], 1, nblocks, L,
+                                  (double*)(static_cast<char*>(ctx->pinned) + 8 * B), res, ctx->pinned,
+                                  (int64_t)8 * B, s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
-  HIP_TRY(to_pinned(ctx, res, res_bytes, s), "result copy");
   HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
   const double* shift = static_cast<const double*>(ctx->pinned);
   std::vector<double> G1;

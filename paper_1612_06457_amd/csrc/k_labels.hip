@@ -11,9 +11,11 @@
 // passes need (the training pixels are a few percent of the page, scattered
 // over it, so every step holds several classes).
 //   k_label_count: class counts per wave tile, class-major (K x nW), with
-//                  LDS counters private to the wave;
+//                  LDS counters private to the wave, and a row of flags
+//                  for entries outside -1..K-1;
 //   k_label_scan:  one block per class turns its row of counts into
 //                  exclusive offsets within the class, and the class total;
+//                  one more block turns the flags into the error flag;
 //   k_label_index: each wave starts from its offsets (class base + its
 //                  offset within the class), compacts the valid labelled
 //                  entries of a step, in raster order, into a per-wave LDS
@@ -150,8 +152,7 @@ __device__ __forceinline__ int wave_inclusive(int x) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_label_count(const int8_t* __restrict__ labels, int64_t P, int K,
-                                                        int nW, int32_t* __restrict__ wave_counts,
-                                                        int32_t* __restrict__ err) {
+                                                        int nW, int32_t* __restrict__ wave_counts) {
   __shared__ int cnt[kWaves][128];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wv = blockIdx.x * kWaves + w;
@@ -171,21 +172,24 @@ __global__ __launch_bounds__(kBlock) void k_label_count(const int8_t* __restrict
       atomicAdd(&my[byte_at(cur, i)], 1);
     }
   });
-  if (bad) atomicOr(err, 1);
   wave_lds_sync();
   for (int k = lane; k < K; k += 64) wave_counts[(int64_t)k * nW + wv] = my[k];
+  const bool any_bad = __ballot(bad) != 0;
+  if (lane == 0) wave_counts[(int64_t)K * nW + wv] = any_bad ? 1 : 0;
 }
 
-// Block k: row k of the K x nW counts becomes exclusive offsets within the
-// class (in place), and class_total[k] its sum.  Chunks of kScanThreads x
+// Block k < K: row k of the counts becomes exclusive offsets within the
+// class (in place), and class_total[k] its sum.  Block K sums the row of
+// flags the same way and sets the error flag from it.  Chunks of kScanThreads x
 // kPer entries (one chunk covers a page of 67 M entries): each thread loads
 // kPer consecutive ones, all in flight together, and the block scans the
 // thread sums.
 constexpr int kPer = 16;
 constexpr int kScanThreads = 1024;
 constexpr int kScanWaves = kScanThreads / 64;
-__global__ __launch_bounds__(kScanThreads) void k_label_scan(int32_t* __restrict__ wave_counts, int nW,
-                                                             int32_t* __restrict__ class_total) {
+__global__ __launch_bounds__(kScanThreads) void k_label_scan(int32_t* __restrict__ wave_counts, int nW, int K,
+                                                             int32_t* __restrict__ class_total,
+                                                             int32_t* __restrict__ err) {
   __shared__ int wsum[kScanWaves];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int32_t* row = wave_counts + (int64_t)blockIdx.x * nW;
@@ -216,7 +220,14 @@ __global__ __launch_bounds__(kScanThreads) void k_label_scan(int32_t* __restrict
     }
     carry += tot;
   }
-  if (threadIdx.x == 0) class_total[blockIdx.x] = carry;
+  if (threadIdx.x == 0) {
+    if ((int)blockIdx.x < K) {
+      class_total[blockIdx.x] = carry;
+    } else {
+      err[0] = carry > 0 ? 1 : 0;
+      err[1] = 0;
+    }
+  }
 }
 
 // Compact the valid labelled entries of one wave step into list[] (raster
@@ -322,14 +333,16 @@ hipError_t launch_points_to_pixels(const int64_t* pixels, int32_t* idx, const in
 }
 
 hipError_t launch_label_count(const int8_t* labels, int64_t P, int K, int nW, int32_t* wave_counts,
-                              int32_t* err_flag, hipStream_t s) {
+                              hipStream_t s) {
   hipLaunchKernelGGL(k_label_count, dim3((nW + kWaves - 1) / kWaves), dim3(kBlock), 0, s, labels, P, K, nW,
-                     wave_counts, err_flag);
+                     wave_counts);
   return hipGetLastError();
 }
 
-hipError_t launch_label_scan(int32_t* wave_counts, int nW, int K, int32_t* class_total, hipStream_t s) {
-  hipLaunchKernelGGL(k_label_scan, dim3(K), dim3(kScanThreads), 0, s, wave_counts, nW, class_total);
+hipError_t launch_label_scan(int32_t* wave_counts, int nW, int K, int32_t* class_total, int32_t* err_flag,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_label_scan, dim3(K + 1), dim3(kScanThreads), 0, s, wave_counts, nW, K, class_total,
+                     err_flag);
   return hipGetLastError();
 }
 

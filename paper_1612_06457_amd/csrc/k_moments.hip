@@ -103,9 +103,18 @@ __global__ __launch_bounds__(kBlock) void k_pca_gram(const typename Elem<DT>::T*
 // 16 entries x 16 slices of g per block: slice j sums g = j, j + 16, ...
 // (four independent chains in flight), then the 16 slice sums are added
 // in slice order.  Fixed order throughout.
+//
+// With hdr_bytes > 0, block (0, 0) also copies hdr_bytes (a multiple of 4)
+// from hdr_src to hdr_dst: a fit's small results (counts, offsets, flags,
+// shifts) then reach page-locked host memory in the same launch as its
+// Gram, which the kernel writes there directly.
 __global__ __launch_bounds__(kBlock) void k_reduce_part(const double* __restrict__ part, int nsets,
-                                                        int G, int L, double* __restrict__ out) {
+                                                        int G, int L, double* __restrict__ out,
+                                                        const uint32_t* __restrict__ hdr_src,
+                                                        uint32_t* __restrict__ hdr_dst, int64_t hdr_bytes) {
   __shared__ double red[16][17];
+  if (blockIdx.x == 0 && blockIdx.y == 0)
+    for (int64_t i = threadIdx.x; i < hdr_bytes / 4; i += kBlock) hdr_dst[i] = hdr_src[i];
   const int s = blockIdx.y;
   const int tl = threadIdx.x & 15, sl = threadIdx.x >> 4;
   const int t = blockIdx.x * 16 + tl;
@@ -186,7 +195,15 @@ hipError_t launch_pca_gram(int dtype, const void* cube, int B, int64_t P, const 
 hipError_t launch_reduce_part(const double* part, int nsets, int G, int L, double* out,
                               hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_part, dim3((unsigned)((L + 15) / 16), nsets), dim3(kBlock), 0, s, part,
-                     nsets, G, L, out);
+                     nsets, G, L, out, (const uint32_t*)nullptr, (uint32_t*)nullptr, (int64_t)0);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_part_out(const double* part, int nsets, int G, int L, double* out_host,
+                                  const void* hdr_src, void* hdr_dst, int64_t hdr_bytes, hipStream_t s) {
+  if (hdr_bytes % 4 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce_part, dim3((unsigned)((L + 15) / 16), nsets), dim3(kBlock), 0, s, part,
+                     nsets, G, L, out_host, (const uint32_t*)hdr_src, (uint32_t*)hdr_dst, hdr_bytes);
   return hipGetLastError();
 }
 

@@ -30,13 +30,16 @@ struct SoftBwdArgs {
 
 // label bookkeeping
 // label bookkeeping over nW = ceil(P / kLabelWave) wave tiles:
-// wave_counts is K x nW (class-major); the count kernel writes the counts,
+// wave_counts is (K + 1) x nW (class-major; row K: a flag per wave tile for
+// entries outside -1..K-1); the count kernel writes the counts and flags,
 // the scan kernel turns each class row into exclusive offsets within the
-// class (in place) and writes the K class totals, the index kernel writes
-// the class-grouped list and the counts and offsets
+// class (in place), writes the K class totals and sets err_flag[0] to 1 or
+// 0 (err_flag[1] to 0), the index kernel writes the class-grouped list and
+// the counts and offsets
 hipError_t launch_label_count(const int8_t* labels, int64_t P, int K, int nW, int32_t* wave_counts,
-                              int32_t* err_flag, hipStream_t s);
-hipError_t launch_label_scan(int32_t* wave_counts, int nW, int K, int32_t* class_total, hipStream_t s);
+                              hipStream_t s);
+hipError_t launch_label_scan(int32_t* wave_counts, int nW, int K, int32_t* class_total, int32_t* err_flag,
+                             hipStream_t s);
 hipError_t launch_label_index(const int8_t* labels, int64_t P, int K, int nW, const int32_t* wave_off,
                               const int32_t* class_total, int32_t* idx, int64_t* counts_out, int32_t* offsets_out,
                               hipStream_t s);
@@ -67,6 +70,10 @@ hipError_t launch_pca_gram_mfma(int dtype, int split, const void* cube, int B, i
 // out[s * L + t] = sum_g part[(s * G + g) * L + t]
 hipError_t launch_reduce_part(const double* part, int nsets, int G, int L, double* out,
                               hipStream_t s);
+// the same with out in page-locked host memory, and hdr_bytes (a multiple
+// of 4) copied from hdr_src to hdr_dst in the same launch
+hipError_t launch_reduce_part_out(const double* part, int nsets, int G, int L, double* out_host,
+                                  const void* hdr_src, void* hdr_dst, int64_t hdr_bytes, hipStream_t s);
 
 // projection, pass 1 (range) and pass 2 (stretch to uint8); plain = the
 // FP32 vector-ALU kernels whatever the page type (else float32 pages only)
