@@ -229,7 +229,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the timings of the rescaling, colour, assessment and many-page calls")
+                    help="skip the timings of the rescaling, colour, assessment and many-page calls "
+                         "and of the plain FP32 path")
     ap.add_argument("--copy-gib", type=int, default=0,
                     help="after the timed steps, copy this many GiB device to device (a plain copy of "
                          "known size, to calibrate hardware byte counters against)")
@@ -367,7 +368,8 @@ def main():
         "kernels_ms_per_launch": {k: round(v[1] / max(v[0], 1), 4) for k, v in prof.items()},
         "roofline": roof,
     }
-    out["vs_plain_fp32"] = vs_plain(cx, torch, cube, labels, K, img, pimg, fit_proj_bytes, per, mean_fp, P, B)
+    if not args.no_extras:
+        out["vs_plain_fp32"] = vs_plain(cx, torch, cube, labels, K, img, pimg, fit_proj_bytes, per, mean_fp, P, B)
     if not args.no_extras:
         out["extras"] = extras(cx, torch, case, cube, fit_last(cx, cube, labels, K), dev, labels)
     if args.copy_gib > 0:
