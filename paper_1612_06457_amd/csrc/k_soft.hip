@@ -162,8 +162,14 @@ __device__ __forceinline__ f32x4 mma_f32(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Three waves per SIMD where the registers allow it without spilling (up to
+// 48 padded bands with the small prefetch: 153 VGPRs); measured 16 % faster
+// than two at 33 bands and 8 classes.
+template <int NRB, int QX>
+constexpr int scatter_waves() { return (NRB <= 2 || (NRB == 3 && QX == 5)) ? 3 : 1; }
+
 template <int NRB, int QX, int QW>
-__global__ __launch_bounds__(kBlock) void k_soft_scatter_mfma(const float* __restrict__ X,
+__global__ __launch_bounds__(kBlock, (scatter_waves<NRB, QX>())) void k_soft_scatter_mfma(const float* __restrict__ X,
                                                               const float* __restrict__ W, int64_t N, int B, int K,
                                                               const float* __restrict__ mc_f,
                                                               double* __restrict__ part) {
