@@ -385,10 +385,12 @@ int cvamx_set_plain_fp32(cvamx_ctx* ctx, int enable);
 
 /* ---- kernel timing ------------------------------------------------------ */
 
-/* Enable (1) or disable (0) per-kernel timing on this context: every kernel
- * the library launches is bracketed by a pair of HIP events on the caller's
- * stream.  Enabling clears the accumulated totals.  Costs two event records
- * per launch while enabled. */
+/* Per-kernel timing on this context: with enable = 1 every kernel the
+ * library launches is bracketed by a pair of HIP events on its stream; with
+ * 2 only the page-streaming projection passes are (their names begin with
+ * "project_"), which keeps the event records out of the short kernels of
+ * the fits; 0 (or any other value) disables it.  Enabling clears the
+ * accumulated totals.  Costs two event records per timed launch. */
 int cvamx_profile_enable(cvamx_ctx* ctx, int enable);
 
 /* Wait for the timed kernels and write one text line per kernel name,

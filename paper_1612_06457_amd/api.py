@@ -541,11 +541,13 @@ def set_plain_fp32(enable: bool = True, device: int = 0) -> None:
     check(lib().cvamx_set_plain_fp32(ctx, 1 if enable else 0), ctx)
 
 
-def profile_enable(enable: bool = True, device: int = 0) -> None:
+def profile_enable(enable=True, device: int = 0) -> None:
     """Bracket every kernel the library launches on `device` with HIP events
-    (on the stream it is launched on); clears earlier totals."""
+    (on the stream it is launched on); enable="projection" brackets only the
+    page-streaming projection passes; clears earlier totals."""
     ctx = context(device)
-    check(lib().cvamx_profile_enable(ctx, 1 if enable else 0), ctx)
+    mode = 2 if enable == "projection" else (1 if enable else 0)
+    check(lib().cvamx_profile_enable(ctx, mode), ctx)
 
 
 def profile_report(device: int = 0) -> dict:

@@ -38,7 +38,7 @@ struct cvamx_ctx {
   float* range_dev = nullptr;    // 16 floats: scale[8], offset[8] of the current group
   float* ab_dev = nullptr;       // 2 * CVAMX_MAX_BANDS floats: (min, max) per component
   // kernel timing (cvamx_profile_enable)
-  bool prof = false;
+  int prof = 0;   // 0 off, 1 every kernel, 2 the page-streaming projection passes only
   struct Pending {
     const char* name;
     hipEvent_t a, b;
@@ -121,6 +121,7 @@ hipEvent_t get_event(cvamx_ctx* ctx) {
 // Bracket one kernel launch with events when timing is enabled.
 void prof_begin(cvamx_ctx* ctx, hipStream_t s, const char* name) {
   if (!ctx->prof) return;
+  if (ctx->prof == 2 && std::strncmp(name, "project_", 8) != 0) return;
   hipEvent_t a = get_event(ctx);
   if (!a) return;
   (void)hipEventRecord(a, s);
@@ -1110,7 +1111,7 @@ int cvamx_profile_enable(cvamx_ctx* ctx, int enable) {
   if (ctx->device < 0) return fail(ctx, CVAMX_E_DEVICE, "context has no device");
   prof_collect(ctx);
   ctx->prof_acc.clear();
-  ctx->prof = enable != 0;
+  ctx->prof = (enable == 1 || enable == 2) ? enable : 0;
   return CVAMX_OK;
 }
 
