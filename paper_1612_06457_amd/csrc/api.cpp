@@ -561,8 +561,8 @@ static int fit_from_index(cvamx_ctx* ctx, const cvamx_cube* cube, int32_t K, int
 
 static int fit_layout_and_buffers(cvamx_ctx* ctx, int K, int B, int& G, int& L, char*& res) {
   L = cvx::tri_blocks(B) * 16;
-  // blocks per class: about four resident blocks per CU over all classes
-  G = std::max(1, std::min(256, 4 * ctx->num_cu / K));
+  // blocks per class: three per CU over all classes (one round at three resident blocks)
+  G = std::max(1, std::min(256, 3 * ctx->num_cu / K));
   const FitLayout lay(K, B, L);
   if (int st = ensure(ctx, B_PART, (size_t)K * G * L * 8)) return st;
   if (int st = ensure(ctx, B_RES, lay.total)) return st;

@@ -281,8 +281,12 @@ __global__ __launch_bounds__(kBlock) void k_class_split(const void* __restrict__
 // operands built exactly by bit operations (U16Lane, k_split.hpp), summed as
 // HH + HL + LH + LL and unscaled by 2^20 in FP64.  Same gather, shift and
 // output layout as k_class_split; every product is exact.
+// Three waves per SIMD where the registers allow it without spilling.
 template <int NRB, int UM>
-__global__ __launch_bounds__(kBlock) void k_class_u16(const void* __restrict__ cube, int B, int64_t P,
+constexpr int class_u16_waves() { return ((NRB == 2 && UM <= 9) || (NRB == 3 && UM <= 5)) ? 3 : 1; }
+
+template <int NRB, int UM>
+__global__ __launch_bounds__(kBlock, (class_u16_waves<NRB, UM>())) void k_class_u16(const void* __restrict__ cube, int B, int64_t P,
                                                       const int32_t* __restrict__ idx,
                                                       const int32_t* __restrict__ offsets, int G,
                                                       double* __restrict__ part, double* __restrict__ shift_out) {
