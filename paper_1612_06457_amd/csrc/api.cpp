@@ -996,7 +996,7 @@ int cva_soft_forward(cvamx_ctx* ctx, const float* X, const float* w, int64_t N, 
   const int BP = cvx::padded_bp(B), KP = (K + 3) & ~3;
   const int L = cvx::tri_blocks(B) * 16;
   const int64_t nch = (N + cvx::kChunk - 1) / cvx::kChunk;
-  const int nb1 = (int)std::max<int64_t>(1, std::min<int64_t>(2 * ctx->num_cu, nch));
+  const int nb1 = (int)std::max<int64_t>(1, std::min<int64_t>(3 * ctx->num_cu, nch));
   // pass 2: about three blocks per CU over all class groups of four
   const int groups = (K + cvx::kWaves - 1) / cvx::kWaves;
   const int G = (int)std::max<int64_t>(1, std::min<int64_t>(3 * ctx->num_cu / groups, nch));

@@ -75,7 +75,7 @@ __device__ __forceinline__ void for_each_chunk(const float* __restrict__ X, cons
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_soft_first(const float* __restrict__ X, const float* __restrict__ W,
+__global__ __launch_bounds__(kBlock, 3) void k_soft_first(const float* __restrict__ X, const float* __restrict__ W,
                                                        int64_t N, int B, int K, double* __restrict__ part) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int BP = (B + 1 + 3) & ~3, KP = (K + 3) & ~3;
