@@ -154,6 +154,52 @@ def vs_plain(cx, torch, cube, labels, K, img, pimg, fit_proj_bytes, per, mean_fp
     }
 
 
+def copy_bandwidth(torch, gib: int = 1) -> float:
+    """GB/s of a plain device-to-device copy (bytes read + bytes written
+    over the median time of 5), the measured roof beside the nominal one."""
+    src = torch.ones(gib << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    ms = _timed(torch, lambda: dst.copy_(src))
+    del src, dst
+    return 2 * (gib << 30) / (ms * 1e-3) / 1e9
+
+
+def mixed_half_pages(cx, torch, dev):
+    """The 4096 x 4096 x 23 page (4 classes, 200,000 training pixels) as bf16
+    and as fp16 values: CVA fit + project and PCA fit with the FP32 request
+    (vector-ALU moments; exact split projection on the matrix cores), with
+    the bf16x3 / f16x3 split (moments on the matrix cores too) and on the
+    plain FP32 path; every variant meets the FP32 tolerances against the
+    oracle (GPU tests)."""
+    from synth import make_case, to_half_cube
+    c = make_case(3, threads=16)
+    P, B, K = c.H * c.W, c.B, c.K
+    labels = torch.from_numpy(c.labels).to(dev)
+    img = torch.empty((K - 1, c.H, c.W), dtype=torch.uint8, device=dev)
+    nbytes = 2 * P * B * 2 + P * (K - 1) + c.labels.size + int((c.labels >= 0).sum()) * B * 2
+    res = {"workload": c.workload, "algorithmic_MB": round(nbytes / 1e6, 1)}
+    for kind, split in (("bf16", "bf16x3"), ("f16", "f16x3")):
+        cube = to_half_cube(c.cube, kind).to(dev)
+        r = {}
+        for name, prec, plain in (("fp32", "fp32", False), (split, split, False), ("plain_fp32", "fp32", True)):
+            cx.set_plain_fp32(plain)
+            try:
+                t = _timed(torch, lambda: cx.cva_fit_project(cube, labels, K, precision=prec, out=img))
+                tp = _timed(torch, lambda: cx.pca_fit(cube, n_comp=3, precision=prec))
+            finally:
+                cx.set_plain_fp32(False)
+            r[name] = {"cva_fit_project_ms": round(t, 4), "Gpix_band_per_s": round(P * B / (t * 1e-3) / 1e9, 1),
+                       "frac_of_8TBps": round(nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "pca_fit_ms": round(tp, 4)}
+        r["speedup_vs_plain"] = {k: round(r["plain_fp32"]["cva_fit_project_ms"] / r[k]["cva_fit_project_ms"], 3)
+                                 for k in ("fp32", split)}
+        r["pca_speedup_vs_plain"] = {k: round(r["plain_fp32"]["pca_fit_ms"] / r[k]["pca_fit_ms"], 3)
+                                     for k in ("fp32", split)}
+        res[kind] = r
+        del cube
+    return res
+
+
 def extras(cx, torch, case, cube, fit, dev, labels=None):
     """Timings of the calls beyond the headline path on the same page:
     float images, the three rescaling modes, 16-bit output, the RGB
@@ -377,8 +423,13 @@ def main():
         "kernels_ms_per_launch": {k: round(v[1] / max(v[0], 1), 4) for k, v in sorted(prof_all.items())},
         "roofline": roof,
     }
+    copy_gbs = copy_bandwidth(torch)
+    roof["measured_copy_GBps"] = round(copy_gbs, 1)
+    roof["frac_of_measured_copy"] = round(achieved / copy_gbs, 4)
+    roof["fit_plus_project"]["frac_of_measured_copy"] = round(fit_proj_bytes / (mean_fp * 1e-3) / 1e9 / copy_gbs, 4)
     if not args.no_extras:
         out["vs_plain_fp32"] = vs_plain(cx, torch, cube, labels, K, img, pimg, fit_proj_bytes, per, mean_fp, P, B)
+        out["vs_plain_fp32"]["half_pages"] = mixed_half_pages(cx, torch, dev)
     if not args.no_extras:
         out["extras"] = extras(cx, torch, case, cube, fit_last(cx, cube, labels, K), dev, labels)
     if args.copy_gib > 0:

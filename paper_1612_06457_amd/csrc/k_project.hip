@@ -1,6 +1,9 @@
-// Projection passes on the VALU (float32 pages, and every page type on the
-// plain FP32 reference path), and the dispatchers: otherwise uint16 pages go
-// to k_project_u16.hip, bf16 / fp16 pages to k_project_mfma.hip.
+// Projection passes on the VALU, and the dispatchers.  uint16 pages take the
+// matrix-core passes of k_project_u16.hip, except on the plain FP32
+// reference path; float32, bf16 and fp16 pages take the VALU passes here.
+// For 16-bit float pages the VALU measured faster than a matrix-core form
+// with split operands at every band and component count tried (1.2-2.7x at
+// 16 to 48 bands and 1 to 12 components): the products are few per byte.
 #include "k_project.hpp"
 
 namespace cvx {
@@ -43,27 +46,23 @@ hipError_t project_float_generic(int dtype, int nc, const void* cube, int B, int
 hipError_t launch_project_range(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
                                 const ProjArgs& a, int nblocks, float* part, unsigned* ticket,
                                 float* range_dev, float* ab_dev, hipStream_t s) {
-  if (plain || dtype == DT_F32)
-    return project_range_generic(dtype, nc, cube, B, P, a, nblocks, part, ticket, range_dev, ab_dev, s);
-  if (dtype == DT_U16)
+  if (dtype == DT_U16 && !plain)
     return launch_project_range_u16(cube, B, P, nc, a, nblocks, part, ticket, range_dev, ab_dev, s);
-  return launch_project_range_mfma(dtype, cube, B, P, nc, a, nblocks, part, ticket, range_dev, ab_dev, s);
+  return project_range_generic(dtype, nc, cube, B, P, a, nblocks, part, ticket, range_dev, ab_dev, s);
 }
 
 hipError_t launch_project_stretch(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
                                   const ProjArgs& a, int nblocks, const float* range_dev, uint8_t* images,
                                   hipStream_t s) {
-  if (plain || dtype == DT_F32)
-    return project_stretch_generic(dtype, nc, cube, B, P, a, nblocks, range_dev, images, s);
-  if (dtype == DT_U16) return launch_project_stretch_u16(cube, B, P, nc, a, nblocks, range_dev, images, s);
-  return launch_project_stretch_mfma(dtype, cube, B, P, nc, a, nblocks, range_dev, images, s);
+  if (dtype == DT_U16 && !plain)
+    return launch_project_stretch_u16(cube, B, P, nc, a, nblocks, range_dev, images, s);
+  return project_stretch_generic(dtype, nc, cube, B, P, a, nblocks, range_dev, images, s);
 }
 
 hipError_t launch_project_float(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
                                 const ProjArgs& a, int nblocks, float* y, hipStream_t s) {
-  if (plain || dtype == DT_F32) return project_float_generic(dtype, nc, cube, B, P, a, nblocks, y, s);
-  if (dtype == DT_U16) return launch_project_float_u16(cube, B, P, nc, a, nblocks, y, s);
-  return launch_project_float_mfma(dtype, cube, B, P, nc, a, nblocks, y, s);
+  if (dtype == DT_U16 && !plain) return launch_project_float_u16(cube, B, P, nc, a, nblocks, y, s);
+  return project_float_generic(dtype, nc, cube, B, P, a, nblocks, y, s);
 }
 
 }  // namespace cvx

@@ -85,25 +85,16 @@ hipError_t launch_project_stretch(int dtype, bool plain, const void* cube, int B
                                   const ProjArgs& a, int nblocks, const float* range_dev, uint8_t* images,
                                   hipStream_t s);
 
-// matrix-core projection (same contract as above): uint16 pages, and
-// bf16 / fp16 pages
+// matrix-core projection of uint16 pages (same contract as above)
 hipError_t launch_project_range_u16(const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
                                     int nblocks, float* part, unsigned* ticket, float* range_dev,
                                     float* ab_dev, hipStream_t s);
 hipError_t launch_project_stretch_u16(const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
                                       int nblocks, const float* range_dev, uint8_t* images,
                                       hipStream_t s);
-hipError_t launch_project_range_mfma(int dtype, const void* cube, int B, int64_t P, int nc,
-                                     const ProjArgs& a, int nblocks, float* part, unsigned* ticket,
-                                     float* range_dev, float* ab_dev, hipStream_t s);
-hipError_t launch_project_stretch_mfma(int dtype, const void* cube, int B, int64_t P, int nc,
-                                       const ProjArgs& a, int nblocks, const float* range_dev,
-                                       uint8_t* images, hipStream_t s);
 
 hipError_t launch_project_float_u16(const void* cube, int B, int64_t P, int nc, const ProjArgs& a, int nblocks,
                                     float* y, hipStream_t s);
-hipError_t launch_project_float_mfma(int dtype, const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
-                                     int nblocks, float* y, hipStream_t s);
 
 // rescaling from FP32 component planes y (nc planes of P floats, nc <= 64)
 constexpr int kSelTargets = 4;   // order statistics wanted per plane by one select
