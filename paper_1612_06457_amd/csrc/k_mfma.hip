@@ -7,6 +7,8 @@
 //
 // Shift: the mean of 64 pixels spread evenly over the page (rounded to the
 // element type for 16-bit pages), summed in a fixed order by every block.
+#include <type_traits>
+
 #include "k_split.hpp"
 #include "k_tile.hpp"
 #include "launch.hpp"
@@ -158,27 +160,34 @@ __global__ __launch_bounds__(kBlock) void k_pca_gram_u16(const void* __restrict_
       wave_lds_sync();
     }
     const uint16_t* tile = reinterpret_cast<const uint16_t*>(my);
-    for (int k0 = 0; k0 < tp; k0 += 32) {
-      f16x8 Hv[NRB], Lv[NRB];
+    // whole tiles (the common case) build their operands with no row mask
+    auto ksteps = [&](auto whole) {
+      constexpr bool WHOLE = decltype(whole)::value;
+      for (int k0 = 0; k0 < tp; k0 += 32) {
+        f16x8 Hv[NRB], Lv[NRB];
 #pragma unroll
-      for (int rb = 0; rb < NRB; ++rb) {
-        u32x4 H, L;
+        for (int rb = 0; rb < NRB; ++rb) {
+          u32x4 H, L;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int r = k0 + 8 * grp + 2 * u;
-          const uint32_t d = (uint32_t)tile[r * B + ln.bcol[rb]] | ((uint32_t)tile[(r + 1) * B + ln.bcol[rb]] << 16);
-          uint32_t rm = 0xffffffffu;
-          if (!full) rm = (vrow[w][r] ? 0x0000ffffu : 0u) | (vrow[w][r + 1] ? 0xffff0000u : 0u);
-          uint32_t h, l;
-          ln.terms(d, rb, rm, mk, h, l);
-          H[u] = h;
-          L[u] = l;
+          for (int u = 0; u < 4; ++u) {
+            const int r = k0 + 8 * grp + 2 * u;
+            const uint32_t d =
+                (uint32_t)tile[r * B + ln.bcol[rb]] | ((uint32_t)tile[(r + 1) * B + ln.bcol[rb]] << 16);
+            uint32_t rm = 0xffffffffu;
+            if constexpr (!WHOLE) rm = (vrow[w][r] ? 0x0000ffffu : 0u) | (vrow[w][r + 1] ? 0xffff0000u : 0u);
+            uint32_t h, l;
+            ln.terms(d, rb, rm, mk, h, l);
+            H[u] = h;
+            L[u] = l;
+          }
+          Hv[rb] = __builtin_bit_cast(f16x8, H);
+          Lv[rb] = __builtin_bit_cast(f16x8, L);
         }
-        Hv[rb] = __builtin_bit_cast(f16x8, H);
-        Lv[rb] = __builtin_bit_cast(f16x8, L);
+        u16_tile_products<NRB>(Hv, Lv, acc);
       }
-      u16_tile_products<NRB>(Hv, Lv, acc);
-    }
+    };
+    if (full) ksteps(std::true_type{});
+    else ksteps(std::false_type{});
     fold<NRB>(acc, accd);
   });
   __syncthreads();
