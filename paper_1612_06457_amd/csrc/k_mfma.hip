@@ -63,25 +63,33 @@ __global__ __launch_bounds__(kBlock) void k_pca_gram_mfma(const void* __restrict
   const unsigned char* base = reinterpret_cast<const unsigned char*>(cube);
   for_each_tile<Q>(base, total_bytes, nt, S, my, [&](int64_t t) {
     const int64_t pix0 = t * tp;
-    // row validity for this tile (page end, mask)
-    for (int r = lane; r < tp; r += 64) {
-      const int64_t p = pix0 + r;
-      vrow[w][r] = (p < P && (mask == nullptr || mask[p] != 0)) ? 1 : 0;
-    }
-    wave_lds_sync();
-    auto get = [&](int r, int band) {
-      float v = 0.f;
-      if (vrow[w][r]) {
-        if (band < B) {
-          if constexpr (DT == DT_F32) v = (reinterpret_cast<const float*>(my)[r * B + band] - cs[band]) * scale;
-          else v = (to_float<DT>(reinterpret_cast<const uint16_t*>(my)[r * B + band]) - cs[band]) * scale;
-        } else if (band == B) {
-          v = 1.f;
-        }
+    // row validity (page end, mask), needed only for tiles not wholly taken
+    const bool full = pix0 + tp <= P && mask == nullptr;
+    if (!full) {
+      for (int r = lane; r < tp; r += 64) {
+        const int64_t p = pix0 + r;
+        vrow[w][r] = (p < P && (mask == nullptr || mask[p] != 0)) ? 1 : 0;
       }
-      return v;
+      wave_lds_sync();
+    }
+    auto ksteps = [&](auto whole) {
+      constexpr bool WHOLE = decltype(whole)::value;
+      auto get = [&](int r, int band) {
+        float v = 0.f;
+        if (WHOLE || vrow[w][r]) {
+          if (band < B) {
+            if constexpr (DT == DT_F32) v = (reinterpret_cast<const float*>(my)[r * B + band] - cs[band]) * scale;
+            else v = (to_float<DT>(reinterpret_cast<const uint16_t*>(my)[r * B + band]) - cs[band]) * scale;
+          } else if (band == B) {
+            v = 1.f;
+          }
+        }
+        return v;
+      };
+      for (int k0 = 0; k0 < tp; k0 += 32) kstep<SPLIT, NRB>(get, k0, acc);
     };
-    for (int k0 = 0; k0 < tp; k0 += 32) kstep<SPLIT, NRB>(get, k0, acc);
+    if (full) ksteps(std::true_type{});
+    else ksteps(std::false_type{});
     fold<NRB>(acc, accd);
   });
   __syncthreads();
