@@ -257,8 +257,10 @@ void make_proj_args(const cvamx_cube* cube, const double* W, const double* cente
   for (int b = 0; b < B; ++b) {
     // uint16 pages: an integer centre, passed as 2^23 + c (exact in FP32),
     // which the kernels subtract from the bit-built float 2^23 + x
-    // bf16 / fp16 pages: a centre of the page's own type, so x - c has at
-    // most 16 (bf16) or 22 (fp16) significant bits and splits exactly
+    // bf16 / fp16 pages: a centre of the page's own type, so that x - c of
+    // two such values is exact in FP32 whenever their exponents are within
+    // 16 (bf16) or 13 (fp16) of each other; the FP64 offset below absorbs
+    // the difference between c and the requested centre either way
     switch (cube->dtype) {
       case CVAMX_U16: c[b] = std::nearbyint(center[b]); break;
       case CVAMX_BF16: c[b] = bf16_round(center[b]); break;
