@@ -61,11 +61,11 @@ typedef enum {
   CVAMX_F32 = 1,
   CVAMX_BF16 = 2,
   CVAMX_F16 = 3,
-  CVAMX_U8 = 4     /* 8-bit images: accepted by cvamx_cluster_indices only */
+  CVAMX_U8 = 4     /* 8-bit values: band images for cvamx_bands_to_cube and cvamx_run_pages, images for cvamx_cluster_indices */
 } cvamx_dtype;
 
 typedef enum {
-  CVAMX_PREC_FP32 = 0,    /* plain FP32 products and sums, FP64 combine */
+  CVAMX_PREC_FP32 = 0,    /* FP32 accuracy: FP32 sums, FP64 combine; on uint16 pages the products run exactly on the matrix cores (bit-built fp16 terms), elsewhere plain FP32 on the vector ALUs (cvamx_set_plain_fp32: vector ALUs everywhere) */
   CVAMX_PREC_BF16X3 = 1,  /* MFMA, values split hi+lo in bf16, hi*hi + hi*lo + lo*hi (+ lo*lo for integer pages), FP32 accumulate, FP64 combine */
   CVAMX_PREC_F16X3 = 2    /* same with an fp16 split */
 } cvamx_prec;
