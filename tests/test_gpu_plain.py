@@ -117,3 +117,32 @@ def test_plain_equals_default_within_fp32(dev, kind):
     assert np.max(np.abs(ab1 - base[2]) / span[:, None]) <= TOL_Y
     assert np.max(np.abs(y1 - base[3]).reshape(y1.shape[0], -1) / span[:, None]) <= TOL_Y
     assert np.max(np.abs(q1.cpu().numpy().astype(int) - base[1].astype(int))) <= 1
+
+
+def test_kernel_timing_modes(dev):
+    """Per-kernel timing: every kernel, or only the page-streaming
+    projection passes; the counts match the launches."""
+    say("kernel timing modes")
+    import paper_1612_06457_amd as cx
+    c, cube, _ = _page("u16", odd=True)
+    tc, tl = _t(cube, dev), _t(c.labels, dev)
+    cx.profile_enable(True)
+    try:
+        cx.cva_fit_project(tc, tl, c.K)
+        rep = cx.profile_report()
+    finally:
+        cx.profile_enable(False)
+    C = c.K - 1
+    for name in ("label_count", "label_scan", "label_index", "class_moments_mfma", "reduce_partials",
+                 f"project_range_nc{C}", f"project_stretch_nc{C}"):
+        assert rep.get(name, (0, 0.0))[0] == 1, (name, rep)
+        assert rep[name][1] > 0.0
+    cx.profile_enable("projection")
+    try:
+        cx.cva_fit_project(tc, tl, c.K)
+        cx.cva_fit_project(tc, tl, c.K)
+        rep = cx.profile_report()
+    finally:
+        cx.profile_enable(False)
+    assert sorted(rep) == sorted([f"project_range_nc{C}", f"project_stretch_nc{C}"]), rep
+    assert all(v[0] == 2 for v in rep.values())
