@@ -550,3 +550,41 @@ def test_full_page_cfg5_mixed(dev):
     assert np.max(np.abs(lam - pr["eigvals"]) / pr["eigvals"]) <= TOL_LAM
     check_vectors(V, pr["V"], pr["all_eigvals"][:3])
     say("cfg5 mixed pca ok")
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("kind", ["bf16", "f16"])
+def test_full_half_page_cfg3(dev, kind):
+    """The 4096 x 4096 x 23 page as bf16 / fp16 values (4 classes, 50,000
+    training pixels each), at full size: the FP32 fit and the split fit
+    against the oracle on the same 16-bit values, every pixel of the three
+    projected images, and the split PCA covariance."""
+    say(f"cfg3 full page 4096x4096x23 {kind}")
+    import paper_1612_06457_amd as cx
+    c = make_case(3, threads=16)
+    cube = to_half_cube(c.cube, kind)
+    host = cube.float().numpy()
+    del c.cube
+    dcube = _t(cube, dev)
+    prec = "bf16x3" if kind == "bf16" else "f16x3"
+    ref = oracle.cva_fit(host, c.labels, c.K)
+    got = cx.cva_fit(dcube, _t(c.labels, dev), c.K)
+    assert got.counts.tolist() == ref["counts"].tolist()
+    assert rel_max(got.Sw, ref["Sw"]) <= TOL_S
+    assert rel_max(got.Sb, ref["Sb"]) <= TOL_S
+    assert np.max(np.abs(got.eigvals - ref["eigvals"]) / ref["eigvals"]) <= TOL_LAM
+    check_vectors(got.W, ref["W"], ref["eigvals"])
+    _mixed_fit_check(dcube, host, c.labels, c.K, dev, prec, BOUND_EXACT)
+    say(f"cfg3 {kind} fits ok")
+    q, ab = cx.cva_project(dcube, ref["W"], ref["mean"], return_range=True)
+    q_ref, ab_ref = oracle.cva_project(host, ref["W"], ref["mean"])
+    span = ab_ref[:, 1] - ab_ref[:, 0]
+    assert np.max(np.abs(ab - ab_ref) / span[:, None]) <= TOL_Y
+    frac = check_images(q.cpu().numpy(), q_ref)
+    say(f"cfg3 {kind} project ok, differing bytes {frac:.2e}")
+    del q, q_ref
+    pr = oracle.pca_fit(host, n_comp=3)
+    V, lam, mean, cov = cx.pca_fit(dcube, n_comp=3, precision=prec)
+    assert rel_max(cov, pr["cov"]) <= 10 * BOUND_EXACT + TOL_S
+    check_vectors(V, pr["V"], pr["all_eigvals"][:3])
+    say(f"cfg3 {kind} pca ok")
