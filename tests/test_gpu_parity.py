@@ -65,10 +65,10 @@ def _project_parity(cube_host, W, center, dev, signs=None):
     return q, q_ref, frac
 
 
-# ------------------------------------------------------------------ configs
+# ------------------------------------------------------------------ workloads
 
-def test_cfg1_fit_and_project(dev):
-    say("cfg1 512x512x16 u16 K=3")
+def test_page_512x512x16_fit_and_project(dev):
+    say("512x512x16 u16 page, K=3")
     c = make_case(1)
     ref, got, signs = _fit_parity(c.cube, c.labels, c.K, dev)
     # projection with the oracle's own vectors isolates the projection kernel
@@ -78,11 +78,11 @@ def test_cfg1_fit_and_project(dev):
     q = cx.cva_project(_t(c.cube, dev), got.W, got.mean).cpu().numpy()
     q_ref, _ = oracle.cva_project(c.cube, ref["W"], ref["mean"])
     frac = check_images(q, q_ref, signs)
-    say(f"cfg1 differing bytes {frac:.2e}")
+    say(f"512x512x16 page: differing bytes {frac:.2e}")
 
 
-def test_cfg2_scaled_cva_and_pca(dev):
-    say("cfg2 at 1024x1024x23 u16 K=4")
+def test_page_4096x4096x23_structure_scaled_cva_and_pca(dev):
+    say("4096x4096x23 page structure at 1024x1024x23 u16, K=4")
     import paper_1612_06457_amd as cx
     c = make_case(2, scale=0.25)
     ref, got, signs = _fit_parity(c.cube, c.labels, c.K, dev)
@@ -309,7 +309,7 @@ def _soft_parity(X, w, dev, gtol=1e-4):
 
 
 def test_soft_label_small(dev):
-    say("soft-label CVA, cfg4 structure at 1/16 scale")
+    say("soft-label CVA, 1M x 23 structure at 1/16 scale")
     X, w, cls, idx, case = make_soft_case(4, scale=0.25)
     _soft_parity(X, w, dev)
 
@@ -378,15 +378,15 @@ def test_soft_label_shapes_and_scales(dev, N, B, K, xs, ws, neg):
 # ------------------------------------------------------------ full sizes
 
 @pytest.mark.timeout(900)
-def test_full_page_cfg5(dev):
+def test_full_page_7216x5412x33(dev):
     """7216 x 5412 x 33 uint16 page, K = 8, 200k training pixels per class:
     fit parity, every pixel of the 7 projected images, and PCA."""
-    say("cfg5 full page 7216x5412x33 u16 K=8")
+    say("full page 7216x5412x33 u16 K=8")
     import paper_1612_06457_amd as cx
     c = full_page()
-    say("cfg5 generated")
+    say("page generated")
     ref, got, signs = _fit_parity(c.cube, c.labels, c.K, dev)
-    say("cfg5 fit ok", got.eigvals)
+    say("fit ok", got.eigvals)
     cube = _t(c.cube, dev)
     q, ab = cx.cva_project(cube, ref["W"], ref["mean"], return_range=True)
     q = q.cpu().numpy()
@@ -394,22 +394,22 @@ def test_full_page_cfg5(dev):
     span = ab_ref[:, 1] - ab_ref[:, 0]
     assert np.max(np.abs(ab - ab_ref) / span[:, None]) <= TOL_Y
     frac = check_images(q, q_ref)
-    say(f"cfg5 project ok, differing bytes {frac:.2e}")
+    say(f"project ok, differing bytes {frac:.2e}")
     del q, q_ref
     pr = oracle.pca_fit(c.cube, n_comp=3)
     V, lam, mean, cov = cx.pca_fit(cube, n_comp=3)
     assert rel_max(cov, pr["cov"]) <= TOL_S
     assert np.max(np.abs(lam - pr["eigvals"]) / pr["eigvals"]) <= TOL_LAM
     check_vectors(V, pr["V"], pr["all_eigvals"][:3])
-    say("cfg5 pca ok")
+    say("pca ok")
 
 
 @pytest.mark.timeout(600)
-def test_full_soft_cfg4(dev):
+def test_full_soft_1M_x23(dev):
     """1,000,000 x 23 float32 training pixels, K = 5, Dirichlet(0.5) weights
     near class borders: J, gradient against the closed form, and central
     differences of the exact finite change on 64 random pixels."""
-    say("cfg4 soft label 1M x 23, K=5")
+    say("soft label 1M x 23, K=5")
     X, w, cls, idx, case = make_soft_case(4)
     fit, g, g_ref = _soft_parity(X, w, dev)
     rng = np.random.default_rng(4)
@@ -464,7 +464,7 @@ BOUND_F32 = {"bf16x3": 2.0 ** -15 + 1e-5, "f16x3": 2.0 ** -21 + 1e-5}
 
 @pytest.mark.parametrize("prec", ["bf16x3", "f16x3"])
 def test_mixed_cva_and_pca_u16(dev, prec):
-    say(f"mixed {prec} on cfg2 at 1024x1024x23 u16")
+    say(f"mixed {prec} on the 4096x4096x23 structure at 1024x1024x23 u16")
     import paper_1612_06457_amd as cx
     c = make_case(2, scale=0.25)
     cube = _t(c.cube, dev)
@@ -480,7 +480,7 @@ def test_mixed_cva_and_pca_u16(dev, prec):
 @pytest.mark.parametrize("kind,prec", [("bf16", "bf16x3"), ("f16", "f16x3"), ("bf16", "f16x3"),
                                        ("f16", "bf16x3")])
 def test_mixed_half_pages(dev, kind, prec):
-    say(f"mixed {prec} on a {kind} page (cfg3 structure at 1/4 scale)")
+    say(f"mixed {prec} on a {kind} page (4096x4096x23 structure at 1/4 scale)")
     import paper_1612_06457_amd as cx
     c = make_case(2, scale=0.25)
     cube = to_half_cube(c.cube, kind)
@@ -535,31 +535,31 @@ def test_mixed_pca_mask(dev):
 
 
 @pytest.mark.timeout(900)
-def test_full_page_cfg5_mixed(dev):
-    """The benchmark configuration: 7216 x 5412 x 33 uint16, K = 8, BF16
+def test_full_page_7216x5412x33_mixed(dev):
+    """The benchmark workload: 7216 x 5412 x 33 uint16, K = 8, BF16
     compensated scatter on MFMA, FP64 eigensolve; PCA on all pixels."""
-    say("cfg5 full page, bf16x3")
+    say("full page 7216x5412x33, bf16x3")
     import paper_1612_06457_amd as cx
     c = full_page()
     cube = _t(c.cube, dev)
     ref, got = _mixed_fit_check(cube, c.cube, c.labels, c.K, dev, "bf16x3", BOUND_EXACT)
-    say("cfg5 mixed fit ok", got.eigvals)
+    say("mixed fit ok", got.eigvals)
     pr = oracle.pca_fit(c.cube, n_comp=3)
     V, lam, mean, cov = cx.pca_fit(cube, n_comp=3, precision="bf16x3")
     assert rel_max(cov, pr["cov"]) <= TOL_S
     assert np.max(np.abs(lam - pr["eigvals"]) / pr["eigvals"]) <= TOL_LAM
     check_vectors(V, pr["V"], pr["all_eigvals"][:3])
-    say("cfg5 mixed pca ok")
+    say("mixed pca ok")
 
 
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("kind", ["bf16", "f16"])
-def test_full_half_page_cfg3(dev, kind):
+def test_full_half_page_4096x4096x23(dev, kind):
     """The 4096 x 4096 x 23 page as bf16 / fp16 values (4 classes, 50,000
     training pixels each), at full size: the FP32 fit and the split fit
     against the oracle on the same 16-bit values, every pixel of the three
     projected images, and the split PCA covariance."""
-    say(f"cfg3 full page 4096x4096x23 {kind}")
+    say(f"full page 4096x4096x23 {kind}")
     import paper_1612_06457_amd as cx
     c = make_case(3, threads=16)
     cube = to_half_cube(c.cube, kind)
@@ -575,16 +575,16 @@ def test_full_half_page_cfg3(dev, kind):
     assert np.max(np.abs(got.eigvals - ref["eigvals"]) / ref["eigvals"]) <= TOL_LAM
     check_vectors(got.W, ref["W"], ref["eigvals"])
     _mixed_fit_check(dcube, host, c.labels, c.K, dev, prec, BOUND_EXACT)
-    say(f"cfg3 {kind} fits ok")
+    say(f"{kind} fits ok")
     q, ab = cx.cva_project(dcube, ref["W"], ref["mean"], return_range=True)
     q_ref, ab_ref = oracle.cva_project(host, ref["W"], ref["mean"])
     span = ab_ref[:, 1] - ab_ref[:, 0]
     assert np.max(np.abs(ab - ab_ref) / span[:, None]) <= TOL_Y
     frac = check_images(q.cpu().numpy(), q_ref)
-    say(f"cfg3 {kind} project ok, differing bytes {frac:.2e}")
+    say(f"{kind} project ok, differing bytes {frac:.2e}")
     del q, q_ref
     pr = oracle.pca_fit(host, n_comp=3)
     V, lam, mean, cov = cx.pca_fit(dcube, n_comp=3, precision=prec)
     assert rel_max(cov, pr["cov"]) <= 10 * BOUND_EXACT + TOL_S
     check_vectors(V, pr["V"], pr["all_eigvals"][:3])
-    say(f"cfg3 {kind} pca ok")
+    say(f"{kind} pca ok")

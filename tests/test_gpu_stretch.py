@@ -320,11 +320,11 @@ def test_compose_rgb(dev, H, W):
 
 
 @pytest.mark.timeout(900)
-def test_full_page_percentile_cfg5(dev):
+def test_full_page_percentile_7216x5412x33(dev):
     """7216 x 5412 x 33 uint16 page, the 7 CVA components: the selected order
     statistics against a CPU partition of the same FP32 values, and the
     16-bit images on sampled pixels against the oracle's map."""
-    say("cfg5 full page: float planes, percentile and 16-bit stretch")
+    say("full page 7216x5412x33: float planes, percentile and 16-bit stretch")
     import paper_1612_06457_amd as cx
     c = full_page()
     cd = _t(c.cube, dev)
