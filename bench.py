@@ -228,9 +228,9 @@ def extras(cx, torch, case, cube, fit, dev, labels=None):
     train = torch.from_numpy(np.flatnonzero(flat >= 0).astype(np.int64)).to(dev)
     rec("stretch_training_8bit", _timed(torch, lambda: cx.stretch(y, "training", train_pixels=train, out=q8)),
         P * C * 4 + P * C + train.numel() * (8 + 4 * C))
-    # four radix passes read every value once each, then the stretch pass
+    # three radix passes read every value once each, then the stretch pass
     rec("stretch_percentile_16bit", _timed(torch, lambda: cx.stretch(y, "percentile", pct=1.0, bits=16, out=q16)),
-        5 * P * C * 4 + P * C * 2)
+        4 * P * C * 4 + P * C * 2)
     rec("compose_rgb", _timed(torch, lambda: cx.compose_rgb(q8[0], q8[1], q8[2])), 6 * P)
     cls = torch.from_numpy(flat[flat >= 0].astype(np.int8)).to(dev)
     rec("cluster_indices_7x8bit", _timed(torch, lambda: cx.cluster_indices(q8, train, cls, K)),

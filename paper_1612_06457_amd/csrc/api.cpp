@@ -764,7 +764,7 @@ int cvamx_stretch(cvamx_ctx* ctx, const float* y, int64_t P, int32_t n_comp, int
     vindex(pct / 100.0, ranks[0], ranks[1], g_lo);
     vindex((100.0 - pct) / 100.0, ranks[2], ranks[3], g_hi);
     nb = cvx::stretch_reduce_blocks(P, n_comp, ctx->num_cu);
-    if (int st = ensure(ctx, B_SHIST, (size_t)2 * n_comp * cvx::kSelTargets * 256 * 4)) return st;
+    if (int st = ensure(ctx, B_SHIST, (size_t)2 * n_comp * cvx::kSelTargets * cvx::kSelBins * 4)) return st;
     prof_begin(ctx, s, "select");
     e = cvx::launch_select(y, P, n_comp, ranks, nb, sel, (uint32_t*)ctx->buf[B_SHIST], s);
     prof_end(ctx, s);

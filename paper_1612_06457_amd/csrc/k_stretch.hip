@@ -11,8 +11,9 @@
 // FP32 affine form of the same map).
 //
 // Order statistics are found exactly by a most-significant-digit radix
-// select on the order-preserving 32-bit keys of the FP32 values: four
-// passes of 8 bits.  A pass builds, per component and per wanted rank, the
+// select on the order-preserving 32-bit keys of the FP32 values: three
+// passes, of 11, 11 and 10 bits (2,048-bin histograms in LDS; one pass, a
+// full read of the planes, fewer than with 8-bit digits).  A pass builds, per component and per wanted rank, the
 // histogram of the current digit over the keys that share the digits found
 // so far (ranks whose found digits coincide share one histogram); a small
 // kernel then picks the digit that holds the rank and the rank left within
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void k_plane_minmax(const float* __restrict
 }
 
 // sel[j][t] = {bits found so far, rank still wanted}; both histogram
-// buffers (2 x nc x kSelTargets x 256) cleared.
+// buffers (2 x nc x kSelTargets x kSelBins) cleared.
 __global__ __launch_bounds__(kBlock) void k_select_init(int nc, uint32_t r0, uint32_t r1, uint32_t r2, uint32_t r3,
                                                         uint2* __restrict__ sel, uint32_t* __restrict__ hist) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -108,15 +109,15 @@ __global__ __launch_bounds__(kBlock) void k_select_init(int nc, uint32_t r0, uin
     const int t = i % kSelTargets;
     sel[i] = make_uint2(0u, t == 0 ? r0 : t == 1 ? r1 : t == 2 ? r2 : r3);
   }
-  const int nh = 2 * nc * kSelTargets * 256;
+  const int nh = 2 * nc * kSelTargets * kSelBins;
   for (int e = i; e < nh; e += gridDim.x * kBlock) hist[e] = 0u;
 }
 
 // The target whose histogram target t uses in this pass: the first one whose
-// found bits (the top 8 pass bits) equal t's.
+// found bits (all above this pass's digit) equal t's.
 __device__ __forceinline__ int rep_of(const uint32_t (&pre)[kSelTargets], int t, int pass) {
   if (pass == 0) return 0;
-  const int sh = 32 - 8 * pass;
+  const int sh = sel_shift(pass) + sel_width(pass);
   for (int u = 0; u < t; ++u)
     if ((pre[u] >> sh) == (pre[t] >> sh)) return u;
   return t;
@@ -124,20 +125,20 @@ __device__ __forceinline__ int rep_of(const uint32_t (&pre)[kSelTargets], int t,
 
 __device__ __forceinline__ void count_key(uint32_t* __restrict__ h, uint32_t key, int pass,
                                           const uint32_t (&pre)[kSelTargets], const bool (&own)[kSelTargets]) {
-  const int shift = 24 - 8 * pass;
-  const uint32_t digit = (key >> shift) & 255u;
+  const int shift = sel_shift(pass);
+  const uint32_t digit = (key >> shift) & ((1u << sel_width(pass)) - 1u);
   const uint32_t d0 = __builtin_amdgcn_readfirstlane(digit);
   const bool uniform = __all(digit == d0);
 #pragma unroll
   for (int t = 0; t < kSelTargets; ++t) {
     if (!own[t]) continue;
-    const bool m = pass == 0 || ((key ^ pre[t]) >> (shift + 8)) == 0u;
+    const bool m = pass == 0 || ((key ^ pre[t]) >> (shift + sel_width(pass))) == 0u;
     if (uniform) {
       // the whole wave has one digit (typical of the leading digit): one add
       const unsigned cnt = (unsigned)__popcll((unsigned long long)__ballot(m));
-      if (cnt && first_active()) atomicAdd(&h[t * 256 + d0], cnt);
+      if (cnt && first_active()) atomicAdd(&h[t * kSelBins + d0], cnt);
     } else if (m) {
-      atomicAdd(&h[t * 256 + digit], 1u);
+      atomicAdd(&h[t * kSelBins + digit], 1u);
     }
   }
 }
@@ -146,9 +147,9 @@ __device__ __forceinline__ void count_key(uint32_t* __restrict__ h, uint32_t key
 __global__ __launch_bounds__(kBlock) void k_select_hist(const float* __restrict__ y, int64_t P,
                                                         const uint2* __restrict__ sel, int pass,
                                                         uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[kSelTargets * 256];
+  __shared__ uint32_t h[kSelTargets * kSelBins];
   const int j = blockIdx.y;
-  for (int i = threadIdx.x; i < kSelTargets * 256; i += kBlock) h[i] = 0u;
+  for (int i = threadIdx.x; i < kSelTargets * kSelBins; i += kBlock) h[i] = 0u;
   uint32_t pre[kSelTargets];
   bool own[kSelTargets];
 #pragma unroll
@@ -172,17 +173,19 @@ __global__ __launch_bounds__(kBlock) void k_select_hist(const float* __restrict_
       count_key(h, f2ord(yj[i]), pass, pre, own);
   }
   __syncthreads();
-  uint32_t* out = hist + (int64_t)j * kSelTargets * 256;
-  for (int i = threadIdx.x; i < kSelTargets * 256; i += kBlock)
+  uint32_t* out = hist + (int64_t)j * kSelTargets * kSelBins;
+  for (int i = threadIdx.x; i < kSelTargets * kSelBins; i += kBlock)
     if (h[i]) atomicAdd(&out[i], h[i]);
 }
 
 // Block j (one per plane), wave t (one per target): find the digit of the
 // histogram `cur` that holds target t's rank, record it, and clear target
-// t's row of `nxt` (the buffer the next pass fills).
+// t's row of `nxt` (the buffer the next pass fills).  Lane l holds bins
+// 32 l .. 32 l + 31.
 __global__ __launch_bounds__(kBlock) void k_select_pick(int pass, uint2* __restrict__ sel,
                                                         const uint32_t* __restrict__ cur,
                                                         uint32_t* __restrict__ nxt) {
+  constexpr int kPerLane = kSelBins / 64;
   const int j = blockIdx.x, t = threadIdx.x >> 6, lane = threadIdx.x & 63;
   uint32_t pre[kSelTargets];
 #pragma unroll
@@ -190,8 +193,19 @@ __global__ __launch_bounds__(kBlock) void k_select_pick(int pass, uint2* __restr
   const uint32_t want = sel[j * kSelTargets + t].y;
   __syncthreads();   // every wave has read sel before any wave updates it
   const int r = rep_of(pre, t, pass);
-  const uint4 c = *reinterpret_cast<const uint4*>(cur + ((int64_t)j * kSelTargets + r) * 256 + 4 * lane);
-  const uint32_t mine = c.x + c.y + c.z + c.w;
+  const uint4* row = reinterpret_cast<const uint4*>(cur + ((int64_t)j * kSelTargets + r) * kSelBins + kPerLane * lane);
+  uint32_t bins[kPerLane];
+#pragma unroll
+  for (int q = 0; q < kPerLane / 4; ++q) {
+    const uint4 c = row[q];
+    bins[4 * q] = c.x;
+    bins[4 * q + 1] = c.y;
+    bins[4 * q + 2] = c.z;
+    bins[4 * q + 3] = c.w;
+  }
+  uint32_t mine = 0;
+#pragma unroll
+  for (int e = 0; e < kPerLane; ++e) mine += bins[e];
   uint32_t incl = mine;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -202,19 +216,19 @@ __global__ __launch_bounds__(kBlock) void k_select_pick(int pass, uint2* __restr
   const int L = hit ? __ffsll(hit) - 1 : 63;
   if (lane == L) {
     uint32_t below = incl - mine;
-    const uint32_t bins[4] = {c.x, c.y, c.z, c.w};
-    int d = 4 * lane + 3;
-    for (int e = 0; e < 4; ++e) {
+    int d = kPerLane * lane + kPerLane - 1;
+    for (int e = 0; e < kPerLane; ++e) {
       if (below + bins[e] > want) {
-        d = 4 * lane + e;
+        d = kPerLane * lane + e;
         break;
       }
       below += bins[e];
     }
-    const int shift = 24 - 8 * pass;
-    sel[j * kSelTargets + t] = make_uint2(pre[t] | ((uint32_t)d << shift), want - below);
+    sel[j * kSelTargets + t] = make_uint2(pre[t] | ((uint32_t)d << sel_shift(pass)), want - below);
   }
-  *reinterpret_cast<uint4*>(nxt + ((int64_t)j * kSelTargets + t) * 256 + 4 * lane) = make_uint4(0u, 0u, 0u, 0u);
+  uint4* z = reinterpret_cast<uint4*>(nxt + ((int64_t)j * kSelTargets + t) * kSelBins + kPerLane * lane);
+#pragma unroll
+  for (int q = 0; q < kPerLane / 4; ++q) z[q] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // NumPy's linear interpolation between neighbouring order statistics, in
@@ -351,11 +365,11 @@ hipError_t launch_plane_minmax(const float* y, int64_t P, int nc, const int64_t*
 hipError_t launch_select(const float* y, int64_t P, int nc, const uint32_t (&ranks)[kSelTargets], int nb,
                          uint2* sel, uint32_t* hist, hipStream_t s) {
   if (nc < 1 || nc > kMaxB || nb < 1) return hipErrorInvalidValue;
-  const int nh = 2 * nc * kSelTargets * 256;
+  const int nh = 2 * nc * kSelTargets * kSelBins;
   hipLaunchKernelGGL(k_select_init, dim3((nh + kBlock - 1) / kBlock), dim3(kBlock), 0, s, nc, ranks[0], ranks[1],
                      ranks[2], ranks[3], sel, hist);
-  const int64_t half = (int64_t)nc * kSelTargets * 256;
-  for (int pass = 0; pass < 4; ++pass) {
+  const int64_t half = (int64_t)nc * kSelTargets * kSelBins;
+  for (int pass = 0; pass < kSelPasses; ++pass) {
     uint32_t* cur = hist + (pass & 1) * half;
     uint32_t* nxt = hist + ((pass + 1) & 1) * half;
     hipLaunchKernelGGL(k_select_hist, dim3(nb, nc), dim3(kBlock), 0, s, y, P, (const uint2*)sel, pass, cur);

@@ -98,6 +98,11 @@ hipError_t launch_project_float_u16(const void* cube, int B, int64_t P, int nc, 
 
 // rescaling from FP32 component planes y (nc planes of P floats, nc <= 64)
 constexpr int kSelTargets = 4;   // order statistics wanted per plane by one select
+constexpr int kSelPasses = 3;    // radix passes of 11, 11 and 10 bits over the 32-bit keys
+constexpr int kSelBins = 2048;   // histogram bins per pass (the widest digit)
+// low bit and width of the digit of pass p
+__host__ __device__ constexpr int sel_shift(int p) { return p == 0 ? 21 : p == 1 ? 10 : 0; }
+__host__ __device__ constexpr int sel_width(int p) { return p == 2 ? 10 : 11; }
 // blocks per plane for the reductions over m values of each of nc planes
 int stretch_reduce_blocks(int64_t m, int nc, int num_cu);
 // part[(j * nb + blk) * 2 + {0, 1}]: block partial min/max of plane j over
@@ -107,7 +112,7 @@ hipError_t launch_plane_minmax(const float* y, int64_t P, int nc, const int64_t*
                                float* part, int32_t* err, hipStream_t s);
 // exact order statistics of ranks[t] (0-based) in every plane: sel
 // (nc x kSelTargets) ends with their order-preserving keys; hist holds
-// 2 x nc x kSelTargets x 256 counters
+// 2 x nc x kSelTargets x kSelBins counters
 hipError_t launch_select(const float* y, int64_t P, int nc, const uint32_t (&ranks)[kSelTargets], int nb,
                          uint2* sel, uint32_t* hist, hipStream_t s);
 // range ab[2 j + {0, 1}] = (a_j, b_j): mode 1 / 2 fold the nb partials per
