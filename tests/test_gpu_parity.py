@@ -185,6 +185,27 @@ def test_pca_mask(dev):
     check_vectors(V, pr["V"], pr["all_eigvals"][:4])
 
 
+@pytest.mark.parametrize("H,W,B,masked", [
+    (61, 67, 33, False), (29, 31, 64, False), (17, 19, 5, False), (40, 40, 16, True), (45, 47, 47, True)])
+def test_pca_u16_full_range(dev, H, W, B, masked):
+    """uint16 values over the whole 16-bit range (two populations, near 0
+    and near 65535, so both bytes of a value take every size).  The page
+    covariance of a uint16 page is built from exact integer sums, so it
+    matches the FP64 oracle to rounding."""
+    say(f"pca full 16-bit range H={H} W={W} B={B} masked={masked}")
+    import paper_1612_06457_amd as cx
+    rng = np.random.default_rng(H * 100 + B)
+    hi = rng.random(H * W) < 0.4
+    mu = np.where(hi[:, None], rng.uniform(60000, 65000, B), rng.uniform(50, 3000, B))
+    cube = np.clip(np.rint(mu + rng.normal(0, 900, (H * W, B))), 0, 65535).astype(np.uint16).reshape(H, W, B)
+    mask = (rng.random((H, W)) < 0.6).astype(np.uint8) if masked else None
+    pr = oracle.pca_fit(cube, mask=mask, n_comp=2)
+    V, lam, mean, cov = cx.pca_fit(_t(cube, dev), mask=None if mask is None else _t(mask, dev), n_comp=2)
+    assert rel_max(cov, pr["cov"]) <= 1e-11
+    assert rel_max(mean, pr["mean"]) <= 1e-12
+    check_vectors(V, pr["V"], pr["all_eigvals"][:2])
+
+
 def test_many_components_and_groups(dev):
     say("projection with 11 components (two groups)")
     rng = np.random.default_rng(3)
