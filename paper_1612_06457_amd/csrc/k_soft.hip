@@ -162,14 +162,28 @@ __device__ __forceinline__ f32x4 mma_f32(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Three waves per SIMD where the registers allow it without spilling (up to
-// 48 padded bands with the small prefetch: 153 VGPRs); measured 16 % faster
-// than two at 33 bands and 8 classes.
-template <int NRB, int QX>
-constexpr int scatter_waves() { return (NRB <= 2 || (NRB == 3 && QX == 5)) ? 3 : 1; }
+// Tail columns.  When B + 1 = 16 NRB + T with T = 1 or 2, the matrix cores
+// take the 16 NRB leading columns and the vector ALU the T trailing ones:
+// the ones column (T = 1), or the last band and the ones column (T = 2).
+// Each lane then also accumulates, for its band j and pixel row,
+// sum w d_j (the ones column), for T = 2 sum w d_t d_j with t = B - 1, and
+// the corner sums sum w, sum w d_t, sum w d_t^2.  At 33 bands this halves
+// the matrix instructions (three tile pairs instead of six per 4 rows) for
+// a few vector ones.  The tail sums fold into FP64 after every chunk like the
+// tiles, and the four row groups of a wave combine at the end in a fixed
+// order.  T = 0: the ones column is a column of the last row block.
+//
+// Three waves per SIMD where the registers allow it without spilling (at
+// most 168 VGPRs; measured 16 % faster than two at 33 bands and 8 classes
+// before the tail columns), else two or one.
+template <int NRB, int QX, int T>
+constexpr int scatter_waves() {
+  return (NRB <= 1 || (NRB == 2 && (QX == 5 || T < 2)) || (NRB == 3 && QX == 5 && T == 0)) ? 3
+         : (NRB == 2 ? 2 : 1);
+}
 
-template <int NRB, int QX, int QW>
-__global__ __launch_bounds__(kBlock, (scatter_waves<NRB, QX>())) void k_soft_scatter_mfma(const float* __restrict__ X,
+template <int NRB, int QX, int QW, int T>
+__global__ __launch_bounds__(kBlock, (scatter_waves<NRB, QX, T>())) void k_soft_scatter_mfma(const float* __restrict__ X,
                                                               const float* __restrict__ W, int64_t N, int B, int K,
                                                               const float* __restrict__ mc_f,
                                                               double* __restrict__ part) {
@@ -192,6 +206,7 @@ __global__ __launch_bounds__(kBlock, (scatter_waves<NRB, QX>())) void k_soft_sca
     mrb[rb] = (live && band < B) ? mc_f[c * B + band] : 0.f;
     onev[rb] = band == B ? 1.f : 0.f;
   }
+  const float mt = (T == 2 && live) ? mc_f[c * B + B - 1] : 0.f;
   constexpr int NP = npairs(NRB);
   f32x4 acc[NP];
   double accd[NP][4];
@@ -202,6 +217,14 @@ __global__ __launch_bounds__(kBlock, (scatter_waves<NRB, QX>())) void k_soft_sca
       acc[p][e] = 0.f;
       accd[p][e] = 0.0;
     }
+  // tail sums: ts = sum w d_j, te = sum w d_t d_j, and the corner tw, tst, ttt
+  float ts[NRB], te[NRB], tw = 0.f, tst = 0.f, ttt = 0.f;
+  double tsd[NRB], ted[NRB], twd = 0.0, tstd = 0.0, tttd = 0.0;
+#pragma unroll
+  for (int rb = 0; rb < NRB; ++rb) {
+    ts[rb] = te[rb] = 0.f;
+    tsd[rb] = ted[rb] = 0.0;
+  }
   const float* xf = reinterpret_cast<const float*>(xr);
   const float* wf = reinterpret_cast<const float*>(wr);
   auto body = [&](int64_t, int) {
@@ -213,8 +236,22 @@ __global__ __launch_bounds__(kBlock, (scatter_waves<NRB, QX>())) void k_soft_sca
       float a[NRB], d[NRB];
 #pragma unroll
       for (int rb = 0; rb < NRB; ++rb) {
-        d[rb] = real[rb] ? xf[r * B + bcol[rb]] - mrb[rb] : onev[rb];
+        if constexpr (T > 0) d[rb] = xf[r * B + 16 * rb + col] - mrb[rb];   // every band is real
+        else d[rb] = real[rb] ? xf[r * B + bcol[rb]] - mrb[rb] : onev[rb];
         a[rb] = wv * d[rb];
+      }
+      if constexpr (T > 0) {
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb) ts[rb] += a[rb];
+        tw += wv;
+        if constexpr (T == 2) {
+          const float dt = xf[r * B + B - 1] - mt;
+          const float at = wv * dt;
+#pragma unroll
+          for (int rb = 0; rb < NRB; ++rb) te[rb] = fmaf(at, d[rb], te[rb]);
+          tst += at;
+          ttt = fmaf(at, dt, ttt);
+        }
       }
       int p = 0;
 #pragma unroll
@@ -223,11 +260,27 @@ __global__ __launch_bounds__(kBlock, (scatter_waves<NRB, QX>())) void k_soft_sca
         for (int rj = ri; rj < NRB; ++rj, ++p) acc[p] = mma_f32(a[ri], d[rj], acc[p]);
     }
     fold<NRB>(acc, accd);
+    if constexpr (T > 0) {
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb) {
+        tsd[rb] += (double)ts[rb];
+        ted[rb] += (double)te[rb];
+        ts[rb] = te[rb] = 0.f;
+      }
+      twd += (double)tw;
+      tstd += (double)tst;
+      tttd += (double)ttt;
+      tw = tst = ttt = 0.f;
+    }
   };
   for_each_chunk<QX, QW>(X, W, N, B, K, g, G, xr, wr, body);
   if (!live) return;
   const int BP = (B + 1 + 3) & ~3, nb = BP / 4, L = nb * (nb + 1) / 2 * 16;
   double* out = part + ((int64_t)c * G + g) * L;
+  auto pos = [&](int I, int J) {   // packed index of (I, J), tile row <= tile column
+    const int bi = I >> 2, bj = J >> 2;
+    return (bi * nb - bi * (bi - 1) / 2 + (bj - bi)) * 16 + (I & 3) * 4 + (J & 3);
+  };
   int p = 0;
 #pragma unroll
   for (int ri = 0; ri < NRB; ++ri) {
@@ -237,12 +290,48 @@ __global__ __launch_bounds__(kBlock, (scatter_waves<NRB, QX>())) void k_soft_sca
       for (int e = 0; e < 4; ++e) {
         const int I = 16 * ri + 4 * grp + e, J = 16 * rj + col;
         // every packed entry (4 x 4 tiles bi <= bj of the padded matrix) once
-        if ((I >> 2) <= (J >> 2) && I < BP && J < BP) {
-          const int bi = I >> 2, bj = J >> 2;
-          const int tix = bi * nb - bi * (bi - 1) / 2 + (bj - bi);
-          out[tix * 16 + (I & 3) * 4 + (J & 3)] = accd[p][e];
-        }
+        if ((I >> 2) <= (J >> 2) && I < BP && J < BP) out[pos(I, J)] = accd[p][e];
       }
+    }
+  }
+  if constexpr (T > 0) {
+    // the four row groups in a fixed order, then the last tile column
+    // (columns 16 NRB .. 16 NRB + 3) and its diagonal tile
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) {
+      tsd[rb] += __shfl_xor(tsd[rb], 16);
+      tsd[rb] += __shfl_xor(tsd[rb], 32);
+      ted[rb] += __shfl_xor(ted[rb], 16);
+      ted[rb] += __shfl_xor(ted[rb], 32);
+    }
+    twd += __shfl_xor(twd, 16);
+    twd += __shfl_xor(twd, 32);
+    tstd += __shfl_xor(tstd, 16);
+    tstd += __shfl_xor(tstd, 32);
+    tttd += __shfl_xor(tttd, 16);
+    tttd += __shfl_xor(tttd, 32);
+    const int jt = 16 * NRB;
+    if (grp == 0) {
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb) {
+        const int j = 16 * rb + col;
+        out[pos(j, jt)] = T == 2 ? ted[rb] : tsd[rb];
+        out[pos(j, jt + 1)] = T == 2 ? tsd[rb] : 0.0;
+        out[pos(j, jt + 2)] = 0.0;
+        out[pos(j, jt + 3)] = 0.0;
+      }
+    }
+    if (lane < 16) {
+      const int I = jt + (lane >> 2), J = jt + (lane & 3);
+      double v = 0.0;
+      if (T == 2) {
+        if (I == jt && J == jt) v = tttd;
+        else if (I + J == 2 * jt + 1) v = tstd;
+        else if (I == jt + 1 && J == jt + 1) v = twd;
+      } else if (I == jt && J == jt) {
+        v = twd;
+      }
+      out[pos(I, J)] = v;
     }
   }
 }
@@ -298,16 +387,16 @@ size_t first_smem(int B, int K) {
 
 size_t scatter_smem(int B, int K) { return (size_t)kChunk * (B + K) * sizeof(float); }
 
-template <int NRB>
+template <int NRB, int T>
 hipError_t scatter_nrb(const float* X, const float* w, int64_t N, int B, int K, int G, const float* mc_f,
                        double* part, hipStream_t s) {
   const dim3 grid(G, (K + kWaves - 1) / kWaves);
   if (B <= 40 && K <= 8)
-    hipLaunchKernelGGL((k_soft_scatter_mfma<NRB, 5, 1>), grid, dim3(kBlock), scatter_smem(B, K), s, X, w, N, B, K,
-                       mc_f, part);
+    hipLaunchKernelGGL((k_soft_scatter_mfma<NRB, 5, 1, T>), grid, dim3(kBlock), scatter_smem(B, K), s, X, w, N,
+                       B, K, mc_f, part);
   else
-    hipLaunchKernelGGL((k_soft_scatter_mfma<NRB, 8, 4>), grid, dim3(kBlock), scatter_smem(B, K), s, X, w, N, B, K,
-                       mc_f, part);
+    hipLaunchKernelGGL((k_soft_scatter_mfma<NRB, 8, 4, T>), grid, dim3(kBlock), scatter_smem(B, K), s, X, w, N,
+                       B, K, mc_f, part);
   return hipGetLastError();
 }
 
@@ -328,10 +417,21 @@ hipError_t launch_soft_means(int B, int K, const double* fp, double* first, floa
 hipError_t launch_soft_scatter(const float* X, const float* w, int64_t N, int B, int K, int G,
                                const float* mc_f, double* part, hipStream_t s) {
   if (B < 1 || B > kMaxB || K < 1 || K > 32 || G < 1) return hipErrorInvalidValue;
+  // B + 1 = 16 m + 1 or 16 m + 2: m row blocks on the matrix cores and the
+  // tail columns on the vector ALU
+  switch (B) {
+    case 16: return scatter_nrb<1, 1>(X, w, N, B, K, G, mc_f, part, s);
+    case 17: return scatter_nrb<1, 2>(X, w, N, B, K, G, mc_f, part, s);
+    case 32: return scatter_nrb<2, 1>(X, w, N, B, K, G, mc_f, part, s);
+    case 33: return scatter_nrb<2, 2>(X, w, N, B, K, G, mc_f, part, s);
+    case 48: return scatter_nrb<3, 1>(X, w, N, B, K, G, mc_f, part, s);
+    case 49: return scatter_nrb<3, 2>(X, w, N, B, K, G, mc_f, part, s);
+    case 64: return scatter_nrb<4, 1>(X, w, N, B, K, G, mc_f, part, s);
+  }
   switch (nrb_for(B)) {
-    case 2: return scatter_nrb<2>(X, w, N, B, K, G, mc_f, part, s);
-    case 3: return scatter_nrb<3>(X, w, N, B, K, G, mc_f, part, s);
-    default: return scatter_nrb<5>(X, w, N, B, K, G, mc_f, part, s);
+    case 2: return scatter_nrb<2, 0>(X, w, N, B, K, G, mc_f, part, s);
+    case 3: return scatter_nrb<3, 0>(X, w, N, B, K, G, mc_f, part, s);
+    default: return scatter_nrb<5, 0>(X, w, N, B, K, G, mc_f, part, s);
   }
 }
 
