@@ -75,62 +75,102 @@ __device__ __forceinline__ void for_each_chunk(const float* __restrict__ X, cons
   }
 }
 
-__global__ __launch_bounds__(kBlock, 3) void k_soft_first(const float* __restrict__ X, const float* __restrict__ W,
+__device__ __forceinline__ f32x4 mma_f32(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Pass 1 on the FP32 matrix instruction (v_mfma_f32_16x16x4_f32, FP32
+// operands and products, as on the vector ALU): per 4 rows,
+// C[c][j] += sum_r w[r][c] [x_r, 1][j] with A = w (lane: class 16 cb + l % 16,
+// row l / 16) and B = [X, 1] (lane: column 16 rb + l % 16, same row).  Wave
+// v takes rows 32 v .. 32 v + 31 of each chunk; its FP32 tiles fold into
+// FP64 after every chunk, and the waves of a block combine in a fixed order
+// into the block partial [c][j], c < KP, j < BP.  Rows past N have zero
+// weights (the partial chunk is zero-filled), so they add nothing.
+template <int NCB, int NRB, int QX, int QW>
+__global__ __launch_bounds__(kBlock) void k_soft_first(const float* __restrict__ X, const float* __restrict__ W,
                                                        int64_t N, int B, int K, double* __restrict__ part) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+  extern __shared__ __align__(16) uint32_t lds[];
+  uint32_t* xr = lds;                 // kChunk x B raw rows of X
+  uint32_t* wr = lds + kChunk * B;    // kChunk x K raw rows of w
+  double* red = reinterpret_cast<double*>(lds);
+  const int v = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, grp = lane >> 4;
   const int BP = (B + 1 + 3) & ~3, KP = (K + 3) & ~3;
-  float* xs = reinterpret_cast<float*>(smem_raw);                 // kChunk x BP: [x, 1]
-  float* ws = xs + kChunk * BP;                                    // kChunk x KP
-  uint32_t* xr = reinterpret_cast<uint32_t*>(ws + kChunk * KP);    // raw rows of X
-  uint32_t* wr = xr + kChunk * B;                                  // raw rows of w
-  double* red = reinterpret_cast<double*>(smem_raw);
-  const int nbi = KP / 4, nbj = BP / 4, nblk = nbi * nbj;
-  const int nslice = kBlock / nblk;
-  const int blk = threadIdx.x % nblk, slice = threadIdx.x / nblk;
-  const bool active = slice < nslice;
-  const int bi = blk / nbj, bj = blk % nbj;
-  float acc[16];
-  double accd[16];
+  int bcol[NRB], kcol[NCB];
+  bool real[NRB], kreal[NCB];
+  float onev[NRB];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    acc[e] = 0.f;
-    accd[e] = 0.0;
+  for (int rb = 0; rb < NRB; ++rb) {
+    const int band = 16 * rb + col;
+    real[rb] = band < B;
+    bcol[rb] = band < B ? band : 0;
+    onev[rb] = band == B ? 1.f : 0.f;
   }
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) {
+    const int cl = 16 * cb + col;
+    kreal[cb] = cl < K;
+    kcol[cb] = cl < K ? cl : 0;
+  }
+  f32x4 acc[NCB][NRB];
+  double accd[NCB][NRB][4];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        acc[cb][rb][e] = 0.f;
+        accd[cb][rb][e] = 0.0;
+      }
   const float* xf = reinterpret_cast<const float*>(xr);
   const float* wf = reinterpret_cast<const float*>(wr);
-  auto body = [&](int64_t, int rows) {
-    for (int e = threadIdx.x; e < kChunk * BP; e += kBlock) {
-      const int r = e / BP, b = e - r * BP;
-      xs[e] = r < rows ? (b < B ? xf[r * B + b] : (b == B ? 1.f : 0.f)) : 0.f;
+  auto body = [&](int64_t, int) {
+#pragma unroll
+    for (int s = 0; s < kChunk / (4 * kWaves); ++s) {
+      const int r = (kChunk / kWaves) * v + 4 * s + grp;
+      float a[NCB], x[NRB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) a[cb] = kreal[cb] ? wf[r * K + kcol[cb]] : 0.f;
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb) x[rb] = real[rb] ? xf[r * B + bcol[rb]] : onev[rb];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb) acc[cb][rb] = mma_f32(a[cb], x[rb], acc[cb][rb]);
     }
-    for (int e = threadIdx.x; e < kChunk * KP; e += kBlock) {
-      const int r = e / KP, c = e - r * KP;
-      ws[e] = (r < rows && c < K) ? wf[r * K + c] : 0.f;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          accd[cb][rb][e] += (double)acc[cb][rb][e];
+          acc[cb][rb][e] = 0.f;
+        }
+  };
+  for_each_chunk<QX, QW>(X, W, N, B, K, blockIdx.x, gridDim.x, xr, wr, body);
+  // waves in a fixed order into the block partial [c][j]
+  const int L = KP * BP;
+  for (int t = threadIdx.x; t < L; t += kBlock) red[t] = 0.0;
+  __syncthreads();
+  for (int ww = 0; ww < kWaves; ++ww) {
+    if (v == ww) {
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int c = 16 * cb + 4 * grp + e, j = 16 * rb + col;
+            if (c < KP && j < BP) red[c * BP + j] += accd[cb][rb][e];
+          }
     }
     __syncthreads();
-    if (active) tile_acc(ws, KP, xs, BP, bi, bj, slice, kChunk, nslice, acc);
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      accd[e] += (double)acc[e];
-      acc[e] = 0.f;
-    }
-  };
-  if (B <= 40 && K <= 8) for_each_chunk<5, 1>(X, W, N, B, K, blockIdx.x, gridDim.x, xr, wr, body);
-  else for_each_chunk<8, 4>(X, W, N, B, K, blockIdx.x, gridDim.x, xr, wr, body);
-  // slice reduction -> block partial laid out as [c][e] for c < KP, e < BP
-  __syncthreads();
-  if (active)
-    for (int e = 0; e < 16; ++e) red[(slice * nblk + blk) * 16 + e] = accd[e];
-  __syncthreads();
-  const int L = KP * BP;
-  double* mine = part + (int64_t)blockIdx.x * L;
-  for (int t = threadIdx.x; t < nblk * 16; t += kBlock) {
-    double s = 0.0;
-    for (int sl = 0; sl < nslice; ++sl) s += red[sl * nblk * 16 + t];
-    const int bk = t / 16, e = t % 16;
-    const int c = 4 * (bk / nbj) + e / 4, col = 4 * (bk % nbj) + e % 4;
-    mine[c * BP + col] = s;
   }
+  double* mine = part + (int64_t)blockIdx.x * L;
+  for (int t = threadIdx.x; t < L; t += kBlock) mine[t] = red[t];
 }
 
 // One block: from the reduced first moments (KP x BP, packed by class), the
@@ -158,9 +198,6 @@ __global__ __launch_bounds__(kBlock) void k_soft_means(int B, int K, const doubl
 // 4 (l / 16) + e, column l % 16).  Rows past N have zero weights (the partial
 // chunk is zero-filled), so they add nothing.  Each wave writes its class's
 // partial in the packed layout of the fixed-order reduction.
-__device__ __forceinline__ f32x4 mma_f32(float a, float b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
 
 // Tail columns.  When B + 1 = 16 NRB + T with T = 1 or 2, the matrix cores
 // take the 16 NRB leading columns and the vector ALU the T trailing ones:
@@ -375,13 +412,11 @@ __global__ __launch_bounds__(kBlock) void k_soft_backward(const float* __restric
   });
 }
 
-// LDS of the forward kernels: padded rows plus the raw chunk tiles, or the
-// slice-combine buffer, whichever is larger.
+// LDS of the forward kernels: the raw chunk tiles, or the first pass's
+// combine buffer, whichever is larger.
 size_t first_smem(int B, int K) {
-  const int BP = padded_bp(B), KP = (K + 3) & ~3;
-  const size_t a = (size_t)kChunk * (BP + KP + B + K) * sizeof(float);
-  const int nblk = (KP / 4) * (BP / 4);
-  const size_t r = (size_t)(kBlock / nblk) * nblk * 16 * sizeof(double);
+  const size_t a = (size_t)kChunk * (B + K) * sizeof(float);
+  const size_t r = (size_t)((K + 3) & ~3) * ((B + 1 + 3) & ~3) * sizeof(double);
   return a > r ? a : r;
 }
 
@@ -405,7 +440,19 @@ hipError_t scatter_nrb(const float* X, const float* w, int64_t N, int B, int K, 
 hipError_t launch_soft_first(const float* X, const float* w, int64_t N, int B, int K, int nblocks,
                              double* part, hipStream_t s) {
   if (B < 1 || B > kMaxB || K < 1 || K > 32 || nblocks < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_soft_first, dim3(nblocks), dim3(kBlock), first_smem(B, K), s, X, w, N, B, K, part);
+  const int nrb = nrb_for(B);
+  const bool small = B <= 40 && K <= 8;
+  const size_t sm = first_smem(B, K);
+  const dim3 grid(nblocks);
+#define CVX_F(NCB, NRB)                                                                                      \
+  if (small) hipLaunchKernelGGL((k_soft_first<NCB, NRB, 5, 1>), grid, dim3(kBlock), sm, s, X, w, N, B, K, part); \
+  else hipLaunchKernelGGL((k_soft_first<NCB, NRB, 8, 4>), grid, dim3(kBlock), sm, s, X, w, N, B, K, part);
+  if (K <= 16) {
+    if (nrb == 2) { CVX_F(1, 2) } else if (nrb == 3) { CVX_F(1, 3) } else { CVX_F(1, 5) }
+  } else {
+    if (nrb == 2) { CVX_F(2, 2) } else if (nrb == 3) { CVX_F(2, 3) } else { CVX_F(2, 5) }
+  }
+#undef CVX_F
   return hipGetLastError();
 }
 
