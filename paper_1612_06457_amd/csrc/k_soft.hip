@@ -3,7 +3,7 @@
 // the paper's CVA (Section 2, canonical variates paragraph).
 //
 // Forward, two passes over X:
-//   1. n_c = sum_p w_pc and t_c = sum_p w_pc x_p (register-tiled w^T [X, 1])
+//   1. n_c = sum_p w_pc and t_c = sum_p w_pc x_p (w^T [X, 1] on the FP32 matrix instruction)
 //      into block partials; the partials are combined by the fixed-order
 //      reduction, and a one-block kernel stores the class means
 //      m_c = t_c / n_c;
