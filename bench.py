@@ -416,8 +416,9 @@ def main():
         "config": {"workload": "cva_pca_page_7216x5412x33_u16_k8", "H": H, "W": W, "B": B, "K": K,
                    "train_pixels": int(N), "cva_components": C, "pca_components": 3,
                    "precision": args.precision,
-                   "arithmetic": "u16 page; exact split products on the matrix cores (fp16 in the projection, "
-                                 "bf16 in the scatter) with FP32 accumulation, FP64 combine and eigensolve"},
+                   "arithmetic": "u16 page; exact fp16 split products on the matrix cores (projection, class "
+                                 "scatter) with FP32 accumulation, exact int8 digit products (PCA covariance), "
+                                 "FP64 combine and eigensolve"},
         "phases_ms": {k: round(v, 4) for k, v in per.items()},
         "soft_fwd_bwd_ms": round(per["soft_fwd"] + per["soft_bwd"], 4),
         "kernels_ms_per_launch": {k: round(v[1] / max(v[0], 1), 4) for k, v in sorted(prof_all.items())},
