@@ -89,9 +89,10 @@ typedef struct {
  * Launch shapes can be set for measurement from the environment when the
  * context is made: CVAMX_PROJ_BLOCKS (blocks of the page-streaming
  * projection passes; default 8 per compute unit) and CVAMX_GRAM_BLOCKS
- * (blocks of the PCA Gram pass).  The images and ranges do not depend on
- * them; the PCA covariance may change in its last bits (another summation
- * order). */
+ * (blocks of the PCA Gram pass; default one resident round for uint16
+ * pages on the matrix cores, 4 per compute unit otherwise).  The images and
+ * ranges do not depend on them; the PCA covariance may change in its last
+ * bits (another summation order). */
 int cvamx_create(cvamx_ctx** out, int device);
 void cvamx_destroy(cvamx_ctx* ctx);
 const char* cvamx_status_str(int status);

@@ -926,7 +926,11 @@ int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t
   hipStream_t s = (hipStream_t)stream;
   const int64_t P = cube->height * cube->width;
   const int L = cvx::tri_blocks(B) * 16;
-  int nblocks = ctx->gram_blocks > 0 ? ctx->gram_blocks : ctx->num_cu * 4;
+  const bool vector_path = prec == CVAMX_PREC_FP32 && (ctx->plain || !split_is_exact(cube->dtype));
+  // uint16 pages on the matrix cores: one resident round of blocks (a
+  // partial second round cost 4 % at 33 bands); else four blocks per CU
+  const int per_cu = (!vector_path && cube->dtype == CVAMX_U16) ? cvx::pca_u16_blocks_per_cu(B) : 4;
+  int nblocks = ctx->gram_blocks > 0 ? ctx->gram_blocks : ctx->num_cu * per_cu;
   nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(nblocks, (P + cvx::kChunk - 1) / cvx::kChunk));
   const size_t res_bytes = 8 * (size_t)B + 8 * (size_t)L;
   if (int st = ensure(ctx, B_PART, (size_t)nblocks * L * 8)) return st;
@@ -934,7 +938,7 @@ int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t
   if (int st = ensure_pinned(ctx, res_bytes)) return st;
   char* res = static_cast<char*>(ctx->buf[B_RES]);
   hipError_t e;
-  if (prec == CVAMX_PREC_FP32 && (ctx->plain || !split_is_exact(cube->dtype))) {
+  if (vector_path) {
     prof_begin(ctx, s, "pca_gram");
     e = cvx::launch_pca_gram(cube->dtype, cube->data, B, P, mask, nblocks, (double*)ctx->buf[B_PART],
                              (double*)res, s);

@@ -379,6 +379,14 @@ hipError_t pca_launch(int dtype, const void* cube, int B, int64_t P, const uint8
 
 }  // namespace
 
+int pca_u16_blocks_per_cu(int B) {
+  switch (nrb_for(B)) {
+    case 2: return pca_u16_waves<2>();
+    case 3: return pca_u16_waves<3>();
+    default: return pca_u16_waves<5>();
+  }
+}
+
 hipError_t launch_pca_gram_mfma(int dtype, int split, const void* cube, int B, int64_t P, const uint8_t* mask,
                                 int nblocks, double* part, double* shift_out, hipStream_t s) {
   if (B < 1 || B > kMaxB || nblocks < 1) return hipErrorInvalidValue;

@@ -67,6 +67,9 @@ hipError_t launch_class_moments_mfma(int dtype, int split, const void* cube, int
 hipError_t launch_pca_gram_mfma(int dtype, int split, const void* cube, int B, int64_t P,
                                 const uint8_t* mask, int nblocks, double* part,
                                 double* shift_out, hipStream_t s);
+// Blocks per CU that the uint16 page-covariance kernel keeps resident at
+// B bands (its waves per SIMD): the grid that fills the device in one round.
+int pca_u16_blocks_per_cu(int B);
 // out[s * L + t] = sum_g part[(s * G + g) * L + t]
 hipError_t launch_reduce_part(const double* part, int nsets, int G, int L, double* out,
                               hipStream_t s);
