@@ -446,6 +446,27 @@ def test_full_soft_1M_x23(dev):
         assert abs(g[p, k] - fd) <= 1e-4 * gmax
 
 
+@pytest.mark.timeout(900)
+def test_full_soft_page_1600k_x33(dev):
+    """The soft-label workload of the benchmark: the 1.6 M training pixels
+    of the 7216 x 5412 x 33 page (K = 8), Dirichlet(0.5) weights within two
+    pixels of a class border and one-hot weights inside, in the launch shape
+    the benchmark uses (33 bands: the last band and the ones column on the
+    vector ALU).  J, eigenvalues, vectors and the whole gradient."""
+    say("soft label, full page training pixels 1.6M x 33, K=8")
+    from synth import border_map, soft_weights
+    c = full_page()
+    flat = c.labels.reshape(-1)
+    idx = np.flatnonzero(flat >= 0)
+    cls = flat[idx].astype(np.int64)
+    rng = np.random.default_rng([c.seed, 0x50F7])
+    nb = border_map(c.class_map)[np.unravel_index(idx, c.labels.shape)]
+    w = soft_weights(cls, nb, c.K, rng)
+    X = c.cube.reshape(-1, c.B)[idx].astype(np.float32)
+    say(f"N={X.shape[0]}")
+    _soft_parity(X, w, dev)
+
+
 # ------------------------------------------------- compensated MFMA scatter
 
 def _abs_gram(cube_host, labels, K):
