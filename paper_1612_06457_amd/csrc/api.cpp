@@ -1003,9 +1003,11 @@ int cva_soft_forward(cvamx_ctx* ctx, const float* X, const float* w, int64_t N, 
   const int L = cvx::tri_blocks(B) * 16;
   const int64_t nch = (N + cvx::kChunk - 1) / cvx::kChunk;
   const int nb1 = (int)std::max<int64_t>(1, std::min<int64_t>(3 * ctx->num_cu, nch));
-  // pass 2: about three blocks per CU over all class groups of four
-  const int groups = (K + cvx::kWaves - 1) / cvx::kWaves;
-  const int G = (int)std::max<int64_t>(1, std::min<int64_t>(3 * ctx->num_cu / groups, nch));
+  // pass 2: one resident round of blocks over all class groups
+  const int cpb = cvx::soft_scatter_classes_per_block(B, K);
+  const int groups = (K + cpb - 1) / cpb;
+  const int G = (int)std::max<int64_t>(
+      1, std::min<int64_t>(cvx::soft_scatter_blocks_per_cu(B, K) * ctx->num_cu / groups, nch));
   const size_t first_bytes = 8 * (size_t)K * (B + 1);
   const size_t mcf_off = first_bytes;
   const size_t gram_off = (mcf_off + 4 * (size_t)K * B + 7) & ~size_t(7);

@@ -210,165 +210,200 @@ __global__ __launch_bounds__(kBlock) void k_soft_means(int B, int K, const doubl
 // tiles, and the four row groups of a wave combine at the end in a fixed
 // order.  T = 0: the ones column is a column of the last row block.
 //
-// Three waves per SIMD where the registers allow it without spilling (at
-// most 168 VGPRs; measured 16 % faster than two at 33 bands and 8 classes
-// before the tail columns), else two or one.
-template <int NRB, int QX, int T>
+// Classes per wave: CPW = 2 lets one pass over the chunk serve eight
+// classes (two per wave) where the registers allow it, so the training
+// pixels are read once for K <= 8 instead of once per group of four.
+//
+// Waves per SIMD: three where the registers allow it without spilling (at
+// most 168 VGPRs), else two or one.
+template <int NRB, int QX, int T, int CPW>
 constexpr int scatter_waves() {
+  if (CPW == 2) return 2;
   return (NRB <= 1 || (NRB == 2 && (QX == 5 || T < 2)) || (NRB == 3 && QX == 5 && T == 0)) ? 3
          : (NRB == 2 ? 2 : 1);
 }
 
-template <int NRB, int QX, int QW, int T>
-__global__ __launch_bounds__(kBlock, (scatter_waves<NRB, QX, T>())) void k_soft_scatter_mfma(const float* __restrict__ X,
-                                                              const float* __restrict__ W, int64_t N, int B, int K,
-                                                              const float* __restrict__ mc_f,
-                                                              double* __restrict__ part) {
+template <int NRB, int QX, int QW, int T, int CPW>
+__global__ __launch_bounds__(kBlock, (scatter_waves<NRB, QX, T, CPW>())) void k_soft_scatter_mfma(
+    const float* __restrict__ X, const float* __restrict__ W, int64_t N, int B, int K,
+    const float* __restrict__ mc_f, double* __restrict__ part) {
   extern __shared__ __align__(16) uint32_t lds[];
   uint32_t* xr = lds;                 // kChunk x B raw rows of X
   uint32_t* wr = lds + kChunk * B;    // kChunk x K raw rows of w
   const int G = gridDim.x, g = blockIdx.x;
   const int v = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, grp = lane >> 4;
-  const int c = blockIdx.y * kWaves + v;
-  const bool live = c < K;
+  // wave v takes classes c[u] = blockIdx.y kWaves CPW + kWaves u + v
+  int cls[CPW];
+  bool live[CPW];
+#pragma unroll
+  for (int u = 0; u < CPW; ++u) {
+    cls[u] = blockIdx.y * kWaves * CPW + kWaves * u + v;
+    live[u] = cls[u] < K;
+  }
   int bcol[NRB];
-  float mrb[NRB], onev[NRB];
+  float mrb[CPW][NRB], onev[NRB], mt[CPW];
   bool real[NRB];
 #pragma unroll
   for (int rb = 0; rb < NRB; ++rb) {
     const int band = 16 * rb + col;
     real[rb] = band < B;
     bcol[rb] = band < B ? band : 0;
-    mrb[rb] = (live && band < B) ? mc_f[c * B + band] : 0.f;
     onev[rb] = band == B ? 1.f : 0.f;
+#pragma unroll
+    for (int u = 0; u < CPW; ++u) mrb[u][rb] = (live[u] && band < B) ? mc_f[cls[u] * B + band] : 0.f;
   }
-  const float mt = (T == 2 && live) ? mc_f[c * B + B - 1] : 0.f;
+#pragma unroll
+  for (int u = 0; u < CPW; ++u) mt[u] = (T == 2 && live[u]) ? mc_f[cls[u] * B + B - 1] : 0.f;
   constexpr int NP = npairs(NRB);
-  f32x4 acc[NP];
-  double accd[NP][4];
-#pragma unroll
-  for (int p = 0; p < NP; ++p)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      acc[p][e] = 0.f;
-      accd[p][e] = 0.0;
-    }
+  f32x4 acc[CPW][NP];
+  double accd[CPW][NP][4];
   // tail sums: ts = sum w d_j, te = sum w d_t d_j, and the corner tw, tst, ttt
-  float ts[NRB], te[NRB], tw = 0.f, tst = 0.f, ttt = 0.f;
-  double tsd[NRB], ted[NRB], twd = 0.0, tstd = 0.0, tttd = 0.0;
+  float ts[CPW][NRB], te[CPW][NRB], tw[CPW], tst[CPW], ttt[CPW];
+  double tsd[CPW][NRB], ted[CPW][NRB], twd[CPW], tstd[CPW], tttd[CPW];
 #pragma unroll
-  for (int rb = 0; rb < NRB; ++rb) {
-    ts[rb] = te[rb] = 0.f;
-    tsd[rb] = ted[rb] = 0.0;
+  for (int u = 0; u < CPW; ++u) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        acc[u][p][e] = 0.f;
+        accd[u][p][e] = 0.0;
+      }
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) {
+      ts[u][rb] = te[u][rb] = 0.f;
+      tsd[u][rb] = ted[u][rb] = 0.0;
+    }
+    tw[u] = tst[u] = ttt[u] = 0.f;
+    twd[u] = tstd[u] = tttd[u] = 0.0;
   }
   const float* xf = reinterpret_cast<const float*>(xr);
   const float* wf = reinterpret_cast<const float*>(wr);
   auto body = [&](int64_t, int) {
-    if (!live) return;
-#pragma unroll 4
+    if (!live[0]) return;
+    constexpr int kUnroll = 4 / CPW;
+#pragma unroll kUnroll
     for (int k0 = 0; k0 < kChunk; k0 += 4) {
       const int r = k0 + grp;
-      const float wv = wf[r * K + c];
-      float a[NRB], d[NRB];
+      float xv[NRB];
 #pragma unroll
       for (int rb = 0; rb < NRB; ++rb) {
-        if constexpr (T > 0) d[rb] = xf[r * B + 16 * rb + col] - mrb[rb];   // every band is real
-        else d[rb] = real[rb] ? xf[r * B + bcol[rb]] - mrb[rb] : onev[rb];
-        a[rb] = wv * d[rb];
+        if constexpr (T > 0) xv[rb] = xf[r * B + 16 * rb + col];   // every band is real
+        else xv[rb] = real[rb] ? xf[r * B + bcol[rb]] : 0.f;
       }
+      const float xt = T == 2 ? xf[r * B + B - 1] : 0.f;
+#pragma unroll
+      for (int u = 0; u < CPW; ++u) {
+        if (u > 0 && !live[u]) break;
+        const float wv = wf[r * K + cls[u]];
+        float a[NRB], d[NRB];
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb) {
+          if constexpr (T > 0) d[rb] = xv[rb] - mrb[u][rb];
+          else d[rb] = real[rb] ? xv[rb] - mrb[u][rb] : onev[rb];
+          a[rb] = wv * d[rb];
+        }
+        if constexpr (T > 0) {
+#pragma unroll
+          for (int rb = 0; rb < NRB; ++rb) ts[u][rb] += a[rb];
+          tw[u] += wv;
+          if constexpr (T == 2) {
+            const float dt = xt - mt[u];
+            const float at = wv * dt;
+#pragma unroll
+            for (int rb = 0; rb < NRB; ++rb) te[u][rb] = fmaf(at, d[rb], te[u][rb]);
+            tst[u] += at;
+            ttt[u] = fmaf(at, dt, ttt[u]);
+          }
+        }
+        int p = 0;
+#pragma unroll
+        for (int ri = 0; ri < NRB; ++ri)
+#pragma unroll
+          for (int rj = ri; rj < NRB; ++rj, ++p) acc[u][p] = mma_f32(a[ri], d[rj], acc[u][p]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CPW; ++u) {
+      fold<NRB>(acc[u], accd[u]);
       if constexpr (T > 0) {
 #pragma unroll
-        for (int rb = 0; rb < NRB; ++rb) ts[rb] += a[rb];
-        tw += wv;
-        if constexpr (T == 2) {
-          const float dt = xf[r * B + B - 1] - mt;
-          const float at = wv * dt;
-#pragma unroll
-          for (int rb = 0; rb < NRB; ++rb) te[rb] = fmaf(at, d[rb], te[rb]);
-          tst += at;
-          ttt = fmaf(at, dt, ttt);
+        for (int rb = 0; rb < NRB; ++rb) {
+          tsd[u][rb] += (double)ts[u][rb];
+          ted[u][rb] += (double)te[u][rb];
+          ts[u][rb] = te[u][rb] = 0.f;
         }
+        twd[u] += (double)tw[u];
+        tstd[u] += (double)tst[u];
+        tttd[u] += (double)ttt[u];
+        tw[u] = tst[u] = ttt[u] = 0.f;
       }
-      int p = 0;
-#pragma unroll
-      for (int ri = 0; ri < NRB; ++ri)
-#pragma unroll
-        for (int rj = ri; rj < NRB; ++rj, ++p) acc[p] = mma_f32(a[ri], d[rj], acc[p]);
-    }
-    fold<NRB>(acc, accd);
-    if constexpr (T > 0) {
-#pragma unroll
-      for (int rb = 0; rb < NRB; ++rb) {
-        tsd[rb] += (double)ts[rb];
-        ted[rb] += (double)te[rb];
-        ts[rb] = te[rb] = 0.f;
-      }
-      twd += (double)tw;
-      tstd += (double)tst;
-      tttd += (double)ttt;
-      tw = tst = ttt = 0.f;
     }
   };
   for_each_chunk<QX, QW>(X, W, N, B, K, g, G, xr, wr, body);
-  if (!live) return;
   const int BP = (B + 1 + 3) & ~3, nb = BP / 4, L = nb * (nb + 1) / 2 * 16;
-  double* out = part + ((int64_t)c * G + g) * L;
   auto pos = [&](int I, int J) {   // packed index of (I, J), tile row <= tile column
     const int bi = I >> 2, bj = J >> 2;
     return (bi * nb - bi * (bi - 1) / 2 + (bj - bi)) * 16 + (I & 3) * 4 + (J & 3);
   };
-  int p = 0;
 #pragma unroll
-  for (int ri = 0; ri < NRB; ++ri) {
+  for (int u = 0; u < CPW; ++u) {
+    if (!live[u]) break;
+    double* out = part + ((int64_t)cls[u] * G + g) * L;
+    int p = 0;
 #pragma unroll
-    for (int rj = ri; rj < NRB; ++rj, ++p) {
+    for (int ri = 0; ri < NRB; ++ri) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int I = 16 * ri + 4 * grp + e, J = 16 * rj + col;
-        // every packed entry (4 x 4 tiles bi <= bj of the padded matrix) once
-        if ((I >> 2) <= (J >> 2) && I < BP && J < BP) out[pos(I, J)] = accd[p][e];
+      for (int rj = ri; rj < NRB; ++rj, ++p) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int I = 16 * ri + 4 * grp + e, J = 16 * rj + col;
+          // every packed entry (4 x 4 tiles bi <= bj of the padded matrix) once
+          if ((I >> 2) <= (J >> 2) && I < BP && J < BP) out[pos(I, J)] = accd[u][p][e];
+        }
       }
     }
-  }
-  if constexpr (T > 0) {
-    // the four row groups in a fixed order, then the last tile column
-    // (columns 16 NRB .. 16 NRB + 3) and its diagonal tile
-#pragma unroll
-    for (int rb = 0; rb < NRB; ++rb) {
-      tsd[rb] += __shfl_xor(tsd[rb], 16);
-      tsd[rb] += __shfl_xor(tsd[rb], 32);
-      ted[rb] += __shfl_xor(ted[rb], 16);
-      ted[rb] += __shfl_xor(ted[rb], 32);
-    }
-    twd += __shfl_xor(twd, 16);
-    twd += __shfl_xor(twd, 32);
-    tstd += __shfl_xor(tstd, 16);
-    tstd += __shfl_xor(tstd, 32);
-    tttd += __shfl_xor(tttd, 16);
-    tttd += __shfl_xor(tttd, 32);
-    const int jt = 16 * NRB;
-    if (grp == 0) {
+    if constexpr (T > 0) {
+      // the four row groups in a fixed order, then the last tile column
+      // (columns 16 NRB .. 16 NRB + 3) and its diagonal tile
+      double sd[NRB], ed[NRB];
 #pragma unroll
       for (int rb = 0; rb < NRB; ++rb) {
-        const int j = 16 * rb + col;
-        out[pos(j, jt)] = T == 2 ? ted[rb] : tsd[rb];
-        out[pos(j, jt + 1)] = T == 2 ? tsd[rb] : 0.0;
-        out[pos(j, jt + 2)] = 0.0;
-        out[pos(j, jt + 3)] = 0.0;
+        sd[rb] = tsd[u][rb] + __shfl_xor(tsd[u][rb], 16);
+        sd[rb] += __shfl_xor(sd[rb], 32);
+        ed[rb] = ted[u][rb] + __shfl_xor(ted[u][rb], 16);
+        ed[rb] += __shfl_xor(ed[rb], 32);
       }
-    }
-    if (lane < 16) {
-      const int I = jt + (lane >> 2), J = jt + (lane & 3);
-      double v = 0.0;
-      if (T == 2) {
-        if (I == jt && J == jt) v = tttd;
-        else if (I + J == 2 * jt + 1) v = tstd;
-        else if (I == jt + 1 && J == jt + 1) v = twd;
-      } else if (I == jt && J == jt) {
-        v = twd;
+      double sw = twd[u] + __shfl_xor(twd[u], 16);
+      sw += __shfl_xor(sw, 32);
+      double st = tstd[u] + __shfl_xor(tstd[u], 16);
+      st += __shfl_xor(st, 32);
+      double tt = tttd[u] + __shfl_xor(tttd[u], 16);
+      tt += __shfl_xor(tt, 32);
+      const int jt = 16 * NRB;
+      if (grp == 0) {
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb) {
+          const int j = 16 * rb + col;
+          out[pos(j, jt)] = T == 2 ? ed[rb] : sd[rb];
+          out[pos(j, jt + 1)] = T == 2 ? sd[rb] : 0.0;
+          out[pos(j, jt + 2)] = 0.0;
+          out[pos(j, jt + 3)] = 0.0;
+        }
       }
-      out[pos(I, J)] = v;
+      if (lane < 16) {
+        const int I = jt + (lane >> 2), J = jt + (lane & 3);
+        double val = 0.0;
+        if (T == 2) {
+          if (I == jt && J == jt) val = tt;
+          else if (I + J == 2 * jt + 1) val = st;
+          else if (I == jt + 1 && J == jt + 1) val = sw;
+        } else if (I == jt && J == jt) {
+          val = sw;
+        }
+        out[pos(I, J)] = val;
+      }
     }
   }
 }
@@ -422,17 +457,33 @@ size_t first_smem(int B, int K) {
 
 size_t scatter_smem(int B, int K) { return (size_t)kChunk * (B + K) * sizeof(float); }
 
+// Two classes per wave for the narrow instances (up to two row blocks on
+// the matrix cores) once there are more than four classes.
+int scatter_cpw(int B, int K) {
+  const bool narrow = nrb_for(B) == 2 || B == 16 || B == 17 || B == 32 || B == 33;
+  return (narrow && K > kWaves) ? 2 : 1;
+}
+
+template <int NRB, int T, int CPW>
+hipError_t scatter_launch(const float* X, const float* w, int64_t N, int B, int K, int G, const float* mc_f,
+                          double* part, hipStream_t s) {
+  const dim3 grid(G, (K + kWaves * CPW - 1) / (kWaves * CPW));
+  if (B <= 40 && K <= 8)
+    hipLaunchKernelGGL((k_soft_scatter_mfma<NRB, 5, 1, T, CPW>), grid, dim3(kBlock), scatter_smem(B, K), s, X,
+                       w, N, B, K, mc_f, part);
+  else
+    hipLaunchKernelGGL((k_soft_scatter_mfma<NRB, 8, 4, T, CPW>), grid, dim3(kBlock), scatter_smem(B, K), s, X,
+                       w, N, B, K, mc_f, part);
+  return hipGetLastError();
+}
+
 template <int NRB, int T>
 hipError_t scatter_nrb(const float* X, const float* w, int64_t N, int B, int K, int G, const float* mc_f,
                        double* part, hipStream_t s) {
-  const dim3 grid(G, (K + kWaves - 1) / kWaves);
-  if (B <= 40 && K <= 8)
-    hipLaunchKernelGGL((k_soft_scatter_mfma<NRB, 5, 1, T>), grid, dim3(kBlock), scatter_smem(B, K), s, X, w, N,
-                       B, K, mc_f, part);
-  else
-    hipLaunchKernelGGL((k_soft_scatter_mfma<NRB, 8, 4, T>), grid, dim3(kBlock), scatter_smem(B, K), s, X, w, N,
-                       B, K, mc_f, part);
-  return hipGetLastError();
+  if constexpr (NRB <= 2) {
+    if (scatter_cpw(B, K) == 2) return scatter_launch<NRB, T, 2>(X, w, N, B, K, G, mc_f, part, s);
+  }
+  return scatter_launch<NRB, T, 1>(X, w, N, B, K, G, mc_f, part, s);
 }
 
 }  // namespace
@@ -460,6 +511,10 @@ hipError_t launch_soft_means(int B, int K, const double* fp, double* first, floa
   hipLaunchKernelGGL(k_soft_means, dim3(1), dim3(kBlock), 0, s, B, K, fp, first, mc_f);
   return hipGetLastError();
 }
+
+int soft_scatter_classes_per_block(int B, int K) { return kWaves * scatter_cpw(B, K); }
+
+int soft_scatter_blocks_per_cu(int B, int K) { return scatter_cpw(B, K) == 2 ? 2 : 3; }
 
 hipError_t launch_soft_scatter(const float* X, const float* w, int64_t N, int B, int K, int G,
                                const float* mc_f, double* part, hipStream_t s) {

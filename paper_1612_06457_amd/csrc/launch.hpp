@@ -155,6 +155,9 @@ hipError_t launch_soft_first(const float* X, const float* w, int64_t N, int B, i
 // means in FP32
 hipError_t launch_soft_means(int B, int K, const double* fp, double* first, float* mc_f, hipStream_t s);
 // pass 2: per-class weighted Gram partials part[(c * G + g) * L + t]
+// classes one scatter block takes, and the blocks per CU it keeps resident
+int soft_scatter_classes_per_block(int B, int K);
+int soft_scatter_blocks_per_cu(int B, int K);
 hipError_t launch_soft_scatter(const float* X, const float* w, int64_t N, int B, int K, int G,
                                const float* mc_f, double* part, hipStream_t s);
 hipError_t launch_soft_backward(const float* X, int64_t N, int B, int K, const SoftBwdArgs& a,
