@@ -186,9 +186,9 @@ __global__ __launch_bounds__(kBlock) void k_soft_means(int B, int K, const doubl
   }
 }
 
-// Pass 2 on the matrix cores, grid (G, ceil(K / 4)): block (g, q) takes
-// chunks g, g + G, ... of X and w (through the prefetching driver) and its
-// wave v the class c = 4 q + v.  The weighted Gram of d = [x - m_c, 1] is
+// Pass 2 on the matrix cores, grid (G, ceil(K / (4 CPW))): block (g, q)
+// takes chunks g, g + G, ... of X and w (through the prefetching driver) and
+// its wave v the classes c = 4 CPW q + 4 u + v, u < CPW.  The weighted Gram of d = [x - m_c, 1] is
 // sum_p a_p d_p^T with a = w_pc d, accumulated with the FP32 matrix
 // instruction v_mfma_f32_16x16x4_f32: FP32 operands, FP32 products and
 // accumulation, so the arithmetic is that of the plain FP32 path; the FP32
@@ -196,8 +196,8 @@ __global__ __launch_bounds__(kBlock) void k_soft_means(int B, int K, const doubl
 // pixel k0 + l / 16 and band 16 r + l % 16 of both operands (A[i][k] and
 // B[k][j]); the output tile as for the other MFMA shapes (rows
 // 4 (l / 16) + e, column l % 16).  Rows past N have zero weights (the partial
-// chunk is zero-filled), so they add nothing.  Each wave writes its class's
-// partial in the packed layout of the fixed-order reduction.
+// chunk is zero-filled), so they add nothing.  Each wave writes its classes'
+// partials in the packed layout of the fixed-order reduction.
 
 // Tail columns.  When B + 1 = 16 NRB + T with T = 1 or 2, the matrix cores
 // take the 16 NRB leading columns and the vector ALU the T trailing ones:
