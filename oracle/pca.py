@@ -10,7 +10,7 @@ Readings: covariance PCA on the raw values (no standardisation), divided by
 P - 1; components sorted by descending eigenvalue; sign as in CVA (largest
 entry of each eigenvector positive).
 
-Pinned by tests/test_oracle_pca.py: trace(cov) equals the sum of all
+Pinned by tests/test_oracle_pca_soft.py: trace(cov) equals the sum of all
 eigenvalues, V is orthonormal, a brute-force loop covariance on tiny pages,
 numpy.cov, and constructed data whose covariance eigenvalues are known.
 """

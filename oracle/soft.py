@@ -20,7 +20,7 @@ dJ = tr(S_w^-1 dS_b) - tr(S_w^-1 dS_w S_w^-1 S_b)):
   dJ/dw_pc = (x_p-m)^T S_w^-1 (x_p-m)
              - (x_p-m_c)^T (S_w^-1 + S_w^-1 S_b S_w^-1) (x_p-m_c).
 
-Pinned by tests/test_oracle_soft.py: one-hot weights reproduce hard-label
+Pinned by tests/test_oracle_pca_soft.py: one-hot weights reproduce hard-label
 CVA; central differences of the exact finite change of J (rank-one moment
 updates) on random (p, c); exact rational arithmetic on a tiny case; and
 Euler's identity sum_pc w_pc dJ/dw_pc = 0 (J is homogeneous of degree 0).

@@ -160,8 +160,9 @@ def cva_fit_project(cube: torch.Tensor, labels: torch.Tensor, K: int, precision:
     H, Wd = cube.shape[0], cube.shape[1]
     if out is None:
         out = torch.empty((n_comp, H, Wd), dtype=torch.uint8, device=cube.device)
-    elif out.dtype != torch.uint8 or tuple(out.shape) != (n_comp, H, Wd) or not out.is_contiguous():
-        raise ValueError("out must be a contiguous uint8 n_comp x H x W tensor")
+    elif out.dtype != torch.uint8 or tuple(out.shape) != (n_comp, H, Wd) or not out.is_contiguous() \
+            or out.device != cube.device:
+        raise ValueError("out must be a contiguous uint8 n_comp x H x W tensor on the cube's device")
     W = np.empty((B, n_comp))
     lam = np.empty(n_comp)
     mean = np.empty(B)
@@ -192,8 +193,9 @@ def cva_project(cube: torch.Tensor, W, center, out: Optional[torch.Tensor] = Non
     H, Wd = cube.shape[0], cube.shape[1]
     if out is None:
         out = torch.empty((n, H, Wd), dtype=torch.uint8, device=cube.device)
-    elif out.dtype != torch.uint8 or tuple(out.shape) != (n, H, Wd) or not out.is_contiguous():
-        raise ValueError("out must be a contiguous uint8 n x H x W tensor")
+    elif out.dtype != torch.uint8 or tuple(out.shape) != (n, H, Wd) or not out.is_contiguous() \
+            or out.device != cube.device:
+        raise ValueError("out must be a contiguous uint8 n x H x W tensor on the cube's device")
     rng = np.empty((n, 2), dtype=np.float32) if return_range else None
     dev = _dev_index(cube)
     ctx = context(dev)
@@ -468,14 +470,27 @@ def cva_soft_forward(X: torch.Tensor, w: torch.Tensor, precision: str = "fp32",
 
 def cva_soft_backward(X: torch.Tensor, fit: SoftFit, dJ: float, K: int,
                       out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """dJ * dJ/dw for the training pixels X (N x B float32, contiguous, on the
+    GPU) of a soft-label fit with K classes; out (N x K float32, contiguous,
+    on X's device) receives it, or a new tensor does."""
+    if X.dtype != torch.float32 or X.dim() != 2 or not X.is_contiguous():
+        raise ValueError("X must be a contiguous N x B float32 tensor")
     N, B = X.shape
+    C = min(int(K) - 1, B)
+    if np.shape(fit.class_means) != (K, B) or np.shape(fit.W) != (B, C) or np.size(fit.eigvals) != C \
+            or np.size(fit.mean) != B:
+        raise ValueError("fit does not belong to K classes of X's bands: class_means must be K x B, "
+                         "W B x min(K-1, B), eigvals min(K-1, B) and mean B")
+    if out is not None and (out.dtype != torch.float32 or tuple(out.shape) != (N, K) or not out.is_contiguous()
+                            or out.device != X.device):
+        raise ValueError("out must be a contiguous float32 N x K tensor on X's device")
+    dev = _dev_index(X)
     if out is None:
         out = torch.empty((N, K), dtype=torch.float32, device=X.device)
     W = _f64(fit.W)
     lam = _f64(fit.eigvals)
     mean = _f64(fit.mean)
     cm = _f64(fit.class_means)
-    dev = _dev_index(X)
     ctx = context(dev)
     st = lib().cva_soft_backward(ctx, _ptr(X), _ptr(W), _ptr(lam), _ptr(mean), _ptr(cm), N, B, K,
                                  float(dJ), _ptr(out), _stream(X.device))

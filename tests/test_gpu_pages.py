@@ -15,7 +15,7 @@ import pytest
 import oracle
 from synth import make_case
 from tests._cases import full_page
-from tests._parity import TOL_LAM, check_images, check_vectors
+from tests._parity import TOL_LAM, check_cva_vectors, check_images
 
 pytestmark = pytest.mark.gpu
 
@@ -131,7 +131,7 @@ def test_run_pages_against_oracle_and_failures(dev):
         pg = pages[i]
         ref = oracle.cva_fit_points(pg["cube8"].astype(np.uint16), pg["pixels"].numpy(), pg["classes"].numpy(), K)
         assert np.max(np.abs(out[i]["eigvals"] - ref["eigvals"]) / ref["eigvals"]) <= TOL_LAM
-        signs, _ = check_vectors(out[i]["W"], ref["W"], ref["eigvals"])
+        signs, _ = check_cva_vectors(out[i]["W"], ref)
         q_ref, _ = oracle.cva_project(pg["cube8"].astype(np.uint16), ref["W"], ref["mean"])
         check_images(out[i]["images"].numpy(), q_ref, signs)
 

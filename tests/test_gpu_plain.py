@@ -16,7 +16,7 @@ import pytest
 
 import oracle
 from synth import make_case, to_half_cube
-from tests._parity import TOL_LAM, TOL_S, TOL_Y, check_images, check_vectors, rel_max
+from tests._parity import TOL_LAM, TOL_S, TOL_Y, check_cva_vectors, check_images, check_pca_vectors, rel_max
 
 pytestmark = pytest.mark.gpu
 
@@ -80,7 +80,7 @@ def test_plain_path_against_oracle(dev, plain, kind, odd):
     assert rel_max(fit.Sw, ref["Sw"]) <= TOL_S
     assert rel_max(fit.Sb, ref["Sb"]) <= TOL_S
     assert np.max(np.abs(fit.eigvals - ref["eigvals"]) / ref["eigvals"]) <= TOL_LAM
-    signs, _ = check_vectors(fit.W, ref["W"], ref["eigvals"])
+    signs, _ = check_cva_vectors(fit.W, ref)
     q_ref, ab_ref = oracle.cva_project(host, fit.W, fit.mean)
     span = ab_ref[:, 1] - ab_ref[:, 0]
     assert np.max(np.abs(ab - ab_ref) / span[:, None]) <= TOL_Y
@@ -89,7 +89,7 @@ def test_plain_path_against_oracle(dev, plain, kind, odd):
     assert np.max(np.abs(y - y_ref).reshape(y.shape[0], -1) / span[:, None]) <= TOL_Y
     pr = oracle.pca_fit(host, n_comp=3)
     assert rel_max(pca[3], pr["cov"]) <= TOL_S
-    check_vectors(pca[0], pr["V"], pr["all_eigvals"][:3])
+    check_pca_vectors(pca[0], pr)
 
 
 @pytest.mark.parametrize("kind", ["u16", "bf16"])
