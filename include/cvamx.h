@@ -166,6 +166,26 @@ int cva_project(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W,
                 const double* center, int32_t n_comp, uint8_t* images,
                 float* range, void* stream);
 
+/* cva_project for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, images and range, with every piece of device scratch (block
+ * partials, the last-block ticket, the stretch map and range slots) in a
+ * fixed array of 513 KiB that each GPU holds from the first cvamx_create on
+ * it until the process ends.  The call makes no hipMalloc, hipFree or other
+ * allocating call; it launches a one-element fill kernel that clears the
+ * ticket, then the same two passes as cva_project.  Limit: a projection grid
+ * of at most 4096 blocks (the default grid is 8 blocks per compute unit;
+ * CVAMX_PROJ_BLOCKS above that fails with CVAMX_E_UNSUPPORTED).  All calls
+ * on one GPU share the array, which keeps the last call's contents: calls
+ * that overlap on one GPU (other streams, other contexts, other threads)
+ * race and must be serialised by the caller.  With range = NULL the call
+ * is asynchronous on `stream` and records only kernel launches; a non-NULL
+ * range is copied to the host with hipMemcpyAsync and synchronises. */
+int cva_project_noalloc(cvamx_ctx* ctx, const cvamx_cube* cube,
+                        const double* W, const double* center,
+                        int32_t n_comp, uint8_t* images, float* range,
+                        void* stream);
+
 /* cva_fit followed by cva_project with the fitted (W, mean), in one call:
  * the projection is launched straight after the host's FP64 finish, with
  * no return to the caller in between.  Arguments as for the two calls

@@ -64,6 +64,7 @@ EXPORTS = {
                                        _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cvamx_label_index": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp]),
     "cva_project": (ctypes.c_int, [_vp, ctypes.POINTER(Cube), _vp, _vp, _i32, _vp, _vp, _vp]),
+    "cva_project_noalloc": (ctypes.c_int, [_vp, ctypes.POINTER(Cube), _vp, _vp, _i32, _vp, _vp, _vp]),
     "cvamx_project_float": (ctypes.c_int, [_vp, ctypes.POINTER(Cube), _vp, _vp, _i32, _vp, _vp]),
     "cvamx_stretch": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _f64, _vp, _i64, _i32, _vp, _vp, _vp]),
     "cvamx_compose_rgb": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp]),

@@ -205,6 +205,30 @@ def cva_project(cube: torch.Tensor, W, center, out: Optional[torch.Tensor] = Non
     return (out, rng) if return_range else out
 
 
+def cva_project_noalloc(cube: torch.Tensor, W, center, out: torch.Tensor, return_range: bool = False):
+    """cva_project through the library's allocation-free entry point: the
+    caller passes the n x H x W uint8 output, and the library's device
+    scratch is a fixed array per GPU (calls overlapping on one GPU race)."""
+    c = _cube(cube)
+    B = c.bands
+    W = _f64(W)
+    if W.ndim != 2 or W.shape[0] != B:
+        raise ValueError("W must be B x n")
+    n = W.shape[1]
+    center = _f64(center, B)
+    H, Wd = cube.shape[0], cube.shape[1]
+    if out is None or out.dtype != torch.uint8 or tuple(out.shape) != (n, H, Wd) or not out.is_contiguous() \
+            or out.device != cube.device:
+        raise ValueError("out must be a contiguous uint8 n x H x W tensor on the cube's device")
+    rng = np.empty((n, 2), dtype=np.float32) if return_range else None
+    dev = _dev_index(cube)
+    ctx = context(dev)
+    st = lib().cva_project_noalloc(ctx, ctypes.byref(c), _ptr(W), _ptr(center), n, _ptr(out), _ptr(rng),
+                                   _stream(cube.device))
+    check(st, ctx)
+    return (out, rng) if return_range else out
+
+
 def project_float(cube: torch.Tensor, W, center, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """The float images y_j = w_j^T (x - center) of every pixel (the (W, mean)
     of a CVA fit or the (V, mean) of a PCA fit) as an n x H x W float32

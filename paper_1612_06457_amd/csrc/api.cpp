@@ -253,7 +253,7 @@ void make_proj_args(const cvamx_cube* cube, const double* W, const double* cente
                     bool plain, cvx::ProjArgs& a) {
   const int B = (int)cube->bands;
   std::memset(&a, 0, sizeof(a));
-  std::vector<double> c(B);
+  double c[CVAMX_MAX_BANDS];   // on the stack: the allocation-free entry point comes through here
   for (int b = 0; b < B; ++b) {
     // uint16 pages: an integer centre, passed as 2^23 + c (exact in FP32),
     // which the kernels subtract from the bit-built float 2^23 + x
@@ -291,13 +291,21 @@ void make_proj_args(const cvamx_cube* cube, const double* W, const double* cente
   }
 }
 
-int proj_groups(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const double* center,
-                int n_comp, uint8_t* images, hipStream_t s) {
+// Device buffers of the two projection passes: block partials (at most 32
+// floats per block), the last-block ticket (zero between calls), the
+// stretch map of the current group and the range of every component.
+struct ProjBufs {
+  float* part;
+  unsigned* ticket;
+  float* range_dev;
+  float* ab_dev;
+};
+
+int proj_groups_with(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const double* center,
+                     int n_comp, uint8_t* images, const ProjBufs& pb, bool timed, hipStream_t s) {
   const int B = (int)cube->bands;
   const int64_t P = cube->height * cube->width;
   const int nblocks = proj_nblocks(ctx, cube);
-  // block partials: 16 floats (VALU kernels) or 32 (matrix-core kernels)
-  if (int st = ensure(ctx, B_PROJPART, (size_t)nblocks * 32 * sizeof(float))) return st;
   for (int g0 = 0; g0 < n_comp; g0 += 8) {
     const int nc = std::min(8, n_comp - g0);   // the kernels are instantiated for 1..8 components
     cvx::ProjArgs a;
@@ -308,19 +316,27 @@ int proj_groups(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const d
     static const char* kStretchName[9] = {"", "project_stretch_nc1", "project_stretch_nc2", "project_stretch_nc3",
                                           "project_stretch_nc4", "project_stretch_nc5", "project_stretch_nc6",
                                           "project_stretch_nc7", "project_stretch_nc8"};
-    prof_begin(ctx, s, kRangeName[nc]);
-    hipError_t e = cvx::launch_project_range(cube->dtype, ctx->plain, cube->data, B, P, nc, a, nblocks,
-                                             (float*)ctx->buf[B_PROJPART], ctx->tickets,
-                                             ctx->range_dev, ctx->ab_dev + 2 * g0, s);
-    prof_end(ctx, s);
+    if (timed) prof_begin(ctx, s, kRangeName[nc]);
+    hipError_t e = cvx::launch_project_range(cube->dtype, ctx->plain, cube->data, B, P, nc, a, nblocks, pb.part,
+                                             pb.ticket, pb.range_dev, pb.ab_dev + 2 * g0, s);
+    if (timed) prof_end(ctx, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "project range launch");
-    prof_begin(ctx, s, kStretchName[nc]);
-    e = cvx::launch_project_stretch(cube->dtype, ctx->plain, cube->data, B, P, nc, a, nblocks, ctx->range_dev,
+    if (timed) prof_begin(ctx, s, kStretchName[nc]);
+    e = cvx::launch_project_stretch(cube->dtype, ctx->plain, cube->data, B, P, nc, a, nblocks, pb.range_dev,
                                     images + (int64_t)g0 * P, s);
-    prof_end(ctx, s);
+    if (timed) prof_end(ctx, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "project stretch launch");
   }
   return 0;
+}
+
+int proj_groups(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const double* center,
+                int n_comp, uint8_t* images, hipStream_t s) {
+  const int nblocks = proj_nblocks(ctx, cube);
+  // block partials: 16 floats (VALU kernels) or 32 (matrix-core kernels)
+  if (int st = ensure(ctx, B_PROJPART, (size_t)nblocks * 32 * sizeof(float))) return st;
+  const ProjBufs pb{(float*)ctx->buf[B_PROJPART], ctx->tickets, ctx->range_dev, ctx->ab_dev};
+  return proj_groups_with(ctx, cube, W, center, n_comp, images, pb, true, s);
 }
 
 // Checks shared by the projection entry points.
@@ -416,6 +432,11 @@ int cvamx_create(cvamx_ctx** out, int device) {
       return CVAMX_E_NO_MEMORY;
     }
     if (hipMemset(p, 0, small) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+      (void)hipFree(p);
+      delete ctx;
+      return CVAMX_E_DEVICE;
+    }
+    if (cvx::scratch_setup(device) != hipSuccess) {
       (void)hipFree(p);
       delete ctx;
       return CVAMX_E_DEVICE;
@@ -662,6 +683,32 @@ int cvamx_label_index(cvamx_ctx* ctx, const int8_t* labels, int64_t n, int32_t K
 int cva_project(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const double* center,
                 int32_t n_comp, uint8_t* images, float* range, void* stream) {
   return project_common(ctx, cube, W, center, n_comp, images, range, stream);
+}
+
+int cva_project_noalloc(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const double* center,
+                        int32_t n_comp, uint8_t* images, float* range, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (int st = check_proj_args(ctx, cube, W, center, n_comp, images)) return st;
+  if (int st = check_device(ctx)) return st;
+  char* base = static_cast<char*>(cvx::scratch_address(ctx->device));
+  if (!base) return fail(ctx, CVAMX_E_DEVICE, "the fixed scratch has no address on this device");
+  const int nblocks = proj_nblocks(ctx, cube);
+  if (nblocks > cvx::kScratchBlocks)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "the projection grid (" + std::to_string(nblocks) +
+                                              " blocks) exceeds the fixed scratch's " +
+                                              std::to_string(cvx::kScratchBlocks));
+  hipStream_t s = (hipStream_t)stream;
+  const ProjBufs pb{reinterpret_cast<float*>(base + cvx::kScratchPartOffset), reinterpret_cast<unsigned*>(base),
+                    reinterpret_cast<float*>(base + 256), reinterpret_cast<float*>(base + 512)};
+  // the ticket must start at zero: a fill kernel, not a memset, so that the
+  // call can be captured into a graph
+  HIP_TRY(cvx::launch_zero_u32(pb.ticket, 1, s), "ticket clear");
+  if (int st = proj_groups_with(ctx, cube, W, center, n_comp, images, pb, false, s)) return st;
+  if (range) {
+    HIP_TRY(hipMemcpyAsync(range, pb.ab_dev, 2 * sizeof(float) * n_comp, hipMemcpyDeviceToHost, s), "range copy");
+    HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+  }
+  return 0;
 }
 
 int pca_project(cvamx_ctx* ctx, const cvamx_cube* cube, const double* V, const double* mean,

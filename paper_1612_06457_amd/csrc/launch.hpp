@@ -144,6 +144,20 @@ hipError_t launch_cluster_moments(int dtype, const void* img, int64_t P, int n, 
 // band-interleaved page (uint16 for 8/16-bit bands, float32 for float)
 hipError_t launch_bands_to_cube(int in_dtype, const void* bands, int B, int64_t P, void* cube, hipStream_t s);
 
+// Fixed device scratch of the allocation-free projection entry point, one
+// copy per GPU (k_scratch.hip).  Layout in bytes: [0, 256) tickets,
+// [256, 512) the stretch map of the current group, [512, 1024) the range
+// (min, max) of up to 64 components, then the block partials of up to
+// kScratchBlocks blocks (32 floats each).
+constexpr int kScratchBlocks = 4096;
+constexpr int kScratchPartOffset = 1024;
+constexpr size_t kScratchBytes = (size_t)kScratchPartOffset + (size_t)kScratchBlocks * 32 * sizeof(float);
+// looks up the scratch's device address on `device`, which must be current;
+// once per device (later calls return at once)
+hipError_t scratch_setup(int device);
+// that address, or nullptr before scratch_setup succeeded on `device`
+void* scratch_address(int device);
+
 // n bytes from device memory to page-locked host memory, by a kernel
 hipError_t launch_copy_out(void* dst, const void* src, int64_t n, hipStream_t s);
 
