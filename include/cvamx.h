@@ -161,7 +161,8 @@ int cvamx_label_index(cvamx_ctx* ctx, const int8_t* labels, int64_t n,
  *   images   device, n_comp x height x width uint8 (planar)
  *   range    host, 2*n_comp float (min_j, max_j pairs) or NULL
  * Asynchronous on `stream` unless `range` is non-NULL (then it
- * synchronises).  W and center are read before the call returns. */
+ * synchronises).  W and center are read before the call returns.  The
+ * page is read once or twice (cvamx_set_schedule). */
 int cva_project(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W,
                 const double* center, int32_t n_comp, uint8_t* images,
                 float* range, void* stream);
@@ -369,7 +370,14 @@ int cvamx_cluster_indices(cvamx_ctx* ctx, const void* images, int32_t dtype,
  * the paper: it reduces to the paper's CVA for one-hot weights.
  *   X        device, N x B float32 (row-major), 16-byte aligned
  *   w        device, N x K float32 (row-major), 16-byte aligned
- *   prec     CVAMX_PREC_FP32 only (others: CVAMX_E_UNSUPPORTED)
+ *   prec     CVAMX_PREC_FP32: FP32 products and accumulation, on the FP32
+ *            matrix instruction (or, with cvamx_set_plain_fp32, on the
+ *            vector ALU); CVAMX_PREC_BF16X3 / F16X3: the weighted scatter
+ *            on the 16-bit matrix units with each operand split into a
+ *            16-bit head and tail (four products, FP32 accumulation, a
+ *            power of two per chunk keeping the values in range); error
+ *            per S_w entry at most (2 u^2 + 512 2^-24) sum_p |w_pc|
+ *            |d_i| |d_j|, u = 2^-8 (bf16) or 2^-11 (fp16)
  * Host outputs: J; W B x C, eigvals C, mean B, class_means K x B (all
  * float64; keep them for cva_soft_backward).  Synchronises `stream`.
  * Misaligned X or w: CVAMX_E_UNSUPPORTED. */
@@ -391,18 +399,77 @@ int cva_soft_backward(cvamx_ctx* ctx, const float* X, const double* W,
                       const double* class_means, int64_t N, int32_t B,
                       int32_t K, double dJ, float* dw, void* stream);
 
+/* One refinement step of the class weights along the gradient of J (paper
+ * Section 4 calls for an automatic choice of training points; Section 3,
+ * Eqs. 1-5, measures the result): for each pixel p,
+ *   d = grad_p - mean_c(grad_pc)   (the part within the simplex's plane)
+ *   v = w_p + step * d / max_c |d_c|   (v = w_p if d = 0)
+ *   w_p = the Euclidean projection of v onto {w >= 0, sum_c w_c = 1}.
+ * A pixel labelled with the wrong class has its weight moved towards the
+ * class that raises the Fisher criterion most; a correctly labelled
+ * one-hot pixel stays where it is.  grad: device N x K float32 (e.g. from
+ * cva_soft_backward with dJ = 1); w: device N x K float32, updated in place;
+ * both 4-byte aligned.  K in 2..32, step finite and >= 0.  Asynchronous on
+ * `stream`. */
+int cva_soft_update(cvamx_ctx* ctx, const float* grad, float* w, int64_t N,
+                    int32_t K, double step, void* stream);
+
 /* ---- plain FP32 reference path ------------------------------------------ */
 
 /* With enable = 1, every FP32 request on this context runs the plain FP32
  * vector-ALU kernels whatever the page type: the class moments of the fits
  * and the PCA covariance (prec CVAMX_PREC_FP32), and all projections
- * (cva_project, pca_project, cva_fit_project, cvamx_project_float).  By
+ * (cva_project, pca_project, cva_fit_project, cvamx_project_float), and
+ * the two forward passes of cva_soft_forward.  By
  * default uint16 pages take the matrix cores with exactly split operands
  * and bf16 / fp16 pages take them for the projections; the plain path is
  * the reference those paths are measured against (same FP32 accumulation,
  * so the same tolerances hold).  0 restores the default.  Host-only: never
  * fails for a valid context. */
 int cvamx_set_plain_fp32(cvamx_ctx* ctx, int enable);
+
+/* ---- projection schedule ------------------------------------------------ */
+
+/* How cva_project, pca_project and cva_fit_project read the page (paper
+ * Section 2: the float arrays are rescaled onto 0..255 by their page-wide
+ * min and max, so every value is needed twice: once for the range, once
+ * for the map).
+ *   CVAMX_SCHEDULE_AUTO (default): on uint16 pages (matrix-core path) the
+ *     page is read once; pass 1 finds the range and stores every component
+ *     value as fp16 (2 bytes per pixel and component, in scratch owned by
+ *     the context: n_comp <= 8 planes of the page rounded up to 256
+ *     pixels), pass 2 maps the stored values.  Pass 1 also bounds how far
+ *     the fp16 rounding can move the argument of the map's floor:
+ *     255 (2^-11 max(|a_j|, |b_j|) + tiny terms) / (b_j - a_j) grey levels,
+ *     at most 0.125 when the center lies inside the page's projected range
+ *     (the fit's mean always does).  Beyond 0.5 levels for some component
+ *     pass 2 re-reads the page instead (decided on the device), so every
+ *     byte stays within one level of the two-read result.  Other page
+ *     types, and the plain FP32 path, read the page twice.
+ *   CVAMX_SCHEDULE_TWO_READS: the page is read twice (range, then map), as
+ *     for the other page types.
+ *   CVAMX_SCHEDULE_FORCE_REREAD: pass 1 of the one-read schedule, then the
+ *     fallback of pass 2, whatever the bound (for testing the fallback).
+ * The ranges are identical under all three. */
+enum {
+  CVAMX_SCHEDULE_AUTO = 0,
+  CVAMX_SCHEDULE_TWO_READS = 1,
+  CVAMX_SCHEDULE_FORCE_REREAD = 2
+};
+/* Host-only; unknown values: CVAMX_E_INVALID_ARG. */
+int cvamx_set_schedule(cvamx_ctx* ctx, int schedule);
+
+/* ---- measurement ----------------------------------------------------------- */
+
+/* The read ceiling the page passes are measured against: reads `bytes` (a
+ * positive multiple of 16) of device memory at src (16-byte aligned) once,
+ * with non-temporal 16-byte loads, eight in flight per thread, as the page
+ * passes stream the page, and no arithmetic beyond folding the words
+ * together.  sink (device, 4-byte aligned) receives one word only if the
+ * fold happens to equal a fixed key (a guard against the loads being
+ * optimised away).  Asynchronous on `stream`. */
+int cvamx_stream_read(cvamx_ctx* ctx, const void* src, int64_t bytes,
+                      uint32_t* sink, void* stream);
 
 /* ---- kernel timing ------------------------------------------------------ */
 

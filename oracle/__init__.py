@@ -33,7 +33,7 @@ from .cva import (class_counts, class_index_lists, class_moments, within_scatter
                   cva_fit, cva_fit_points, project, cva_project)
 from .stretch import compose_rgb, stretch_minmax, stretch_training_range, stretch_percentile
 from .pca import pca_fit, pca_project
-from .soft import soft_moments, soft_fit, soft_grad, soft_delta_J
+from .soft import soft_moments, soft_fit, soft_grad, soft_delta_J, simplex_projection, soft_update
 from .cluster import cluster_indices
 
 __all__ = [
@@ -41,5 +41,6 @@ __all__ = [
     "between_scatter", "total_scatter", "generalized_eig", "sign_rule",
     "cva_fit", "cva_fit_points", "project", "cva_project", "stretch_minmax",
     "stretch_training_range", "stretch_percentile", "compose_rgb", "pca_fit", "pca_project",
-    "soft_moments", "soft_fit", "soft_grad", "soft_delta_J", "cluster_indices",
+    "soft_moments", "soft_fit", "soft_grad", "soft_delta_J", "simplex_projection", "soft_update",
+    "cluster_indices",
 ]

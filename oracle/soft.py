@@ -24,6 +24,20 @@ Pinned by tests/test_oracle_pca_soft.py: one-hot weights reproduce hard-label
 CVA; central differences of the exact finite change of J (rank-one moment
 updates) on random (p, c); exact rational arithmetic on a tiny case; and
 Euler's identity sum_pc w_pc dJ/dw_pc = 0 (J is homogeneous of degree 0).
+
+Mask refinement (a reading: the paper asks for an automatic choice of
+training points, Section 4, and scores images by Eqs. 1-5 of Section 3,
+but gives no update rule): one step moves each pixel's weights along the
+part of its gradient within the simplex's plane, d = g_p - mean_c g_pc,
+scaled so that max_c |d_c| = step, and projects the result back onto the
+probability simplex {w >= 0, sum_c w_c = 1} (Euclidean projection by the
+sort-based rule of Held, Wolfe and Crowder).  Pinned by
+tests/test_oracle_pca_soft.py: the projection satisfies its optimality
+conditions (entries above the threshold sum to one; v - w is the same on
+the support and v <= theta off it), leaves simplex points unchanged, and
+equals a brute-force search for K = 2 and 3; the step leaves a correctly
+labelled one-hot pixel in place and moves a mislabelled one to the class
+its gradient favours.
 """
 from __future__ import annotations
 
@@ -110,3 +124,28 @@ def soft_delta_J(X, w, p: int, c: int, h: float, moments=None) -> float:
     Av = A @ v
     vSv = v @ Av - a * (Au @ v) ** 2 / den
     return float(term_w + b * vSv)
+
+
+def simplex_projection(V):
+    """Rows of V projected onto the probability simplex (Euclidean): sort each
+    row descending, take the largest rho with u_rho > (sum_{i<=rho} u_i - 1)
+    / rho, and theta = (sum_{i<=rho} u_i - 1) / rho; w = max(v - theta, 0)."""
+    V = np.asarray(V, dtype=np.float64)
+    K = V.shape[1]
+    U = -np.sort(-V, axis=1)
+    css = np.cumsum(U, axis=1) - 1.0
+    j = np.arange(1, K + 1)
+    ok = U - css / j > 0
+    rho = K - 1 - np.argmax(ok[:, ::-1], axis=1)
+    theta = css[np.arange(V.shape[0]), rho] / (rho + 1)
+    return np.maximum(V - theta[:, None], 0.0)
+
+
+def soft_update(w, g, step: float):
+    """One refinement step of the weights w (N x K) along the gradient g."""
+    w = np.asarray(w, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    d = g - g.mean(axis=1, keepdims=True)
+    s = np.abs(d).max(axis=1, keepdims=True)
+    d = np.divide(d, s, out=np.zeros_like(d), where=s > 0)
+    return simplex_projection(w + step * d)

@@ -542,6 +542,37 @@ class SoftCVA(torch.autograd.Function):
         return None, dw, None, None
 
 
+def cva_soft_update(w: torch.Tensor, grad: torch.Tensor, step: float) -> torch.Tensor:
+    """One refinement step of the class weights w (N x K float32, updated in
+    place) along grad (N x K float32, e.g. cva_soft_backward with dJ = 1):
+    the mean-free gradient, scaled to `step` at its largest entry, then the
+    projection of each row onto the probability simplex.  Returns w."""
+    for name, t in (("w", w), ("grad", grad)):
+        if t.dtype != torch.float32 or t.dim() != 2 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous N x K float32 tensor")
+    if grad.shape != w.shape or grad.device != w.device:
+        raise ValueError("grad must have w's shape and device")
+    dev = _dev_index(w)
+    ctx = context(dev)
+    N, K = w.shape
+    check(lib().cva_soft_update(ctx, _ptr(grad), _ptr(w), N, K, float(step), _stream(w.device)), ctx)
+    return w
+
+
+def refine_weights(X: torch.Tensor, w: torch.Tensor, steps: int = 3, step: float = 0.5,
+                   precision: str = "fp32") -> SoftFit:
+    """Refine an analyst's class weights (N x K float32 on the GPU, updated
+    in place) by `steps` gradient steps on the Fisher criterion: soft-label
+    forward, hand-written backward, cva_soft_update.  Returns the fit of the
+    refined weights."""
+    g = torch.empty_like(w)
+    for _ in range(int(steps)):
+        fit = cva_soft_forward(X, w, precision)
+        cva_soft_backward(X, fit, 1.0, w.shape[1], out=g)
+        cva_soft_update(w, g, step)
+    return cva_soft_forward(X, w, precision)
+
+
 # ------------------------------------------------------------ host-only calls
 
 def cva_solve_moments(counts, class_means, Sw, ridge: float = 0.0, n_comp: Optional[int] = None):
@@ -578,6 +609,37 @@ def set_plain_fp32(enable: bool = True, device: int = 0) -> None:
     paths; False restores the default.  The reference for the speed-ups."""
     ctx = context(device)
     check(lib().cvamx_set_plain_fp32(ctx, 1 if enable else 0), ctx)
+
+
+def stream_read(buf: torch.Tensor, sink: Optional[torch.Tensor] = None) -> None:
+    """Read every byte of a contiguous device tensor once (the reference
+    read stream of the page passes), asynchronously on torch's current
+    stream; for timing the device's read ceiling."""
+    if buf.device.type != "cuda" or not buf.is_contiguous():
+        raise ValueError("buf must be a contiguous device tensor")
+    nbytes = buf.numel() * buf.element_size()
+    if nbytes < 16 or nbytes % 16 != 0:
+        raise ValueError("buf must hold a positive multiple of 16 bytes")
+    if sink is None:
+        sink = torch.zeros(1, dtype=torch.int32, device=buf.device)
+    elif sink.device != buf.device or sink.dtype != torch.int32 or sink.numel() < 1:
+        raise ValueError("sink must be an int32 tensor on buf's device")
+    ctx = context(_dev_index(buf))
+    check(lib().cvamx_stream_read(ctx, _ptr(buf), nbytes, _ptr(sink), _stream(buf.device)), ctx)
+
+
+_SCHEDULES = {"auto": 0, "two_reads": 1, "force_reread": 2}
+
+
+def set_schedule(schedule: str = "auto", device: int = 0) -> None:
+    """How the projections read the page on `device`: "auto" (uint16 pages:
+    once, with an fp16 intermediate whose error bound is checked on the
+    device), "two_reads", or "force_reread" (the one-read pass 1, then its
+    page re-reading fallback; for tests)."""
+    if schedule not in _SCHEDULES:
+        raise ValueError(f"schedule must be one of {sorted(_SCHEDULES)}")
+    ctx = context(device)
+    check(lib().cvamx_set_schedule(ctx, _SCHEDULES[schedule]), ctx)
 
 
 def profile_enable(enable=True, device: int = 0) -> None:

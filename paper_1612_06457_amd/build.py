@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcvamx.so")
 
 HIP_SOURCES = ["k_labels.hip", "k_moments.hip", "k_project.hip", "k_project_u16.hip", "k_soft.hip", "k_class.hip",
-               "k_mfma.hip", "k_stretch.hip", "k_cluster.hip", "k_bands.hip", "k_scratch.hip"]
+               "k_mfma.hip", "k_stretch.hip", "k_cluster.hip", "k_bands.hip", "k_scratch.hip", "k_roof.hip"]
 HOST_SOURCES = ["api.cpp", "finisher.cpp", "pipeline.cpp"]
 
 ARCH = os.environ.get("CVAMX_ARCH", "gfx950")

@@ -19,7 +19,7 @@
 
 namespace {
 
-enum Buf { B_TILECNT, B_IDX, B_PART, B_RES, B_PROJPART, B_FIRST, B_MCF, B_SPART, B_SHIST, B_SFIX, B_COUNT };
+enum Buf { B_TILECNT, B_IDX, B_PART, B_RES, B_PROJPART, B_FIRST, B_MCF, B_SPART, B_SHIST, B_SFIX, B_H16, B_COUNT };
 
 }  // namespace
 
@@ -28,6 +28,7 @@ struct cvamx_ctx {
   int num_cu = 256;
   int proj_blocks = 0;   // 0 = automatic
   bool plain = false;    // FP32 requests on the plain vector-ALU kernels
+  int schedule = CVAMX_SCHEDULE_AUTO;   // projection schedule (cvamx_set_schedule)
   int gram_blocks = 0;
   std::string err;
   void* buf[B_COUNT] = {};
@@ -330,12 +331,78 @@ int proj_groups_with(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, co
   return 0;
 }
 
+// Storage factors of the fp16 intermediate for one group of uint16-page
+// components: the power of two f_j that keeps the largest value the scaled
+// sum 2^s_j y_j can take on any uint16 page, |y_j| <= sum_b |W[b][j]|
+// max(|c_b|, |65535 - c_b|), at or below 2^15 (fp16's largest value is
+// 65504), with a margin for the FP32 rounding of the sum.
+void h16_args(const cvx::ProjArgs& a, const double* center, int B, int nc, float limit, cvx::H16Args& h) {
+  std::memset(&h, 0, sizeof(h));
+  for (int j = 0; j < nc; ++j) {
+    double bnd = 0.0;
+    for (int b = 0; b < B; ++b)
+      bnd += std::fabs((double)a.w[b * nc + j]) * std::max(std::fabs(center[b]), std::fabs(65535.0 - center[b]));
+    bnd *= (double)a.scale[j] * (1.0 + 1.0 / 1024.0);
+    int ex = 0;
+    if (bnd > 0.0) {
+      std::frexp(32768.0 / bnd, &ex);   // 32768 / bnd in [2^(ex-1), 2^ex)
+      ex -= 1;
+    }
+    ex = std::max(-60, std::min(60, ex));
+    h.f[j] = (float)std::ldexp(1.0, ex);
+  }
+  h.limit = limit;
+}
+
+// The one-read schedule on uint16 pages: pass 1 reads the page once for the
+// range and stores every component value in fp16; pass 2 quantises the
+// stored values (or re-reads the page, decided on the device, when their
+// error bound exceeds the limit).
+int proj_groups_h16(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const double* center, int n_comp,
+                    uint8_t* images, const ProjBufs& pb, hipStream_t s) {
+  const int B = (int)cube->bands;
+  const int64_t P = cube->height * cube->width;
+  const int64_t Pp = (P + 255) / 256 * 256;
+  const int nblocks = proj_nblocks(ctx, cube);
+  if (int st = ensure(ctx, B_H16, (size_t)std::min(n_comp, 8) * (size_t)Pp * 2)) return st;
+  uint16_t* planes = static_cast<uint16_t*>(ctx->buf[B_H16]);
+  const float limit = ctx->schedule == CVAMX_SCHEDULE_FORCE_REREAD ? -1.f : 0.5f;
+  for (int g0 = 0; g0 < n_comp; g0 += 8) {
+    const int nc = std::min(8, n_comp - g0);
+    cvx::ProjArgs a;
+    make_proj_args(cube, W, center, n_comp, g0, nc, false, a);
+    cvx::H16Args h;
+    h16_args(a, center, B, nc, limit, h);
+    static const char* kRangeName[9] = {"", "project_range_store_nc1", "project_range_store_nc2",
+                                        "project_range_store_nc3", "project_range_store_nc4",
+                                        "project_range_store_nc5", "project_range_store_nc6",
+                                        "project_range_store_nc7", "project_range_store_nc8"};
+    static const char* kStretchName[9] = {"", "project_stretch_stored_nc1", "project_stretch_stored_nc2",
+                                          "project_stretch_stored_nc3", "project_stretch_stored_nc4",
+                                          "project_stretch_stored_nc5", "project_stretch_stored_nc6",
+                                          "project_stretch_stored_nc7", "project_stretch_stored_nc8"};
+    prof_begin(ctx, s, kRangeName[nc]);
+    hipError_t e = cvx::launch_project_range_h16_u16(cube->data, B, P, nc, a, nblocks, pb.part, pb.ticket,
+                                                     pb.range_dev, pb.ab_dev + 2 * g0, h, planes, Pp, s);
+    prof_end(ctx, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "project range launch");
+    prof_begin(ctx, s, kStretchName[nc]);
+    e = cvx::launch_project_stretch_h16_u16(cube->data, B, P, nc, a, nblocks, pb.range_dev, planes, Pp,
+                                            images + (int64_t)g0 * P, s);
+    prof_end(ctx, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "project stretch launch");
+  }
+  return 0;
+}
+
 int proj_groups(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const double* center,
                 int n_comp, uint8_t* images, hipStream_t s) {
   const int nblocks = proj_nblocks(ctx, cube);
   // block partials: 16 floats (VALU kernels) or 32 (matrix-core kernels)
   if (int st = ensure(ctx, B_PROJPART, (size_t)nblocks * 32 * sizeof(float))) return st;
   const ProjBufs pb{(float*)ctx->buf[B_PROJPART], ctx->tickets, ctx->range_dev, ctx->ab_dev};
+  if (cube->dtype == CVAMX_U16 && !ctx->plain && ctx->schedule != CVAMX_SCHEDULE_TWO_READS)
+    return proj_groups_h16(ctx, cube, W, center, n_comp, images, pb, s);
   return proj_groups_with(ctx, cube, W, center, n_comp, images, pb, true, s);
 }
 
@@ -1042,19 +1109,29 @@ int cva_soft_forward(cvamx_ctx* ctx, const float* X, const float* w, int64_t N, 
     return fail(ctx, CVAMX_E_INVALID_ARG, "J, W, eigvals, mean and class_means must be non-NULL");
   if ((reinterpret_cast<uintptr_t>(X) & 15u) != 0 || (reinterpret_cast<uintptr_t>(w) & 15u) != 0)
     return fail(ctx, CVAMX_E_UNSUPPORTED, "X and w must be 16-byte aligned");
-  if (prec != CVAMX_PREC_FP32)
-    return fail(ctx, CVAMX_E_UNSUPPORTED, "soft-label CVA runs the FP32 scatter path only");
   if (int st = check_device(ctx)) return st;
   hipStream_t s = (hipStream_t)stream;
   const int BP = cvx::padded_bp(B), KP = (K + 3) & ~3;
   const int L = cvx::tri_blocks(B) * 16;
   const int64_t nch = (N + cvx::kChunk - 1) / cvx::kChunk;
   const int nb1 = (int)std::max<int64_t>(1, std::min<int64_t>(3 * ctx->num_cu, nch));
-  // pass 2: one resident round of blocks over all class groups
-  const int cpb = cvx::soft_scatter_classes_per_block(B, K);
-  const int groups = (K + cpb - 1) / cpb;
-  const int G = (int)std::max<int64_t>(
-      1, std::min<int64_t>(cvx::soft_scatter_blocks_per_cu(B, K) * ctx->num_cu / groups, nch));
+  // the scatter's path: FP32 products on the FP32 matrix instruction (the
+  // default), the plain FP32 vector-ALU reference (cvamx_set_plain_fp32),
+  // or the compensated bf16 / fp16 split on the 16-bit matrix units
+  const bool plain = prec == CVAMX_PREC_FP32 && ctx->plain;
+  const bool split = prec != CVAMX_PREC_FP32;
+  // pass 2: about one resident round of blocks over all class groups
+  int G;
+  if (plain) {
+    G = (int)std::max<int64_t>(1, std::min<int64_t>(3 * ctx->num_cu / K, nch));
+  } else if (split) {
+    const int groups = (K + cvx::kWaves - 1) / cvx::kWaves;
+    G = (int)std::max<int64_t>(1, std::min<int64_t>(2 * ctx->num_cu / groups, nch));
+  } else {
+    const int cpb = cvx::soft_scatter_classes_per_block(B, K);
+    const int groups = (K + cpb - 1) / cpb;
+    G = (int)std::max<int64_t>(1, std::min<int64_t>(cvx::soft_scatter_blocks_per_cu(B, K) * ctx->num_cu / groups, nch));
+  }
   const size_t first_bytes = 8 * (size_t)K * (B + 1);
   const size_t mcf_off = first_bytes;
   const size_t gram_off = (mcf_off + 4 * (size_t)K * B + 7) & ~size_t(7);
@@ -1067,16 +1144,27 @@ int cva_soft_forward(cvamx_ctx* ctx, const float* X, const float* w, int64_t N, 
   if (int st = ensure_pinned(ctx, res_bytes)) return st;
   char* res = static_cast<char*>(ctx->buf[B_RES]);
   char* f1 = static_cast<char*>(ctx->buf[B_FIRST]);
-  prof_begin(ctx, s, "soft_first");
-  hipError_t e = cvx::launch_soft_first(X, w, N, B, K, nb1, (double*)f1, s);
+  prof_begin(ctx, s, plain ? "soft_first_plain" : "soft_first");
+  hipError_t e = plain ? cvx::launch_soft_first_plain(X, w, N, B, K, nb1, (double*)f1, s)
+                       : cvx::launch_soft_first(X, w, N, B, K, nb1, (double*)f1, s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "soft first launch");
   e = cvx::launch_reduce_part((const double*)f1, 1, nb1, KP * BP, (double*)(f1 + fp_off), s);
   if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
   e = cvx::launch_soft_means(B, K, (const double*)(f1 + fp_off), (double*)res, (float*)(res + mcf_off), s);
   if (e != hipSuccess) return hip_fail(ctx, e, "class means launch");
-  prof_begin(ctx, s, "soft_scatter");
-  e = cvx::launch_soft_scatter(X, w, N, B, K, G, (const float*)(res + mcf_off), (double*)ctx->buf[B_PART], s);
+  const float* mcf_d = (const float*)(res + mcf_off);
+  double* part = (double*)ctx->buf[B_PART];
+  if (plain) {
+    prof_begin(ctx, s, "soft_scatter_plain");
+    e = cvx::launch_soft_scatter_plain(X, w, N, B, K, G, mcf_d, part, s);
+  } else if (split) {
+    prof_begin(ctx, s, "soft_scatter_split");
+    e = cvx::launch_soft_scatter_split(prec == CVAMX_PREC_F16X3 ? 1 : 0, X, w, N, B, K, G, mcf_d, part, s);
+  } else {
+    prof_begin(ctx, s, "soft_scatter");
+    e = cvx::launch_soft_scatter(X, w, N, B, K, G, mcf_d, part, s);
+  }
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "soft scatter launch");
   prof_begin(ctx, s, "reduce_partials");
@@ -1155,9 +1243,50 @@ int cva_soft_backward(cvamx_ctx* ctx, const float* X, const double* W, const dou
   return CVAMX_OK;
 }
 
+int cva_soft_update(cvamx_ctx* ctx, const float* grad, float* w, int64_t N, int32_t K, double step, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (!grad || !w) return fail(ctx, CVAMX_E_INVALID_ARG, "grad and w must be non-NULL");
+  if (N < 1 || N >= (int64_t(1) << 31)) return fail(ctx, CVAMX_E_INVALID_ARG, "N must lie in 1..2^31-1");
+  if (K < 2 || K > 32) return fail(ctx, CVAMX_E_INVALID_ARG, "soft-label CVA supports K in 2..32");
+  if (!finite_nonneg(step)) return fail(ctx, CVAMX_E_INVALID_ARG, "step must be finite and >= 0");
+  if ((reinterpret_cast<uintptr_t>(grad) & 3u) != 0 || (reinterpret_cast<uintptr_t>(w) & 3u) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "grad and w must be 4-byte aligned");
+  if (int st = check_device(ctx)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  prof_begin(ctx, s, "soft_update");
+  hipError_t e = cvx::launch_soft_update(grad, w, N, K, (float)step, ctx->num_cu, s);
+  prof_end(ctx, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "soft update launch");
+  return CVAMX_OK;
+}
+
 int cvamx_set_plain_fp32(cvamx_ctx* ctx, int enable) {
   if (!ctx) return CVAMX_E_INVALID_ARG;
   ctx->plain = enable != 0;
+  return CVAMX_OK;
+}
+
+int cvamx_stream_read(cvamx_ctx* ctx, const void* src, int64_t bytes, uint32_t* sink, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (!src || !sink) return fail(ctx, CVAMX_E_INVALID_ARG, "src and sink must be non-NULL");
+  if (bytes < 16 || bytes % 16 != 0) return fail(ctx, CVAMX_E_INVALID_ARG, "bytes must be a positive multiple of 16");
+  if ((reinterpret_cast<uintptr_t>(src) & 15u) != 0 || (reinterpret_cast<uintptr_t>(sink) & 3u) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "src must be 16-byte aligned and sink 4-byte aligned");
+  if (int st = check_device(ctx)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  prof_begin(ctx, s, "stream_read");
+  hipError_t e = cvx::launch_stream_read(src, bytes, 0x9e3779b9u, sink, ctx->num_cu, s);
+  prof_end(ctx, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "stream read launch");
+  return CVAMX_OK;
+}
+
+int cvamx_set_schedule(cvamx_ctx* ctx, int schedule) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (schedule != CVAMX_SCHEDULE_AUTO && schedule != CVAMX_SCHEDULE_TWO_READS &&
+      schedule != CVAMX_SCHEDULE_FORCE_REREAD)
+    return fail(ctx, CVAMX_E_INVALID_ARG, "unknown projection schedule");
+  ctx->schedule = schedule;
   return CVAMX_OK;
 }
 

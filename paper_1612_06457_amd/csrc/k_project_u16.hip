@@ -231,16 +231,45 @@ __device__ __forceinline__ void run_tiles(const void* __restrict__ cube, int B, 
   });
 }
 
-template <int NKB, int G2>
+// Four consecutive pixels of this lane's component plane from the tile's
+// row block rb: for two-pixel rows the partner lane l ^ 8 holds the other
+// pixel of each row, and the two lanes swap halves; *px receives the first
+// pixel's index.
+template <int G2>
+__device__ __forceinline__ f32x4 four_pixels(const f32x4& acc, int g, int p, int rb, int64_t pb, int64_t* px) {
+  if constexpr (G2 == 2) {
+    const float s0 = p == 0 ? acc[2] : acc[0];
+    const float s1 = p == 0 ? acc[3] : acc[1];
+    const float r0 = __shfl_xor(s0, 8, 64), r1 = __shfl_xor(s1, 8, 64);
+    *px = pb + 2 * (16 * rb + 4 * g) + 4 * p;
+    return p == 0 ? f32x4{acc[0], r0, acc[1], r1} : f32x4{r0, acc[2], r1, acc[3]};
+  } else {
+    *px = pb + 16 * rb + 4 * g;
+    return acc;
+  }
+}
+
+// Pass 1.  With H16 it also stores every component value as fp16 of the
+// scaled sum times a power of two f_j (planes of Pp >= P values, Pp a
+// multiple of 256, so whole tiles are stored without a bound check), and
+// the last block derives the map of those stored values: q = floor(h s' + o)
+// with s' = s / f_j exact, and a bound on how far the stored values move
+// the argument of the floor (rounding to fp16: 2^-11 relative, 2^-25
+// absolute below fp16's normal range; FP32 rounding of the map).  If the
+// bound exceeds h.limit for some component, or a stored value could have
+// overflowed, the flag in range_dev[32] tells pass 2 to re-read the page.
+template <int NKB, int G2, bool H16>
 __global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_range_u16(const void* __restrict__ cube, int B, int64_t P, int nc,
                                                       ProjArgs a, float* __restrict__ part,
                                                       unsigned* __restrict__ ticket, float* __restrict__ range_dev,
-                                                      float* __restrict__ ab_dev) {
+                                                      float* __restrict__ ab_dev, H16Args h,
+                                                      _Float16* __restrict__ planes, int64_t Pp) {
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ float wred[kWaves][16];
   __shared__ bool am_last;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int g = lane >> 4, p = (lane & 15) >> 3;
+  const int g = lane >> 4, p = (lane & 15) >> 3, jc = lane & 7;
+  const bool live = p < G2 && jc < nc;
   constexpr int RB = row_blocks<NKB>();
   ProjArgs& sa = *reinterpret_cast<ProjArgs*>(lds);   // set-up only: the tiles reuse it
   stage_args(a, sa);
@@ -248,9 +277,21 @@ __global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_range_u16(const vo
   const float acc0 = build_ops<NKB, G2>(sa, B, nc, tab);
   const float inv = 1.f / sa.scale[threadIdx.x & 7];   // a power of two: exact
   __syncthreads();
+  const float hf = H16 ? h.f[jc] : 0.f;
+  _Float16* plane = planes + (int64_t)(live ? jc : 0) * Pp;
   float mn = __builtin_inff(), mx = -__builtin_inff();
   run_tiles<NKB, G2>(cube, B, P, tab, acc0, lds, [&](int64_t t, const f32x4 (&acc)[RB]) {
     const int64_t pb = t * 16 * RB * G2;
+    if constexpr (H16) {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        int64_t px;
+        const f32x4 v = four_pixels<G2>(acc[rb], g, p, rb, pb, &px);
+        const uint32_t lo = h16((_Float16)(v[0] * hf)) | (h16((_Float16)(v[1] * hf)) << 16);
+        const uint32_t hi = h16((_Float16)(v[2] * hf)) | (h16((_Float16)(v[3] * hf)) << 16);
+        if (live) *reinterpret_cast<u32x2*>(plane + px) = u32x2{lo, hi};
+      }
+    }
     if (pb + 16 * RB * G2 <= P) {   // whole tile: every row is a pixel
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
@@ -337,6 +378,28 @@ __global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_range_u16(const vo
     range_dev[8 + jj] = o;
     ab_dev[2 * jj] = l2 * inv;
     ab_dev[2 * jj + 1] = h2 * inv;
+    if constexpr (H16) {
+      const float f = h.f[jj];
+      range_dev[16 + jj] = s / f;   // f a power of two: exact
+      range_dev[24 + jj] = o;
+      const float M = fmaxf(fabsf(l2), fabsf(h2));
+      float bound = 0.f;
+      bool bad = !(M * f < 32768.f);   // stored values stay far below fp16's largest, 65504
+      if (h2 > l2) {
+        bound = s * (M * (0x1p-11f + 0x1p-22f) + 0x1p-25f / f) + 0x1p-22f * (s * M + 1.f);
+        bad = bad || !(bound <= h.limit);
+      }
+      range_dev[40 + jj] = bound;
+      wred[0][jj] = bad ? 1.f : 0.f;
+    }
+  }
+  if constexpr (H16) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned flag = 0u;
+      for (int jj = 0; jj < nc; ++jj) flag |= wred[0][jj] != 0.f ? 1u : 0u;
+      reinterpret_cast<unsigned*>(range_dev)[32] = flag;
+    }
   }
   if (threadIdx.x == 0) *ticket = 0u;
 }
@@ -347,15 +410,14 @@ __device__ __forceinline__ uint32_t quant(float y, float s, float o) {
   return (uint32_t)t;
 }
 
-// Pass 2: the quantised bytes of a wave tile are gathered per component
-// plane in LDS (8 planes x the tile's pixels, in the wave's own tile slice)
-// and written as 16-byte chunks, so each plane receives whole segments.
+// Pass 2 from the page: the quantised bytes of a wave tile are gathered per
+// component plane in LDS (8 planes x the tile's pixels, in the wave's own
+// tile slice) and written as 16-byte chunks, so each plane receives whole
+// segments.
 template <int NKB, int G2>
-__global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_stretch_u16(const void* __restrict__ cube, int B,
-                                                                        int64_t P, int nc, ProjArgs a,
-                                                                        const float* __restrict__ range_dev,
-                                                                        uint8_t* __restrict__ images) {
-  extern __shared__ __align__(16) uint32_t lds[];
+__device__ __forceinline__ void stretch_page(const void* __restrict__ cube, int B, int64_t P, int nc,
+                                             const ProjArgs& a, const float* __restrict__ range_dev,
+                                             uint8_t* __restrict__ images, uint32_t* __restrict__ lds) {
   constexpr int RB = row_blocks<NKB>();
   constexpr int TP = 16 * RB * G2;   // pixels per wave tile
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -407,6 +469,83 @@ __global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_stretch_u16(const 
       }
     }
   });
+}
+
+template <int NKB, int G2>
+__global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_stretch_u16(const void* __restrict__ cube, int B,
+                                                                        int64_t P, int nc, ProjArgs a,
+                                                                        const float* __restrict__ range_dev,
+                                                                        uint8_t* __restrict__ images) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  stretch_page<NKB, G2>(cube, B, P, nc, a, range_dev, images, lds);
+}
+
+// Quantises the 16 stored values of one chunk (two 16-byte words) with the
+// map of the stored values and writes them at pixel px of the plane dst
+// (one 16-byte store when the plane rows allow, else byte by byte up to P).
+__device__ __forceinline__ void quant_chunk(const u32x4& v0, const u32x4& v1, float s, float o, int64_t px,
+                                            int64_t P, bool aligned, uint8_t* __restrict__ dst) {
+  if (px >= P) return;
+  // value 2 m + h of the chunk is half h of word m
+  const uint32_t wd[8] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+  uint32_t qb[16];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    qb[2 * m] = quant((float)__builtin_bit_cast(_Float16, (uint16_t)(wd[m] & 0xffffu)), s, o);
+    qb[2 * m + 1] = quant((float)__builtin_bit_cast(_Float16, (uint16_t)(wd[m] >> 16)), s, o);
+  }
+  u32x4 q;
+#pragma unroll
+  for (int d = 0; d < 4; ++d)
+    q[d] = qb[4 * d] | (qb[4 * d + 1] << 8) | (qb[4 * d + 2] << 16) | (qb[4 * d + 3] << 24);
+  if (aligned && px + 16 <= P) {
+    *reinterpret_cast<u32x4*>(dst + px) = q;
+  } else {
+    for (int e = 0; e < 16; ++e)
+      if (px + e < P) dst[px + e] = (uint8_t)(q[e >> 2] >> (8 * (e & 3)));
+  }
+}
+
+// Pass 2 from the stored fp16 planes: 16 values per lane and step, two
+// steps' loads in flight (the second index clamped to the plane's last
+// chunk, so no branch separates the loads).
+__device__ __forceinline__ void stretch_stored(const _Float16* __restrict__ planes, int64_t Pp, int64_t P, int nc,
+                                               const float* __restrict__ range_dev, uint8_t* __restrict__ images) {
+  const int64_t cpp = Pp / 16;   // chunks per plane
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  const int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool aligned = (P % 16) == 0 && (reinterpret_cast<uintptr_t>(images) % 16) == 0;
+  for (int j = 0; j < nc; ++j) {
+    const float s = range_dev[16 + j], o = range_dev[24 + j];
+    const u32x4* src = reinterpret_cast<const u32x4*>(planes + (int64_t)j * Pp);
+    uint8_t* dst = images + (int64_t)j * P;
+    for (int64_t i = t0; i < cpp; i += 2 * stride) {
+      const int64_t i1 = i + stride < cpp ? i + stride : cpp - 1;
+      const u32x4 a0 = __builtin_nontemporal_load(src + 2 * i);
+      const u32x4 a1 = __builtin_nontemporal_load(src + 2 * i + 1);
+      const u32x4 b0 = __builtin_nontemporal_load(src + 2 * i1);
+      const u32x4 b1 = __builtin_nontemporal_load(src + 2 * i1 + 1);
+      quant_chunk(a0, a1, s, o, 16 * i, P, aligned, dst);
+      if (i + stride < cpp) quant_chunk(b0, b1, s, o, 16 * i1, P, aligned, dst);
+    }
+  }
+}
+
+// Pass 2 after a pass 1 that stored fp16 planes: from the planes, unless
+// pass 1 found their error bound too large for some component (a flag
+// uniform over the grid), then from the page as k_stretch_u16.
+template <int NKB, int G2>
+__global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_stretch_h16(const void* __restrict__ cube, int B,
+                                                                        int64_t P, int nc, ProjArgs a,
+                                                                        const float* __restrict__ range_dev,
+                                                                        const _Float16* __restrict__ planes,
+                                                                        int64_t Pp, uint8_t* __restrict__ images) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  if (reinterpret_cast<const unsigned*>(range_dev)[32] != 0u) {
+    stretch_page<NKB, G2>(cube, B, P, nc, a, range_dev, images, lds);
+    return;
+  }
+  stretch_stored(planes, Pp, P, nc, range_dev, images);
 }
 
 // The FP32 component planes, scaled back by 2^-s_j (exact), so they hold
@@ -485,14 +624,15 @@ int grid(const void* kernel, size_t sm, int nblocks, int64_t P, int B, int rows)
   return (int)std::max<int64_t>(n, 1);
 }
 
-template <int NKB, int G2>
+template <int NKB, int G2, bool H16>
 hipError_t range_k(const void* cube, int B, int64_t P, int nc, const ProjArgs& a, int nblocks, float* part,
-                   unsigned* ticket, float* range_dev, float* ab_dev, hipStream_t s) {
+                   unsigned* ticket, float* range_dev, float* ab_dev, const H16Args& h, _Float16* planes,
+                   int64_t Pp, hipStream_t s) {
   const size_t sm = smem<NKB, G2>(B);
-  const void* k = reinterpret_cast<const void*>(&k_range_u16<NKB, G2>);
+  const void* k = reinterpret_cast<const void*>(&k_range_u16<NKB, G2, H16>);
   const int nb = grid(k, sm, nblocks, P, B, 16 * row_blocks<NKB>());
-  hipLaunchKernelGGL((k_range_u16<NKB, G2>), dim3(nb), dim3(kBlock), sm, s, cube, B, P, nc, a, part, ticket,
-                     range_dev, ab_dev);
+  hipLaunchKernelGGL((k_range_u16<NKB, G2, H16>), dim3(nb), dim3(kBlock), sm, s, cube, B, P, nc, a, part, ticket,
+                     range_dev, ab_dev, h, planes, Pp);
   return hipGetLastError();
 }
 
@@ -504,6 +644,18 @@ hipError_t stretch_k(const void* cube, int B, int64_t P, int nc, const ProjArgs&
   const int nb = grid(k, sm, nblocks, P, B, 16 * row_blocks<NKB>());
   hipLaunchKernelGGL((k_stretch_u16<NKB, G2>), dim3(nb), dim3(kBlock), sm, s, cube, B, P, nc, a, range_dev,
                      images);
+  return hipGetLastError();
+}
+
+template <int NKB, int G2>
+hipError_t stretch_h16_k(const void* cube, int B, int64_t P, int nc, const ProjArgs& a, int nblocks,
+                         const float* range_dev, const _Float16* planes, int64_t Pp, uint8_t* images,
+                         hipStream_t s) {
+  const size_t sm = smem<NKB, G2>(B);
+  const void* k = reinterpret_cast<const void*>(&k_stretch_h16<NKB, G2>);
+  const int nb = grid(k, sm, nblocks, P, B, 16 * row_blocks<NKB>());
+  hipLaunchKernelGGL((k_stretch_h16<NKB, G2>), dim3(nb), dim3(kBlock), sm, s, cube, B, P, nc, a, range_dev,
+                     planes, Pp, images);
   return hipGetLastError();
 }
 
@@ -542,9 +694,31 @@ hipError_t launch_project_range_u16(const void* cube, int B, int64_t P, int nc, 
                                     float* part, unsigned* ticket, float* range_dev, float* ab_dev,
                                     hipStream_t s) {
   if (B < 1 || B > kMaxB || nc < 1 || nc > 8) return hipErrorInvalidValue;
-#define CVX_R(N, G) range_k<N, G>(cube, B, P, nc, a, nblocks, part, ticket, range_dev, ab_dev, s)
+  const H16Args h{};
+#define CVX_R(N, G) range_k<N, G, false>(cube, B, P, nc, a, nblocks, part, ticket, range_dev, ab_dev, h, nullptr, 0, s)
   CVX_U16_SWITCH(CVX_R)
 #undef CVX_R
+}
+
+hipError_t launch_project_range_h16_u16(const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
+                                        int nblocks, float* part, unsigned* ticket, float* range_dev,
+                                        float* ab_dev, const H16Args& h, uint16_t* planes16, int64_t Pp,
+                                        hipStream_t s) {
+  if (B < 1 || B > kMaxB || nc < 1 || nc > 8 || Pp < P || Pp % 256 != 0) return hipErrorInvalidValue;
+  _Float16* planes = reinterpret_cast<_Float16*>(planes16);
+#define CVX_R(N, G) range_k<N, G, true>(cube, B, P, nc, a, nblocks, part, ticket, range_dev, ab_dev, h, planes, Pp, s)
+  CVX_U16_SWITCH(CVX_R)
+#undef CVX_R
+}
+
+hipError_t launch_project_stretch_h16_u16(const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
+                                          int nblocks, const float* range_dev, const uint16_t* planes16, int64_t Pp,
+                                          uint8_t* images, hipStream_t s) {
+  if (B < 1 || B > kMaxB || nc < 1 || nc > 8 || Pp < P || Pp % 256 != 0) return hipErrorInvalidValue;
+  const _Float16* planes = reinterpret_cast<const _Float16*>(planes16);
+#define CVX_S(N, G) stretch_h16_k<N, G>(cube, B, P, nc, a, nblocks, range_dev, planes, Pp, images, s)
+  CVX_U16_SWITCH(CVX_S)
+#undef CVX_S
 }
 
 hipError_t launch_project_stretch_u16(const void* cube, int B, int64_t P, int nc, const ProjArgs& a,

@@ -408,6 +408,247 @@ __global__ __launch_bounds__(kBlock, (scatter_waves<NRB, QX, T, CPW>())) void k_
   }
 }
 
+// The plain FP32 reference path of the forward passes, on the vector ALU.
+//
+// First moments: thread t owns the entries o = t, t + 256, ... of the KP x BP
+// block partial ([c][j] = sum_r w[r][c] [x_r, 1][j], zero padding) and sums
+// the chunk's rows for each in FP32, folding into FP64 after every chunk;
+// every entry has one owner, so the partial is written without a combine.
+template <int QX, int QW>
+__global__ __launch_bounds__(kBlock) void k_soft_first_valu(const float* __restrict__ X, const float* __restrict__ W,
+                                                            int64_t N, int B, int K, double* __restrict__ part) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  uint32_t* xr = lds;
+  uint32_t* wr = lds + kChunk * B;
+  const int BP = (B + 1 + 3) & ~3, KP = (K + 3) & ~3, L = KP * BP;
+  constexpr int U = 9;   // entries per thread: KP BP <= 32 x 68 < 9 x 256
+  double accd[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) accd[u] = 0.0;
+  const float* xf = reinterpret_cast<const float*>(xr);
+  const float* wf = reinterpret_cast<const float*>(wr);
+  auto body = [&](int64_t, int rows) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int o = threadIdx.x + kBlock * u;
+      const int c = o / BP, j = o - c * BP;
+      if (o >= L || c >= K || j > B) continue;
+      float acc = 0.f;
+      for (int r = 0; r < rows; ++r) {
+        const float xv = j < B ? xf[r * B + j] : 1.f;
+        acc = fmaf(wf[r * K + c], xv, acc);
+      }
+      accd[u] += (double)acc;
+    }
+  };
+  for_each_chunk<QX, QW>(X, W, N, B, K, blockIdx.x, gridDim.x, xr, wr, body);
+  double* mine = part + (int64_t)blockIdx.x * L;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int o = threadIdx.x + kBlock * u;
+    if (o < L) mine[o] = accd[u];
+  }
+}
+
+// Scatter: block (g, c) takes chunks g, g + G, ... of X and w for class c
+// (the training pixels are read once per class), and thread (slice, tile)
+// owns a 4 x 4 tile of the weighted augmented Gram of d = [x - m_c, 1]:
+// sum over its rows of (w d_I) d_J in FP32, with d formed from the staged
+// raw rows, folded into FP64 after every chunk; the slices combine in a
+// fixed order into the packed block partial.
+template <int QX, int QW>
+__global__ __launch_bounds__(kBlock) void k_soft_scatter_valu(const float* __restrict__ X,
+                                                              const float* __restrict__ W, int64_t N, int B, int K,
+                                                              const float* __restrict__ mc_f,
+                                                              double* __restrict__ part) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  uint32_t* xr = lds;
+  uint32_t* wr = lds + kChunk * B;
+  double* red = reinterpret_cast<double*>(lds);
+  const int G = gridDim.x, g = blockIdx.x, c = blockIdx.y;
+  const int BP = (B + 1 + 3) & ~3;
+  const TileAssign ta = assign_tiles(BP);
+  // this thread's eight columns: value = x - m (band < B), 1 (band B), 0
+  float mi[4], mj[4];
+  int ki[4], kj[4];   // 0: band, 1: the ones column, 2: padding
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int I = 4 * ta.bi + e, J = 4 * ta.bj + e;
+    ki[e] = I < B ? 0 : (I == B ? 1 : 2);
+    kj[e] = J < B ? 0 : (J == B ? 1 : 2);
+    mi[e] = I < B ? mc_f[c * B + I] : 0.f;
+    mj[e] = J < B ? mc_f[c * B + J] : 0.f;
+  }
+  float acc[16];
+  double accd[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    acc[e] = 0.f;
+    accd[e] = 0.0;
+  }
+  const float* xf = reinterpret_cast<const float*>(xr);
+  const float* wf = reinterpret_cast<const float*>(wr);
+  auto body = [&](int64_t, int rows) {
+    if (ta.active) {
+      for (int r = ta.slice; r < rows; r += ta.nslice) {
+        const float wv = wf[r * K + c];
+        float a[4], b[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float xi = ki[e] == 0 ? xf[r * B + 4 * ta.bi + e] - mi[e] : (ki[e] == 1 ? 1.f : 0.f);
+          const float xj = kj[e] == 0 ? xf[r * B + 4 * ta.bj + e] - mj[e] : (kj[e] == 1 ? 1.f : 0.f);
+          a[e] = wv * xi;
+          b[e] = xj;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[4 * i + j] = fmaf(a[i], b[j], acc[4 * i + j]);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      accd[e] += (double)acc[e];
+      acc[e] = 0.f;
+    }
+  };
+  for_each_chunk<QX, QW>(X, W, N, B, K, g, G, xr, wr, body);
+  write_partial(ta, accd, red, part + ((int64_t)c * G + g) * ta.nblk * 16);
+}
+
+// The mixed-precision scatter: per class (one per wave, four per block) the
+// same weighted Gram, sum_p a_p d_p^T with a = w d and d = [x - m_c, 1], on
+// v_mfma_f32_16x16x32_{bf16,f16} with the compensated split: a = a_h + a_l,
+// d = d_h + d_l (each the nearest 16-bit value to what is left), and every
+// tile pair sums a_h d_h + a_h d_l + a_l d_h + a_l d_l over 32 rows per
+// instruction with FP32 accumulation, folded into FP64 after every chunk of
+// 128 rows.  All B + 1 columns run on the matrix cores (NRB row blocks of
+// 16).  Per entry the error is at most (2 u^2 + 512 2^-24) sum_p |w_p|
+// |d_pi| |d_pj| (u = 2^-8 for bf16, 2^-11 for fp16; 512 FP32 terms per
+// fold), plus, for values whose tail falls below fp16's normal range, at
+// most 2^-40 of the chunk's largest product per term.
+// Operand layout as in k_split.hpp: lane l holds row k0 + 8 (l / 16) + t,
+// band 16 rb + l % 16 of both operands.
+template <int SPLIT, int NRB, int QX, int QW>
+__global__ __launch_bounds__(kBlock) void k_soft_scatter_split(const float* __restrict__ X,
+                                                               const float* __restrict__ W, int64_t N, int B,
+                                                               int K, const float* __restrict__ mc_f,
+                                                               double* __restrict__ part) {
+  using ST = SplitT<SPLIT>;
+  using V = typename ST::V;
+  using S = typename ST::S;
+  extern __shared__ __align__(16) uint32_t lds[];
+  uint32_t* xr = lds;
+  uint32_t* wr = lds + kChunk * B;
+  const int G = gridDim.x, g = blockIdx.x;
+  const int v = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, grp = lane >> 4;
+  const int cls = blockIdx.y * kWaves + v;
+  const bool live = cls < K;
+  float mrb[NRB];
+  int kind[NRB];   // 0: band, 1: the ones column, 2: padding
+#pragma unroll
+  for (int rb = 0; rb < NRB; ++rb) {
+    const int band = 16 * rb + col;
+    kind[rb] = band < B ? 0 : (band == B ? 1 : 2);
+    mrb[rb] = (live && band < B) ? mc_f[cls * B + band] : 0.f;
+  }
+  constexpr int NP = npairs(NRB);
+  f32x4 acc[NP];
+  double accd[NP][4];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      acc[p][e] = 0.f;
+      accd[p][e] = 0.0;
+    }
+  const float* xf = reinterpret_cast<const float*>(xr);
+  const float* wf = reinterpret_cast<const float*>(wr);
+  auto dval = [&](int r, int rb) {
+    return kind[rb] == 0 ? xf[r * B + 16 * rb + col] - mrb[rb] : (kind[rb] == 1 ? 1.f : 0.f);
+  };
+  auto body = [&](int64_t, int) {
+    if (!live) return;
+    // a power of two per operand and chunk brings the chunk's largest |d|
+    // and |w d| into [2^14, 2^15): the split values stay inside fp16's
+    // range, far above its subnormals; the tiles are unscaled exactly when
+    // they fold into FP64
+    float md = 0.f, ma = 0.f;
+    for (int r = grp; r < kChunk; r += 4) {
+      const float wv = fabsf(wf[r * K + cls]);
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb) {
+        const float d = fabsf(dval(r, rb));
+        md = fmaxf(md, d);
+        ma = fmaxf(ma, wv * d);
+      }
+    }
+    md = wave_max(md);
+    ma = wave_max(ma);
+    int ed = 0, ea = 0;
+    if (md > 0.f) frexpf(md, &ed);
+    if (ma > 0.f) frexpf(ma, &ea);
+    const float sd = md > 0.f ? ldexpf(1.f, 15 - ed) : 1.f;
+    const float sa = ma > 0.f ? ldexpf(1.f, 15 - ea) : 1.f;
+    for (int k0 = 0; k0 < kChunk; k0 += 32) {
+      V ah[NRB], al[NRB], dh[NRB], dl[NRB];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int r = k0 + 8 * grp + t;
+        const float wv = wf[r * K + cls];
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb) {
+          const float d0 = dval(r, rb);
+          const float a = (wv * d0) * sa;
+          const float d = d0 * sd;
+          const S h1 = (S)a, h2 = (S)d;
+          ah[rb][t] = h1;
+          al[rb][t] = (S)(a - (float)h1);
+          dh[rb][t] = h2;
+          dl[rb][t] = (S)(d - (float)h2);
+        }
+      }
+      int p = 0;
+#pragma unroll
+      for (int ri = 0; ri < NRB; ++ri)
+#pragma unroll
+        for (int rj = ri; rj < NRB; ++rj, ++p) {
+          acc[p] = ST::mma(al[ri], dl[rj], acc[p]);   // smallest terms first
+          acc[p] = ST::mma(ah[ri], dl[rj], acc[p]);
+          acc[p] = ST::mma(al[ri], dh[rj], acc[p]);
+          acc[p] = ST::mma(ah[ri], dh[rj], acc[p]);
+        }
+    }
+    const double inv = 1.0 / ((double)sa * (double)sd);   // powers of two: exact
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        accd[p][e] += (double)acc[p][e] * inv;
+        acc[p][e] = 0.f;
+      }
+  };
+  for_each_chunk<QX, QW>(X, W, N, B, K, g, G, xr, wr, body);
+  if (!live) return;
+  const int BP = (B + 1 + 3) & ~3, nb = BP / 4, L = nb * (nb + 1) / 2 * 16;
+  double* out = part + ((int64_t)cls * G + g) * L;
+  int p = 0;
+#pragma unroll
+  for (int ri = 0; ri < NRB; ++ri)
+#pragma unroll
+    for (int rj = ri; rj < NRB; ++rj, ++p)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int I = 16 * ri + 4 * grp + e, J = 16 * rj + col;
+        // every packed entry (4 x 4 tiles bi <= bj of the padded matrix) once
+        if ((I >> 2) <= (J >> 2) && I < BP && J < BP) {
+          const int bi = I >> 2, bj = J >> 2;
+          out[(bi * nb - bi * (bi - 1) / 2 + (bj - bi)) * 16 + (I & 3) * 4 + (J & 3)] = accd[p][e];
+        }
+      }
+}
+
 __global__ __launch_bounds__(kBlock) void k_soft_backward(const float* __restrict__ X, int64_t N, int B,
                                                           int K, SoftBwdArgs a, int accumulate,
                                                           float* __restrict__ dw) {
@@ -445,6 +686,62 @@ __global__ __launch_bounds__(kBlock) void k_soft_backward(const float* __restric
       }
     }
   });
+}
+
+// One step of mask refinement by the gradient of J (paper Section 4 calls
+// for an automatic choice of training points; the step itself is not in the
+// paper): per pixel, the gradient minus its mean over the classes (its part
+// within the plane of the simplex), scaled so that its largest entry is
+// `step`, is added to the weights, and the sum is projected onto the
+// probability simplex, w = max(v - theta, 0) with theta making the entries
+// sum to one.  theta comes from Michelot's active-set iteration: start with
+// every class, set theta = (sum of the active v - 1) / (their number), drop
+// the classes with v <= theta, repeat until none drops (at most K rounds;
+// exact).  A pixel whose gradient is the same for every class keeps its
+// weights, projected.
+__global__ __launch_bounds__(kBlock) void k_soft_update(const float* __restrict__ g, float* __restrict__ w,
+                                                        int64_t N, int K, float step) {
+  constexpr int KM = 32;
+  for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < N; p += (int64_t)gridDim.x * kBlock) {
+    float gv[KM], v[KM];
+    float mean = 0.f;
+#pragma unroll
+    for (int c = 0; c < KM; ++c) {
+      gv[c] = c < K ? g[p * K + c] : 0.f;
+      v[c] = c < K ? w[p * K + c] : 0.f;
+      mean += gv[c];
+    }
+    mean /= (float)K;
+    float smax = 0.f;
+#pragma unroll
+    for (int c = 0; c < KM; ++c)
+      if (c < K) smax = fmaxf(smax, fabsf(gv[c] - mean));
+    const float sc = smax > 0.f ? step / smax : 0.f;
+#pragma unroll
+    for (int c = 0; c < KM; ++c) v[c] = fmaf(gv[c] - mean, sc, v[c]);
+    uint32_t active = K >= 32 ? 0xffffffffu : ((1u << K) - 1u);
+    float theta = 0.f;
+    for (int it = 0; it <= K; ++it) {
+      float sum = 0.f;
+      int cnt = 0;
+#pragma unroll
+      for (int c = 0; c < KM; ++c)
+        if ((active >> c) & 1u) {
+          sum += v[c];
+          ++cnt;
+        }
+      theta = (sum - 1.f) / (float)cnt;
+      uint32_t next = 0u;
+#pragma unroll
+      for (int c = 0; c < KM; ++c)
+        if (((active >> c) & 1u) && v[c] > theta) next |= 1u << c;
+      if (next == active || next == 0u) break;
+      active = next;
+    }
+#pragma unroll
+    for (int c = 0; c < KM; ++c)
+      if (c < K) w[p * K + c] = fmaxf(v[c] - theta, 0.f);
+  }
 }
 
 // LDS of the forward kernels: the raw chunk tiles, or the first pass's
@@ -535,6 +832,68 @@ hipError_t launch_soft_scatter(const float* X, const float* w, int64_t N, int B,
     case 3: return scatter_nrb<3, 0>(X, w, N, B, K, G, mc_f, part, s);
     default: return scatter_nrb<5, 0>(X, w, N, B, K, G, mc_f, part, s);
   }
+}
+
+hipError_t launch_soft_first_plain(const float* X, const float* w, int64_t N, int B, int K, int nblocks,
+                                   double* part, hipStream_t s) {
+  if (B < 1 || B > kMaxB || K < 1 || K > 32 || nblocks < 1) return hipErrorInvalidValue;
+  const size_t sm = scatter_smem(B, K);
+  if (B <= 40 && K <= 8)
+    hipLaunchKernelGGL((k_soft_first_valu<5, 1>), dim3(nblocks), dim3(kBlock), sm, s, X, w, N, B, K, part);
+  else
+    hipLaunchKernelGGL((k_soft_first_valu<8, 4>), dim3(nblocks), dim3(kBlock), sm, s, X, w, N, B, K, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_soft_scatter_plain(const float* X, const float* w, int64_t N, int B, int K, int G,
+                                     const float* mc_f, double* part, hipStream_t s) {
+  if (B < 1 || B > kMaxB || K < 1 || K > 32 || G < 1) return hipErrorInvalidValue;
+  const int BP = padded_bp(B), nb = BP / 4, nblk = nb * (nb + 1) / 2;
+  const size_t red = (size_t)(kBlock / nblk) * nblk * 16 * sizeof(double);
+  const size_t sm = std::max(scatter_smem(B, K), red);
+  const dim3 grid(G, K);
+  if (B <= 40 && K <= 8)
+    hipLaunchKernelGGL((k_soft_scatter_valu<5, 1>), grid, dim3(kBlock), sm, s, X, w, N, B, K, mc_f, part);
+  else
+    hipLaunchKernelGGL((k_soft_scatter_valu<8, 4>), grid, dim3(kBlock), sm, s, X, w, N, B, K, mc_f, part);
+  return hipGetLastError();
+}
+
+template <int SPLIT, int NRB>
+hipError_t split_scatter_nrb(const float* X, const float* w, int64_t N, int B, int K, int G, const float* mc_f,
+                             double* part, hipStream_t s) {
+  const dim3 grid(G, (K + kWaves - 1) / kWaves);
+  const size_t sm = scatter_smem(B, K);
+  if (B <= 40 && K <= 8)
+    hipLaunchKernelGGL((k_soft_scatter_split<SPLIT, NRB, 5, 1>), grid, dim3(kBlock), sm, s, X, w, N, B, K, mc_f,
+                       part);
+  else
+    hipLaunchKernelGGL((k_soft_scatter_split<SPLIT, NRB, 8, 4>), grid, dim3(kBlock), sm, s, X, w, N, B, K, mc_f,
+                       part);
+  return hipGetLastError();
+}
+
+hipError_t launch_soft_scatter_split(int split, const float* X, const float* w, int64_t N, int B, int K, int G,
+                                     const float* mc_f, double* part, hipStream_t s) {
+  if (B < 1 || B > kMaxB || K < 1 || K > 32 || G < 1) return hipErrorInvalidValue;
+  const int nrb = nrb_for(B);
+#define CVX_S(SP)                                                                                 \
+  switch (nrb) {                                                                                  \
+    case 2: return split_scatter_nrb<SP, 2>(X, w, N, B, K, G, mc_f, part, s);                     \
+    case 3: return split_scatter_nrb<SP, 3>(X, w, N, B, K, G, mc_f, part, s);                     \
+    default: return split_scatter_nrb<SP, 5>(X, w, N, B, K, G, mc_f, part, s);                    \
+  }
+  if (split == 0) { CVX_S(0) }
+  CVX_S(1)
+#undef CVX_S
+}
+
+hipError_t launch_soft_update(const float* g, float* w, int64_t N, int K, float step, int num_cu, hipStream_t s) {
+  if (K < 2 || K > 32 || N < 1) return hipErrorInvalidValue;
+  const int64_t need = (N + kBlock - 1) / kBlock;
+  const int nb = (int)std::min<int64_t>(need, (int64_t)num_cu * 8);
+  hipLaunchKernelGGL(k_soft_update, dim3(nb), dim3(kBlock), 0, s, g, w, N, K, step);
+  return hipGetLastError();
 }
 
 hipError_t launch_soft_backward(const float* X, int64_t N, int B, int K, const SoftBwdArgs& a,

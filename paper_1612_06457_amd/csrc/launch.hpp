@@ -20,6 +20,16 @@ struct ProjArgs {
   float scale[8];    // power of two per component (uint16 matrix-core kernels)
 };
 
+// The fp16 intermediate of the one-read projection schedule: pass 1 stores
+// each component value as fp16 of (scaled sum x f[j]), f[j] a power of two
+// chosen on the host so that no stored value can overflow; pass 2 re-reads
+// the page instead of the stored values when its computed error bound (in
+// grey levels) exceeds `limit`.
+struct H16Args {
+  float f[8];
+  float limit;
+};
+
 struct SoftBwdArgs {
   float w[64 * 8];   // W[b * 8 + j] for this group of 8 components (zero padded)
   float m[64];       // grand mean
@@ -99,6 +109,19 @@ hipError_t launch_project_stretch_u16(const void* cube, int B, int64_t P, int nc
 hipError_t launch_project_float_u16(const void* cube, int B, int64_t P, int nc, const ProjArgs& a, int nblocks,
                                     float* y, hipStream_t s);
 
+// the one-read schedule on uint16 pages: pass 1 as launch_project_range_u16
+// and also the fp16 planes (nc planes of Pp >= P values, Pp a multiple of
+// 256; range_dev[16..32) the map of the stored values, range_dev[32] the
+// fallback flag, range_dev[40..48) the error bounds); pass 2 quantises the
+// planes, or re-reads the page when the flag is set
+hipError_t launch_project_range_h16_u16(const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
+                                        int nblocks, float* part, unsigned* ticket, float* range_dev,
+                                        float* ab_dev, const H16Args& h, uint16_t* planes, int64_t Pp,
+                                        hipStream_t s);
+hipError_t launch_project_stretch_h16_u16(const void* cube, int B, int64_t P, int nc, const ProjArgs& a,
+                                          int nblocks, const float* range_dev, const uint16_t* planes, int64_t Pp,
+                                          uint8_t* images, hipStream_t s);
+
 // rescaling from FP32 component planes y (nc planes of P floats, nc <= 64)
 constexpr int kSelTargets = 4;   // order statistics wanted per plane by one select
 constexpr int kSelPasses = 3;    // radix passes of 11, 11 and 10 bits over the 32-bit keys
@@ -158,6 +181,10 @@ hipError_t scratch_setup(int device);
 // that address, or nullptr before scratch_setup succeeded on `device`
 void* scratch_address(int device);
 
+// the reference read stream: bytes (a multiple of 16) from src, once
+hipError_t launch_stream_read(const void* src, int64_t bytes, uint32_t key, uint32_t* sink, int num_cu,
+                              hipStream_t s);
+
 // n bytes from device memory to page-locked host memory, by a kernel
 hipError_t launch_copy_out(void* dst, const void* src, int64_t n, hipStream_t s);
 
@@ -174,6 +201,18 @@ int soft_scatter_classes_per_block(int B, int K);
 int soft_scatter_blocks_per_cu(int B, int K);
 hipError_t launch_soft_scatter(const float* X, const float* w, int64_t N, int B, int K, int G,
                                const float* mc_f, double* part, hipStream_t s);
+// the plain FP32 reference path of the two forward passes (vector ALU;
+// same outputs and layouts), and the split scatter on the bf16 (split 0) or
+// fp16 (split 1) matrix units
+hipError_t launch_soft_first_plain(const float* X, const float* w, int64_t N, int B, int K, int nblocks,
+                                   double* part, hipStream_t s);
+hipError_t launch_soft_scatter_plain(const float* X, const float* w, int64_t N, int B, int K, int G,
+                                     const float* mc_f, double* part, hipStream_t s);
+hipError_t launch_soft_scatter_split(int split, const float* X, const float* w, int64_t N, int B, int K, int G,
+                                     const float* mc_f, double* part, hipStream_t s);
+// one refinement step of the weights w (N x K) along the gradient g:
+// mean-free, scaled to `step` at its largest entry, projected onto the simplex
+hipError_t launch_soft_update(const float* g, float* w, int64_t N, int K, float step, int num_cu, hipStream_t s);
 hipError_t launch_soft_backward(const float* X, int64_t N, int B, int K, const SoftBwdArgs& a,
                                 bool accumulate, int nblocks, float* dw, hipStream_t s);
 

@@ -134,7 +134,7 @@ def test_kernel_timing_modes(dev):
         cx.profile_enable(False)
     C = c.K - 1
     for name in ("label_count", "label_scan", "label_index", "class_moments_mfma", "reduce_partials",
-                 f"project_range_nc{C}", f"project_stretch_nc{C}"):
+                 f"project_range_store_nc{C}", f"project_stretch_stored_nc{C}"):
         assert rep.get(name, (0, 0.0))[0] == 1, (name, rep)
         assert rep[name][1] > 0.0
     cx.profile_enable("projection")
@@ -144,5 +144,16 @@ def test_kernel_timing_modes(dev):
         rep = cx.profile_report()
     finally:
         cx.profile_enable(False)
+    assert sorted(rep) == sorted([f"project_range_store_nc{C}", f"project_stretch_stored_nc{C}"]), rep
+    assert all(v[0] == 2 for v in rep.values()), rep
+    # the two-read schedule's passes
+    cx.set_schedule("two_reads")
+    cx.profile_enable("projection")
+    try:
+        cx.cva_fit_project(tc, tl, c.K)
+        rep = cx.profile_report()
+    finally:
+        cx.profile_enable(False)
+        cx.set_schedule("auto")
     assert sorted(rep) == sorted([f"project_range_nc{C}", f"project_stretch_nc{C}"]), rep
-    assert all(v[0] == 2 for v in rep.values())
+    assert all(v[0] == 1 for v in rep.values()), rep

@@ -168,3 +168,71 @@ def test_soft_weights_generator_shapes():
     assert np.allclose(w.sum(1), 1.0, atol=1e-5)
     assert (w >= 0).all()
     assert ((w.max(1) < 1).sum()) > 0          # some pixels lie near a border
+
+
+# ------------------------------------------------ mask refinement step
+
+def _kkt_ok(v, w, tol=1e-12):
+    """w is the Euclidean projection of v onto the simplex iff w >= 0,
+    sum w = 1, and for some theta: v_c - w_c = theta where w_c > 0 and
+    v_c <= theta where w_c = 0 (the optimality conditions)."""
+    if np.any(w < 0) or abs(w.sum() - 1.0) > tol:
+        return False
+    sup = w > 0
+    theta = np.mean(v[sup] - w[sup])
+    return bool(np.all(np.abs(v[sup] - w[sup] - theta) <= tol) and np.all(v[~sup] <= theta + tol))
+
+
+def test_simplex_projection_optimality_conditions():
+    rng = np.random.default_rng(40)
+    for K in (2, 3, 5, 8, 32):
+        V = rng.normal(0, 2, (200, K))
+        W = oracle.simplex_projection(V)
+        for v, w in zip(V, W):
+            assert _kkt_ok(v, w)
+
+
+def test_simplex_projection_fixes_simplex_points():
+    rng = np.random.default_rng(41)
+    W0 = rng.dirichlet(np.full(6, 0.7), 100)
+    W0[:10] = np.eye(6)[rng.integers(0, 6, 10)]
+    assert np.allclose(oracle.simplex_projection(W0), W0, atol=1e-15)
+
+
+def test_simplex_projection_brute_force_small_k():
+    rng = np.random.default_rng(42)
+    # K = 2: the segment w = (t, 1 - t), t in [0, 1]; K = 3: a fine triangle grid
+    t = np.linspace(0, 1, 20001)
+    seg = np.stack([t, 1 - t], 1)
+    a, b = np.meshgrid(np.linspace(0, 1, 401), np.linspace(0, 1, 401))
+    tri = np.stack([a.ravel(), b.ravel(), 1 - a.ravel() - b.ravel()], 1)
+    tri = tri[tri[:, 2] >= -1e-12]
+    for grid in (seg, tri):
+        K = grid.shape[1]
+        for _ in range(20):
+            v = rng.normal(0, 1.5, K)
+            best = grid[np.argmin(((grid - v) ** 2).sum(1))]
+            w = oracle.simplex_projection(v[None, :])[0]
+            assert np.max(np.abs(w - best)) <= 2.0 / (len(t) - 1 if K == 2 else 400)
+            assert ((w - v) ** 2).sum() <= ((best - v) ** 2).sum() + 1e-12
+
+
+def test_refinement_step_moves_mislabelled_pixels_only():
+    """Two well separated classes: a pixel drawn from class 0 but labelled
+    1 moves towards class 0; correctly labelled one-hot pixels stay put."""
+    rng = np.random.default_rng(43)
+    N, B = 400, 3
+    cls = np.arange(N) % 2
+    X = np.where(cls[:, None] == 0, 0.0, 10.0) + rng.normal(0, 1, (N, B))
+    lab = cls.copy()
+    lab[:20:2] = 1                              # ten class-0 pixels labelled 1
+    w = np.eye(2)[lab]
+    g = oracle.soft_grad(X, w)
+    w1 = oracle.soft_update(w, g, 0.5)
+    assert np.allclose(w1.sum(1), 1.0) and (w1 >= 0).all()
+    bad = np.zeros(N, bool)
+    bad[:20:2] = True
+    assert np.all(w1[bad, 0] > 0.4)             # moved by the full step towards class 0
+    assert np.allclose(w1[~bad], w[~bad])       # the rest stay one-hot
+    # the direction lies in the simplex's plane: a zero step changes nothing
+    assert np.allclose(oracle.soft_update(w, g, 0.0), w)
