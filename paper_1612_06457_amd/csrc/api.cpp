@@ -331,18 +331,32 @@ int proj_groups_with(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, co
   return 0;
 }
 
-// Storage factors of the fp16 intermediate for one group of uint16-page
-// components: the power of two f_j that keeps the largest value the scaled
-// sum 2^s_j y_j can take on any uint16 page, |y_j| <= sum_b |W[b][j]|
-// max(|c_b|, |65535 - c_b|), at or below 2^15 (fp16's largest value is
-// 65504), with a margin for the FP32 rounding of the sum.
-void h16_args(const cvx::ProjArgs& a, const double* center, int B, int nc, float limit, cvx::H16Args& h) {
+// Storage factors of the fp16 intermediate for one group of components: the
+// power of two f_j that keeps a bound on the values the kernels store at or
+// below 2^15 (fp16's largest value is 65504), with a margin for the FP32
+// rounding of the sums.  uint16 and fp16 pages bound every value:
+// |y_j| <= sum_b |W[b][j]| max |x - c_b| over the element range; the
+// matrix-core passes of uint16 pages store 2^s_j y_j.  bf16 and float32
+// pages have no useful bound, so |x - c_b| <= 1024 (|c_b| + 1) is assumed:
+// a page outside it makes pass 1 see a stored value beyond the limit and
+// pass 2 re-read the page, so the images are right either way, and fp16's
+// thirty binades leave that much headroom at no cost in precision.
+void h16_args(const cvx::ProjArgs& a, const double* center, int B, int nc, int dtype, bool scaled, float limit,
+              cvx::H16Args& h) {
   std::memset(&h, 0, sizeof(h));
   for (int j = 0; j < nc; ++j) {
     double bnd = 0.0;
-    for (int b = 0; b < B; ++b)
-      bnd += std::fabs((double)a.w[b * nc + j]) * std::max(std::fabs(center[b]), std::fabs(65535.0 - center[b]));
-    bnd *= (double)a.scale[j] * (1.0 + 1.0 / 1024.0);
+    for (int b = 0; b < B; ++b) {
+      const double c = std::fabs(center[b]);
+      double dx;
+      switch (dtype) {
+        case CVAMX_U16: dx = std::max(c, std::fabs(65535.0 - center[b])); break;
+        case CVAMX_F16: dx = 65504.0 + c; break;
+        default: dx = 1024.0 * (c + 1.0); break;
+      }
+      bnd += std::fabs((double)a.w[b * nc + j]) * dx;
+    }
+    bnd *= (scaled ? (double)a.scale[j] : 1.0) * (1.0 + 1.0 / 1024.0);
     int ex = 0;
     if (bnd > 0.0) {
       std::frexp(32768.0 / bnd, &ex);   // 32768 / bnd in [2^(ex-1), 2^ex)
@@ -354,10 +368,10 @@ void h16_args(const cvx::ProjArgs& a, const double* center, int B, int nc, float
   h.limit = limit;
 }
 
-// The one-read schedule on uint16 pages: pass 1 reads the page once for the
-// range and stores every component value in fp16; pass 2 quantises the
-// stored values (or re-reads the page, decided on the device, when their
-// error bound exceeds the limit).
+// The one-read schedule: pass 1 reads the page once for the range and
+// stores every component value in fp16; pass 2 quantises the stored values
+// (or re-reads the page, decided on the device, when their error bound
+// exceeds the limit).
 int proj_groups_h16(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const double* center, int n_comp,
                     uint8_t* images, const ProjBufs& pb, hipStream_t s) {
   const int B = (int)cube->bands;
@@ -370,9 +384,9 @@ int proj_groups_h16(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, con
   for (int g0 = 0; g0 < n_comp; g0 += 8) {
     const int nc = std::min(8, n_comp - g0);
     cvx::ProjArgs a;
-    make_proj_args(cube, W, center, n_comp, g0, nc, false, a);
+    make_proj_args(cube, W, center, n_comp, g0, nc, ctx->plain, a);
     cvx::H16Args h;
-    h16_args(a, center, B, nc, limit, h);
+    h16_args(a, center, B, nc, cube->dtype, cube->dtype == CVAMX_U16 && !ctx->plain, limit, h);
     static const char* kRangeName[9] = {"", "project_range_store_nc1", "project_range_store_nc2",
                                         "project_range_store_nc3", "project_range_store_nc4",
                                         "project_range_store_nc5", "project_range_store_nc6",
@@ -382,13 +396,13 @@ int proj_groups_h16(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, con
                                           "project_stretch_stored_nc5", "project_stretch_stored_nc6",
                                           "project_stretch_stored_nc7", "project_stretch_stored_nc8"};
     prof_begin(ctx, s, kRangeName[nc]);
-    hipError_t e = cvx::launch_project_range_h16_u16(cube->data, B, P, nc, a, nblocks, pb.part, pb.ticket,
-                                                     pb.range_dev, pb.ab_dev + 2 * g0, h, planes, Pp, s);
+    hipError_t e = cvx::launch_project_range_h16(cube->dtype, ctx->plain, cube->data, B, P, nc, a, nblocks, pb.part,
+                                                 pb.ticket, pb.range_dev, pb.ab_dev + 2 * g0, h, planes, Pp, s);
     prof_end(ctx, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "project range launch");
     prof_begin(ctx, s, kStretchName[nc]);
-    e = cvx::launch_project_stretch_h16_u16(cube->data, B, P, nc, a, nblocks, pb.range_dev, planes, Pp,
-                                            images + (int64_t)g0 * P, s);
+    e = cvx::launch_project_stretch_h16(cube->dtype, ctx->plain, cube->data, B, P, nc, a, nblocks, pb.range_dev,
+                                        planes, Pp, images + (int64_t)g0 * P, s);
     prof_end(ctx, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "project stretch launch");
   }
@@ -401,8 +415,7 @@ int proj_groups(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, const d
   // block partials: 16 floats (VALU kernels) or 32 (matrix-core kernels)
   if (int st = ensure(ctx, B_PROJPART, (size_t)nblocks * 32 * sizeof(float))) return st;
   const ProjBufs pb{(float*)ctx->buf[B_PROJPART], ctx->tickets, ctx->range_dev, ctx->ab_dev};
-  if (cube->dtype == CVAMX_U16 && !ctx->plain && ctx->schedule != CVAMX_SCHEDULE_TWO_READS)
-    return proj_groups_h16(ctx, cube, W, center, n_comp, images, pb, s);
+  if (ctx->schedule != CVAMX_SCHEDULE_TWO_READS) return proj_groups_h16(ctx, cube, W, center, n_comp, images, pb, s);
   return proj_groups_with(ctx, cube, W, center, n_comp, images, pb, true, s);
 }
 

@@ -41,7 +41,45 @@ hipError_t project_float_generic(int dtype, int nc, const void* cube, int B, int
 #undef CVX_C
 }
 
+hipError_t project_range_h16_generic(int dtype, int nc, const void* cube, int B, int64_t P, const ProjArgs& a,
+                                     int nblocks, float* part, unsigned* ticket, float* range_dev, float* ab_dev,
+                                     const H16Args& h, _Float16* planes, int64_t Pp, hipStream_t s) {
+#define CVX_C(D) proj::range_nc<D, true>(nc, cube, B, P, a, nblocks, part, ticket, range_dev, ab_dev, s, h, planes, Pp)
+  CVX_GENERIC(CVX_C)
+#undef CVX_C
+}
+
+hipError_t project_stretch_h16_generic(int dtype, int nc, const void* cube, int B, int64_t P, const ProjArgs& a,
+                                       int nblocks, const float* range_dev, const _Float16* planes, int64_t Pp,
+                                       uint8_t* images, hipStream_t s) {
+#define CVX_C(D) proj::stretch_h16_nc<D>(nc, cube, B, P, a, nblocks, range_dev, planes, Pp, images, s)
+  CVX_GENERIC(CVX_C)
+#undef CVX_C
+}
+
 #undef CVX_GENERIC
+
+hipError_t launch_project_range_h16(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
+                                    const ProjArgs& a, int nblocks, float* part, unsigned* ticket,
+                                    float* range_dev, float* ab_dev, const H16Args& h, uint16_t* planes,
+                                    int64_t Pp, hipStream_t s) {
+  if (Pp < P || Pp % 256 != 0) return hipErrorInvalidValue;
+  if (dtype == DT_U16 && !plain)
+    return launch_project_range_h16_u16(cube, B, P, nc, a, nblocks, part, ticket, range_dev, ab_dev, h, planes, Pp,
+                                        s);
+  return project_range_h16_generic(dtype, nc, cube, B, P, a, nblocks, part, ticket, range_dev, ab_dev, h,
+                                   reinterpret_cast<_Float16*>(planes), Pp, s);
+}
+
+hipError_t launch_project_stretch_h16(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
+                                      const ProjArgs& a, int nblocks, const float* range_dev,
+                                      const uint16_t* planes, int64_t Pp, uint8_t* images, hipStream_t s) {
+  if (Pp < P || Pp % 256 != 0) return hipErrorInvalidValue;
+  if (dtype == DT_U16 && !plain)
+    return launch_project_stretch_h16_u16(cube, B, P, nc, a, nblocks, range_dev, planes, Pp, images, s);
+  return project_stretch_h16_generic(dtype, nc, cube, B, P, a, nblocks, range_dev,
+                                     reinterpret_cast<const _Float16*>(planes), Pp, images, s);
+}
 
 hipError_t launch_project_range(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
                                 const ProjArgs& a, int nblocks, float* part, unsigned* ticket,

@@ -14,6 +14,7 @@
 // s = 255 / (b - a), o = 1/2 - a s.  Pass 2 recomputes y bit for bit,
 // quantises, clamps to 0..255 and writes planar bytes.
 #pragma once
+#include "k_stored.hpp"
 #include "k_tile.hpp"
 #include "launch.hpp"
 
@@ -103,13 +104,18 @@ __device__ __forceinline__ void tile_loop(const void* __restrict__ cube, int B, 
   });
 }
 
-template <int DT, int NC>
+// Pass 1; with H16 it also stores every value as fp16 (k_stored.hpp): the
+// lane's pixel (or pair of pixels, one dword) in each plane, so a wave
+// writes 64 consecutive pixels per plane; the last tile's pixels beyond P
+// land in the planes' padding (Pp >= P rounded up to whole tiles).
+template <int DT, int NC, bool H16>
 __global__ __launch_bounds__(kBlock) void k_project_range(const void* __restrict__ cube, int B,
                                                           int64_t P, ProjArgs a,
                                                           float* __restrict__ part,
                                                           unsigned* __restrict__ ticket,
                                                           float* __restrict__ range_dev,
-                                                          float* __restrict__ ab_dev) {
+                                                          float* __restrict__ ab_dev, H16Args h,
+                                                          _Float16* __restrict__ planes, int64_t Pp) {
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ float wred[kWaves][2 * NC];
   __shared__ bool am_last;
@@ -121,6 +127,21 @@ __global__ __launch_bounds__(kBlock) void k_project_range(const void* __restrict
     mx[j] = -__builtin_inff();
   }
   tile_loop<DT, NC>(cube, B, P, a, lds, [&](int64_t pix, int g2, const float (&y0)[NC], const float (&y1)[NC]) {
+    if constexpr (H16) {
+      if (g2 == 2) {
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const uint32_t v = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(y0[j] * h.f[j])) |
+                             ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(y1[j] * h.f[j])) << 16);
+          __builtin_nontemporal_store(v, reinterpret_cast<uint32_t*>(planes + (int64_t)j * Pp + pix));
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+          __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, (_Float16)(y0[j] * h.f[j])),
+                                      reinterpret_cast<uint16_t*>(planes + (int64_t)j * Pp + pix));
+      }
+    }
     if (pix < P) {
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
@@ -206,6 +227,15 @@ __global__ __launch_bounds__(kBlock) void k_project_range(const void* __restrict
     range_dev[8 + j] = o;
     ab_dev[2 * j] = lo;
     ab_dev[2 * j + 1] = hi;
+    if constexpr (H16) wred[0][j] = stored_map(lo, hi, s, o, h.f[j], h.limit, j, range_dev) ? 1.f : 0.f;
+  }
+  if constexpr (H16) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned flag = 0u;
+      for (int j = 0; j < NC; ++j) flag |= wred[0][j] != 0.f ? 1u : 0u;
+      reinterpret_cast<unsigned*>(range_dev)[32] = flag;
+    }
   }
   if (threadIdx.x == 0) *ticket = 0u;
 }
@@ -216,12 +246,11 @@ __device__ __forceinline__ uint32_t quant(float y, float s, float o) {
   return (uint32_t)t;
 }
 
+// Pass 2 from the page.
 template <int DT, int NC>
-__global__ __launch_bounds__(kBlock) void k_project_stretch(const void* __restrict__ cube, int B,
-                                                            int64_t P, ProjArgs a,
-                                                            const float* __restrict__ range_dev,
-                                                            uint8_t* __restrict__ images) {
-  extern __shared__ __align__(16) uint32_t lds[];
+__device__ __forceinline__ void stretch_page_valu(const void* __restrict__ cube, int B, int64_t P, const ProjArgs& a,
+                                                  const float* __restrict__ range_dev, uint8_t* __restrict__ images,
+                                                  uint32_t* __restrict__ lds) {
   float sc[NC], of[NC];
 #pragma unroll
   for (int j = 0; j < NC; ++j) {
@@ -254,6 +283,31 @@ __global__ __launch_bounds__(kBlock) void k_project_stretch(const void* __restri
   });
 }
 
+template <int DT, int NC>
+__global__ __launch_bounds__(kBlock) void k_project_stretch(const void* __restrict__ cube, int B,
+                                                            int64_t P, ProjArgs a,
+                                                            const float* __restrict__ range_dev,
+                                                            uint8_t* __restrict__ images) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  stretch_page_valu<DT, NC>(cube, B, P, a, range_dev, images, lds);
+}
+
+// Pass 2 after a pass 1 that stored fp16 planes: from the planes, or from
+// the page when pass 1 set the flag.
+template <int DT, int NC>
+__global__ __launch_bounds__(kBlock) void k_project_stretch_h16(const void* __restrict__ cube, int B,
+                                                                int64_t P, ProjArgs a,
+                                                                const float* __restrict__ range_dev,
+                                                                const _Float16* __restrict__ planes, int64_t Pp,
+                                                                uint8_t* __restrict__ images) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  if (reinterpret_cast<const unsigned*>(range_dev)[32] != 0u) {
+    stretch_page_valu<DT, NC>(cube, B, P, a, range_dev, images, lds);
+    return;
+  }
+  stretch_stored(planes, Pp, P, NC, range_dev, images);
+}
+
 // The FP32 component planes themselves: y[j][p] for every pixel, the same
 // values the two passes above compute (lanes write consecutive pixels).
 template <int DT, int NC>
@@ -278,14 +332,15 @@ inline size_t smem_bytes(int dtype, int B) {
 }
 
 // Launch a pass's kernel for one element type with the exact component count.
-template <int DT>
+template <int DT, bool H16 = false>
 hipError_t range_nc(int nc, const void* cube, int B, int64_t P, const ProjArgs& a, int nblocks, float* part,
-                    unsigned* ticket, float* range_dev, float* ab_dev, hipStream_t s) {
+                    unsigned* ticket, float* range_dev, float* ab_dev, hipStream_t s, const H16Args& h = H16Args{},
+                    _Float16* planes = nullptr, int64_t Pp = 0) {
   const size_t sm = smem_bytes(DT, B);
 #define CVX_RANGE(N)                                                                                          \
   case N:                                                                                                     \
-    hipLaunchKernelGGL((k_project_range<DT, N>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a, part, \
-                       ticket, range_dev, ab_dev);                                                            \
+    hipLaunchKernelGGL((k_project_range<DT, N, H16>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a,   \
+                       part, ticket, range_dev, ab_dev, h, planes, Pp);                                      \
     break;
   switch (nc) {
     CVX_RANGE(1) CVX_RANGE(2) CVX_RANGE(3) CVX_RANGE(4) CVX_RANGE(5) CVX_RANGE(6) CVX_RANGE(7) CVX_RANGE(8)
@@ -304,6 +359,26 @@ hipError_t stretch_nc(int nc, const void* cube, int B, int64_t P, const ProjArgs
   case N:                                                                                                     \
     hipLaunchKernelGGL((k_project_stretch<DT, N>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a,     \
                        range_dev, images);                                                                    \
+    break;
+  switch (nc) {
+    CVX_STRETCH(1) CVX_STRETCH(2) CVX_STRETCH(3) CVX_STRETCH(4) CVX_STRETCH(5) CVX_STRETCH(6) CVX_STRETCH(7)
+    CVX_STRETCH(8)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef CVX_STRETCH
+  return hipGetLastError();
+}
+
+template <int DT>
+hipError_t stretch_h16_nc(int nc, const void* cube, int B, int64_t P, const ProjArgs& a, int nblocks,
+                          const float* range_dev, const _Float16* planes, int64_t Pp, uint8_t* images,
+                          hipStream_t s) {
+  const size_t sm = smem_bytes(DT, B);
+#define CVX_STRETCH(N)                                                                                        \
+  case N:                                                                                                     \
+    hipLaunchKernelGGL((k_project_stretch_h16<DT, N>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a, \
+                       range_dev, planes, Pp, images);                                                        \
     break;
   switch (nc) {
     CVX_STRETCH(1) CVX_STRETCH(2) CVX_STRETCH(3) CVX_STRETCH(4) CVX_STRETCH(5) CVX_STRETCH(6) CVX_STRETCH(7)
@@ -342,4 +417,10 @@ hipError_t project_stretch_generic(int dtype, int nc, const void* cube, int B, i
                                    int nblocks, const float* range_dev, uint8_t* images, hipStream_t s);
 hipError_t project_float_generic(int dtype, int nc, const void* cube, int B, int64_t P, const ProjArgs& a,
                                  int nblocks, float* y, hipStream_t s);
+hipError_t project_range_h16_generic(int dtype, int nc, const void* cube, int B, int64_t P, const ProjArgs& a,
+                                     int nblocks, float* part, unsigned* ticket, float* range_dev, float* ab_dev,
+                                     const H16Args& h, _Float16* planes, int64_t Pp, hipStream_t s);
+hipError_t project_stretch_h16_generic(int dtype, int nc, const void* cube, int B, int64_t P, const ProjArgs& a,
+                                       int nblocks, const float* range_dev, const _Float16* planes, int64_t Pp,
+                                       uint8_t* images, hipStream_t s);
 }  // namespace cvx

@@ -46,6 +46,7 @@
 // prefetched tile were both slower.
 #include <algorithm>
 
+#include "k_stored.hpp"
 #include "k_tile.hpp"
 
 namespace cvx {
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_range_u16(const vo
         const f32x4 v = four_pixels<G2>(acc[rb], g, p, rb, pb, &px);
         const uint32_t lo = h16((_Float16)(v[0] * hf)) | (h16((_Float16)(v[1] * hf)) << 16);
         const uint32_t hi = h16((_Float16)(v[2] * hf)) | (h16((_Float16)(v[3] * hf)) << 16);
-        if (live) *reinterpret_cast<u32x2*>(plane + px) = u32x2{lo, hi};
+        if (live) __builtin_nontemporal_store(u32x2{lo, hi}, reinterpret_cast<u32x2*>(plane + px));
       }
     }
     if (pb + 16 * RB * G2 <= P) {   // whole tile: every row is a pixel
@@ -378,20 +379,7 @@ __global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_range_u16(const vo
     range_dev[8 + jj] = o;
     ab_dev[2 * jj] = l2 * inv;
     ab_dev[2 * jj + 1] = h2 * inv;
-    if constexpr (H16) {
-      const float f = h.f[jj];
-      range_dev[16 + jj] = s / f;   // f a power of two: exact
-      range_dev[24 + jj] = o;
-      const float M = fmaxf(fabsf(l2), fabsf(h2));
-      float bound = 0.f;
-      bool bad = !(M * f < 32768.f);   // stored values stay far below fp16's largest, 65504
-      if (h2 > l2) {
-        bound = s * (M * (0x1p-11f + 0x1p-22f) + 0x1p-25f / f) + 0x1p-22f * (s * M + 1.f);
-        bad = bad || !(bound <= h.limit);
-      }
-      range_dev[40 + jj] = bound;
-      wred[0][jj] = bad ? 1.f : 0.f;
-    }
+    if constexpr (H16) wred[0][jj] = stored_map(l2, h2, s, o, h.f[jj], h.limit, jj, range_dev) ? 1.f : 0.f;
   }
   if constexpr (H16) {
     __syncthreads();
@@ -478,57 +466,6 @@ __global__ __launch_bounds__(kBlock, NKB <= 5 ? 2 : 1) void k_stretch_u16(const 
                                                                         uint8_t* __restrict__ images) {
   extern __shared__ __align__(16) uint32_t lds[];
   stretch_page<NKB, G2>(cube, B, P, nc, a, range_dev, images, lds);
-}
-
-// Quantises the 16 stored values of one chunk (two 16-byte words) with the
-// map of the stored values and writes them at pixel px of the plane dst
-// (one 16-byte store when the plane rows allow, else byte by byte up to P).
-__device__ __forceinline__ void quant_chunk(const u32x4& v0, const u32x4& v1, float s, float o, int64_t px,
-                                            int64_t P, bool aligned, uint8_t* __restrict__ dst) {
-  if (px >= P) return;
-  // value 2 m + h of the chunk is half h of word m
-  const uint32_t wd[8] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
-  uint32_t qb[16];
-#pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    qb[2 * m] = quant((float)__builtin_bit_cast(_Float16, (uint16_t)(wd[m] & 0xffffu)), s, o);
-    qb[2 * m + 1] = quant((float)__builtin_bit_cast(_Float16, (uint16_t)(wd[m] >> 16)), s, o);
-  }
-  u32x4 q;
-#pragma unroll
-  for (int d = 0; d < 4; ++d)
-    q[d] = qb[4 * d] | (qb[4 * d + 1] << 8) | (qb[4 * d + 2] << 16) | (qb[4 * d + 3] << 24);
-  if (aligned && px + 16 <= P) {
-    *reinterpret_cast<u32x4*>(dst + px) = q;
-  } else {
-    for (int e = 0; e < 16; ++e)
-      if (px + e < P) dst[px + e] = (uint8_t)(q[e >> 2] >> (8 * (e & 3)));
-  }
-}
-
-// Pass 2 from the stored fp16 planes: 16 values per lane and step, two
-// steps' loads in flight (the second index clamped to the plane's last
-// chunk, so no branch separates the loads).
-__device__ __forceinline__ void stretch_stored(const _Float16* __restrict__ planes, int64_t Pp, int64_t P, int nc,
-                                               const float* __restrict__ range_dev, uint8_t* __restrict__ images) {
-  const int64_t cpp = Pp / 16;   // chunks per plane
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  const int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool aligned = (P % 16) == 0 && (reinterpret_cast<uintptr_t>(images) % 16) == 0;
-  for (int j = 0; j < nc; ++j) {
-    const float s = range_dev[16 + j], o = range_dev[24 + j];
-    const u32x4* src = reinterpret_cast<const u32x4*>(planes + (int64_t)j * Pp);
-    uint8_t* dst = images + (int64_t)j * P;
-    for (int64_t i = t0; i < cpp; i += 2 * stride) {
-      const int64_t i1 = i + stride < cpp ? i + stride : cpp - 1;
-      const u32x4 a0 = __builtin_nontemporal_load(src + 2 * i);
-      const u32x4 a1 = __builtin_nontemporal_load(src + 2 * i + 1);
-      const u32x4 b0 = __builtin_nontemporal_load(src + 2 * i1);
-      const u32x4 b1 = __builtin_nontemporal_load(src + 2 * i1 + 1);
-      quant_chunk(a0, a1, s, o, 16 * i, P, aligned, dst);
-      if (i + stride < cpp) quant_chunk(b0, b1, s, o, 16 * i1, P, aligned, dst);
-    }
-  }
 }
 
 // Pass 2 after a pass 1 that stored fp16 planes: from the planes, unless

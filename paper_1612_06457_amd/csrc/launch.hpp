@@ -109,6 +109,15 @@ hipError_t launch_project_stretch_u16(const void* cube, int B, int64_t P, int nc
 hipError_t launch_project_float_u16(const void* cube, int B, int64_t P, int nc, const ProjArgs& a, int nblocks,
                                     float* y, hipStream_t s);
 
+// the one-read schedule for any page type (dispatching as the two-pass
+// launchers above): pass 1 also stores the fp16 planes, pass 2 maps them
+hipError_t launch_project_range_h16(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
+                                    const ProjArgs& a, int nblocks, float* part, unsigned* ticket,
+                                    float* range_dev, float* ab_dev, const H16Args& h, uint16_t* planes,
+                                    int64_t Pp, hipStream_t s);
+hipError_t launch_project_stretch_h16(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
+                                      const ProjArgs& a, int nblocks, const float* range_dev,
+                                      const uint16_t* planes, int64_t Pp, uint8_t* images, hipStream_t s);
 // the one-read schedule on uint16 pages: pass 1 as launch_project_range_u16
 // and also the fp16 planes (nc planes of Pp >= P values, Pp a multiple of
 // 256; range_dev[16..32) the map of the stored values, range_dev[32] the

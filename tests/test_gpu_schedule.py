@@ -1,6 +1,7 @@
-"""The projection schedules of uint16 pages through the C ABI: one page read
-with an fp16 intermediate (the default), two page reads, and the one-read
-pass 1 followed by its page re-reading fallback.
+"""The projection schedules through the C ABI: one page read with an fp16
+intermediate (the default), two page reads, and the one-read pass 1
+followed by its page re-reading fallback; on uint16 pages (matrix cores),
+and on float32, bf16 and fp16 pages and the plain FP32 path (vector ALU).
 
 Bars: the ranges equal bit for bit under every schedule (pass 1 is the same
 FP32 computation); the forced fallback equals the two-read images bit for
@@ -55,12 +56,14 @@ def _t(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
 
-def _run(cx, cube_d, Wm, center, schedule):
+def _run(cx, cube_d, Wm, center, schedule, plain=False):
     cx.set_schedule(schedule)
+    cx.set_plain_fp32(plain)
     try:
         q, ab = cx.cva_project(cube_d, Wm, center, return_range=True)
     finally:
         cx.set_schedule("auto")
+        cx.set_plain_fp32(False)
     return q.cpu().numpy().astype(np.int32), ab
 
 
@@ -157,3 +160,56 @@ def test_constant_component(dev):
     assert np.array_equal(ab1, ab2)
     assert (q1[1] == 0).all() and (q2[1] == 0).all()
     check_images(q1, q2)
+
+
+def _typed(cube, kind, dev):
+    """The page as `kind` values (float32, bf16, fp16 scaled to [0, 1]) on the
+    device, and the FP64 values the oracle sees."""
+    import torch
+    from synth import to_half_cube
+    if kind == "u16":
+        return _t(cube, dev), cube
+    if kind == "f32":
+        c = (cube.astype(np.float32) / np.float32(4095.0))
+        return _t(c, dev), c
+    h = to_half_cube(cube, kind)
+    return h.to(dev), h.float().numpy()
+
+
+@pytest.mark.parametrize("kind,plain", [("f32", False), ("bf16", False), ("f16", False), ("u16", True),
+                                        ("bf16", True)])
+@pytest.mark.parametrize("H,W,B,n", [(37, 53, 23, 3), (64, 64, 16, 8), (19, 23, 1, 1), (41, 40, 64, 10)])
+def test_schedules_other_pages(dev, kind, plain, H, W, B, n):
+    say(f"schedules: {H}x{W}x{B} {kind}{' plain' if plain else ''}, {n} components")
+    import paper_1612_06457_amd as cx
+    cube, host = _typed(_page(H, W, B, H + B), kind, dev)
+    rng = np.random.default_rng(H + n)
+    Wm = rng.normal(size=(B, n))
+    center = np.asarray(host, dtype=np.float64).reshape(-1, B).mean(0)
+    q1, ab1 = _run(cx, cube, Wm, center, "auto", plain)
+    q2, ab2 = _run(cx, cube, Wm, center, "two_reads", plain)
+    q3, ab3 = _run(cx, cube, Wm, center, "force_reread", plain)
+    assert np.array_equal(ab1, ab2) and np.array_equal(ab1, ab3)
+    assert np.array_equal(q3, q2), "the forced fallback differs from the two-read images"
+    frac = check_images(q1, q2)
+    q_ref, ab_ref = oracle.cva_project(np.asarray(host, dtype=np.float64), Wm, center)
+    check_images(q1, q_ref)
+    y_ref = oracle.project(np.asarray(host, dtype=np.float64), Wm, center)
+    allowed = _bound_frac(y_ref, ab1)
+    say(f"  one-read bytes differing from two-read: {frac:.3e} (bound allows {allowed:.3e})")
+    assert frac <= allowed + 1e-12
+
+
+def test_float_page_beyond_the_assumed_range_falls_back(dev):
+    say("schedules: float32 values far beyond 1024 (|centre| + 1) -> device fallback")
+    import paper_1612_06457_amd as cx
+    rng = np.random.default_rng(11)
+    H, W, B = 50, 60, 9
+    x = rng.normal(0, 1e6, (H, W, B)).astype(np.float32)          # centre near 0, spread 1e6
+    Wm = rng.normal(size=(B, 3))
+    center = np.zeros(B)
+    cd = _t(x, dev)
+    q1, ab1 = _run(cx, cd, Wm, center, "auto")
+    q2, ab2 = _run(cx, cd, Wm, center, "two_reads")
+    assert np.array_equal(ab1, ab2)
+    assert np.array_equal(q1, q2), "the overflow check did not send pass 2 back to the page"
