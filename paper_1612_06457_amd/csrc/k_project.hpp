@@ -87,7 +87,9 @@ __device__ __forceinline__ void project_group(const uint32_t* __restrict__ d, in
 }
 
 // The tile loop shared by both passes: body(pix, g2, y0, y1) per lane group.
-template <int DT, int NC, typename Body>
+// Q 16-byte loads per lane hold a tile of S <= 4 Q dwords per lane group
+// (fewer registers for narrower pages leave room for more waves).
+template <int DT, int NC, int Q, typename Body>
 __device__ __forceinline__ void tile_loop(const void* __restrict__ cube, int B, int64_t P,
                                           const ProjArgs& a, uint32_t* __restrict__ lds, Body body) {
   const int S = Geo<DT>::S(B), g2 = Geo<DT>::g2(B);
@@ -97,7 +99,7 @@ __device__ __forceinline__ void tile_loop(const void* __restrict__ cube, int B, 
   const int64_t nt = (P + tp - 1) / tp;
   const int64_t total_bytes = P * B * Geo<DT>::esize;
   const unsigned char* base = reinterpret_cast<const unsigned char*>(cube);
-  for_each_tile<kMaxQ>(base, total_bytes, nt, S, my, [&](int64_t t) {
+  for_each_tile<Q>(base, total_bytes, nt, S, my, [&](int64_t t) {
     float y0[NC], y1[NC];
     project_group<DT, NC>(my + lane * S, B, a, y0, y1);
     body(t * tp + (int64_t)lane * g2, g2, y0, y1);
@@ -108,7 +110,7 @@ __device__ __forceinline__ void tile_loop(const void* __restrict__ cube, int B, 
 // lane's pixel (or pair of pixels, one dword) in each plane, so a wave
 // writes 64 consecutive pixels per plane; the last tile's pixels beyond P
 // land in the planes' padding (Pp >= P rounded up to whole tiles).
-template <int DT, int NC, bool H16>
+template <int DT, int NC, bool H16, int Q>
 __global__ __launch_bounds__(kBlock) void k_project_range(const void* __restrict__ cube, int B,
                                                           int64_t P, ProjArgs a,
                                                           float* __restrict__ part,
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_project_range(const void* __restrict
     mn[j] = __builtin_inff();
     mx[j] = -__builtin_inff();
   }
-  tile_loop<DT, NC>(cube, B, P, a, lds, [&](int64_t pix, int g2, const float (&y0)[NC], const float (&y1)[NC]) {
+  tile_loop<DT, NC, Q>(cube, B, P, a, lds, [&](int64_t pix, int g2, const float (&y0)[NC], const float (&y1)[NC]) {
     if constexpr (H16) {
       if (g2 == 2) {
 #pragma unroll
@@ -247,7 +249,7 @@ __device__ __forceinline__ uint32_t quant(float y, float s, float o) {
 }
 
 // Pass 2 from the page.
-template <int DT, int NC>
+template <int DT, int NC, int Q>
 __device__ __forceinline__ void stretch_page_valu(const void* __restrict__ cube, int B, int64_t P, const ProjArgs& a,
                                                   const float* __restrict__ range_dev, uint8_t* __restrict__ images,
                                                   uint32_t* __restrict__ lds) {
@@ -258,7 +260,7 @@ __device__ __forceinline__ void stretch_page_valu(const void* __restrict__ cube,
     of[j] = range_dev[8 + j];
   }
   const bool even = (P & 1) == 0;
-  tile_loop<DT, NC>(cube, B, P, a, lds, [&](int64_t pix, int g2, const float (&y0)[NC], const float (&y1)[NC]) {
+  tile_loop<DT, NC, Q>(cube, B, P, a, lds, [&](int64_t pix, int g2, const float (&y0)[NC], const float (&y1)[NC]) {
     if (g2 == 2) {
       if (pix + 1 < P && even) {
 #pragma unroll
@@ -283,18 +285,18 @@ __device__ __forceinline__ void stretch_page_valu(const void* __restrict__ cube,
   });
 }
 
-template <int DT, int NC>
+template <int DT, int NC, int Q>
 __global__ __launch_bounds__(kBlock) void k_project_stretch(const void* __restrict__ cube, int B,
                                                             int64_t P, ProjArgs a,
                                                             const float* __restrict__ range_dev,
                                                             uint8_t* __restrict__ images) {
   extern __shared__ __align__(16) uint32_t lds[];
-  stretch_page_valu<DT, NC>(cube, B, P, a, range_dev, images, lds);
+  stretch_page_valu<DT, NC, Q>(cube, B, P, a, range_dev, images, lds);
 }
 
 // Pass 2 after a pass 1 that stored fp16 planes: from the planes, or from
 // the page when pass 1 set the flag.
-template <int DT, int NC>
+template <int DT, int NC, int Q>
 __global__ __launch_bounds__(kBlock) void k_project_stretch_h16(const void* __restrict__ cube, int B,
                                                                 int64_t P, ProjArgs a,
                                                                 const float* __restrict__ range_dev,
@@ -302,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_project_stretch_h16(const void* __re
                                                                 uint8_t* __restrict__ images) {
   extern __shared__ __align__(16) uint32_t lds[];
   if (reinterpret_cast<const unsigned*>(range_dev)[32] != 0u) {
-    stretch_page_valu<DT, NC>(cube, B, P, a, range_dev, images, lds);
+    stretch_page_valu<DT, NC, Q>(cube, B, P, a, range_dev, images, lds);
     return;
   }
   stretch_stored(planes, Pp, P, NC, range_dev, images);
@@ -310,11 +312,11 @@ __global__ __launch_bounds__(kBlock) void k_project_stretch_h16(const void* __re
 
 // The FP32 component planes themselves: y[j][p] for every pixel, the same
 // values the two passes above compute (lanes write consecutive pixels).
-template <int DT, int NC>
+template <int DT, int NC, int Q>
 __global__ __launch_bounds__(kBlock) void k_project_float(const void* __restrict__ cube, int B, int64_t P,
                                                           ProjArgs a, float* __restrict__ y) {
   extern __shared__ __align__(16) uint32_t lds[];
-  tile_loop<DT, NC>(cube, B, P, a, lds, [&](int64_t pix, int g2, const float (&y0)[NC], const float (&y1)[NC]) {
+  tile_loop<DT, NC, Q>(cube, B, P, a, lds, [&](int64_t pix, int g2, const float (&y0)[NC], const float (&y1)[NC]) {
     if (pix < P) {
 #pragma unroll
       for (int j = 0; j < NC; ++j) y[(int64_t)j * P + pix] = y0[j];
@@ -324,6 +326,12 @@ __global__ __launch_bounds__(kBlock) void k_project_float(const void* __restrict
       for (int j = 0; j < NC; ++j) y[(int64_t)j * P + pix + 1] = y1[j];
     }
   });
+}
+
+// 16-byte loads per lane for a tile of S dwords per lane group
+inline int q_for(int dtype, int B) {
+  const int S = (dtype == DT_F32 || (B & 1)) ? B : B / 2;
+  return S <= 32 ? 8 : kMaxQ;
 }
 
 inline size_t smem_bytes(int dtype, int B) {
@@ -337,10 +345,15 @@ hipError_t range_nc(int nc, const void* cube, int B, int64_t P, const ProjArgs& 
                     unsigned* ticket, float* range_dev, float* ab_dev, hipStream_t s, const H16Args& h = H16Args{},
                     _Float16* planes = nullptr, int64_t Pp = 0) {
   const size_t sm = smem_bytes(DT, B);
+  const int q = q_for(DT, B);
 #define CVX_RANGE(N)                                                                                          \
   case N:                                                                                                     \
-    hipLaunchKernelGGL((k_project_range<DT, N, H16>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a,   \
-                       part, ticket, range_dev, ab_dev, h, planes, Pp);                                      \
+    if (q == 8)                                                                                               \
+      hipLaunchKernelGGL((k_project_range<DT, N, H16, 8>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a, \
+                         part, ticket, range_dev, ab_dev, h, planes, Pp);                                    \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_project_range<DT, N, H16, kMaxQ>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, \
+                         a, part, ticket, range_dev, ab_dev, h, planes, Pp);                                 \
     break;
   switch (nc) {
     CVX_RANGE(1) CVX_RANGE(2) CVX_RANGE(3) CVX_RANGE(4) CVX_RANGE(5) CVX_RANGE(6) CVX_RANGE(7) CVX_RANGE(8)
@@ -355,10 +368,15 @@ template <int DT>
 hipError_t stretch_nc(int nc, const void* cube, int B, int64_t P, const ProjArgs& a, int nblocks,
                       const float* range_dev, uint8_t* images, hipStream_t s) {
   const size_t sm = smem_bytes(DT, B);
+  const int q = q_for(DT, B);
 #define CVX_STRETCH(N)                                                                                        \
   case N:                                                                                                     \
-    hipLaunchKernelGGL((k_project_stretch<DT, N>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a,     \
-                       range_dev, images);                                                                    \
+    if (q == 8)                                                                                               \
+      hipLaunchKernelGGL((k_project_stretch<DT, N, 8>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a,    \
+                         range_dev, images);                                                                  \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_project_stretch<DT, N, kMaxQ>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a, \
+                         range_dev, images);                                                                  \
     break;
   switch (nc) {
     CVX_STRETCH(1) CVX_STRETCH(2) CVX_STRETCH(3) CVX_STRETCH(4) CVX_STRETCH(5) CVX_STRETCH(6) CVX_STRETCH(7)
@@ -375,10 +393,15 @@ hipError_t stretch_h16_nc(int nc, const void* cube, int B, int64_t P, const Proj
                           const float* range_dev, const _Float16* planes, int64_t Pp, uint8_t* images,
                           hipStream_t s) {
   const size_t sm = smem_bytes(DT, B);
+  const int q = q_for(DT, B);
 #define CVX_STRETCH(N)                                                                                        \
   case N:                                                                                                     \
-    hipLaunchKernelGGL((k_project_stretch_h16<DT, N>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a, \
-                       range_dev, planes, Pp, images);                                                        \
+    if (q == 8)                                                                                               \
+      hipLaunchKernelGGL((k_project_stretch_h16<DT, N, 8>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a, \
+                         range_dev, planes, Pp, images);                                                      \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_project_stretch_h16<DT, N, kMaxQ>), dim3(nblocks), dim3(kBlock), sm, s, cube, B,   \
+                         P, a, range_dev, planes, Pp, images);                                                \
     break;
   switch (nc) {
     CVX_STRETCH(1) CVX_STRETCH(2) CVX_STRETCH(3) CVX_STRETCH(4) CVX_STRETCH(5) CVX_STRETCH(6) CVX_STRETCH(7)
@@ -394,9 +417,13 @@ template <int DT>
 hipError_t float_nc(int nc, const void* cube, int B, int64_t P, const ProjArgs& a, int nblocks, float* y,
                     hipStream_t s) {
   const size_t sm = smem_bytes(DT, B);
+  const int q = q_for(DT, B);
 #define CVX_FLOAT(N)                                                                                          \
   case N:                                                                                                     \
-    hipLaunchKernelGGL((k_project_float<DT, N>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a, y);       \
+    if (q == 8)                                                                                               \
+      hipLaunchKernelGGL((k_project_float<DT, N, 8>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a, y);  \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_project_float<DT, N, kMaxQ>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a, y); \
     break;
   switch (nc) {
     CVX_FLOAT(1) CVX_FLOAT(2) CVX_FLOAT(3) CVX_FLOAT(4) CVX_FLOAT(5) CVX_FLOAT(6) CVX_FLOAT(7) CVX_FLOAT(8)
