@@ -90,9 +90,12 @@ typedef struct {
  * context is made: CVAMX_PROJ_BLOCKS (blocks of the page-streaming
  * projection passes; default 8 per compute unit) and CVAMX_GRAM_BLOCKS
  * (blocks of the PCA Gram pass; default one resident round for uint16
- * pages on the matrix cores, 4 per compute unit otherwise).  The images and
- * ranges do not depend on them; the PCA covariance may change in its last
- * bits (another summation order). */
+ * pages on the matrix cores, 4 per compute unit otherwise; for the exact
+ * integer covariance of uint16 pages it is raised where needed so that no
+ * block covers more than 2^21 pixels).  The images and ranges do not
+ * depend on them; the PCA covariance may change in its last bits (another
+ * summation order), except that of uint16 pages on the matrix cores, which
+ * is exact. */
 int cvamx_create(cvamx_ctx** out, int device);
 void cvamx_destroy(cvamx_ctx* ctx);
 const char* cvamx_status_str(int status);

@@ -12,7 +12,9 @@ import os
 
 import torch  # noqa: F401  (loads the HIP runtime before libcvamx)
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcvamx.so")
+# CVAMX_LIB_PATH selects another build of the same library (the host-sanitizer
+# build the tests make); by default the in-tree one.
+LIB_PATH = os.environ.get("CVAMX_LIB_PATH") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcvamx.so")
 
 OK = 0
 E_INVALID_ARG = -1

@@ -72,5 +72,34 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_host_sanitized(out_dir: str) -> str:
+    """The library with its host code (argument checks, scratch management,
+    the FP64 finisher, the page pipeline) built by g++ with AddressSanitizer
+    and UndefinedBehaviorSanitizer, linked with the device objects of the
+    regular build (built first if missing).  Returns the path of
+    libcvamx_asan.so in out_dir; load it with CVAMX_LIB_PATH pointing at it
+    and the sanitizer runtime preloaded."""
+    if not all(os.path.exists(os.path.join(BUILD, s + ".o")) for s in HIP_SOURCES):
+        build()
+    hipcc = _hipcc()
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(hipcc)))
+    os.makedirs(out_dir, exist_ok=True)
+    san = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined"]
+    objs = []
+    jobs = []
+    for src in HOST_SOURCES:
+        obj = os.path.join(out_dir, src + ".asan.o")
+        jobs.append(["g++", "-O1", "-g", "-std=c++17", "-fPIC", *san, "-Wall", "-D__HIP_PLATFORM_AMD__",
+                     "-I", os.path.join(rocm, "include"), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+                     "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        list(ex.map(_run, jobs))
+    lib = os.path.join(out_dir, "libcvamx_asan.so")
+    _run(["g++", "-shared", *san, "-o", lib, *objs, *[os.path.join(BUILD, s + ".o") for s in HIP_SOURCES],
+          "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(rocm, "lib")])
+    return lib
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))

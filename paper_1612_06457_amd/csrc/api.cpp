@@ -1059,6 +1059,11 @@ int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t
   const int per_cu = (!vector_path && cube->dtype == CVAMX_U16) ? cvx::pca_u16_blocks_per_cu(B) : 4;
   int nblocks = ctx->gram_blocks > 0 ? ctx->gram_blocks : ctx->num_cu * per_cu;
   nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(nblocks, (P + cvx::kChunk - 1) / cvx::kChunk));
+  // the exact integer Gram of uint16 pages needs every block to cover fewer
+  // than 2^22 pixels (its LDS sums stay integers below 2^53): a smaller grid,
+  // asked for through CVAMX_GRAM_BLOCKS, is raised to keep at most 2^21
+  if (!vector_path && cube->dtype == CVAMX_U16)
+    nblocks = (int)std::max<int64_t>(nblocks, (P + (int64_t(1) << 21) - 1) >> 21);
   const size_t res_bytes = 8 * (size_t)B + 8 * (size_t)L;
   if (int st = ensure(ctx, B_PART, (size_t)nblocks * L * 8)) return st;
   if (int st = ensure(ctx, B_RES, res_bytes)) return st;

@@ -681,3 +681,31 @@ def test_full_half_page_4096x4096x23(dev, kind):
     assert rel_max(cov, pr["cov"]) <= 10 * BOUND_EXACT + TOL_S
     check_pca_vectors(V, pr, tol_s=10 * BOUND_EXACT + TOL_S)
     say(f"{kind} pca ok")
+
+
+def test_pca_u16_exact_with_a_one_block_gram(dev):
+    """CVAMX_GRAM_BLOCKS=1 on a uint16 page of 4.4 M pixels (over the 2^22
+    pixels one block of the exact integer Gram may cover): the library
+    raises the grid, and the covariance stays exact (within 1e-11 of the
+    oracle's largest entry, as at every other grid).  Run in a fresh process,
+    since the variable is read when the context is made."""
+    say("PCA u16 with CVAMX_GRAM_BLOCKS=1, 2200 x 2000 x 5")
+    import os
+    import subprocess
+    code = r"""
+import sys, numpy as np, torch
+sys.path.insert(0, %r)
+import oracle, paper_1612_06457_amd as cx
+rng = np.random.default_rng(3)
+x = rng.integers(0, 65536, (2200, 2000, 5)).astype(np.uint16)
+x[:, :, 1] = (x[:, :, 0] // 2 + rng.integers(0, 4000, (2200, 2000))).astype(np.uint16)
+pr = oracle.pca_fit(x, n_comp=3)
+V, lam, mean, cov = cx.pca_fit(torch.from_numpy(x).cuda(), n_comp=3)
+err = np.max(np.abs(cov - pr["cov"])) / np.max(np.abs(pr["cov"]))
+print("cov_err", err, flush=True)
+assert err <= 1e-11
+""" % os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, CVAMX_GRAM_BLOCKS="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240)
+    say(r.stdout.strip()[-200:])
+    assert r.returncode == 0, (r.stdout + r.stderr)[-3000:]
