@@ -229,6 +229,17 @@ def read_bandwidth(cx, torch, buf) -> float:
     return buf.numel() * buf.element_size() / (ms * 1e-3) / 1e9
 
 
+def mix_bandwidth(cx, torch, buf, write_bytes: int) -> float:
+    """GB/s (bytes read + bytes written) of the library's mixed reference
+    stream: `buf` read once and `write_bytes` written once, the writes spread
+    evenly over the reads; the ceiling of a pass with that read/write mix."""
+    dst = torch.empty(write_bytes, dtype=torch.uint8, device=buf.device)
+    sink = torch.zeros(1, dtype=torch.int32, device=buf.device)
+    ms = _timed(torch, lambda: cx.stream_mix(buf, dst, sink))
+    del dst
+    return (buf.numel() * buf.element_size() + write_bytes) / (ms * 1e-3) / 1e9
+
+
 def config2_page(cx, torch, dev):
     """The 4096 x 4096 x 23 uint16 page, 4 classes, 200,000 training pixels:
     CVA fit + project (default, two reads, plain FP32), PCA fit and project."""
@@ -393,6 +404,9 @@ def main():
     ap.add_argument("--copy-gib", type=int, default=0,
                     help="after the timed steps, copy this many GiB device to device (a plain copy of "
                          "known size, to calibrate hardware byte counters against)")
+    ap.add_argument("--only", default=None,
+                    choices=["cva_pca_4096x4096x23_u16_k4", "cva_mixed_4096x4096x23_half_k4", "soft_1000000x23_k5"],
+                    help="time only this workload (no headline line): for profiling its kernels")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no multi-GPU "
@@ -404,6 +418,13 @@ def main():
     from synth import make_case, soft_weights, border_map
 
     dev = torch.device("cuda:0")
+    if args.only is not None:
+        fn = {"cva_pca_4096x4096x23_u16_k4": config2_page, "cva_mixed_4096x4096x23_half_k4": mixed_half_pages,
+              "soft_1000000x23_k5": config4_soft}[args.only]
+        print(json.dumps({"workload": args.only, "results": fn(cx, torch, dev)}), flush=True)
+        if args.copy_gib > 0:
+            copy_bandwidth(torch, args.copy_gib)
+        return
     t0 = time.time()
     case = make_case(5, threads=16)
     log(f"page generated in {time.time() - t0:.1f}s: {case.H}x{case.W}x{case.B} u16, K={case.K}")
@@ -486,11 +507,12 @@ def main():
     n_str, ms_str = prof.get(f"project_stretch_stored_nc{C}", (0, 0.0))
     rng_bytes = cube_bytes + 2 * P * C
     str_bytes = 2 * P * C + P * C
+    plane_bytes = (2 * P * C) // 16 * 16
     avg_rng = ms_rng / max(n_rng, 1)
     avg_str = ms_str / max(n_str, 1)
     achieved = rng_bytes / (avg_rng * 1e-3) / 1e9 if avg_rng > 0 else 0.0
     train_bytes = labels.numel() + N * B * 2
-    # the survey's algorithmic bytes of fit + project (two page reads + the
+    # the nominal algorithmic bytes of fit + project (two page reads + the
     # images), and the bytes the one-read schedule itself moves
     alg_bytes = 2 * cube_bytes + P * C + train_bytes
     sched_bytes = cube_bytes + 2 * (2 * P * C) + P * C + train_bytes
@@ -550,7 +572,10 @@ def main():
     }
     read_gbs = read_bandwidth(cx, torch, cube)
     copy_gbs = copy_bandwidth(torch)
+    mix_gbs = mix_bandwidth(cx, torch, cube, plane_bytes)
     roof["measured_read_GBps"] = round(read_gbs, 1)
+    roof["measured_mix_GBps"] = round(mix_gbs, 1)
+    roof["frac_of_measured_mix"] = round(achieved / mix_gbs, 4)
     roof["measured_copy_GBps"] = round(copy_gbs, 1)
     roof["frac_of_measured_read"] = round(achieved / read_gbs, 4)
     roof["fit_plus_project"]["frac_of_measured_read_schedule_bytes"] = round(

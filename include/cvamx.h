@@ -474,6 +474,17 @@ int cvamx_set_schedule(cvamx_ctx* ctx, int schedule);
 int cvamx_stream_read(cvamx_ctx* ctx, const void* src, int64_t bytes,
                       uint32_t* sink, void* stream);
 
+/* The ceiling for a pass that writes as it reads: the stream above over
+ * read_bytes of src, and, spread evenly over it, write_bytes of dst (device,
+ * 16-byte aligned, write_bytes <= read_bytes, both positive multiples of
+ * 16) written once with non-temporal 16-byte stores of the words just read.
+ * dst's contents afterwards are unspecified.  Bad sizes:
+ * CVAMX_E_INVALID_ARG; misaligned pointers: CVAMX_E_UNSUPPORTED.
+ * Asynchronous on `stream`. */
+int cvamx_stream_mix(cvamx_ctx* ctx, const void* src, int64_t read_bytes,
+                     void* dst, int64_t write_bytes, uint32_t* sink,
+                     void* stream);
+
 /* ---- kernel timing ------------------------------------------------------ */
 
 /* Per-kernel timing on this context: with enable = 1 every kernel the

@@ -628,6 +628,27 @@ def stream_read(buf: torch.Tensor, sink: Optional[torch.Tensor] = None) -> None:
     check(lib().cvamx_stream_read(ctx, _ptr(buf), nbytes, _ptr(sink), _stream(buf.device)), ctx)
 
 
+def stream_mix(src: torch.Tensor, dst: torch.Tensor, sink: Optional[torch.Tensor] = None) -> None:
+    """Read every byte of src once and write every byte of dst once, the
+    writes spread evenly over the reads (the ceiling of a pass that writes
+    as it reads in that proportion); dst's contents afterwards are
+    unspecified.  Asynchronous on torch's current stream."""
+    for name, t in (("src", src), ("dst", dst)):
+        if t.device.type != "cuda" or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous device tensor")
+    if dst.device != src.device:
+        raise ValueError("dst must be on src's device")
+    nr, nw = src.numel() * src.element_size(), dst.numel() * dst.element_size()
+    if nr < 16 or nr % 16 != 0 or nw < 16 or nw % 16 != 0 or nw > nr:
+        raise ValueError("src and dst must hold positive multiples of 16 bytes, dst no more than src")
+    if sink is None:
+        sink = torch.zeros(1, dtype=torch.int32, device=src.device)
+    elif sink.device != src.device or sink.dtype != torch.int32 or sink.numel() < 1:
+        raise ValueError("sink must be an int32 tensor on src's device")
+    ctx = context(_dev_index(src))
+    check(lib().cvamx_stream_mix(ctx, _ptr(src), nr, _ptr(dst), nw, _ptr(sink), _stream(src.device)), ctx)
+
+
 _SCHEDULES = {"auto": 0, "two_reads": 1, "force_reread": 2}
 
 

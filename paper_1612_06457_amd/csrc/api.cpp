@@ -1299,6 +1299,25 @@ int cvamx_stream_read(cvamx_ctx* ctx, const void* src, int64_t bytes, uint32_t* 
   return CVAMX_OK;
 }
 
+int cvamx_stream_mix(cvamx_ctx* ctx, const void* src, int64_t read_bytes, void* dst, int64_t write_bytes,
+                     uint32_t* sink, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (!src || !dst || !sink) return fail(ctx, CVAMX_E_INVALID_ARG, "src, dst and sink must be non-NULL");
+  if (read_bytes < 16 || read_bytes % 16 != 0 || write_bytes < 16 || write_bytes % 16 != 0)
+    return fail(ctx, CVAMX_E_INVALID_ARG, "read_bytes and write_bytes must be positive multiples of 16");
+  if (write_bytes > read_bytes) return fail(ctx, CVAMX_E_INVALID_ARG, "write_bytes must not exceed read_bytes");
+  if ((reinterpret_cast<uintptr_t>(src) & 15u) != 0 || (reinterpret_cast<uintptr_t>(dst) & 15u) != 0 ||
+      (reinterpret_cast<uintptr_t>(sink) & 3u) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "src and dst must be 16-byte aligned and sink 4-byte aligned");
+  if (int st = check_device(ctx)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  prof_begin(ctx, s, "stream_mix");
+  hipError_t e = cvx::launch_stream_mix(src, read_bytes, dst, write_bytes, 0x9e3779b9u, sink, ctx->num_cu, s);
+  prof_end(ctx, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "stream mix launch");
+  return CVAMX_OK;
+}
+
 int cvamx_set_schedule(cvamx_ctx* ctx, int schedule) {
   if (!ctx) return CVAMX_E_INVALID_ARG;
   if (schedule != CVAMX_SCHEDULE_AUTO && schedule != CVAMX_SCHEDULE_TWO_READS &&

@@ -7,13 +7,16 @@
 // Both passes stream the band-interleaved cube in wave tiles (k_tile.hpp);
 // the next tile's loads are issued before the current one is computed.
 // Each lane reads its own S dwords from LDS (with S odd those reads hit
-// distinct banks).  y_j = sum_b W[b][j] (x_b - c_b) + off_j is accumulated
+// distinct banks), and each band's centre and weights as broadcast LDS
+// reads of a per-block table.  y_j = sum_b W[b][j] (x_b - c_b) + off_j is accumulated
 // in FP32.  Pass 1 keeps running min/max per component; the last block to
 // finish combines the block partials (all its threads, fixed assignment)
 // and stores the affine map of the stretch, q = floor(y s + o) with
 // s = 255 / (b - a), o = 1/2 - a s.  Pass 2 recomputes y bit for bit,
 // quantises, clamps to 0..255 and writes planar bytes.
 #pragma once
+#include <algorithm>
+
 #include "k_stored.hpp"
 #include "k_tile.hpp"
 #include "launch.hpp"
@@ -40,48 +43,87 @@ __device__ __forceinline__ float centred_hi(uint32_t d, float cb) {
   }
 }
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// 16-byte band records per band: the centre c_b, then W[b][0..NC), zero
+// padded.
 template <int NC>
-__device__ __forceinline__ void accum(float (&acc)[NC], const ProjArgs& a, int b, float x) {
-#pragma unroll
-  for (int j = 0; j < NC; ++j) acc[j] = fmaf(a.w[b * NC + j], x, acc[j]);
+constexpr int band_f4() { return (NC + 4) / 4; }
+
+// The band records, staged once per block from the kernel arguments: in the
+// band loop each band's centre and weights are then broadcast 16-byte LDS
+// reads (scalar loads of the arguments at a runtime band index serialised
+// that loop on the scalar cache).
+template <int NC>
+__device__ __forceinline__ void stage_bands(const ProjArgs& a, int B, f4v* __restrict__ rec) {
+  constexpr int F = 4 * band_f4<NC>();
+  for (int i = threadIdx.x; i < B * F; i += kBlock) {
+    const int b = i / F, k = i - b * F;
+    reinterpret_cast<float*>(rec)[i] = k == 0 ? a.c[b] : (k <= NC ? a.w[b * NC + k - 1] : 0.f);
+  }
+  __syncthreads();
 }
 
-// y for the lane group at LDS dwords d[0..S): acc0 gets pixel 0, acc1 pixel 1.
+template <int NC>
+__device__ __forceinline__ void band(const f4v* __restrict__ rec, int b, float& c, float (&wv)[NC]) {
+  constexpr int R = band_f4<NC>();
+  f4v r[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) r[k] = rec[b * R + k];
+  c = r[0][0];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) wv[j] = r[(j + 1) >> 2][(j + 1) & 3];
+}
+
+template <int NC>
+__device__ __forceinline__ void fma_band(float (&acc)[NC], const float (&wv)[NC], float x) {
+#pragma unroll
+  for (int j = 0; j < NC; ++j) acc[j] = fmaf(wv[j], x, acc[j]);
+}
+
+// y for the lane group at LDS dwords d[0..S): acc0 gets pixel 0, acc1 pixel
+// 1; each pixel's bands are added in ascending order.
 template <int DT, int NC>
-__device__ __forceinline__ void project_group(const uint32_t* __restrict__ d, int B,
-                                              const ProjArgs& a, float (&acc0)[NC],
-                                              float (&acc1)[NC]) {
+__device__ __forceinline__ void project_group(const uint32_t* __restrict__ d, int B, const f4v* __restrict__ rec,
+                                              const ProjArgs& a, float (&acc0)[NC], float (&acc1)[NC]) {
 #pragma unroll
   for (int j = 0; j < NC; ++j) {
     acc0[j] = a.off[j];
     acc1[j] = a.off[j];
   }
+  float c, wv[NC];
   if constexpr (DT == DT_F32) {
-    for (int b = 0; b < B; ++b) accum<NC>(acc0, a, b, __uint_as_float(d[b]) - a.c[b]);
+    for (int b = 0; b < B; ++b) {
+      band<NC>(rec, b, c, wv);
+      fma_band<NC>(acc0, wv, __uint_as_float(d[b]) - c);
+    }
   } else {
     if (!(B & 1)) {
       for (int q = 0; q < B / 2; ++q) {
         const uint32_t v = d[q];
-        accum<NC>(acc0, a, 2 * q, centred_lo<DT>(v, a.c[2 * q]));
-        accum<NC>(acc0, a, 2 * q + 1, centred_hi<DT>(v, a.c[2 * q + 1]));
+        band<NC>(rec, 2 * q, c, wv);
+        fma_band<NC>(acc0, wv, centred_lo<DT>(v, c));
+        band<NC>(rec, 2 * q + 1, c, wv);
+        fma_band<NC>(acc0, wv, centred_hi<DT>(v, c));
       }
     } else {
+      // two pixels of B (odd) bands in 2B halves: pixel 0's band b is half
+      // b, pixel 1's is half B + b, so one band record serves both pixels
       const int h = (B - 1) / 2;
+      uint32_t carry = d[h];   // high half: pixel 1, band 0
       for (int q = 0; q < h; ++q) {
-        const uint32_t v = d[q];
-        accum<NC>(acc0, a, 2 * q, centred_lo<DT>(v, a.c[2 * q]));
-        accum<NC>(acc0, a, 2 * q + 1, centred_hi<DT>(v, a.c[2 * q + 1]));
+        const uint32_t v = d[q], nxt = d[h + q + 1];
+        band<NC>(rec, 2 * q, c, wv);
+        fma_band<NC>(acc0, wv, centred_lo<DT>(v, c));
+        fma_band<NC>(acc1, wv, centred_hi<DT>(carry, c));
+        band<NC>(rec, 2 * q + 1, c, wv);
+        fma_band<NC>(acc0, wv, centred_hi<DT>(v, c));
+        fma_band<NC>(acc1, wv, centred_lo<DT>(nxt, c));
+        carry = nxt;
       }
-      {
-        const uint32_t v = d[h];
-        accum<NC>(acc0, a, B - 1, centred_lo<DT>(v, a.c[B - 1]));
-        accum<NC>(acc1, a, 0, centred_hi<DT>(v, a.c[0]));
-      }
-      for (int q = h + 1; q < B; ++q) {
-        const uint32_t v = d[q];
-        accum<NC>(acc1, a, 2 * q - B, centred_lo<DT>(v, a.c[2 * q - B]));
-        accum<NC>(acc1, a, 2 * q + 1 - B, centred_hi<DT>(v, a.c[2 * q + 1 - B]));
-      }
+      band<NC>(rec, B - 1, c, wv);
+      fma_band<NC>(acc0, wv, centred_lo<DT>(d[h], c));
+      fma_band<NC>(acc1, wv, centred_hi<DT>(carry, c));
     }
   }
 }
@@ -99,9 +141,11 @@ __device__ __forceinline__ void tile_loop(const void* __restrict__ cube, int B, 
   const int64_t nt = (P + tp - 1) / tp;
   const int64_t total_bytes = P * B * Geo<DT>::esize;
   const unsigned char* base = reinterpret_cast<const unsigned char*>(cube);
+  __shared__ f4v rec[kMaxB * band_f4<NC>()];
+  stage_bands<NC>(a, B, rec);
   for_each_tile<Q>(base, total_bytes, nt, S, my, [&](int64_t t) {
     float y0[NC], y1[NC];
-    project_group<DT, NC>(my + lane * S, B, a, y0, y1);
+    project_group<DT, NC>(my + lane * S, B, rec, a, y0, y1);
     body(t * tp + (int64_t)lane * g2, g2, y0, y1);
   });
 }
@@ -135,13 +179,13 @@ __global__ __launch_bounds__(kBlock) void k_project_range(const void* __restrict
         for (int j = 0; j < NC; ++j) {
           const uint32_t v = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(y0[j] * h.f[j])) |
                              ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(y1[j] * h.f[j])) << 16);
-          __builtin_nontemporal_store(v, reinterpret_cast<uint32_t*>(planes + (int64_t)j * Pp + pix));
+          *reinterpret_cast<uint32_t*>(planes + (int64_t)j * Pp + pix) = v;
         }
       } else {
 #pragma unroll
         for (int j = 0; j < NC; ++j)
-          __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, (_Float16)(y0[j] * h.f[j])),
-                                      reinterpret_cast<uint16_t*>(planes + (int64_t)j * Pp + pix));
+          *reinterpret_cast<uint16_t*>(planes + (int64_t)j * Pp + pix) =
+              __builtin_bit_cast(uint16_t, (_Float16)(y0[j] * h.f[j]));
       }
     }
     if (pix < P) {
@@ -339,6 +383,24 @@ inline size_t smem_bytes(int dtype, int B) {
   return (size_t)kWaves * 64 * S * 4;
 }
 
+// The grid of a persistent pass: at most the blocks that are resident at
+// once (a second round of blocks would run its tiles after the first with
+// the device half idle), and at most nblocks.
+inline int resident_grid(const void* kernel, size_t sm, int nblocks) {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, sm) != hipSuccess || per < 1)
+    return nblocks;
+  return std::max(1, std::min(nblocks, per * ncu));
+}
+
+#define CVX_LAUNCH(KERNEL, SM, NB, S, ...)                                                     \
+  do {                                                                                         \
+    const int nb_ = resident_grid(reinterpret_cast<const void*>(&KERNEL), SM, NB);             \
+    hipLaunchKernelGGL(KERNEL, dim3(nb_), dim3(kBlock), SM, S, __VA_ARGS__);                    \
+  } while (0)
+
 // Launch a pass's kernel for one element type with the exact component count.
 template <int DT, bool H16 = false>
 hipError_t range_nc(int nc, const void* cube, int B, int64_t P, const ProjArgs& a, int nblocks, float* part,
@@ -349,10 +411,10 @@ hipError_t range_nc(int nc, const void* cube, int B, int64_t P, const ProjArgs& 
 #define CVX_RANGE(N)                                                                                          \
   case N:                                                                                                     \
     if (q == 8)                                                                                               \
-      hipLaunchKernelGGL((k_project_range<DT, N, H16, 8>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a, \
+      CVX_LAUNCH((k_project_range<DT, N, H16, 8>), sm, nblocks, s, cube, B, P, a, \
                          part, ticket, range_dev, ab_dev, h, planes, Pp);                                    \
     else                                                                                                      \
-      hipLaunchKernelGGL((k_project_range<DT, N, H16, kMaxQ>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, \
+      CVX_LAUNCH((k_project_range<DT, N, H16, kMaxQ>), sm, nblocks, s, cube, B, P, \
                          a, part, ticket, range_dev, ab_dev, h, planes, Pp);                                 \
     break;
   switch (nc) {
@@ -372,10 +434,10 @@ hipError_t stretch_nc(int nc, const void* cube, int B, int64_t P, const ProjArgs
 #define CVX_STRETCH(N)                                                                                        \
   case N:                                                                                                     \
     if (q == 8)                                                                                               \
-      hipLaunchKernelGGL((k_project_stretch<DT, N, 8>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a,    \
+      CVX_LAUNCH((k_project_stretch<DT, N, 8>), sm, nblocks, s, cube, B, P, a,    \
                          range_dev, images);                                                                  \
     else                                                                                                      \
-      hipLaunchKernelGGL((k_project_stretch<DT, N, kMaxQ>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a, \
+      CVX_LAUNCH((k_project_stretch<DT, N, kMaxQ>), sm, nblocks, s, cube, B, P, a, \
                          range_dev, images);                                                                  \
     break;
   switch (nc) {
@@ -397,10 +459,10 @@ hipError_t stretch_h16_nc(int nc, const void* cube, int B, int64_t P, const Proj
 #define CVX_STRETCH(N)                                                                                        \
   case N:                                                                                                     \
     if (q == 8)                                                                                               \
-      hipLaunchKernelGGL((k_project_stretch_h16<DT, N, 8>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a, \
+      CVX_LAUNCH((k_project_stretch_h16<DT, N, 8>), sm, nblocks, s, cube, B, P, a, \
                          range_dev, planes, Pp, images);                                                      \
     else                                                                                                      \
-      hipLaunchKernelGGL((k_project_stretch_h16<DT, N, kMaxQ>), dim3(nblocks), dim3(kBlock), sm, s, cube, B,   \
+      CVX_LAUNCH((k_project_stretch_h16<DT, N, kMaxQ>), sm, nblocks, s, cube, B,   \
                          P, a, range_dev, planes, Pp, images);                                                \
     break;
   switch (nc) {
@@ -421,9 +483,9 @@ hipError_t float_nc(int nc, const void* cube, int B, int64_t P, const ProjArgs& 
 #define CVX_FLOAT(N)                                                                                          \
   case N:                                                                                                     \
     if (q == 8)                                                                                               \
-      hipLaunchKernelGGL((k_project_float<DT, N, 8>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a, y);  \
+      CVX_LAUNCH((k_project_float<DT, N, 8>), sm, nblocks, s, cube, B, P, a, y);  \
     else                                                                                                      \
-      hipLaunchKernelGGL((k_project_float<DT, N, kMaxQ>), dim3(nblocks), dim3(kBlock), sm, s, cube, B, P, a, y); \
+      CVX_LAUNCH((k_project_float<DT, N, kMaxQ>), sm, nblocks, s, cube, B, P, a, y); \
     break;
   switch (nc) {
     CVX_FLOAT(1) CVX_FLOAT(2) CVX_FLOAT(3) CVX_FLOAT(4) CVX_FLOAT(5) CVX_FLOAT(6) CVX_FLOAT(7) CVX_FLOAT(8)

@@ -193,6 +193,8 @@ void* scratch_address(int device);
 // the reference read stream: bytes (a multiple of 16) from src, once
 hipError_t launch_stream_read(const void* src, int64_t bytes, uint32_t key, uint32_t* sink, int num_cu,
                               hipStream_t s);
+hipError_t launch_stream_mix(const void* src, int64_t read_bytes, void* dst, int64_t write_bytes, uint32_t key,
+                             uint32_t* sink, int num_cu, hipStream_t s);
 
 // n bytes from device memory to page-locked host memory, by a kernel
 hipError_t launch_copy_out(void* dst, const void* src, int64_t n, hipStream_t s);

@@ -213,3 +213,29 @@ def test_float_page_beyond_the_assumed_range_falls_back(dev):
     q2, ab2 = _run(cx, cd, Wm, center, "two_reads")
     assert np.array_equal(ab1, ab2)
     assert np.array_equal(q1, q2), "the overflow check did not send pass 2 back to the page"
+
+
+@pytest.mark.parametrize("nr,nw", [(1 << 20, 1 << 20), (3 << 20, 1 << 19), (123456 * 16, 777 * 16), (4096, 16)])
+def test_reference_streams(dev, nr, nw):
+    """The measurement streams run to completion on any size; with equal
+    sizes the mixed stream writes tile t of the output from read tile t,
+    i.e. it copies; with fewer write bytes every write tile is written."""
+    say(f"reference streams: read {nr} B, write {nw} B")
+    import torch
+    import paper_1612_06457_amd as cx
+    g = torch.Generator(device="cpu").manual_seed(nr ^ nw)
+    src = torch.randint(0, 256, (nr,), dtype=torch.uint8, generator=g).to(dev)
+    sink = torch.zeros(1, dtype=torch.int32, device=dev)
+    cx.stream_read(src, sink)
+    dst = torch.zeros(nw, dtype=torch.uint8, device=dev)
+    cx.stream_mix(src, dst, sink)
+    torch.cuda.synchronize()
+    if nw == nr:
+        assert torch.equal(dst, src)
+    else:
+        # each written 16-byte chunk is some chunk of the source
+        d = dst.view(-1, 16).cpu().numpy()
+        s = {bytes(r) for r in src.view(-1, 16).cpu().numpy()}
+        assert all(bytes(r) in s for r in d)
+    with pytest.raises(ValueError):
+        cx.stream_mix(src[:16], dst if nw > 16 else torch.zeros(32, dtype=torch.uint8, device=dev))

@@ -292,6 +292,19 @@ def test_argument_checks_without_a_device():
         assert rp(mode=5) == L.E_INVALID_ARG
         assert rp(bits=4) == L.E_INVALID_ARG
         assert rp() == L.E_DEVICE
+        # reference streams
+        sk = ctypes.c_void_p(0xb0000)
+        a16, b16 = ctypes.c_void_p(0xc0000), ctypes.c_void_p(0xd0000)
+        assert lib.cvamx_stream_read(ctx, None, 64, sk, None) == L.E_INVALID_ARG
+        assert lib.cvamx_stream_read(ctx, a16, 8, sk, None) == L.E_INVALID_ARG
+        assert lib.cvamx_stream_read(ctx, ctypes.c_void_p(0xc0008), 64, sk, None) == L.E_UNSUPPORTED
+        assert lib.cvamx_stream_read(ctx, a16, 64, sk, None) == L.E_DEVICE
+        assert lib.cvamx_stream_mix(ctx, a16, 64, None, 16, sk, None) == L.E_INVALID_ARG
+        assert lib.cvamx_stream_mix(ctx, a16, 64, b16, 0, sk, None) == L.E_INVALID_ARG
+        assert lib.cvamx_stream_mix(ctx, a16, 64, b16, 24, sk, None) == L.E_INVALID_ARG
+        assert lib.cvamx_stream_mix(ctx, a16, 64, b16, 80, sk, None) == L.E_INVALID_ARG
+        assert lib.cvamx_stream_mix(ctx, a16, 64, ctypes.c_void_p(0xd0004), 16, sk, None) == L.E_UNSUPPORTED
+        assert lib.cvamx_stream_mix(ctx, a16, 64, b16, 64, sk, None) == L.E_DEVICE
     finally:
         lib.cvamx_destroy(ctx)
     assert lib.cvamx_status_str(L.E_NOT_PD) == b"within-class scatter not positive definite"
