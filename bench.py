@@ -142,7 +142,7 @@ def _scheduled(cx, schedule, fn):
 def vs_plain(cx, torch, cube, labels, K, img, pimg, alg_bytes, sched_bytes, X, w, dw, P, B):
     """The headline call, the PCA calls and the soft-label passes on every
     path, all timed with one protocol (_timed): the default path (matrix
-    cores; one page read on uint16 pages), the same with two page reads,
+    cores; one page read), the same with two page reads,
     the plain FP32 reference path (FP32 vector-ALU kernels for the class
     moments, the covariance, the projections and the soft-label scatter and
     gradient) and the split requests (bf16x3 / f16x3).  Every path meets

@@ -425,7 +425,9 @@ int cva_soft_update(cvamx_ctx* ctx, const float* grad, float* w, int64_t N,
  * (cva_project, pca_project, cva_fit_project, cvamx_project_float), and
  * the two forward passes of cva_soft_forward.  By
  * default uint16 pages take the matrix cores with exactly split operands
- * and bf16 / fp16 pages take them for the projections; the plain path is
+ * for the moments and for projections of four or more components (up to
+ * three, the vector ALUs measured faster and project them), and the
+ * soft-label passes take the FP32 matrix instruction; the plain path is
  * the reference those paths are measured against (same FP32 accumulation,
  * so the same tolerances hold).  0 restores the default.  Host-only: never
  * fails for a valid context. */
@@ -437,18 +439,19 @@ int cvamx_set_plain_fp32(cvamx_ctx* ctx, int enable);
  * Section 2: the float arrays are rescaled onto 0..255 by their page-wide
  * min and max, so every value is needed twice: once for the range, once
  * for the map).
- *   CVAMX_SCHEDULE_AUTO (default): on uint16 pages (matrix-core path) the
- *     page is read once; pass 1 finds the range and stores every component
- *     value as fp16 (2 bytes per pixel and component, in scratch owned by
- *     the context: n_comp <= 8 planes of the page rounded up to 256
- *     pixels), pass 2 maps the stored values.  Pass 1 also bounds how far
- *     the fp16 rounding can move the argument of the map's floor:
- *     255 (2^-11 max(|a_j|, |b_j|) + tiny terms) / (b_j - a_j) grey levels,
- *     at most 0.125 when the center lies inside the page's projected range
- *     (the fit's mean always does).  Beyond 0.5 levels for some component
- *     pass 2 re-reads the page instead (decided on the device), so every
- *     byte stays within one level of the two-read result.  Other page
- *     types, and the plain FP32 path, read the page twice.
+ *   CVAMX_SCHEDULE_AUTO (default): the page is read once, for every page
+ *     type and on the plain FP32 path too; pass 1 finds the range and
+ *     stores every component value as fp16 (2 bytes per pixel and
+ *     component, in scratch owned by the context: n_comp <= 8 planes of
+ *     the page rounded up to 256 pixels), pass 2 maps the stored values.
+ *     Pass 1 also bounds how far the fp16 rounding can move the argument
+ *     of the map's floor: 255 (2^-11 max(|a_j|, |b_j|) + tiny terms) /
+ *     (b_j - a_j) grey levels, at most 0.125 when the center lies inside
+ *     the page's projected range (the fit's mean always does).  Beyond 0.5
+ *     levels for some component, or when a stored value could have
+ *     overflowed fp16, pass 2 re-reads the page instead (decided on the
+ *     device), so every byte stays within one level of the two-read
+ *     result.
  *   CVAMX_SCHEDULE_TWO_READS: the page is read twice (range, then map), as
  *     for the other page types.
  *   CVAMX_SCHEDULE_FORCE_REREAD: pass 1 of the one-read schedule, then the

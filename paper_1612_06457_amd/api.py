@@ -653,10 +653,10 @@ _SCHEDULES = {"auto": 0, "two_reads": 1, "force_reread": 2}
 
 
 def set_schedule(schedule: str = "auto", device: int = 0) -> None:
-    """How the projections read the page on `device`: "auto" (uint16 pages:
-    once, with an fp16 intermediate whose error bound is checked on the
-    device), "two_reads", or "force_reread" (the one-read pass 1, then its
-    page re-reading fallback; for tests)."""
+    """How the projections read the page on `device`: "auto" (once, with an
+    fp16 intermediate whose error bound is checked on the device, on every
+    page type), "two_reads", or "force_reread" (the one-read pass 1, then
+    its page re-reading fallback; for tests)."""
     if schedule not in _SCHEDULES:
         raise ValueError(f"schedule must be one of {sorted(_SCHEDULES)}")
     ctx = context(device)

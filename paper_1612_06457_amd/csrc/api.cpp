@@ -249,6 +249,16 @@ int proj_nblocks(cvamx_ctx* ctx, const cvamx_cube* cube) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(nblocks, (nt + cvx::kWaves - 1) / cvx::kWaves));
 }
 
+// Whether a group of nc components projects on the vector-ALU passes: on
+// the plain FP32 path, for every page type but uint16, and for uint16 pages
+// at up to three components, where the vector ALUs measured faster than the
+// matrix-core form (4096 x 4096 x 23 and 7216 x 5412 x 33 pages at three
+// components; from four on the matrix cores win, by 13 % at seven).
+constexpr int kU16VectorMaxComp = 3;
+bool proj_vector(const cvamx_ctx* ctx, const cvamx_cube* cube, int nc) {
+  return ctx->plain || cube->dtype != CVAMX_U16 || nc <= kU16VectorMaxComp;
+}
+
 // The kernel arguments of components g0 .. g0 + nc - 1.
 void make_proj_args(const cvamx_cube* cube, const double* W, const double* center, int n_comp, int g0, int nc,
                     bool plain, cvx::ProjArgs& a) {
@@ -309,8 +319,9 @@ int proj_groups_with(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, co
   const int nblocks = proj_nblocks(ctx, cube);
   for (int g0 = 0; g0 < n_comp; g0 += 8) {
     const int nc = std::min(8, n_comp - g0);   // the kernels are instantiated for 1..8 components
+    const bool pv = proj_vector(ctx, cube, nc);
     cvx::ProjArgs a;
-    make_proj_args(cube, W, center, n_comp, g0, nc, ctx->plain, a);
+    make_proj_args(cube, W, center, n_comp, g0, nc, pv, a);
     static const char* kRangeName[9] = {"", "project_range_nc1", "project_range_nc2", "project_range_nc3",
                                         "project_range_nc4", "project_range_nc5", "project_range_nc6",
                                         "project_range_nc7", "project_range_nc8"};
@@ -318,12 +329,12 @@ int proj_groups_with(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, co
                                           "project_stretch_nc4", "project_stretch_nc5", "project_stretch_nc6",
                                           "project_stretch_nc7", "project_stretch_nc8"};
     if (timed) prof_begin(ctx, s, kRangeName[nc]);
-    hipError_t e = cvx::launch_project_range(cube->dtype, ctx->plain, cube->data, B, P, nc, a, nblocks, pb.part,
+    hipError_t e = cvx::launch_project_range(cube->dtype, pv, cube->data, B, P, nc, a, nblocks, pb.part,
                                              pb.ticket, pb.range_dev, pb.ab_dev + 2 * g0, s);
     if (timed) prof_end(ctx, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "project range launch");
     if (timed) prof_begin(ctx, s, kStretchName[nc]);
-    e = cvx::launch_project_stretch(cube->dtype, ctx->plain, cube->data, B, P, nc, a, nblocks, pb.range_dev,
+    e = cvx::launch_project_stretch(cube->dtype, pv, cube->data, B, P, nc, a, nblocks, pb.range_dev,
                                     images + (int64_t)g0 * P, s);
     if (timed) prof_end(ctx, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "project stretch launch");
@@ -383,10 +394,11 @@ int proj_groups_h16(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, con
   const float limit = ctx->schedule == CVAMX_SCHEDULE_FORCE_REREAD ? -1.f : 0.5f;
   for (int g0 = 0; g0 < n_comp; g0 += 8) {
     const int nc = std::min(8, n_comp - g0);
+    const bool pv = proj_vector(ctx, cube, nc);
     cvx::ProjArgs a;
-    make_proj_args(cube, W, center, n_comp, g0, nc, ctx->plain, a);
+    make_proj_args(cube, W, center, n_comp, g0, nc, pv, a);
     cvx::H16Args h;
-    h16_args(a, center, B, nc, cube->dtype, cube->dtype == CVAMX_U16 && !ctx->plain, limit, h);
+    h16_args(a, center, B, nc, cube->dtype, cube->dtype == CVAMX_U16 && !pv, limit, h);
     static const char* kRangeName[9] = {"", "project_range_store_nc1", "project_range_store_nc2",
                                         "project_range_store_nc3", "project_range_store_nc4",
                                         "project_range_store_nc5", "project_range_store_nc6",
@@ -396,12 +408,12 @@ int proj_groups_h16(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W, con
                                           "project_stretch_stored_nc5", "project_stretch_stored_nc6",
                                           "project_stretch_stored_nc7", "project_stretch_stored_nc8"};
     prof_begin(ctx, s, kRangeName[nc]);
-    hipError_t e = cvx::launch_project_range_h16(cube->dtype, ctx->plain, cube->data, B, P, nc, a, nblocks, pb.part,
+    hipError_t e = cvx::launch_project_range_h16(cube->dtype, pv, cube->data, B, P, nc, a, nblocks, pb.part,
                                                  pb.ticket, pb.range_dev, pb.ab_dev + 2 * g0, h, planes, Pp, s);
     prof_end(ctx, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "project range launch");
     prof_begin(ctx, s, kStretchName[nc]);
-    e = cvx::launch_project_stretch_h16(cube->dtype, ctx->plain, cube->data, B, P, nc, a, nblocks, pb.range_dev,
+    e = cvx::launch_project_stretch_h16(cube->dtype, pv, cube->data, B, P, nc, a, nblocks, pb.range_dev,
                                         planes, Pp, images + (int64_t)g0 * P, s);
     prof_end(ctx, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "project stretch launch");
@@ -808,10 +820,11 @@ int cvamx_project_float(cvamx_ctx* ctx, const cvamx_cube* cube, const double* W,
   const int nblocks = proj_nblocks(ctx, cube);
   for (int g0 = 0; g0 < n_comp; g0 += 8) {
     const int nc = std::min(8, n_comp - g0);
+    const bool pv = proj_vector(ctx, cube, nc);
     cvx::ProjArgs a;
-    make_proj_args(cube, W, center, n_comp, g0, nc, ctx->plain, a);
+    make_proj_args(cube, W, center, n_comp, g0, nc, pv, a);
     prof_begin(ctx, s, "project_float");
-    hipError_t e = cvx::launch_project_float(cube->dtype, ctx->plain, cube->data, B, P, nc, a, nblocks,
+    hipError_t e = cvx::launch_project_float(cube->dtype, pv, cube->data, B, P, nc, a, nblocks,
                                              y + (int64_t)g0 * P, s);
     prof_end(ctx, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "project float launch");

@@ -88,13 +88,14 @@ hipError_t launch_reduce_part(const double* part, int nsets, int G, int L, doubl
 hipError_t launch_reduce_part_out(const double* part, int nsets, int G, int L, double* out_host,
                                   const void* hdr_src, void* hdr_dst, int64_t hdr_bytes, hipStream_t s);
 
-// projection, pass 1 (range) and pass 2 (stretch to uint8); plain = the
-// FP32 vector-ALU kernels whatever the page type (else float32 pages only)
-hipError_t launch_project_range(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
+// projection, pass 1 (range) and pass 2 (stretch to uint8); vector = the
+// FP32 vector-ALU kernels whatever the page type (else uint16 pages take the
+// matrix cores); the ProjArgs must be made for the same choice
+hipError_t launch_project_range(int dtype, bool vector, const void* cube, int B, int64_t P, int nc,
                                 const ProjArgs& a, int nblocks, float* part,
                                 unsigned* ticket, float* range_dev, float* ab_dev,
                                 hipStream_t s);
-hipError_t launch_project_stretch(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
+hipError_t launch_project_stretch(int dtype, bool vector, const void* cube, int B, int64_t P, int nc,
                                   const ProjArgs& a, int nblocks, const float* range_dev, uint8_t* images,
                                   hipStream_t s);
 
@@ -111,11 +112,11 @@ hipError_t launch_project_float_u16(const void* cube, int B, int64_t P, int nc, 
 
 // the one-read schedule for any page type (dispatching as the two-pass
 // launchers above): pass 1 also stores the fp16 planes, pass 2 maps them
-hipError_t launch_project_range_h16(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
+hipError_t launch_project_range_h16(int dtype, bool vector, const void* cube, int B, int64_t P, int nc,
                                     const ProjArgs& a, int nblocks, float* part, unsigned* ticket,
                                     float* range_dev, float* ab_dev, const H16Args& h, uint16_t* planes,
                                     int64_t Pp, hipStream_t s);
-hipError_t launch_project_stretch_h16(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
+hipError_t launch_project_stretch_h16(int dtype, bool vector, const void* cube, int B, int64_t P, int nc,
                                       const ProjArgs& a, int nblocks, const float* range_dev,
                                       const uint16_t* planes, int64_t Pp, uint8_t* images, hipStream_t s);
 // the one-read schedule on uint16 pages: pass 1 as launch_project_range_u16
@@ -160,7 +161,7 @@ hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_compose_rgb(const uint8_t* r, const uint8_t* g, const uint8_t* b, int64_t P, uint8_t* rgb,
                               int num_cu, hipStream_t s);
 // projection to FP32 planes (y[j][p] = w_j^T (x_p - c), n_comp x P)
-hipError_t launch_project_float(int dtype, bool plain, const void* cube, int B, int64_t P, int nc,
+hipError_t launch_project_float(int dtype, bool vector, const void* cube, int B, int64_t P, int nc,
                                 const ProjArgs& a, int nblocks, float* y, hipStream_t s);
 
 // cluster-separation indices: per class k of the class-grouped points,
