@@ -1145,7 +1145,15 @@ int cva_soft_forward(cvamx_ctx* ctx, const float* X, const float* w, int64_t N, 
   const int BP = cvx::padded_bp(B), KP = (K + 3) & ~3;
   const int L = cvx::tri_blocks(B) * 16;
   const int64_t nch = (N + cvx::kChunk - 1) / cvx::kChunk;
-  const int nb1 = (int)std::max<int64_t>(1, std::min<int64_t>(3 * ctx->num_cu, nch));
+  // pass 1 finds the shift the scatter centres each class on: the class
+  // means of a strided sample of about kSoftSampleChunks chunks (all of
+  // them when there are fewer).  Any shift is exact, since the scatter also
+  // sums w (x - s) and w and the host removes the shift in FP64; one near
+  // the class mean keeps the FP32 sums as small as the centred ones.
+  constexpr int64_t kSoftSampleChunks = 512;
+  const int64_t every = std::max<int64_t>(1, nch / kSoftSampleChunks);
+  const int64_t nsample = (nch + every - 1) / every;
+  const int nb1 = (int)std::max<int64_t>(1, std::min<int64_t>(3 * ctx->num_cu, nsample));
   // the scatter's path: FP32 products on the FP32 matrix instruction (the
   // default), the plain FP32 vector-ALU reference (cvamx_set_plain_fp32),
   // or the compensated bf16 / fp16 split on the 16-bit matrix units
@@ -1176,8 +1184,8 @@ int cva_soft_forward(cvamx_ctx* ctx, const float* X, const float* w, int64_t N, 
   char* res = static_cast<char*>(ctx->buf[B_RES]);
   char* f1 = static_cast<char*>(ctx->buf[B_FIRST]);
   prof_begin(ctx, s, plain ? "soft_first_plain" : "soft_first");
-  hipError_t e = plain ? cvx::launch_soft_first_plain(X, w, N, B, K, nb1, (double*)f1, s)
-                       : cvx::launch_soft_first(X, w, N, B, K, nb1, (double*)f1, s);
+  hipError_t e = plain ? cvx::launch_soft_first_plain(X, w, N, B, K, every, nb1, (double*)f1, s)
+                       : cvx::launch_soft_first(X, w, N, B, K, every, nb1, (double*)f1, s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "soft first launch");
   e = cvx::launch_reduce_part((const double*)f1, 1, nb1, KP * BP, (double*)(f1 + fp_off), s);

@@ -29,48 +29,57 @@ namespace {
 // Chunks ch = first, first + stride, ... of X and w, staged raw in LDS
 // (xr: kChunk B floats, wr: kChunk K floats), compute(ch, rows) per chunk
 // after a block barrier; a barrier follows it.  QX, QW bound the 16-byte
-// loads per thread of the two tiles.
+// loads per thread of the two tiles.  With every > 1 only the chunks
+// 0, every, 2 every, ... take part (chunk v of that sample is chunk
+// v every of X and w); stride and first count sample chunks.
 template <int QX, int QW, typename Compute>
 __device__ __forceinline__ void for_each_chunk(const float* __restrict__ X, const float* __restrict__ W, int64_t N,
                                                int B, int K, int64_t first, int64_t stride,
                                                uint32_t* __restrict__ xr, uint32_t* __restrict__ wr,
-                                               Compute compute) {
+                                               Compute compute, int64_t every = 1) {
   const int tid = threadIdx.x;
   const unsigned char* xb = reinterpret_cast<const unsigned char*>(X);
   const unsigned char* wb = reinterpret_cast<const unsigned char*>(W);
   const int xbytes = kChunk * B * 4, wbytes = kChunk * K * 4;
   const int64_t xtotal = N * B * 4, wtotal = N * K * 4;
-  const int64_t nch = (N + kChunk - 1) / kChunk;
+  const int64_t nall = (N + kChunk - 1) / kChunk;
+  const int64_t nch = (nall + every - 1) / every;   // sample chunks
   const int64_t nfull = N / kChunk;
-  auto rows_of = [&](int64_t ch) { return (int)(N - ch * kChunk < kChunk ? N - ch * kChunk : kChunk); };
+  auto rows_of = [&](int64_t c) { return (int)(N - c * kChunk < kChunk ? N - c * kChunk : kChunk); };
   int64_t ch = first;
   if (nfull == 0) {
     for (; ch < nch; ch += stride) {
-      copy_partial_tile<kBlock>(xb, xtotal, ch, xbytes, tid, xr);
-      copy_partial_tile<kBlock>(wb, wtotal, ch, wbytes, tid, wr);
+      copy_partial_tile<kBlock>(xb, xtotal, ch * every, xbytes, tid, xr);
+      copy_partial_tile<kBlock>(wb, wtotal, ch * every, wbytes, tid, wr);
       __syncthreads();
-      compute(ch, rows_of(ch));
+      compute(ch * every, rows_of(ch * every));
       __syncthreads();
     }
     return;
   }
-  auto next = [&](int64_t x, int64_t cur) { return x < nfull ? x : (cur < nfull ? cur : nfull - 1); };
+  // the chunk to prefetch for sample chunk x (a whole one: past the end the
+  // current, or the last whole chunk, whose loads are then not stored)
+  auto next = [&](int64_t x, int64_t cur) {
+    const int64_t a = x * every, c = cur * every;
+    return x < nch && a < nfull ? a : (c < nfull ? c : nfull - 1);
+  };
   u32x4 rx[QX], rw[QW];
   load_tile<QX, kBlock, false>(xb, next(ch, ch), xbytes, tid, rx);
   load_tile<QW, kBlock, false>(wb, next(ch, ch), wbytes, tid, rw);
   for (; ch < nch; ch += stride) {
-    if (ch < nfull) {
+    const int64_t a = ch * every;
+    if (a < nfull) {
       store_tile<QX, kBlock>(xr, xbytes, tid, rx);
       store_tile<QW, kBlock>(wr, wbytes, tid, rw);
     } else {
-      copy_partial_tile<kBlock>(xb, xtotal, ch, xbytes, tid, xr);
-      copy_partial_tile<kBlock>(wb, wtotal, ch, wbytes, tid, wr);
+      copy_partial_tile<kBlock>(xb, xtotal, a, xbytes, tid, xr);
+      copy_partial_tile<kBlock>(wb, wtotal, a, wbytes, tid, wr);
     }
     __syncthreads();
     load_tile<QX, kBlock, false>(xb, next(ch + stride, ch), xbytes, tid, rx);
     load_tile<QW, kBlock, false>(wb, next(ch + stride, ch), wbytes, tid, rw);
     __builtin_amdgcn_sched_barrier(0);   // keep the next chunk's loads ahead of the work
-    compute(ch, rows_of(ch));
+    compute(a, rows_of(a));
     __syncthreads();
   }
 }
@@ -89,7 +98,8 @@ __device__ __forceinline__ f32x4 mma_f32(float a, float b, f32x4 c) {
 // weights (the partial chunk is zero-filled), so they add nothing.
 template <int NCB, int NRB, int QX, int QW>
 __global__ __launch_bounds__(kBlock) void k_soft_first(const float* __restrict__ X, const float* __restrict__ W,
-                                                       int64_t N, int B, int K, double* __restrict__ part) {
+                                                       int64_t N, int B, int K, int64_t every,
+                                                       double* __restrict__ part) {
   extern __shared__ __align__(16) uint32_t lds[];
   uint32_t* xr = lds;                 // kChunk x B raw rows of X
   uint32_t* wr = lds + kChunk * B;    // kChunk x K raw rows of w
@@ -150,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_soft_first(const float* __restrict__
           acc[cb][rb][e] = 0.f;
         }
   };
-  for_each_chunk<QX, QW>(X, W, N, B, K, blockIdx.x, gridDim.x, xr, wr, body);
+  for_each_chunk<QX, QW>(X, W, N, B, K, blockIdx.x, gridDim.x, xr, wr, body, every);
   // waves in a fixed order into the block partial [c][j]
   const int L = KP * BP;
   for (int t = threadIdx.x; t < L; t += kBlock) red[t] = 0.0;
@@ -174,15 +184,35 @@ __global__ __launch_bounds__(kBlock) void k_soft_first(const float* __restrict__
 }
 
 // One block: from the reduced first moments (KP x BP, packed by class), the
-// moments n_c, t_c per class (first[c][0..B]) and the class means in FP32.
+// moments n_c, t_c per class (first[c][0..B]) and the shifts the scatter
+// centres each class on, in FP32: the class means of those moments.  When
+// the moments come from a sample of the pixels, a class whose weight in the
+// sample is not positive or below 10^-6 of the largest takes the weighted
+// mean of all classes instead (0 if the total weight is not positive).  Any
+// shift is exact for the scatter, which carries sum w (x - s) and sum w;
+// a shift close to the class mean only keeps its FP32 sums small.
 __global__ __launch_bounds__(kBlock) void k_soft_means(int B, int K, const double* __restrict__ fp,
                                                        double* __restrict__ first, float* __restrict__ mc_f) {
+  __shared__ double tot[kMaxB + 1];
+  __shared__ double nmax;
   const int BP = (B + 1 + 3) & ~3;
   for (int t = threadIdx.x; t < K * (B + 1); t += kBlock) first[t] = fp[(t / (B + 1)) * BP + t % (B + 1)];
+  for (int b = threadIdx.x; b <= B; b += kBlock) {
+    double v = 0.0;
+    for (int c = 0; c < K; ++c) v += fp[c * BP + b];
+    tot[b] = v;
+  }
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int c = 0; c < K; ++c) m = fmax(m, fp[c * BP + B]);
+    nmax = m;
+  }
+  __syncthreads();
   for (int t = threadIdx.x; t < K * B; t += kBlock) {
     const int c = t / B, b = t % B;
     const double n = fp[c * BP + B];
-    mc_f[t] = (n != 0.0) ? (float)(fp[c * BP + b] / n) : 0.f;
+    if (n > 0.0 && n >= 1e-6 * nmax) mc_f[t] = (float)(fp[c * BP + b] / n);
+    else mc_f[t] = tot[B] > 0.0 ? (float)(tot[b] / tot[B]) : 0.f;
   }
 }
 
@@ -416,7 +446,8 @@ __global__ __launch_bounds__(kBlock, (scatter_waves<NRB, QX, T, CPW>())) void k_
 // every entry has one owner, so the partial is written without a combine.
 template <int QX, int QW>
 __global__ __launch_bounds__(kBlock) void k_soft_first_valu(const float* __restrict__ X, const float* __restrict__ W,
-                                                            int64_t N, int B, int K, double* __restrict__ part) {
+                                                            int64_t N, int B, int K, int64_t every,
+                                                            double* __restrict__ part) {
   extern __shared__ __align__(16) uint32_t lds[];
   uint32_t* xr = lds;
   uint32_t* wr = lds + kChunk * B;
@@ -441,7 +472,7 @@ __global__ __launch_bounds__(kBlock) void k_soft_first_valu(const float* __restr
       accd[u] += (double)acc;
     }
   };
-  for_each_chunk<QX, QW>(X, W, N, B, K, blockIdx.x, gridDim.x, xr, wr, body);
+  for_each_chunk<QX, QW>(X, W, N, B, K, blockIdx.x, gridDim.x, xr, wr, body, every);
   double* mine = part + (int64_t)blockIdx.x * L;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -785,16 +816,18 @@ hipError_t scatter_nrb(const float* X, const float* w, int64_t N, int B, int K, 
 
 }  // namespace
 
-hipError_t launch_soft_first(const float* X, const float* w, int64_t N, int B, int K, int nblocks,
+hipError_t launch_soft_first(const float* X, const float* w, int64_t N, int B, int K, int64_t every, int nblocks,
                              double* part, hipStream_t s) {
-  if (B < 1 || B > kMaxB || K < 1 || K > 32 || nblocks < 1) return hipErrorInvalidValue;
+  if (B < 1 || B > kMaxB || K < 1 || K > 32 || nblocks < 1 || every < 1) return hipErrorInvalidValue;
   const int nrb = nrb_for(B);
   const bool small = B <= 40 && K <= 8;
   const size_t sm = first_smem(B, K);
   const dim3 grid(nblocks);
 #define CVX_F(NCB, NRB)                                                                                      \
-  if (small) hipLaunchKernelGGL((k_soft_first<NCB, NRB, 5, 1>), grid, dim3(kBlock), sm, s, X, w, N, B, K, part); \
-  else hipLaunchKernelGGL((k_soft_first<NCB, NRB, 8, 4>), grid, dim3(kBlock), sm, s, X, w, N, B, K, part);
+  if (small)                                                                                                 \
+    hipLaunchKernelGGL((k_soft_first<NCB, NRB, 5, 1>), grid, dim3(kBlock), sm, s, X, w, N, B, K, every, part);  \
+  else                                                                                                       \
+    hipLaunchKernelGGL((k_soft_first<NCB, NRB, 8, 4>), grid, dim3(kBlock), sm, s, X, w, N, B, K, every, part);
   if (K <= 16) {
     if (nrb == 2) { CVX_F(1, 2) } else if (nrb == 3) { CVX_F(1, 3) } else { CVX_F(1, 5) }
   } else {
@@ -834,14 +867,14 @@ hipError_t launch_soft_scatter(const float* X, const float* w, int64_t N, int B,
   }
 }
 
-hipError_t launch_soft_first_plain(const float* X, const float* w, int64_t N, int B, int K, int nblocks,
-                                   double* part, hipStream_t s) {
-  if (B < 1 || B > kMaxB || K < 1 || K > 32 || nblocks < 1) return hipErrorInvalidValue;
+hipError_t launch_soft_first_plain(const float* X, const float* w, int64_t N, int B, int K, int64_t every,
+                                   int nblocks, double* part, hipStream_t s) {
+  if (B < 1 || B > kMaxB || K < 1 || K > 32 || nblocks < 1 || every < 1) return hipErrorInvalidValue;
   const size_t sm = scatter_smem(B, K);
   if (B <= 40 && K <= 8)
-    hipLaunchKernelGGL((k_soft_first_valu<5, 1>), dim3(nblocks), dim3(kBlock), sm, s, X, w, N, B, K, part);
+    hipLaunchKernelGGL((k_soft_first_valu<5, 1>), dim3(nblocks), dim3(kBlock), sm, s, X, w, N, B, K, every, part);
   else
-    hipLaunchKernelGGL((k_soft_first_valu<8, 4>), dim3(nblocks), dim3(kBlock), sm, s, X, w, N, B, K, part);
+    hipLaunchKernelGGL((k_soft_first_valu<8, 4>), dim3(nblocks), dim3(kBlock), sm, s, X, w, N, B, K, every, part);
   return hipGetLastError();
 }
 

@@ -201,8 +201,9 @@ hipError_t launch_stream_mix(const void* src, int64_t read_bytes, void* dst, int
 hipError_t launch_copy_out(void* dst, const void* src, int64_t n, hipStream_t s);
 
 // soft-label CVA
-// pass 1: block partials of w^T [X, 1] (KP x BP each)
-hipError_t launch_soft_first(const float* X, const float* w, int64_t N, int B, int K, int nblocks,
+// pass 1: block partials of w^T [X, 1] (KP x BP each), over the chunks
+// 0, every, 2 every, ... of kChunk rows (every = 1: all of them)
+hipError_t launch_soft_first(const float* X, const float* w, int64_t N, int B, int K, int64_t every, int nblocks,
                              double* part, hipStream_t s);
 // from the reduced first moments fp (KP x BP): first[c][0..B] and the class
 // means in FP32
@@ -216,8 +217,8 @@ hipError_t launch_soft_scatter(const float* X, const float* w, int64_t N, int B,
 // the plain FP32 reference path of the two forward passes (vector ALU;
 // same outputs and layouts), and the split scatter on the bf16 (split 0) or
 // fp16 (split 1) matrix units
-hipError_t launch_soft_first_plain(const float* X, const float* w, int64_t N, int B, int K, int nblocks,
-                                   double* part, hipStream_t s);
+hipError_t launch_soft_first_plain(const float* X, const float* w, int64_t N, int B, int K, int64_t every,
+                                   int nblocks, double* part, hipStream_t s);
 hipError_t launch_soft_scatter_plain(const float* X, const float* w, int64_t N, int B, int K, int G,
                                      const float* mc_f, double* part, hipStream_t s);
 hipError_t launch_soft_scatter_split(int split, const float* X, const float* w, int64_t N, int B, int K, int G,
