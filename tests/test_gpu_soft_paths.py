@@ -151,3 +151,44 @@ def test_split_soft_config4_scale(dev):
         say(f"  {prec}: eigenvalue err {lerr:.2e} (bound {np.max(allowed / ref['eigvals']):.2e}), "
             f"J err {abs(fit.J - ref['J']) / ref['J']:.2e}")
         assert np.all(np.abs(fit.eigvals - ref["eigvals"]) <= allowed)
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_soft_shift_sample_misses_a_class(dev, plain):
+    """The class shifts come from a strided sample of the chunks of 128
+    pixels (every 4th chunk here, 2,048 chunks); a class whose weight lies
+    only in chunks outside the sample is shifted by the weighted mean of all
+    classes, far from its own mean, and the fit still meets the FP32 bars
+    (the scatter carries the shifted sums, so any shift is exact)."""
+    say(f"soft forward with a class outside the shift sample (plain={plain})")
+    import paper_1612_06457_amd as cx
+    N, B, K = 2048 * 128, 23, 5
+    rng = np.random.default_rng(11)
+    mu = rng.uniform(800, 3500, (K, B))
+    chunk = np.arange(N) // 128
+    cls = rng.integers(0, K - 1, N)
+    last = (chunk % 4 == 1) & (rng.random(N) < 0.5)
+    cls[last] = K - 1
+    X = (mu[cls] + rng.normal(0, 60, (N, B))).astype(np.float32)
+    w = 0.8 * np.eye(K)[cls]
+    w[:, : K - 1] += 0.2 * rng.dirichlet(np.full(K - 1, 0.5), N) * (~last)[:, None]
+    w[last, K - 1] = 1.0
+    w = w.astype(np.float32)
+    assert np.all(w[chunk % 4 == 0, K - 1] == 0)
+    ref = oracle.soft_fit(X, w)
+    Xd, wd = _t(X, dev), _t(w, dev)
+    cx.set_plain_fp32(plain)
+    try:
+        fit = cx.cva_soft_forward(Xd, wd)
+        g = cx.cva_soft_backward(Xd, fit, 1.0, K).cpu().numpy()
+    finally:
+        cx.set_plain_fp32(False)
+    lerr = np.max(np.abs(fit.eigvals - ref["eigvals"]) / ref["eigvals"])
+    g_ref = oracle.soft_grad(X, w)
+    gerr = np.max(np.abs(g - g_ref)) / np.max(np.abs(g_ref))
+    say(f"  eigenvalues {lerr:.2e}, class means {rel_max(fit.class_means, ref['class_means']):.2e}, gradient {gerr:.2e}")
+    assert abs(fit.J - ref["J"]) <= TOL_LAM * ref["J"]
+    assert lerr <= TOL_LAM
+    assert rel_max(fit.class_means, ref["class_means"]) <= 1e-6
+    check_cva_vectors(fit.W, ref)
+    assert gerr <= 1e-4
