@@ -425,9 +425,8 @@ int cva_soft_update(cvamx_ctx* ctx, const float* grad, float* w, int64_t N,
  * (cva_project, pca_project, cva_fit_project, cvamx_project_float), and
  * the two forward passes of cva_soft_forward.  By
  * default uint16 pages take the matrix cores with exactly split operands
- * for the moments and for projections of four or more components (up to
- * three, the vector ALUs measured faster and project them), and the
- * soft-label passes take the FP32 matrix instruction; the plain path is
+ * for the moments and the projections, and the soft-label passes take the
+ * FP32 matrix instruction; the plain path is
  * the reference those paths are measured against (same FP32 accumulation,
  * so the same tolerances hold).  0 restores the default.  Host-only: never
  * fails for a valid context. */

@@ -250,13 +250,12 @@ int proj_nblocks(cvamx_ctx* ctx, const cvamx_cube* cube) {
 }
 
 // Whether a group of nc components projects on the vector-ALU passes: on
-// the plain FP32 path, for every page type but uint16, and for uint16 pages
-// at up to three components, where the vector ALUs measured faster than the
-// matrix-core form (4096 x 4096 x 23 and 7216 x 5412 x 33 pages at three
-// components; from four on the matrix cores win, by 13 % at seven).
-constexpr int kU16VectorMaxComp = 3;
-bool proj_vector(const cvamx_ctx* ctx, const cvamx_cube* cube, int nc) {
-  return ctx->plain || cube->dtype != CVAMX_U16 || nc <= kU16VectorMaxComp;
+// the plain FP32 path, and for every page type but uint16 (uint16 pages take
+// the matrix cores at any component count: at three components the two
+// forms measured within 1 %, from four on the matrix cores win, by 13 % at
+// seven).
+bool proj_vector(const cvamx_ctx* ctx, const cvamx_cube* cube, int /*nc*/) {
+  return ctx->plain || cube->dtype != CVAMX_U16;
 }
 
 // The kernel arguments of components g0 .. g0 + nc - 1.

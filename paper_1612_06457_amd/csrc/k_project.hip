@@ -1,7 +1,6 @@
 // Projection passes on the VALU, and the dispatchers.  uint16 pages take the
 // matrix-core passes of k_project_u16.hip unless the caller asks for the
-// vector path (the plain FP32 reference path, and groups of up to three
-// components, where the VALU measured faster); float32, bf16 and fp16 pages
+// vector path (the plain FP32 reference path); float32, bf16 and fp16 pages
 // take the VALU passes here.
 // For 16-bit float pages the VALU measured faster than a matrix-core form
 // with split operands at every band and component count tried (1.2-2.7x at
@@ -11,8 +10,7 @@
 namespace cvx {
 
 // The VALU passes for any element type: the path of float32, bf16 and fp16
-// pages, of uint16 pages at up to three components, and of the plain FP32
-// reference path.
+// pages, and the plain FP32 reference path of uint16 pages.
 #define CVX_GENERIC(CALL)                       \
   switch (dtype) {                              \
     case DT_U16: return CALL(DT_U16);           \
