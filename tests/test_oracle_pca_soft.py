@@ -44,6 +44,49 @@ def test_pca_brute_force_loop_and_mask():
     assert np.max(np.abs(cv - ref)) <= 1e-14 * np.max(np.abs(ref))
 
 
+def _scores(fit, X):
+    return (X - fit["mean"]) @ fit["V"]
+
+
+def test_pca_standardized_scale_invariance_and_definition():
+    """Standardised PCA: the eigenvalues are those of the correlation matrix
+    (summing to B, each band contributing 1); multiplying bands by positive
+    constants leaves the scores unchanged (the vectors scale inversely);
+    and the scores equal the covariance-PCA scores of data standardised
+    beforehand (the plain definition), up to the arbitrary sign."""
+    rng = np.random.default_rng(23)
+    P, B = 2000, 6
+    X = rng.standard_normal((P, B)) @ rng.standard_normal((B, B)) * [1, 10, 100, 0.5, 3, 40] + 500
+    f = oracle.pca_fit(X[:, None, :], n_comp=3, standardize=True)
+    assert abs(f["all_eigvals"].sum() - B) <= 1e-12 * B
+    M = f["metric"]
+    assert np.max(np.abs(f["V"].T @ M @ f["V"] - np.eye(3))) <= 1e-12
+    assert np.max(np.abs(f["V"].T @ f["cov"] @ f["V"] - np.diag(f["eigvals"]))) <= 1e-12 * f["eigvals"][0]
+    a = np.array([3.0, 0.01, 7.0, 250.0, 1.0, 0.2])
+    g = oracle.pca_fit((X * a)[:, None, :], n_comp=3, standardize=True)
+    assert np.max(np.abs(g["eigvals"] - f["eigvals"])) <= 1e-10 * B
+    sf, sg = _scores(f, X), _scores(g, X * a)
+    for j in range(3):
+        s = np.sign(sf[:, j] @ sg[:, j])
+        assert np.max(np.abs(s * sg[:, j] - sf[:, j])) <= 1e-9 * np.max(np.abs(sf[:, j]))
+    mu = X.mean(0)
+    Z = (X - mu) / X.std(0, ddof=1)
+    h = oracle.pca_fit(Z[:, None, :], n_comp=3)
+    assert np.max(np.abs(h["eigvals"] - f["eigvals"])) <= 1e-10 * B
+    sh = _scores(h, Z)
+    for j in range(3):
+        s = np.sign(sf[:, j] @ sh[:, j])
+        assert np.max(np.abs(s * sh[:, j] - sf[:, j])) <= 1e-9 * np.max(np.abs(sf[:, j]))
+    # the default stays covariance PCA: not scale invariant
+    c = oracle.pca_fit(X[:, None, :], n_comp=3)
+    d = oracle.pca_fit((X * a)[:, None, :], n_comp=3)
+    assert np.max(np.abs(c["eigvals"] - d["eigvals"])) > 1.0
+    with pytest.raises(ValueError):
+        Y = X.copy()
+        Y[:, 2] = 7.0
+        oracle.pca_fit(Y[:, None, :], n_comp=2, standardize=True)
+
+
 def test_pca_constructed_eigenvalues():
     rng = np.random.default_rng(22)
     P, B = 500, 5
