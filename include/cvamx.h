@@ -215,6 +215,17 @@ int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask,
             int32_t n_comp, int32_t prec, double* V, double* eigvals,
             double* mean, double* cov, void* stream);
 
+/* With enable = 1, pca_fit on this context standardises every band to unit
+ * variance over the selected pixels first (the methods the paper compares
+ * with standardise their inputs, Section 2): eigvals are those of the
+ * correlation matrix R = D^-1/2 C D^-1/2 (D = diag C, C the covariance, which
+ * cov still returns), and V holds the projection vectors D^-1/2 u_j, so that
+ * pca_project with (V, mean) maps the scores of the standardised bands
+ * (C V = D V diag(eigvals), V^T D V = I).  A band of zero variance
+ * then fails with CVAMX_E_INVALID_ARG.  0 (the default) restores covariance
+ * PCA.  Host-only: never fails for a valid context. */
+int cvamx_set_pca_standardize(cvamx_ctx* ctx, int enable);
+
 /* Same as cva_project with (V, mean) from pca_fit. */
 int pca_project(cvamx_ctx* ctx, const cvamx_cube* cube, const double* V,
                 const double* mean, int32_t n_comp, uint8_t* images,

@@ -88,6 +88,7 @@ EXPORTS = {
     "cvamx_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int]),
     "cvamx_stream_read": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp]),
     "cvamx_stream_mix": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp]),
+    "cvamx_set_pca_standardize": (ctypes.c_int, [_vp, _i32]),
     "cvamx_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "cvamx_profile_report": (ctypes.c_int64, [_vp, ctypes.c_char_p, ctypes.c_int64]),
 }

@@ -430,8 +430,10 @@ def cluster_indices(images: torch.Tensor, pixels: torch.Tensor, classes: torch.T
 
 
 def pca_fit(cube: torch.Tensor, mask: Optional[torch.Tensor] = None, n_comp: int = 3,
-            precision: str = "fp32"):
-    """Covariance PCA of the page (or of the pixels where mask != 0).
+            precision: str = "fp32", standardize: bool = False):
+    """Covariance PCA of the page (or of the pixels where mask != 0); with
+    standardize=True, PCA of the bands scaled to unit variance (correlation
+    matrix), V then holding the projection vectors D^-1/2 u.
     Returns (V B x n, eigvals n, mean B, cov B x B)."""
     c = _cube(cube)
     B = c.bands
@@ -446,8 +448,12 @@ def pca_fit(cube: torch.Tensor, mask: Optional[torch.Tensor] = None, n_comp: int
     cov = np.empty((B, B))
     dev = _dev_index(cube)
     ctx = context(dev)
-    st = lib().pca_fit(ctx, ctypes.byref(c), _ptr(mask), n_comp, _lib.PREC[precision], _ptr(V),
-                       _ptr(lam), _ptr(mean), _ptr(cov), _stream(cube.device))
+    check(lib().cvamx_set_pca_standardize(ctx, 1 if standardize else 0), ctx)
+    try:
+        st = lib().pca_fit(ctx, ctypes.byref(c), _ptr(mask), n_comp, _lib.PREC[precision], _ptr(V),
+                           _ptr(lam), _ptr(mean), _ptr(cov), _stream(cube.device))
+    finally:
+        lib().cvamx_set_pca_standardize(ctx, 0)
     check(st, ctx)
     return V, lam, mean, cov
 

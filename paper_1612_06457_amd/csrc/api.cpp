@@ -29,6 +29,7 @@ struct cvamx_ctx {
   int proj_blocks = 0;   // 0 = automatic
   bool plain = false;    // FP32 requests on the plain vector-ALU kernels
   int schedule = CVAMX_SCHEDULE_AUTO;   // projection schedule (cvamx_set_schedule)
+  bool pca_standardize = false;         // pca_fit on the correlation matrix (cvamx_set_pca_standardize)
   int gram_blocks = 0;
   std::string err;
   void* buf[B_COUNT] = {};
@@ -1111,11 +1112,22 @@ int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t
   for (int i = 0; i < B; ++i)
     for (int j = 0; j < B; ++j)
       C[(size_t)i * B + j] = (G1[(size_t)i * n1 + j] - G1[(size_t)i * n1 + B] * G1[(size_t)j * n1 + B] / n) / (n - 1.0);
-  const int st = cvamx::sym_eig_desc(B, C.data(), w.data(), Vf.data());
+  // standardised: the eigenproblem of R = D^-1/2 C D^-1/2 (D = diag C), and
+  // the projection vectors D^-1/2 u
+  std::vector<double> sd(B, 1.0), A = C;
+  if (ctx->pca_standardize) {
+    for (int i = 0; i < B; ++i) {
+      sd[i] = std::sqrt(C[(size_t)i * B + i]);
+      if (!(sd[i] > 0.0)) return fail(ctx, CVAMX_E_INVALID_ARG, "band " + std::to_string(i) + " has zero variance");
+    }
+    for (int i = 0; i < B; ++i)
+      for (int j = 0; j < B; ++j) A[(size_t)i * B + j] = C[(size_t)i * B + j] / (sd[i] * sd[j]);
+  }
+  const int st = cvamx::sym_eig_desc(B, A.data(), w.data(), Vf.data());
   if (st != 0) return fail(ctx, st, "PCA eigensolver did not converge");
   std::vector<double> Vo((size_t)B * n_comp);
   for (int i = 0; i < B; ++i)
-    for (int j = 0; j < n_comp; ++j) Vo[(size_t)i * n_comp + j] = Vf[(size_t)i * B + j];
+    for (int j = 0; j < n_comp; ++j) Vo[(size_t)i * n_comp + j] = Vf[(size_t)i * B + j] / sd[i];
   cvamx::sign_rule(B, n_comp, Vo.data());
   std::copy(Vo.begin(), Vo.end(), V);
   std::copy(w.begin(), w.begin() + n_comp, eigvals);
@@ -1335,6 +1347,12 @@ int cvamx_stream_mix(cvamx_ctx* ctx, const void* src, int64_t read_bytes, void* 
   hipError_t e = cvx::launch_stream_mix(src, read_bytes, dst, write_bytes, 0x9e3779b9u, sink, ctx->num_cu, s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "stream mix launch");
+  return CVAMX_OK;
+}
+
+int cvamx_set_pca_standardize(cvamx_ctx* ctx, int enable) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  ctx->pca_standardize = enable != 0;
   return CVAMX_OK;
 }
 

@@ -15,7 +15,7 @@ import oracle
 from synth import make_case, make_soft_case, to_half_cube
 from tests._cases import full_page
 from tests._parity import (TOL_LAM, TOL_S, TOL_Y, check_cva_vectors, check_images, check_pca_vectors,
-                           rel_max)
+                           check_vectors, rel_max)
 
 pytestmark = pytest.mark.gpu
 
@@ -184,6 +184,61 @@ def test_pca_mask(dev):
     assert rel_max(cov, pr["cov"]) <= TOL_S
     assert rel_max(mean, pr["mean"]) <= 1e-9
     check_pca_vectors(V, pr)
+
+
+@pytest.mark.parametrize("case,dtype,masked,prec", [
+    (1, "u16", False, "fp32"), (1, "u16", True, "fp32"), (2, "u16", False, "fp32"), (2, "f32", False, "fp32"),
+    (2, "bf16", False, "bf16x3"), (1, "u16", False, "plain")])
+def test_pca_standardized(dev, case, dtype, masked, prec):
+    """Standardised PCA (the bands scaled to unit variance over the selected
+    pixels) against the oracle: the correlation eigenvalues, the projection
+    vectors D^-1/2 u checked through C v = lambda D v and v^T D v = 1 (every
+    column) and against the oracle's vectors where the eigenvalues are
+    apart, and the images of pca_project with the oracle's vectors, within
+    one level."""
+    say(f"standardised pca: config {case} {dtype} masked={masked} {prec}")
+    import paper_1612_06457_amd as cx
+    c = make_case(case, scale=0.5 if case == 1 else 0.08)
+    if dtype == "u16":
+        host, dcube = c.cube, _t(c.cube, dev)
+    elif dtype == "f32":
+        host = (c.cube.astype(np.float32) / 4095.0).astype(np.float32)
+        dcube = _t(host, dev)
+    else:
+        half = to_half_cube(c.cube, dtype)
+        host, dcube = half.float().numpy(), half.contiguous().to(dev)
+    rng = np.random.default_rng(case)
+    mask = (rng.random((c.H, c.W)) < 0.5).astype(np.uint8) if masked else None
+    pr = oracle.pca_fit(host, mask=mask, n_comp=3, standardize=True)
+    cx.set_plain_fp32(prec == "plain")
+    try:
+        V, lam, mean, cov = cx.pca_fit(dcube, mask=None if mask is None else _t(mask, dev), n_comp=3,
+                                       precision="fp32" if prec == "plain" else prec, standardize=True)
+    finally:
+        cx.set_plain_fp32(False)
+    assert rel_max(cov, pr["cov"]) <= TOL_S
+    assert np.max(np.abs(lam - pr["eigvals"]) / pr["eigvals"]) <= TOL_LAM
+    check_vectors(V, pr["V"], pr["eigvals"], A_ref=pr["cov"], M_ref=pr["metric"], lam_next=pr["all_eigvals"][3])
+    # the oracle's projection vectors through the device projection
+    q = cx.pca_project(dcube, pr["V"], pr["mean"]).cpu().numpy()
+    q_ref, _ = oracle.pca_project(host, pr["V"], pr["mean"])
+    check_images(q, q_ref)
+    # and the default stays covariance PCA
+    V0, lam0, _, _ = cx.pca_fit(dcube, mask=None if mask is None else _t(mask, dev), n_comp=3,
+                                precision="fp32" if prec == "plain" else prec)
+    p0 = oracle.pca_fit(host, mask=mask, n_comp=3)
+    assert np.max(np.abs(lam0 - p0["eigvals"]) / p0["eigvals"]) <= TOL_LAM
+
+
+def test_pca_standardized_zero_variance_band(dev):
+    import paper_1612_06457_amd as cx
+    rng = np.random.default_rng(5)
+    cube = rng.integers(0, 4096, (40, 30, 6)).astype(np.uint16)
+    cube[:, :, 2] = 1234
+    with pytest.raises(cx.CvamxError):
+        cx.pca_fit(_t(cube, dev), n_comp=2, standardize=True)
+    V, lam, _, _ = cx.pca_fit(_t(cube, dev), n_comp=2)   # covariance PCA is fine
+    assert lam[0] > 0
 
 
 @pytest.mark.parametrize("H,W,B,masked", [

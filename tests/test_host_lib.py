@@ -249,6 +249,9 @@ def test_argument_checks_without_a_device():
         assert lib.cvamx_set_plain_fp32(None, 1) == L.E_INVALID_ARG
         assert lib.cvamx_set_plain_fp32(ctx, 1) == L.OK
         assert lib.cvamx_set_plain_fp32(ctx, 0) == L.OK
+        assert lib.cvamx_set_pca_standardize(None, 1) == L.E_INVALID_ARG
+        assert lib.cvamx_set_pca_standardize(ctx, 1) == L.OK
+        assert lib.cvamx_set_pca_standardize(ctx, 0) == L.OK
         # class index lists
         off = (ctypes.c_int32 * 129)()
         ix = ctypes.c_void_p(0xa0000)
