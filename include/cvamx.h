@@ -531,6 +531,17 @@ int cva_solve_moments(const int64_t* counts, const double* class_means,
  * Wilkinson shift. */
 int cvamx_sym_eig(int32_t n, const double* A, double* w, double* V);
 
+/* The k leading eigenpairs of an n x n row-major symmetric matrix A (host,
+ * lower triangle read), 1 <= k <= n: all n eigenvalues descending into w[n],
+ * the eigenvectors of the k largest as the orthonormal columns of V (n x k
+ * row-major), sign rule applied.  Eigenvalues by implicit QR steps on the
+ * Householder tridiagonal form with no vector accumulation, the k vectors by
+ * inverse iteration on it (kept orthogonal within clusters of eigenvalues
+ * closer than 1e-3 of the matrix norm), then mapped back through the stored
+ * reflectors; when k exceeds n / 4 it is cvamx_sym_eig's decomposition.
+ * PCA needs only its leading axes (paper Section 2). */
+int cvamx_sym_eig_top(int32_t n, const double* A, int32_t k, double* w, double* V);
+
 #ifdef __cplusplus
 }
 #endif

@@ -84,6 +84,7 @@ EXPORTS = {
     "cva_soft_update": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _f64, _vp]),
     "cva_solve_moments": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _f64, _i32, _vp, _vp, _vp]),
     "cvamx_sym_eig": (ctypes.c_int, [_i32, _vp, _vp, _vp]),
+    "cvamx_sym_eig_top": (ctypes.c_int, [_i32, _vp, _i32, _vp, _vp]),
     "cvamx_set_plain_fp32": (ctypes.c_int, [_vp, ctypes.c_int]),
     "cvamx_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int]),
     "cvamx_stream_read": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp]),

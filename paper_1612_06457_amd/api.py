@@ -607,6 +607,16 @@ def sym_eig(A):
     return w, V
 
 
+def sym_eig_top(A, k: int):
+    """All eigenvalues (descending) and the k leading eigenvectors (no GPU)."""
+    A = _f64(A)
+    n = A.shape[0]
+    w = np.empty(n)
+    V = np.empty((n, int(k)))
+    check(lib().cvamx_sym_eig_top(n, _ptr(A), int(k), _ptr(w), _ptr(V)))
+    return w, V
+
+
 # ------------------------------------------------------------ kernel timing
 
 def set_plain_fp32(enable: bool = True, device: int = 0) -> None:

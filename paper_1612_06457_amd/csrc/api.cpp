@@ -662,7 +662,7 @@ static int fit_from_index(cvamx_ctx* ctx, const cvamx_cube* cube, int32_t K, int
   }
   std::vector<double> Wt((size_t)B * n_comp), lam(n_comp), m(B), Sbv((size_t)B * B);
   const int st = cvamx::cva_solve(K, B, cntd.data(), cm.data(), Swv.data(), ridge, n_comp, Wt.data(),
-                                  lam.data(), m.data(), Sbv.data(), &ctx->err);
+                                  lam.data(), m.data(), Sb ? Sbv.data() : nullptr, &ctx->err);
   if (st != 0) return st;
   std::copy(Wt.begin(), Wt.end(), W);
   std::copy(lam.begin(), lam.end(), eigvals);
@@ -1123,11 +1123,12 @@ int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t
     for (int i = 0; i < B; ++i)
       for (int j = 0; j < B; ++j) A[(size_t)i * B + j] = C[(size_t)i * B + j] / (sd[i] * sd[j]);
   }
-  const int st = cvamx::sym_eig_desc(B, A.data(), w.data(), Vf.data());
+  // the leading n_comp axes only (inverse iteration on the tridiagonal form)
+  const int st = cvamx::sym_eig_top(B, A.data(), n_comp, w.data(), Vf.data());
   if (st != 0) return fail(ctx, st, "PCA eigensolver did not converge");
   std::vector<double> Vo((size_t)B * n_comp);
   for (int i = 0; i < B; ++i)
-    for (int j = 0; j < n_comp; ++j) Vo[(size_t)i * n_comp + j] = Vf[(size_t)i * B + j] / sd[i];
+    for (int j = 0; j < n_comp; ++j) Vo[(size_t)i * n_comp + j] = Vf[(size_t)i * n_comp + j] / sd[i];
   cvamx::sign_rule(B, n_comp, Vo.data());
   std::copy(Vo.begin(), Vo.end(), V);
   std::copy(w.begin(), w.begin() + n_comp, eigvals);

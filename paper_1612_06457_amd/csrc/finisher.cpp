@@ -27,21 +27,28 @@ namespace cvamx {
 // processors and for the baseline, and the loader picks one at run time.
 #define CVX_HOST_SIMD __attribute__((target_clones("arch=haswell", "default")))
 
-int cholesky_lower(int n, const double* A, double* L) {
+// Right-looking: after column j is final, its outer product is taken from
+// the trailing rows at once (independent updates along each row, which
+// vectorise), rather than one dot product per entry.
+CVX_HOST_SIMD int cholesky_lower(int n, const double* A, double* L) {
+  std::vector<double> S((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k <= i; ++k) S[(size_t)i * n + k] = A[(size_t)i * n + k];
   std::fill(L, L + (size_t)n * n, 0.0);
   for (int j = 0; j < n; ++j) {
     const double ajj = A[(size_t)j * n + j];
-    double s = ajj;
-    for (int k = 0; k < j; ++k) s -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+    const double s = S[(size_t)j * n + j];
     // A pivot that lost all but ~13 digits of its diagonal entry is treated
     // as zero: S_w is then singular to working precision.
     if (!std::isfinite(s) || !(s > 1e-13 * std::fabs(ajj))) return CVAMX_E_NOT_PD;
-    const double d = std::sqrt(s);
+    const double d = std::sqrt(s), inv = 1.0 / d;
     L[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) L[(size_t)i * n + j] = S[(size_t)i * n + j] * inv;
     for (int i = j + 1; i < n; ++i) {
-      double t = A[(size_t)i * n + j];
-      for (int k = 0; k < j; ++k) t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
-      L[(size_t)i * n + j] = t / d;
+      const double lij = L[(size_t)i * n + j];
+      double* __restrict__ si = S.data() + (size_t)i * n;
+      const double* __restrict__ lk = L + j;
+      for (int k = j + 1; k <= i; ++k) si[k] -= lij * lk[(size_t)k * n];
     }
   }
   return 0;
@@ -50,8 +57,13 @@ int cholesky_lower(int n, const double* A, double* L) {
 // Householder reduction of the full symmetric matrix T (in place) to
 // tridiagonal form, accumulating the reflectors into Q so that the input
 // equals Q T Q^T.
-CVX_HOST_SIMD static void tridiagonalize(int n, double* T, double* Q) {
+// With Q null the reflectors are kept instead: row k of Vh holds v_k
+// (entries k + 1 .. n - 1) and bk[k] its 2 / v^T v (0: no reflection), and
+// the input equals H_0 H_1 ... T ... H_1 H_0 with H_k = I - bk[k] v_k v_k^T.
+CVX_HOST_SIMD static void tridiagonalize(int n, double* T, double* Q, double* Vh = nullptr,
+                                         double* bk = nullptr) {
   std::vector<double> v(n), p(n), w(n);
+  if (bk) std::fill(bk, bk + n, 0.0);
   for (int k = 0; k + 2 < n; ++k) {
     double xx = 0.0;
     for (int i = k + 1; i < n; ++i) xx += T[(size_t)i * n + k] * T[(size_t)i * n + k];
@@ -83,6 +95,11 @@ CVX_HOST_SIMD static void tridiagonalize(int n, double* T, double* Q) {
       T[(size_t)i * n + k] = 0.0;
       T[(size_t)k * n + i] = 0.0;
     }
+    if (!Q) {
+      for (int j = k + 1; j < n; ++j) Vh[(size_t)k * n + j] = v[j];
+      bk[k] = beta;
+      continue;
+    }
     for (int r = 0; r < n; ++r) {
       double s = 0.0;
       for (int j = k + 1; j < n; ++j) s += Q[(size_t)r * n + j] * v[j];
@@ -101,58 +118,59 @@ static inline double norm2(double x, double z) {
   return std::hypot(x, z);
 }
 
-// Implicit symmetric QR steps with a Wilkinson shift on the tridiagonal T
-// (stored dense), deflating negligible off-diagonal entries, with the
-// rotations accumulated into Zt = Q^T (row i of Zt is column i of Q, so a
-// rotation of two columns of Q touches two contiguous rows).
-CVX_HOST_SIMD static int tridiagonal_qr(int n, double* T, double* Zt) {
+// Implicit symmetric QR steps with a Wilkinson shift on the tridiagonal
+// matrix with diagonal d and off-diagonal e (e[i] couples i and i + 1),
+// deflating negligible off-diagonal entries.  Each step chases the bulge
+// down the unreduced block with Givens rotations of rows and columns
+// (k, k + 1), updating the few entries they touch; the rotations are
+// accumulated into Zt = Q^T (row i of Zt is column i of Q, so a rotation of
+// two columns of Q touches two contiguous rows), or not at all when Zt is
+// null.  The eigenvalues are left in d.
+CVX_HOST_SIMD static int tridiagonal_qr(int n, double* d, double* e, double* Zt) {
   const int maxit = 60 * n + 100;
   int it = 0;
   int m = n - 1;
-  auto at = [&](int i, int j) -> double& { return T[(size_t)i * n + j]; };
   while (m > 0) {
-    for (int i = 0; i < m; ++i) {
-      if (std::fabs(at(i + 1, i)) <= DBL_EPSILON * (std::fabs(at(i, i)) + std::fabs(at(i + 1, i + 1)))) {
-        at(i + 1, i) = 0.0;
-        at(i, i + 1) = 0.0;
-      }
-    }
-    while (m > 0 && at(m, m - 1) == 0.0) --m;
+    for (int i = 0; i < m; ++i)
+      if (std::fabs(e[i]) <= DBL_EPSILON * (std::fabs(d[i]) + std::fabs(d[i + 1]))) e[i] = 0.0;
+    while (m > 0 && e[m - 1] == 0.0) --m;
     if (m == 0) break;
     int l = m - 1;
-    while (l > 0 && at(l, l - 1) != 0.0) --l;
+    while (l > 0 && e[l - 1] != 0.0) --l;
     if (++it > maxit) return CVAMX_E_NUMERIC;
-    const double a = at(m - 1, m - 1), b = at(m, m - 1), c = at(m, m);
-    const double d = 0.5 * (a - c);
-    const double den = d + std::copysign(norm2(d, b), d);
+    const double a = d[m - 1], b = e[m - 1], c = d[m];
+    const double dd = 0.5 * (a - c);
+    const double den = dd + std::copysign(norm2(dd, b), dd);
     const double mu = (den != 0.0) ? c - b * b / den : c - std::fabs(b);
-    double x = at(l, l) - mu;
-    double z = at(l + 1, l);
+    double x = d[l] - mu;
+    double z = e[l];
     for (int k = l; k < m; ++k) {
       const double r = norm2(x, z);
       const double cs = (r == 0.0) ? 1.0 : x / r;
-      const double sn = (r == 0.0) ? 0.0 : -z / r;
-      const int lo = std::max(l, k - 1), hi = std::min(m, k + 2);
-      for (int j = lo; j <= hi; ++j) {
-        const double t1 = at(k, j), t2 = at(k + 1, j);
-        at(k, j) = cs * t1 - sn * t2;
-        at(k + 1, j) = sn * t1 + cs * t2;
-      }
-      for (int i = lo; i <= hi; ++i) {
-        const double t1 = at(i, k), t2 = at(i, k + 1);
-        at(i, k) = cs * t1 - sn * t2;
-        at(i, k + 1) = sn * t1 + cs * t2;
-      }
-      double* __restrict__ z1 = Zt + (size_t)k * n;
-      double* __restrict__ z2 = z1 + n;
-      for (int i = 0; i < n; ++i) {
-        const double q1 = z1[i], q2 = z2[i];
-        z1[i] = cs * q1 - sn * q2;
-        z2[i] = sn * q1 + cs * q2;
-      }
+      const double sn = (r == 0.0) ? 0.0 : z / r;
+      if (k > l) e[k - 1] = r;
+      // rows k, k + 1 of the 2 x 2 block, then its columns
+      const double p = d[k], q = e[k], t = d[k + 1];
+      const double r00 = cs * p + sn * q, r01 = cs * q + sn * t;
+      const double r10 = -sn * p + cs * q, r11 = -sn * q + cs * t;
+      d[k] = cs * r00 + sn * r01;
+      e[k] = cs * r10 + sn * r11;
+      d[k + 1] = -sn * r10 + cs * r11;
       if (k + 1 < m) {
-        x = at(k + 1, k);
-        z = at(k + 2, k);
+        // the rotation of rows k, k + 1 moves part of e[k + 1] into the
+        // bulge at (k, k + 2)
+        z = sn * e[k + 1];
+        e[k + 1] = cs * e[k + 1];
+        x = e[k];
+      }
+      if (Zt) {
+        double* __restrict__ z1 = Zt + (size_t)k * n;
+        double* __restrict__ z2 = z1 + n;
+        for (int i = 0; i < n; ++i) {
+          const double q1 = z1[i], q2 = z2[i];
+          z1[i] = cs * q1 + sn * q2;
+          z2[i] = -sn * q1 + cs * q2;
+        }
       }
     }
   }
@@ -171,16 +189,140 @@ int sym_eig_desc(int n, const double* A, double* w, double* V) {
   std::vector<double> Zt((size_t)n * n);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) Zt[(size_t)j * n + i] = Q[(size_t)i * n + j];
-  const int st = tridiagonal_qr(n, T.data(), Zt.data());
+  std::vector<double> d(n), e(n, 0.0);
+  for (int i = 0; i < n; ++i) d[i] = T[(size_t)i * n + i];
+  for (int i = 0; i + 1 < n; ++i) e[i] = T[(size_t)(i + 1) * n + i];
+  const int st = tridiagonal_qr(n, d.data(), e.data(), Zt.data());
   if (st != 0) return st;
   std::vector<int> ord(n);
   std::iota(ord.begin(), ord.end(), 0);
-  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
-    return T[(size_t)a * n + a] > T[(size_t)b * n + b];
-  });
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return d[a] > d[b]; });
   for (int j = 0; j < n; ++j) {
-    w[j] = T[(size_t)ord[j] * n + ord[j]];
+    w[j] = d[ord[j]];
     for (int i = 0; i < n; ++i) V[(size_t)i * n + j] = Zt[(size_t)ord[j] * n + i];
+  }
+  return 0;
+}
+
+// Solve (T - sigma I) x = b in place for the tridiagonal T (diagonal d,
+// off-diagonal e), by Gaussian elimination with partial pivoting (the
+// factor gains a second superdiagonal); a pivot of zero is replaced by tiny.
+static void tri_shifted_solve(int n, const double* d, const double* e, double sigma, double tiny, double* x) {
+  std::vector<double> u0(n), u1(n, 0.0), u2(n, 0.0), l(n, 0.0);
+  std::vector<char> sw(n, 0);
+  u0[0] = d[0] - sigma;
+  if (n > 1) u1[0] = e[0];
+  for (int i = 0; i + 1 < n; ++i) {
+    const double c = e[i], an = d[i + 1] - sigma, bn = (i + 2 < n) ? e[i + 1] : 0.0;
+    if (std::fabs(u0[i]) >= std::fabs(c)) {
+      if (u0[i] == 0.0) u0[i] = tiny;
+      const double m = c / u0[i];
+      l[i] = m;
+      u0[i + 1] = an - m * u1[i];
+      u1[i + 1] = bn - m * u2[i];
+    } else {
+      const double m = u0[i] / c;
+      l[i] = m;
+      sw[i] = 1;
+      const double r1 = u1[i], r2 = u2[i];
+      u0[i] = c;
+      u1[i] = an;
+      u2[i] = bn;
+      u0[i + 1] = r1 - m * an;
+      u1[i + 1] = r2 - m * bn;
+    }
+  }
+  if (u0[n - 1] == 0.0) u0[n - 1] = tiny;
+  for (int i = 0; i + 1 < n; ++i) {
+    if (sw[i]) std::swap(x[i], x[i + 1]);
+    x[i + 1] -= l[i] * x[i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double t = x[i];
+    if (i + 1 < n) t -= u1[i] * x[i + 1];
+    if (i + 2 < n) t -= u2[i] * x[i + 2];
+    x[i] = t / u0[i];
+  }
+}
+
+int sym_eig_top(int n, const double* A, int k, double* w, double* V) {
+  if (k < 1 || k > n) return CVAMX_E_INVALID_ARG;
+  if (n <= 2 || 4 * k > n) {
+    // small or most of the spectrum: the full decomposition
+    std::vector<double> wf(n), Vf((size_t)n * n);
+    const int st = sym_eig_desc(n, A, wf.data(), Vf.data());
+    if (st != 0) return st;
+    for (int i = 0; i < n; ++i) {
+      w[i] = wf[i];
+      for (int j = 0; j < k; ++j) V[(size_t)i * k + j] = Vf[(size_t)i * n + j];
+    }
+    return 0;
+  }
+  std::vector<double> T((size_t)n * n), Vh((size_t)n * n, 0.0), bk(n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      T[(size_t)i * n + j] = A[(size_t)i * n + j];
+      T[(size_t)j * n + i] = A[(size_t)i * n + j];
+    }
+  tridiagonalize(n, T.data(), nullptr, Vh.data(), bk.data());
+  std::vector<double> d(n), e(n, 0.0);
+  for (int i = 0; i < n; ++i) d[i] = T[(size_t)i * n + i];
+  for (int i = 0; i + 1 < n; ++i) e[i] = T[(size_t)(i + 1) * n + i];
+  double tnorm = 0.0;   // 1-norm of the tridiagonal
+  for (int i = 0; i < n; ++i)
+    tnorm = std::max(tnorm, std::fabs(d[i]) + (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0));
+  std::vector<double> dq(d), eq(e);
+  const int st = tridiagonal_qr(n, dq.data(), eq.data(), nullptr);
+  if (st != 0) return st;
+  std::copy(dq.begin(), dq.end(), w);
+  std::sort(w, w + n, [](double a, double b) { return a > b; });
+  if (tnorm == 0.0) {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < k; ++j) V[(size_t)i * k + j] = i == j ? 1.0 : 0.0;
+    return 0;
+  }
+  // eigenvectors of the tridiagonal by inverse iteration: vectors whose
+  // eigenvalues lie within 1e-3 |T| of each other form a cluster and are
+  // kept orthogonal to one another (modified Gram-Schmidt in every step),
+  // and their shifts are kept at least 10 eps |T| apart
+  const double ortol = 1e-3 * tnorm, pertol = 10.0 * DBL_EPSILON * tnorm, tiny = DBL_EPSILON * tnorm;
+  std::vector<double> X((size_t)k * n), x(n);
+  int c0 = 0;
+  double prev = 0.0;
+  for (int j = 0; j < k; ++j) {
+    double sigma = w[j];
+    if (j > 0 && w[j - 1] - w[j] > ortol) c0 = j;
+    if (j > c0 && sigma > prev - pertol) sigma = prev - pertol;
+    prev = sigma;
+    for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.25 * (double)((7 * i + 3 * j) % 11) / 11.0;
+    for (int it = 0; it < 5; ++it) {
+      tri_shifted_solve(n, d.data(), e.data(), sigma, tiny, x.data());
+      for (int c = c0; c < j; ++c) {
+        const double* xc = X.data() + (size_t)c * n;
+        double dot = 0.0;
+        for (int i = 0; i < n; ++i) dot += xc[i] * x[i];
+        for (int i = 0; i < n; ++i) x[i] -= dot * xc[i];
+      }
+      double nrm = 0.0;
+      for (int i = 0; i < n; ++i) nrm += x[i] * x[i];
+      nrm = std::sqrt(nrm);
+      if (!(nrm > 0.0) || !std::isfinite(nrm)) return CVAMX_E_NUMERIC;
+      for (int i = 0; i < n; ++i) x[i] /= nrm;
+    }
+    std::copy(x.begin(), x.end(), X.begin() + (size_t)j * n);
+  }
+  // back to the input's basis: y = H_0 H_1 ... H_{n-3} x
+  for (int j = 0; j < k; ++j) {
+    double* y = X.data() + (size_t)j * n;
+    for (int r = n - 3; r >= 0; --r) {
+      if (bk[r] == 0.0) continue;
+      const double* v = Vh.data() + (size_t)r * n;
+      double dot = 0.0;
+      for (int i = r + 1; i < n; ++i) dot += v[i] * y[i];
+      dot *= bk[r];
+      for (int i = r + 1; i < n; ++i) y[i] -= dot * v[i];
+    }
+    for (int i = 0; i < n; ++i) V[(size_t)i * k + j] = y[i];
   }
   return 0;
 }
@@ -201,7 +343,7 @@ void sign_rule(int rows, int nc, double* W) {
   }
 }
 
-int cva_solve(int K, int B, const double* cnt, const double* cm, const double* Sw,
+CVX_HOST_SIMD int cva_solve(int K, int B, const double* cnt, const double* cm, const double* Sw,
               double ridge, int nc, double* W, double* eig, double* mean,
               double* Sb_out, std::string* err) {
   const int C = std::min(K - 1, B);
@@ -230,15 +372,20 @@ int cva_solve(int K, int B, const double* cnt, const double* cm, const double* S
     if (err) *err = "cva_solve: S_w + ridge I is not positive definite";
     return CVAMX_E_NOT_PD;
   }
-  // E = L^-1 D, D[:, k] = sqrt(n_k) (m_k - m)
-  std::vector<double> E((size_t)B * K);
-  for (int k = 0; k < K; ++k) {
-    const double sq = std::sqrt(cnt[k]);
-    for (int i = 0; i < B; ++i) {
-      double t = sq * (cm[(size_t)k * B + i] - m[i]);
-      for (int j = 0; j < i; ++j) t -= L[(size_t)i * B + j] * E[(size_t)j * K + k];
-      E[(size_t)i * K + k] = t / L[(size_t)i * B + i];
+  // E = L^-1 D, D[:, k] = sqrt(n_k) (m_k - m): forward substitution by
+  // rows, all K columns at once
+  std::vector<double> E((size_t)B * K), sq(K);
+  for (int k = 0; k < K; ++k) sq[k] = std::sqrt(cnt[k]);
+  for (int i = 0; i < B; ++i) {
+    double* __restrict__ ei = E.data() + (size_t)i * K;
+    for (int k = 0; k < K; ++k) ei[k] = sq[k] * (cm[(size_t)k * B + i] - m[i]);
+    for (int j = 0; j < i; ++j) {
+      const double lij = L[(size_t)i * B + j];
+      const double* __restrict__ ej = E.data() + (size_t)j * K;
+      for (int k = 0; k < K; ++k) ei[k] -= lij * ej[k];
     }
+    const double inv = 1.0 / L[(size_t)i * B + i];
+    for (int k = 0; k < K; ++k) ei[k] *= inv;
   }
   std::vector<double> U((size_t)B * nc), lam(nc);
   bool done = false;
@@ -286,27 +433,35 @@ int cva_solve(int K, int B, const double* cnt, const double* cm, const double* S
       lam[j] = s[j];
     }
   }
-  // W = L^-T U (back substitution)
+  // W = L^-T U: back substitution by rows, all nc columns at once
   std::vector<double> Wt((size_t)B * nc);
-  for (int j = 0; j < nc; ++j) {
-    for (int i = B - 1; i >= 0; --i) {
-      double t = U[(size_t)i * nc + j];
-      for (int r = i + 1; r < B; ++r) t -= L[(size_t)r * B + i] * Wt[(size_t)r * nc + j];
-      Wt[(size_t)i * nc + j] = t / L[(size_t)i * B + i];
+  for (int i = B - 1; i >= 0; --i) {
+    double* __restrict__ wi = Wt.data() + (size_t)i * nc;
+    for (int j = 0; j < nc; ++j) wi[j] = U[(size_t)i * nc + j];
+    for (int r = i + 1; r < B; ++r) {
+      const double lri = L[(size_t)r * B + i];
+      const double* __restrict__ wr = Wt.data() + (size_t)r * nc;
+      for (int j = 0; j < nc; ++j) wi[j] -= lri * wr[j];
     }
+    const double inv = 1.0 / L[(size_t)i * B + i];
+    for (int j = 0; j < nc; ++j) wi[j] *= inv;
   }
   sign_rule(B, nc, Wt.data());
   std::copy(Wt.begin(), Wt.end(), W);
   std::copy(lam.begin(), lam.end(), eig);
   if (mean) std::copy(m.begin(), m.end(), mean);
   if (Sb_out) {
-    for (int i = 0; i < B; ++i)
-      for (int j = 0; j < B; ++j) {
-        double t = 0.0;
-        for (int k = 0; k < K; ++k)
-          t += cnt[k] * (cm[(size_t)k * B + i] - m[i]) * (cm[(size_t)k * B + j] - m[j]);
-        Sb_out[(size_t)i * B + j] = t;
+    // S_b = sum_k n_k (m_k - m)(m_k - m)^T, one rank-one update per class
+    std::fill(Sb_out, Sb_out + (size_t)B * B, 0.0);
+    std::vector<double> dk(B);
+    for (int k = 0; k < K; ++k) {
+      for (int i = 0; i < B; ++i) dk[i] = cm[(size_t)k * B + i] - m[i];
+      for (int i = 0; i < B; ++i) {
+        const double a = cnt[k] * dk[i];
+        double* __restrict__ row = Sb_out + (size_t)i * B;
+        for (int j = 0; j < B; ++j) row[j] += a * dk[j];
       }
+    }
   }
   return 0;
 }
@@ -322,6 +477,14 @@ extern "C" int cva_solve_moments(const int64_t* counts, const double* class_mean
   for (int k = 0; k < K; ++k) c[k] = (double)counts[k];
   return cvamx::cva_solve(K, B, c.data(), class_means, Sw, ridge, n_comp, W, eigvals, mean,
                           nullptr, nullptr);
+}
+
+extern "C" int cvamx_sym_eig_top(int32_t n, const double* A, int32_t k, double* w, double* V) {
+  if (!A || !w || !V || n < 1 || n > 4096 || k < 1 || k > n) return CVAMX_E_INVALID_ARG;
+  const int st = cvamx::sym_eig_top(n, A, k, w, V);
+  if (st != 0) return st;
+  cvamx::sign_rule(n, k, V);
+  return 0;
 }
 
 extern "C" int cvamx_sym_eig(int32_t n, const double* A, double* w, double* V) {

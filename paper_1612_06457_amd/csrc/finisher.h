@@ -16,6 +16,13 @@ int cholesky_lower(int n, const double* A, double* L);
 // CVAMX_E_NUMERIC.
 int sym_eig_desc(int n, const double* A, double* w, double* V);
 
+// All eigenvalues descending into w[n], and the eigenvectors of the k
+// largest into the columns of V (row-major n x k): eigenvalues by implicit
+// QR on the tridiagonal form without vectors, the k vectors by inverse
+// iteration on it and the stored reflectors (the full decomposition when k
+// is more than a quarter of n).  No sign rule.  Returns 0 or a CVAMX status.
+int sym_eig_top(int n, const double* A, int k, double* w, double* V);
+
 // Make the largest-magnitude entry of each of the nc columns of the
 // rows x nc row-major matrix W positive (ties: lowest row).
 void sign_rule(int rows, int nc, double* W);

@@ -109,3 +109,41 @@ def test_fit_label_errors(dev):
     # and the library still fits after the errors
     got = cx.cva_fit(_t(x.reshape(1, P, B), dev), _t(lab.reshape(1, P), dev), K)
     assert got.counts.tolist() == oracle.class_counts(lab, K).tolist()
+
+
+@pytest.mark.parametrize("P,B,K,full16", [
+    (70001, 33, 8, False), (40000, 47, 5, True), (33333, 31, 3, True), (20000, 32, 4, False),
+    (5000, 48, 3, False), (16384, 1, 2, True)])
+def test_fit_label_map_bands(dev, P, B, K, full16):
+    """uint16 label-map fits at band counts on both sides of the matrix-core
+    kernels' 16-band row blocks (31/32, 47/48) and at one band, with values
+    over the whole 16-bit range (both bytes of a value take every size) or
+    in the 12-bit range; and the point-list fit of the same pixels.  Both
+    against the FP64 oracle, with the bars of the other fit tests."""
+    say(f"fit over label map: P={P} B={B} K={K} full16={full16}")
+    import torch
+    import paper_1612_06457_amd as cx
+    rng = np.random.default_rng(P + B)
+    lab = _labels(P, K, "regions", rng)
+    if full16:
+        hi = rng.random(P) < 0.4
+        mu = np.where(hi[:, None], rng.uniform(60000, 65000, B), rng.uniform(50, 3000, B))
+        cls = np.where(lab >= 0, lab, 0)
+        mu = mu + 300.0 * cls[:, None]
+        x = np.clip(np.rint(mu + rng.normal(0, 900, (P, B))), 0, 65535).astype(np.uint16)
+    else:
+        x = _page(lab, B, K, rng)
+    cube = x.reshape(1, P, B)
+    labels = lab.reshape(1, P)
+    ref = oracle.cva_fit(cube, labels, K)
+    pix = np.flatnonzero(lab >= 0).astype(np.int64)
+    fits = {"label map": cx.cva_fit(_t(cube, dev), _t(labels, dev), K),
+            "point list": cx.cva_fit_points(_t(cube, dev), _t(pix, dev), _t(lab[pix], dev), K)}
+    torch.cuda.synchronize()
+    for name, got in fits.items():
+        say(f"  {name}")
+        assert got.counts.tolist() == ref["counts"].tolist()
+        assert rel_max(got.class_means, ref["class_means"]) <= 1e-7
+        assert rel_max(got.Sw, ref["Sw"]) <= TOL_S
+        assert rel_max(got.Sb, ref["Sb"]) <= TOL_S
+        assert np.max(np.abs(got.eigvals - ref["eigvals"]) / ref["eigvals"]) <= TOL_LAM

@@ -49,6 +49,61 @@ def test_sym_eig_matches_lapack():
             assert V[i, j] > 0
 
 
+def _check_top(A, k, w, V, tol_r=1e-11):
+    """Eigenvalues against LAPACK, orthonormal columns, small residuals, the
+    sign rule, and each cluster's span against LAPACK's."""
+    n = A.shape[0]
+    ref_w, ref_V = np.linalg.eigh(A)
+    ref_w, ref_V = ref_w[::-1], ref_V[:, ::-1]
+    scale = max(1.0, np.abs(ref_w).max())
+    assert np.max(np.abs(w - ref_w)) <= 1e-12 * scale
+    assert V.shape == (n, k)
+    assert np.max(np.abs(V.T @ V - np.eye(k))) <= 1e-11
+    assert np.max(np.abs(A @ V - V * w[:k])) <= tol_r * scale
+    for j in range(k):
+        i = int(np.argmax(np.abs(V[:, j])))
+        assert V[i, j] > 0
+    # the span of the leading k vectors (when w[k-1] is apart from w[k])
+    if k < n and ref_w[k - 1] - ref_w[k] > 1e-6 * scale:
+        P = V @ V.T - ref_V[:, :k] @ ref_V[:, :k].T
+        assert np.max(np.abs(P)) <= 1e-8
+
+
+def test_sym_eig_top_matches_lapack():
+    """The leading eigenpairs: random symmetric matrices, covariance-like
+    spectra over eight decades, an exactly threefold eigenvalue, a pair
+    1e-9 apart, a diagonal matrix, a block-diagonal matrix (the tridiagonal
+    form splits) and the zero matrix."""
+    _lib()
+    from paper_1612_06457_amd import sym_eig_top
+    rng = np.random.default_rng(1)
+    for n in (1, 2, 3, 8, 16, 23, 33, 47, 64):
+        G = rng.standard_normal((n, n))
+        A = G + G.T
+        for k in sorted({1, 2, 3, min(n, 8), n} & set(range(1, n + 1))):
+            w, V = sym_eig_top(A, k)
+            _check_top(A, k, w, V)
+    for n in (23, 33, 47):
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        for ev in (np.logspace(6, -2, n), np.r_[[10.0, 10.0, 10.0, 5.0], np.linspace(1, 1e-3, n - 4)],
+                   np.r_[[10.0, 10.0 + 1e-9, 9.0], np.linspace(2, 1, n - 3)]):
+            A = (Q * ev) @ Q.T
+            A = 0.5 * (A + A.T)
+            for k in (1, 3, 4):
+                w, V = sym_eig_top(A, k)
+                _check_top(A, k, w, V)
+    D = np.diag(rng.uniform(1, 5, 33))
+    B2 = np.zeros((33, 33))
+    B2[:16, :16] = D[:16, :16] + 0.1
+    B2[16:, 16:] = D[16:, 16:] - 0.2
+    for A in (D, B2, np.zeros((33, 33))):
+        w, V = sym_eig_top(A, 3)
+        if np.abs(A).max() == 0:
+            assert np.all(w == 0) and np.allclose(V.T @ V, np.eye(3))
+        else:
+            _check_top(A, 3, w, V)
+
+
 def _scatter_case(rng, K, B, cond=1e2):
     counts = rng.integers(1, 5000, K)
     cm = rng.uniform(800, 3500, (K, B))
