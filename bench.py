@@ -342,6 +342,18 @@ def extras(cx, torch, case, cube, fit, dev, labels=None):
         res["cva_project_alone_ms"] = round(_timed(torch, lambda: cx.cva_project(cube, fit.W, fit.mean, out=img)), 4)
         res["cva_project_alone_two_reads_ms"] = round(_scheduled(
             cx, "two_reads", lambda: _timed(torch, lambda: cx.cva_project(cube, fit.W, fit.mean, out=img))), 4)
+        # CVA and PCA of the page: the three separate calls against the one
+        # call that overlaps each host finish with GPU work (same results)
+        pimg = torch.empty((3, H, W), dtype=torch.uint8, device=dev)
+
+        def separate():
+            cx.cva_fit_project(cube, labels, K, out=img)
+            V, _, m, _ = cx.pca_fit(cube, n_comp=3)
+            cx.pca_project(cube, V, m, out=pimg)
+        t_sep = _timed(torch, separate)
+        t_one = _timed(torch, lambda: cx.cva_pca(cube, labels, K, cva_out=img, pca_out=pimg))
+        res["cva_and_pca"] = {"separate_calls_ms": round(t_sep, 4), "one_call_ms": round(t_one, 4)}
+        del pimg
     y = torch.empty((C, H, W), dtype=torch.float32, device=dev)
     rec("project_float", _timed(torch, lambda: cx.project_float(cube, fit.W, fit.mean, out=y)),
         P * B * 2 + P * C * 4)

@@ -231,6 +231,30 @@ int pca_project(cvamx_ctx* ctx, const cvamx_cube* cube, const double* V,
                 const double* mean, int32_t n_comp, uint8_t* images,
                 float* range, void* stream);
 
+/* CVA and PCA of one page in one call (paper Section 2: the canonical
+ * variates and the principal components of the same page, each projected
+ * and stretched to 8-bit images).  The result equals cva_fit_project (with
+ * range = NULL) followed by pca_fit (cov = NULL) and pca_project with its
+ * (V, mean), bit for bit; the call only orders the work so that each FP64
+ * host finish overlaps GPU work: the class moments and then the PCA
+ * covariance pass are queued, the CVA finish runs while the covariance pass
+ * reads the page and queues the CVA projection, and the PCA finish runs
+ * while that projection reads the page and queues the PCA projection.
+ *   labels, K, prec, ridge, n_cva, W, eigvals, mean, counts, cva_images:
+ *            as for cva_fit_project (cva_images device n_cva x height x
+ *            width uint8)
+ *   mask, n_pca, V, pca_eigvals, pca_mean: as for pca_fit with n_comp =
+ *            n_pca; pca_images device n_pca x height x width uint8
+ * The host outputs are set when the call returns; both projections are
+ * asynchronous on `stream`.  Honours cvamx_set_pca_standardize.  Errors as
+ * for the separate calls; after an error the queued work still runs. */
+int cvamx_cva_pca(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels,
+                  int32_t K, int32_t prec, double ridge, int32_t n_cva,
+                  double* W, double* eigvals, double* mean, int64_t* counts,
+                  uint8_t* cva_images, const uint8_t* mask, int32_t n_pca,
+                  double* V, double* pca_eigvals, double* pca_mean,
+                  uint8_t* pca_images, void* stream);
+
 /* ---- float images, rescaling modes, 16-bit output, colour ---------------- */
 
 /* The float images themselves: y_jp = w_j^T (x_p - center) for every pixel

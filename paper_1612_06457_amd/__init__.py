@@ -6,7 +6,7 @@ host finisher behind a C ABI, declared in include/cvamx.h); this package is
 a thin ctypes binding over torch tensors.
 """
 from .api import (ClusterIndices, CvaFit, SoftFit, SoftCVA, bands_to_cube, cluster_indices, compose_rgb,
-                  cva_fit, cva_fit_points, cva_fit_project, cva_project, cva_project_noalloc,
+                  cva_fit, cva_fit_points, cva_fit_project, cva_pca, cva_project, cva_project_noalloc,
                   cva_soft_backward, cva_soft_forward, cva_soft_update, cva_solve_moments, label_index,
                   pca_fit, pca_project, profile_enable, profile_report, project_float, refine_weights,
                   run_pages, set_plain_fp32, set_schedule, stream_mix, stream_read, stretch, sym_eig,
@@ -14,7 +14,7 @@ from .api import (ClusterIndices, CvaFit, SoftFit, SoftCVA, bands_to_cube, clust
 from ._lib import CvamxError, LIB_PATH
 
 __all__ = ["ClusterIndices", "CvaFit", "SoftFit", "SoftCVA", "bands_to_cube", "cluster_indices", "compose_rgb",
-           "cva_fit", "cva_fit_points", "cva_fit_project", "cva_project", "cva_project_noalloc",
+           "cva_fit", "cva_fit_points", "cva_fit_project", "cva_pca", "cva_project", "cva_project_noalloc",
            "cva_soft_backward", "cva_soft_forward", "cva_soft_update", "cva_solve_moments", "label_index",
            "pca_fit", "pca_project", "profile_enable", "profile_report", "project_float", "refine_weights",
            "run_pages", "set_plain_fp32", "set_schedule", "stream_mix", "stream_read", "stretch", "sym_eig",

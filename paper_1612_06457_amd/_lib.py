@@ -76,6 +76,8 @@ EXPORTS = {
     "cvamx_cluster_indices": (ctypes.c_int, [_vp, _vp, _i32, _i64, _i32, _vp, _vp, _i64, _i32, _f64,
                                              _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pca_fit": (ctypes.c_int, [_vp, ctypes.POINTER(Cube), _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "cvamx_cva_pca": (ctypes.c_int, [_vp, ctypes.POINTER(Cube), _vp, _i32, _i32, _f64, _i32, _vp, _vp, _vp, _vp,
+                                     _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "pca_project": (ctypes.c_int, [_vp, ctypes.POINTER(Cube), _vp, _vp, _i32, _vp, _vp, _vp]),
     "cva_soft_forward": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _f64,
                                         _vp, _vp, _vp, _vp, _vp, _vp]),

@@ -93,6 +93,60 @@ def cva_fit(cube: torch.Tensor, labels: torch.Tensor, K: int, precision: str = "
     return CvaFit(W, lam, mean, counts, cm, Sw, Sb)
 
 
+def _image_out(out, n, cube, name):
+    H, Wd = cube.shape[0], cube.shape[1]
+    if out is None:
+        return torch.empty((n, H, Wd), dtype=torch.uint8, device=cube.device)
+    if out.dtype != torch.uint8 or tuple(out.shape) != (n, H, Wd) or not out.is_contiguous() \
+            or out.device != cube.device:
+        raise ValueError(f"{name} must be a contiguous uint8 {n} x H x W tensor on the cube's device")
+    return out
+
+
+def cva_pca(cube: torch.Tensor, labels: torch.Tensor, K: int, mask: Optional[torch.Tensor] = None,
+            n_pca: int = 3, precision: str = "fp32", ridge: float = 0.0, n_cva: Optional[int] = None,
+            cva_out: Optional[torch.Tensor] = None, pca_out: Optional[torch.Tensor] = None,
+            standardize: bool = False):
+    """CVA and PCA of one page in one library call (cvamx_cva_pca): the same
+    results as cva_fit_project, pca_fit (standardize as there) and
+    pca_project, with each host finish overlapping GPU work.  Returns
+    (cva_images, fit, pca_images, (V, eigvals, mean)); fit as for
+    cva_fit_project."""
+    c = _cube(cube)
+    if labels.dtype != torch.int8 or tuple(labels.shape) != tuple(cube.shape[:2]):
+        raise ValueError("labels must be int8 with the page's H x W shape")
+    if labels.device != cube.device or not labels.is_contiguous():
+        raise ValueError("labels must be contiguous and on the cube's device")
+    if mask is not None:
+        if mask.dtype != torch.uint8 or tuple(mask.shape) != tuple(cube.shape[:2]):
+            raise ValueError("mask must be uint8 with the page's H x W shape")
+        if mask.device != cube.device or not mask.is_contiguous():
+            raise ValueError("mask must be contiguous and on the cube's device")
+    B = c.bands
+    n_cva = min(K - 1, B) if n_cva is None else int(n_cva)
+    n_pca = int(n_pca)
+    cva_out = _image_out(cva_out, n_cva, cube, "cva_out")
+    pca_out = _image_out(pca_out, n_pca, cube, "pca_out")
+    W = np.empty((B, n_cva))
+    lam = np.empty(n_cva)
+    mean = np.empty(B)
+    counts = np.empty(K, dtype=np.int64)
+    V = np.empty((B, n_pca))
+    plam = np.empty(n_pca)
+    pmean = np.empty(B)
+    dev = _dev_index(cube)
+    ctx = context(dev)
+    check(lib().cvamx_set_pca_standardize(ctx, 1 if standardize else 0), ctx)
+    try:
+        st = lib().cvamx_cva_pca(ctx, ctypes.byref(c), _ptr(labels), K, _lib.PREC[precision], float(ridge), n_cva,
+                                 _ptr(W), _ptr(lam), _ptr(mean), _ptr(counts), _ptr(cva_out), _ptr(mask), n_pca,
+                                 _ptr(V), _ptr(plam), _ptr(pmean), _ptr(pca_out), _stream(cube.device))
+    finally:
+        lib().cvamx_set_pca_standardize(ctx, 0)
+    check(st, ctx)
+    return cva_out, CvaFit(W, lam, mean, counts, None, None, None), pca_out, (V, plam, pmean)
+
+
 def cva_fit_points(cube: torch.Tensor, pixels: torch.Tensor, classes: torch.Tensor, K: int,
                    precision: str = "fp32", ridge: float = 0.0, n_comp: Optional[int] = None) -> CvaFit:
     """CVA fit on a list of training points: pixels (int64 N, y * W + x) and

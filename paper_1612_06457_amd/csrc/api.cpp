@@ -19,7 +19,8 @@
 
 namespace {
 
-enum Buf { B_TILECNT, B_IDX, B_PART, B_RES, B_PROJPART, B_FIRST, B_MCF, B_SPART, B_SHIST, B_SFIX, B_H16, B_COUNT };
+enum Buf { B_TILECNT, B_IDX, B_PART, B_RES, B_PROJPART, B_FIRST, B_MCF, B_SPART, B_SHIST, B_SFIX, B_H16,
+           B_PPART, B_PRES, B_COUNT };
 
 }  // namespace
 
@@ -34,8 +35,11 @@ struct cvamx_ctx {
   std::string err;
   void* buf[B_COUNT] = {};
   size_t cap[B_COUNT] = {};
-  void* pinned = nullptr;
+  void* pinned = nullptr;     // page-locked staging of small results
   size_t pinned_cap = 0;
+  void* pinned2 = nullptr;    // a second one, for the PCA half of cvamx_cva_pca
+  size_t pinned2_cap = 0;
+  hipEvent_t ev_fit = nullptr, ev_pca = nullptr;   // cvamx_cva_pca's two hand-over points
   unsigned* tickets = nullptr;   // [0] projection range
   float* range_dev = nullptr;    // 16 floats: scale[8], offset[8] of the current group
   float* ab_dev = nullptr;       // 2 * CVAMX_MAX_BANDS floats: (min, max) per component
@@ -87,18 +91,20 @@ int ensure(cvamx_ctx* ctx, Buf b, size_t bytes) {
   return 0;
 }
 
-int ensure_pinned(cvamx_ctx* ctx, size_t bytes) {
-  if (ctx->pinned_cap >= bytes && ctx->pinned) return 0;
-  if (ctx->pinned) {
-    (void)hipHostFree(ctx->pinned);
-    ctx->pinned = nullptr;
-    ctx->pinned_cap = 0;
+int ensure_pinned(cvamx_ctx* ctx, size_t bytes, int slot = 0) {
+  void*& pin = slot == 0 ? ctx->pinned : ctx->pinned2;
+  size_t& cap = slot == 0 ? ctx->pinned_cap : ctx->pinned2_cap;
+  if (cap >= bytes && pin) return 0;
+  if (pin) {
+    (void)hipHostFree(pin);
+    pin = nullptr;
+    cap = 0;
   }
   void* p = nullptr;
   if (hipHostMalloc(&p, std::max<size_t>(bytes, 4096), hipHostMallocDefault) != hipSuccess)
     return fail(ctx, CVAMX_E_NO_MEMORY, "hipHostMalloc of staging failed");
-  ctx->pinned = p;
-  ctx->pinned_cap = std::max<size_t>(bytes, 4096);
+  pin = p;
+  cap = std::max<size_t>(bytes, 4096);
   return 0;
 }
 
@@ -551,6 +557,9 @@ void cvamx_destroy(cvamx_ctx* ctx) {
       if (ctx->buf[b]) (void)hipFree(ctx->buf[b]);
     if (ctx->tickets) (void)hipFree(ctx->tickets);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->pinned2) (void)hipHostFree(ctx->pinned2);
+    if (ctx->ev_fit) (void)hipEventDestroy(ctx->ev_fit);
+    if (ctx->ev_pca) (void)hipEventDestroy(ctx->ev_pca);
     prof_collect(ctx);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   }
@@ -609,10 +618,10 @@ static int build_index(cvamx_ctx* ctx, const int8_t* labels, const int64_t* poin
   return 0;
 }
 
-// Class moments, reduction, the copy to the host and the FP64 finish.
-static int fit_from_index(cvamx_ctx* ctx, const cvamx_cube* cube, int32_t K, int32_t prec, double ridge, int32_t n_comp,
-                   double* W, double* eigvals, double* mean, int64_t* counts, double* class_means, double* Sw,
-                   double* Sb, const FitLayout& lay, char* res, int G, int L, hipStream_t s) {
+// Class moments and their reduction into the page-locked staging buffer
+// (with the results header: counts, offsets, flags, shifts).
+static int fit_moments_launch(cvamx_ctx* ctx, const cvamx_cube* cube, int32_t K, int32_t prec,
+                              const FitLayout& lay, char* res, int G, int L, hipStream_t s) {
   const int B = (int)cube->bands;
   const int64_t P = cube->height * cube->width;
   hipError_t e;
@@ -629,16 +638,20 @@ static int fit_from_index(cvamx_ctx* ctx, const cvamx_cube* cube, int32_t K, int
   }
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "class moments launch");
-  // the Gram reduction writes into page-locked memory and brings the
-  // results header (counts, offsets, flags, shifts) along
   prof_begin(ctx, s, "reduce_partials");
   char* h = static_cast<char*>(ctx->pinned);
   e = cvx::launch_reduce_part_out((const double*)ctx->buf[B_PART], K, G, L, (double*)(h + lay.gram), res, h,
                                   (int64_t)lay.gram, s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
-  HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+  return 0;
+}
 
+// The FP64 finish on the host, once the reduction has landed in staging.
+static int fit_host_finish(cvamx_ctx* ctx, int B, int32_t K, double ridge, int32_t n_comp, double* W,
+                           double* eigvals, double* mean, int64_t* counts, double* class_means, double* Sw,
+                           double* Sb, const FitLayout& lay, int L) {
+  const char* h = static_cast<const char*>(ctx->pinned);
   int32_t errflag;
   std::memcpy(&errflag, h + lay.err, 4);
   if (errflag & 1) return fail(ctx, CVAMX_E_INVALID_ARG, "a label lies outside -1..K-1");
@@ -672,6 +685,16 @@ static int fit_from_index(cvamx_ctx* ctx, const cvamx_cube* cube, int32_t K, int
   if (Sw) std::copy(Swv.begin(), Swv.end(), Sw);
   if (Sb) std::copy(Sbv.begin(), Sbv.end(), Sb);
   return CVAMX_OK;
+}
+
+// Class moments, reduction, the copy to the host and the FP64 finish.
+static int fit_from_index(cvamx_ctx* ctx, const cvamx_cube* cube, int32_t K, int32_t prec, double ridge, int32_t n_comp,
+                   double* W, double* eigvals, double* mean, int64_t* counts, double* class_means, double* Sw,
+                   double* Sb, const FitLayout& lay, char* res, int G, int L, hipStream_t s) {
+  if (int st = fit_moments_launch(ctx, cube, K, prec, lay, res, G, L, s)) return st;
+  HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+  return fit_host_finish(ctx, (int)cube->bands, K, ridge, n_comp, W, eigvals, mean, counts, class_means, Sw, Sb,
+                         lay, L);
 }
 
 static int fit_layout_and_buffers(cvamx_ctx* ctx, int K, int B, int& G, int& L, char*& res) {
@@ -716,6 +739,59 @@ int cva_fit_project(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels
                        nullptr, stream))
     return st;
   return project_common(ctx, cube, W, mean, n_comp, images, range, stream);
+}
+
+static int pca_launch(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t prec, Buf bpart,
+                      Buf bres, int slot, hipStream_t s);
+static int pca_host_finish(cvamx_ctx* ctx, int B, int32_t n_comp, int slot, double* V, double* eigvals,
+                           double* mean, double* cov);
+
+// CVA and PCA of one page in one call, scheduled so that each FP64 host
+// finish runs while the GPU works: the class moments, then the PCA Gram
+// (into buffers of its own) are queued; the CVA finish runs as the Gram
+// streams the page, and queues the CVA projection; the PCA finish runs as
+// that projection streams the page, and queues the PCA projection.  The
+// kernels and their order of arithmetic are those of the separate calls.
+int cvamx_cva_pca(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels, int32_t K, int32_t prec,
+                  double ridge, int32_t n_cva, double* W, double* eigvals, double* mean, int64_t* counts,
+                  uint8_t* cva_images, const uint8_t* mask, int32_t n_pca, double* V, double* pca_eigvals,
+                  double* pca_mean, uint8_t* pca_images, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (int st = check_fit_args(ctx, cube, K, prec, ridge, n_cva, W, eigvals, mean, counts)) return st;
+  if (!labels) return fail(ctx, CVAMX_E_INVALID_ARG, "labels is NULL");
+  if ((reinterpret_cast<uintptr_t>(labels) & 15u) != 0)
+    return fail(ctx, CVAMX_E_UNSUPPORTED, "labels must be 16-byte aligned");
+  const int B = (int)cube->bands;
+  if (n_pca < 1 || n_pca > B) return fail(ctx, CVAMX_E_INVALID_ARG, "n_pca must lie in 1..bands");
+  if (!V || !pca_eigvals || !pca_mean)
+    return fail(ctx, CVAMX_E_INVALID_ARG, "V, pca_eigvals and pca_mean must be non-NULL");
+  if (!cva_images || !pca_images) return fail(ctx, CVAMX_E_INVALID_ARG, "the image outputs must be non-NULL");
+  if (int st = check_device(ctx)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t P = cube->height * cube->width;
+  // the projection buffers of the larger group first: nothing is reallocated
+  // while queued kernels may still use it
+  const int64_t Pp = (P + 255) / 256 * 256;
+  if (int st = ensure(ctx, B_H16, (size_t)std::min(std::max(n_cva, n_pca), 8) * (size_t)Pp * 2)) return st;
+  if (int st = ensure(ctx, B_PROJPART, (size_t)proj_nblocks(ctx, cube) * 32 * sizeof(float))) return st;
+  if (!ctx->ev_fit) HIP_TRY(hipEventCreateWithFlags(&ctx->ev_fit, hipEventDisableTiming), "event create");
+  if (!ctx->ev_pca) HIP_TRY(hipEventCreateWithFlags(&ctx->ev_pca, hipEventDisableTiming), "event create");
+  int G, L;
+  char* res;
+  if (int st = fit_layout_and_buffers(ctx, K, B, G, L, res)) return st;
+  const FitLayout lay(K, B, L);
+  if (int st = build_index(ctx, labels, nullptr, P, P, K, lay, res, s)) return st;
+  if (int st = fit_moments_launch(ctx, cube, K, prec, lay, res, G, L, s)) return st;
+  HIP_TRY(hipEventRecord(ctx->ev_fit, s), "event record");
+  if (int st = pca_launch(ctx, cube, mask, prec, B_PPART, B_PRES, 1, s)) return st;
+  HIP_TRY(hipEventRecord(ctx->ev_pca, s), "event record");
+  HIP_TRY(hipEventSynchronize(ctx->ev_fit), "event synchronise");
+  if (int st = fit_host_finish(ctx, B, K, ridge, n_cva, W, eigvals, mean, counts, nullptr, nullptr, nullptr, lay, L))
+    return st;
+  if (int st = project_common(ctx, cube, W, mean, n_cva, cva_images, nullptr, stream)) return st;
+  HIP_TRY(hipEventSynchronize(ctx->ev_pca), "event synchronise");
+  if (int st = pca_host_finish(ctx, B, n_pca, 1, V, pca_eigvals, pca_mean, nullptr)) return st;
+  return project_common(ctx, cube, V, pca_mean, n_pca, pca_images, nullptr, stream);
 }
 
 int cva_fit_points(cvamx_ctx* ctx, const cvamx_cube* cube, const int64_t* pixels, const int8_t* classes,
@@ -1053,17 +1129,11 @@ int cvamx_cluster_indices(cvamx_ctx* ctx, const void* images, int32_t dtype, int
   return CVAMX_OK;
 }
 
-int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t n_comp, int32_t prec,
-            double* V, double* eigvals, double* mean, double* cov, void* stream) {
-  if (!ctx) return CVAMX_E_INVALID_ARG;
-  if (int st = check_cube(ctx, cube)) return st;
+// The PCA Gram and its reduction into page-locked staging slot `slot`
+// (the shift, then the packed Gram), in device buffers bpart and bres.
+static int pca_launch(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t prec, Buf bpart,
+                      Buf bres, int slot, hipStream_t s) {
   const int B = (int)cube->bands;
-  if (n_comp < 1 || n_comp > B) return fail(ctx, CVAMX_E_INVALID_ARG, "n_comp must lie in 1..bands");
-  if (prec < CVAMX_PREC_FP32 || prec > CVAMX_PREC_F16X3)
-    return fail(ctx, CVAMX_E_INVALID_ARG, "unknown precision");
-  if (!V || !eigvals || !mean) return fail(ctx, CVAMX_E_INVALID_ARG, "V, eigvals and mean must be non-NULL");
-  if (int st = check_device(ctx)) return st;
-  hipStream_t s = (hipStream_t)stream;
   const int64_t P = cube->height * cube->width;
   const int L = cvx::tri_blocks(B) * 16;
   const bool vector_path = prec == CVAMX_PREC_FP32 && (ctx->plain || !split_is_exact(cube->dtype));
@@ -1078,30 +1148,36 @@ int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t
   if (!vector_path && cube->dtype == CVAMX_U16)
     nblocks = (int)std::max<int64_t>(nblocks, (P + (int64_t(1) << 21) - 1) >> 21);
   const size_t res_bytes = 8 * (size_t)B + 8 * (size_t)L;
-  if (int st = ensure(ctx, B_PART, (size_t)nblocks * L * 8)) return st;
-  if (int st = ensure(ctx, B_RES, res_bytes)) return st;
-  if (int st = ensure_pinned(ctx, res_bytes)) return st;
-  char* res = static_cast<char*>(ctx->buf[B_RES]);
+  if (int st = ensure(ctx, bpart, (size_t)nblocks * L * 8)) return st;
+  if (int st = ensure(ctx, bres, res_bytes)) return st;
+  if (int st = ensure_pinned(ctx, res_bytes, slot)) return st;
+  char* res = static_cast<char*>(ctx->buf[bres]);
+  void* pin = slot == 0 ? ctx->pinned : ctx->pinned2;
   hipError_t e;
   if (vector_path) {
     prof_begin(ctx, s, "pca_gram");
-    e = cvx::launch_pca_gram(cube->dtype, cube->data, B, P, mask, nblocks, (double*)ctx->buf[B_PART],
+    e = cvx::launch_pca_gram(cube->dtype, cube->data, B, P, mask, nblocks, (double*)ctx->buf[bpart],
                              (double*)res, s);
   } else {
     prof_begin(ctx, s, "pca_gram_mfma");
     e = cvx::launch_pca_gram_mfma(cube->dtype, prec == CVAMX_PREC_F16X3 ? 1 : 0, cube->data, B, P, mask,
-                                  nblocks, (double*)ctx->buf[B_PART], (double*)res, s);
+                                  nblocks, (double*)ctx->buf[bpart], (double*)res, s);
   }
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "pca gram launch");
   prof_begin(ctx, s, "reduce_partials");
-  e = cvx::launch_reduce_part_out((const double*)ctx->buf[B_PART], 1, nblocks, L,
-                                  (double*)(static_cast<char*>(ctx->pinned) + 8 * B), res, ctx->pinned,
+  e = cvx::launch_reduce_part_out((const double*)ctx->buf[bpart], 1, nblocks, L,
+                                  (double*)(static_cast<char*>(pin) + 8 * B), res, pin,
                                   (int64_t)8 * B, s);
   prof_end(ctx, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
-  HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
-  const double* shift = static_cast<const double*>(ctx->pinned);
+  return 0;
+}
+
+// The covariance and its leading axes from staging slot `slot`.
+static int pca_host_finish(cvamx_ctx* ctx, int B, int32_t n_comp, int slot, double* V, double* eigvals,
+                           double* mean, double* cov) {
+  const double* shift = static_cast<const double*>(slot == 0 ? ctx->pinned : ctx->pinned2);
   std::vector<double> G1;
   unpack_gram(B, shift + B, G1);
   const int n1 = B + 1;
@@ -1135,6 +1211,22 @@ int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t
   std::copy(mu.begin(), mu.end(), mean);
   if (cov) std::copy(C.begin(), C.end(), cov);
   return CVAMX_OK;
+}
+
+int pca_fit(cvamx_ctx* ctx, const cvamx_cube* cube, const uint8_t* mask, int32_t n_comp, int32_t prec,
+            double* V, double* eigvals, double* mean, double* cov, void* stream) {
+  if (!ctx) return CVAMX_E_INVALID_ARG;
+  if (int st = check_cube(ctx, cube)) return st;
+  const int B = (int)cube->bands;
+  if (n_comp < 1 || n_comp > B) return fail(ctx, CVAMX_E_INVALID_ARG, "n_comp must lie in 1..bands");
+  if (prec < CVAMX_PREC_FP32 || prec > CVAMX_PREC_F16X3)
+    return fail(ctx, CVAMX_E_INVALID_ARG, "unknown precision");
+  if (!V || !eigvals || !mean) return fail(ctx, CVAMX_E_INVALID_ARG, "V, eigvals and mean must be non-NULL");
+  if (int st = check_device(ctx)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (int st = pca_launch(ctx, cube, mask, prec, B_PART, B_RES, 0, s)) return st;
+  HIP_TRY(hipStreamSynchronize(s), "stream synchronise");
+  return pca_host_finish(ctx, B, n_comp, 0, V, eigvals, mean, cov);
 }
 
 int cva_soft_forward(cvamx_ctx* ctx, const float* X, const float* w, int64_t N, int32_t B, int32_t K,

@@ -64,3 +64,13 @@ def test_projection_checks():
         cx.cva_fit_project(cube, lab, 3, out=torch.zeros((2, 4, 4), dtype=torch.uint8))
     with pytest.raises(ValueError, match="device"):
         cx.cva_fit_project(cube, lab, 3)
+    with pytest.raises(ValueError, match="labels must be int8"):
+        cx.cva_pca(cube, lab.to(torch.int16), 3)
+    with pytest.raises(ValueError, match="mask must be uint8"):
+        cx.cva_pca(cube, lab, 3, mask=torch.zeros((4, 5), dtype=torch.int8))
+    with pytest.raises(ValueError, match="cva_out must be"):
+        cx.cva_pca(cube, lab, 3, cva_out=torch.zeros((3, 4, 5), dtype=torch.uint8))
+    with pytest.raises(ValueError, match="pca_out must be"):
+        cx.cva_pca(cube, lab, 3, n_pca=2, pca_out=torch.zeros((3, 4, 5), dtype=torch.uint8))
+    with pytest.raises(ValueError, match="device"):
+        cx.cva_pca(cube, lab, 3)

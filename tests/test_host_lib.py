@@ -216,6 +216,22 @@ def test_argument_checks_without_a_device():
                                    None) == L.E_INVALID_ARG
         assert lib.cva_fit_project(ctx, ctypes.byref(good), lab, 3, 0, 0.0, 2, buf, buf, buf, i64, aligned, None,
                                    None) == L.E_DEVICE
+        # CVA and PCA in one call: the checks of both halves
+        def both(labels=lab, K=3, n_cva=2, cva_img=aligned, n_pca=3, V=buf, pca_img=aligned):
+            return lib.cvamx_cva_pca(ctx, ctypes.byref(good), labels, K, 0, 0.0, n_cva, buf, buf, buf, i64,
+                                     cva_img, None, n_pca, V, buf, buf, pca_img, None)
+        assert both(K=1) == L.E_INVALID_ARG
+        assert both(n_cva=3) == L.E_INVALID_ARG
+        assert both(labels=None) == L.E_INVALID_ARG
+        assert both(labels=ctypes.c_void_p(0x20004)) == L.E_UNSUPPORTED
+        assert both(n_pca=0) == L.E_INVALID_ARG
+        assert both(n_pca=9) == L.E_INVALID_ARG
+        assert both(V=None) == L.E_INVALID_ARG
+        assert both(cva_img=None) == L.E_INVALID_ARG
+        assert both(pca_img=None) == L.E_INVALID_ARG
+        assert both() == L.E_DEVICE
+        assert lib.cvamx_cva_pca(None, ctypes.byref(good), lab, 3, 0, 0.0, 2, buf, buf, buf, i64, aligned, None, 3,
+                                 buf, buf, buf, aligned, None) == L.E_INVALID_ARG
         # pca
         assert lib.pca_fit(ctx, ctypes.byref(good), None, 9, 0, buf, buf, buf, None, None) == L.E_INVALID_ARG
         assert lib.pca_fit(ctx, ctypes.byref(good), None, 3, 0, buf, buf, buf, None, None) == L.E_DEVICE
