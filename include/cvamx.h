@@ -247,7 +247,8 @@ int pca_project(cvamx_ctx* ctx, const cvamx_cube* cube, const double* V,
  *            n_pca; pca_images device n_pca x height x width uint8
  * The host outputs are set when the call returns; both projections are
  * asynchronous on `stream`.  Honours cvamx_set_pca_standardize.  Errors as
- * for the separate calls; after an error the queued work still runs. */
+ * for the separate calls; a call that fails after queuing work returns once
+ * `stream` has drained. */
 int cvamx_cva_pca(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels,
                   int32_t K, int32_t prec, double ridge, int32_t n_cva,
                   double* W, double* eigvals, double* mean, int64_t* counts,

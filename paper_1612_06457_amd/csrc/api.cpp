@@ -780,18 +780,25 @@ int cvamx_cva_pca(cvamx_ctx* ctx, const cvamx_cube* cube, const int8_t* labels, 
   char* res;
   if (int st = fit_layout_and_buffers(ctx, K, B, G, L, res)) return st;
   const FitLayout lay(K, B, L);
-  if (int st = build_index(ctx, labels, nullptr, P, P, K, lay, res, s)) return st;
-  if (int st = fit_moments_launch(ctx, cube, K, prec, lay, res, G, L, s)) return st;
-  HIP_TRY(hipEventRecord(ctx->ev_fit, s), "event record");
-  if (int st = pca_launch(ctx, cube, mask, prec, B_PPART, B_PRES, 1, s)) return st;
-  HIP_TRY(hipEventRecord(ctx->ev_pca, s), "event record");
-  HIP_TRY(hipEventSynchronize(ctx->ev_fit), "event synchronise");
-  if (int st = fit_host_finish(ctx, B, K, ridge, n_cva, W, eigvals, mean, counts, nullptr, nullptr, nullptr, lay, L))
+  // once work is queued, an error returns only after the stream has
+  // drained, so that no queued kernel outlives the caller's buffers
+  auto drained = [&](int st) {
+    (void)hipStreamSynchronize(s);
     return st;
-  if (int st = project_common(ctx, cube, W, mean, n_cva, cva_images, nullptr, stream)) return st;
-  HIP_TRY(hipEventSynchronize(ctx->ev_pca), "event synchronise");
-  if (int st = pca_host_finish(ctx, B, n_pca, 1, V, pca_eigvals, pca_mean, nullptr)) return st;
-  return project_common(ctx, cube, V, pca_mean, n_pca, pca_images, nullptr, stream);
+  };
+  if (int st = build_index(ctx, labels, nullptr, P, P, K, lay, res, s)) return drained(st);
+  if (int st = fit_moments_launch(ctx, cube, K, prec, lay, res, G, L, s)) return drained(st);
+  if (hipError_t e = hipEventRecord(ctx->ev_fit, s)) return drained(hip_fail(ctx, e, "event record"));
+  if (int st = pca_launch(ctx, cube, mask, prec, B_PPART, B_PRES, 1, s)) return drained(st);
+  if (hipError_t e = hipEventRecord(ctx->ev_pca, s)) return drained(hip_fail(ctx, e, "event record"));
+  if (hipError_t e = hipEventSynchronize(ctx->ev_fit)) return drained(hip_fail(ctx, e, "event synchronise"));
+  if (int st = fit_host_finish(ctx, B, K, ridge, n_cva, W, eigvals, mean, counts, nullptr, nullptr, nullptr, lay, L))
+    return drained(st);
+  if (int st = project_common(ctx, cube, W, mean, n_cva, cva_images, nullptr, stream)) return drained(st);
+  if (hipError_t e = hipEventSynchronize(ctx->ev_pca)) return drained(hip_fail(ctx, e, "event synchronise"));
+  if (int st = pca_host_finish(ctx, B, n_pca, 1, V, pca_eigvals, pca_mean, nullptr)) return drained(st);
+  if (int st = project_common(ctx, cube, V, pca_mean, n_pca, pca_images, nullptr, stream)) return drained(st);
+  return CVAMX_OK;
 }
 
 int cva_fit_points(cvamx_ctx* ctx, const cvamx_cube* cube, const int64_t* pixels, const int8_t* classes,
