@@ -24,6 +24,8 @@
 
 namespace cvx {
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+
 namespace {
 
 // Chunks ch = first, first + stride, ... of X and w, staged raw in LDS
@@ -686,11 +688,10 @@ __global__ __launch_bounds__(kBlock) void k_soft_backward(const float* __restric
   extern __shared__ __align__(16) uint32_t lds[];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int S = B;                         // a lane group is one row of B dwords
-  uint32_t* my = lds + w * 64 * S;
+  uint32_t* my = lds + w * 64 * (B > K ? B : K);   // a slice fits the tile and its gradients
   const int64_t nt = (N + 63) / 64;
   const unsigned char* base = reinterpret_cast<const unsigned char*>(X);
   for_each_tile<kMaxQ, false>(base, N * B * 4, nt, S, my, [&](int64_t t) {
-    const int64_t row = t * 64 + lane;
     float z[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) z[j] = 0.f;
@@ -700,22 +701,35 @@ __global__ __launch_bounds__(kBlock) void k_soft_backward(const float* __restric
 #pragma unroll
       for (int j = 0; j < 8; ++j) z[j] = fmaf(a.w[b * 8 + j], u, z[j]);
     }
-    if (row < N) {
-      float tz = 0.f;
+    // the tile's 64 x K gradients go through the wave's LDS slice (its rows
+    // have been read) and leave as 16-byte stores of the contiguous block
+    float* gs = reinterpret_cast<float*>(my);
+    float tz = 0.f;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) tz = fmaf(z[j], z[j], tz);
-      for (int c = 0; c < K; ++c) {
-        float q = 0.f;
+    for (int j = 0; j < 8; ++j) tz = fmaf(z[j], z[j], tz);
+    for (int c = 0; c < K; ++c) {
+      float q = 0.f;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const float e = z[j] - a.d[c * 8 + j];
-          q = fmaf(a.lam1[j] * e, e, q);
-        }
-        const float g = a.scale * (tz - q);
-        float* o = dw + row * K + c;
-        *o = accumulate ? (*o + g) : g;
+      for (int j = 0; j < 8; ++j) {
+        const float e = z[j] - a.d[c * 8 + j];
+        q = fmaf(a.lam1[j] * e, e, q);
+      }
+      gs[lane * K + c] = a.scale * (tz - q);
+    }
+    wave_lds_sync();
+    const int64_t r0 = t * 64;
+    const int nv = (int)((N - r0 < 64 ? N - r0 : 64) * K);   // values of the tile inside dw
+    float* out = dw + r0 * K;
+    for (int i = 4 * lane; i < nv; i += 4 * 64) {
+      if (i + 4 <= nv) {
+        f4v v = *reinterpret_cast<const f4v*>(gs + i);
+        if (accumulate) v += *reinterpret_cast<const f4v*>(out + i);
+        *reinterpret_cast<f4v*>(out + i) = v;
+      } else {
+        for (int e = i; e < nv; ++e) out[e] = accumulate ? out[e] + gs[e] : gs[e];
       }
     }
+    wave_lds_sync();
   });
 }
 
@@ -931,7 +945,8 @@ hipError_t launch_soft_update(const float* g, float* w, int64_t N, int K, float 
 
 hipError_t launch_soft_backward(const float* X, int64_t N, int B, int K, const SoftBwdArgs& a,
                                 bool accumulate, int nblocks, float* dw, hipStream_t s) {
-  const size_t sm = (size_t)kWaves * 64 * B * 4;
+  // each wave's slice holds its 64-row tile of X, then the tile's gradients
+  const size_t sm = (size_t)kWaves * 64 * std::max(B, K) * 4;
   hipLaunchKernelGGL(k_soft_backward, dim3(nblocks), dim3(kBlock), sm, s, X, N, B, K, a,
                      accumulate ? 1 : 0, dw);
   return hipGetLastError();

@@ -424,7 +424,8 @@ def test_soft_label_autograd(dev):
     (1000, 23, 5, 1.0, 1.0, False), (100, 7, 3, 1.0, 1.0, False), (5000, 64, 32, 1.0, 1.0, False),
     (3000, 1, 2, 1.0, 1.0, False), (4000, 33, 8, 1e5, 1e3, False), (4000, 33, 8, 1e-4, 1e-3, False),
     (6000, 16, 4, 1.0, 1.0, True), (2000, 17, 3, 1.0, 1.0, False), (3000, 32, 6, 1.0, 1.0, True),
-    (2500, 48, 5, 1.0, 1.0, False), (2500, 49, 9, 1.0, 1.0, False), (4000, 33, 12, 1.0, 1.0, True)])
+    (2500, 48, 5, 1.0, 1.0, False), (2500, 49, 9, 1.0, 1.0, False), (4000, 33, 12, 1.0, 1.0, True),
+    (1001, 7, 3, 1.0, 1.0, False), (4003, 33, 11, 1.0, 1.0, False)])
 def test_soft_label_shapes_and_scales(dev, N, B, K, xs, ws, neg):
     """Ragged and short row counts, every row-block count, the band counts
     whose one or two trailing columns run on the vector ALU (16, 17, 32, 33,
@@ -432,7 +433,8 @@ def test_soft_label_shapes_and_scales(dev, N, B, K, xs, ws, neg):
     fp16 range either way, and weights of both signs: J, eigenvalues, class
     means, W^T S_w W = I against the oracle's S_w, and the whole gradient
     against the oracle's closed form, including C = 11 and C = 31, whose
-    backward runs as two and four accumulating launches."""
+    backward runs as two and four accumulating launches; and last tiles whose
+    gradients end inside a 16-byte store (1001 x 3, 4003 x 11)."""
     say(f"soft-label N={N} B={B} K={K} x*{xs} w*{ws} neg={neg}")
     import paper_1612_06457_amd as cx
     rng = np.random.default_rng(N + B + K)
