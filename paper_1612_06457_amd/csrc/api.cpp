@@ -590,9 +590,10 @@ static int check_fit_args(cvamx_ctx* ctx, const cvamx_cube* cube, int32_t K, int
 static int build_index(cvamx_ctx* ctx, const int8_t* labels, const int64_t* points, int64_t n, int64_t P, int K,
                 const FitLayout& lay, char* res, hipStream_t s) {
   const int nW = (int)((n + cvx::kLabelWave - 1) / cvx::kLabelWave);
-  if (int st = ensure(ctx, B_TILECNT, ((size_t)nW + 1) * (K + 1) * 4)) return st;
+  const size_t ld = (size_t)cvx::label_row_stride(nW);
+  if (int st = ensure(ctx, B_TILECNT, (ld * (K + 1) + K + 1) * 4)) return st;
   int32_t* wave_counts = (int32_t*)ctx->buf[B_TILECNT];
-  int32_t* class_total = wave_counts + (size_t)nW * (K + 1);
+  int32_t* class_total = wave_counts + ld * (K + 1);
   if (int st = ensure(ctx, B_IDX, (size_t)n * 4)) return st;
   hipError_t e;
   prof_begin(ctx, s, "label_count");

@@ -10,7 +10,8 @@
 // path.  Small tiles give many waves, which is what these latency-bound
 // passes need (the training pixels are a few percent of the page, scattered
 // over it, so every step holds several classes).
-//   k_label_count: class counts per wave tile, class-major (K x nW), with
+//   k_label_count: class counts per wave tile, class-major (K rows of nW,
+//                  each row padded to a multiple of four entries), with
 //                  LDS counters private to the wave, and a row of flags
 //                  for entries outside -1..K-1;
 //   k_label_scan:  one block per class turns its row of counts into
@@ -173,17 +174,19 @@ __global__ __launch_bounds__(kBlock) void k_label_count(const int8_t* __restrict
     }
   });
   wave_lds_sync();
-  for (int k = lane; k < K; k += 64) wave_counts[(int64_t)k * nW + wv] = my[k];
+  const int64_t ld = label_row_stride(nW);
+  for (int k = lane; k < K; k += 64) wave_counts[(int64_t)k * ld + wv] = my[k];
   const bool any_bad = __ballot(bad) != 0;
-  if (lane == 0) wave_counts[(int64_t)K * nW + wv] = any_bad ? 1 : 0;
+  if (lane == 0) wave_counts[(int64_t)K * ld + wv] = any_bad ? 1 : 0;
 }
 
 // Block k < K: row k of the counts becomes exclusive offsets within the
 // class (in place), and class_total[k] its sum.  Block K sums the row of
 // flags the same way and sets the error flag from it.  Chunks of kScanThreads x
-// kPer entries (one chunk covers a page of 67 M entries): each thread loads
-// kPer consecutive ones, all in flight together, and the block scans the
-// thread sums.
+// kPer entries (one chunk covers a page of 67 M entries): each thread moves
+// its kPer consecutive entries with 16-byte loads and stores (the rows are
+// padded to a multiple of four entries), all in flight together, and the
+// block scans the thread sums.  Entries past nW read as zero.
 constexpr int kPer = 16;
 constexpr int kScanThreads = 1024;
 constexpr int kScanWaves = kScanThreads / 64;
@@ -192,13 +195,19 @@ __global__ __launch_bounds__(kScanThreads) void k_label_scan(int32_t* __restrict
                                                              int32_t* __restrict__ err) {
   __shared__ int wsum[kScanWaves];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int32_t* row = wave_counts + (int64_t)blockIdx.x * nW;
+  const int ld = (int)label_row_stride(nW);
+  int32_t* row = wave_counts + (int64_t)blockIdx.x * ld;
   int carry = 0;
   for (int c0 = 0; c0 < nW; c0 += kScanThreads * kPer) {
     const int j0 = c0 + (int)threadIdx.x * kPer;
     int v[kPer];
 #pragma unroll
-    for (int e = 0; e < kPer; ++e) v[e] = (j0 + e < nW) ? row[j0 + e] : 0;
+    for (int q = 0; q < kPer / 4; ++q) {
+      const int j = j0 + 4 * q;
+      const u32x4 x = j < ld ? *reinterpret_cast<const u32x4*>(row + j) : u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[4 * q + e] = (j + e < nW) ? (int)x[e] : 0;
+    }
     int sum = 0;
 #pragma unroll
     for (int e = 0; e < kPer; ++e) sum += v[e];
@@ -214,9 +223,15 @@ __global__ __launch_bounds__(kScanThreads) void k_label_scan(int32_t* __restrict
     __syncthreads();
     int run = base + inc - sum;
 #pragma unroll
-    for (int e = 0; e < kPer; ++e) {
-      if (j0 + e < nW) row[j0 + e] = run;
-      run += v[e];
+    for (int q = 0; q < kPer / 4; ++q) {
+      const int j = j0 + 4 * q;
+      u32x4 o;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        o[e] = (uint32_t)run;
+        run += v[4 * q + e];
+      }
+      if (j < ld) *reinterpret_cast<u32x4*>(row + j) = o;   // the padding takes values no one reads
     }
     carry += tot;
   }
@@ -276,8 +291,9 @@ __global__ __launch_bounds__(kBlock) void k_label_index(const int8_t* __restrict
   }
   if (wv >= nW) return;
   LaneClasses at;
-  at.lo = lane < K ? base_lo + wave_off[(int64_t)lane * nW + wv] : 0;
-  at.hi = 64 + lane < K ? base_hi + wave_off[(int64_t)(64 + lane) * nW + wv] : 0;
+  const int64_t ld = label_row_stride(nW);
+  at.lo = lane < K ? base_lo + wave_off[(int64_t)lane * ld + wv] : 0;
+  at.hi = 64 + lane < K ? base_hi + wave_off[(int64_t)(64 + lane) * ld + wv] : 0;
   uint32_t* list = lists[w];
   const int64_t s0 = (int64_t)wv * kLabelWave;
   const int64_t s1 = (s0 + kLabelWave < P) ? s0 + kLabelWave : P;

@@ -40,12 +40,14 @@ struct SoftBwdArgs {
 
 // label bookkeeping
 // label bookkeeping over nW = ceil(P / kLabelWave) wave tiles:
-// wave_counts is (K + 1) x nW (class-major; row K: a flag per wave tile for
-// entries outside -1..K-1); the count kernel writes the counts and flags,
+// wave_counts is K + 1 rows of nW entries, each row label_row_stride(nW)
+// entries apart (class-major; row K: a flag per wave tile for entries
+// outside -1..K-1); the count kernel writes the counts and flags,
 // the scan kernel turns each class row into exclusive offsets within the
 // class (in place), writes the K class totals and sets err_flag[0] to 1 or
 // 0 (err_flag[1] to 0), the index kernel writes the class-grouped list and
 // the counts and offsets
+__host__ __device__ inline int64_t label_row_stride(int nW) { return ((int64_t)nW + 3) & ~int64_t(3); }
 hipError_t launch_label_count(const int8_t* labels, int64_t P, int K, int nW, int32_t* wave_counts,
                               hipStream_t s);
 hipError_t launch_label_scan(int32_t* wave_counts, int nW, int K, int32_t* class_total, int32_t* err_flag,
