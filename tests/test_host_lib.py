@@ -72,8 +72,9 @@ def _check_top(A, k, w, V, tol_r=1e-11):
 def test_sym_eig_top_matches_lapack():
     """The leading eigenpairs: random symmetric matrices, covariance-like
     spectra over eight decades, an exactly threefold eigenvalue, a pair
-    1e-9 apart, a diagonal matrix, a block-diagonal matrix (the tridiagonal
-    form splits) and the zero matrix."""
+    1e-9 apart, diagonal matrices (one with a threefold entry), a
+    block-diagonal matrix (the tridiagonal form splits), a multiple of the
+    identity, the all-ones matrix and the zero matrix."""
     _lib()
     from paper_1612_06457_amd import sym_eig_top
     rng = np.random.default_rng(1)
@@ -96,7 +97,8 @@ def test_sym_eig_top_matches_lapack():
     B2 = np.zeros((33, 33))
     B2[:16, :16] = D[:16, :16] + 0.1
     B2[16:, 16:] = D[16:, 16:] - 0.2
-    for A in (D, B2, np.zeros((33, 33))):
+    for A in (D, B2, np.zeros((33, 33)), 7.0 * np.eye(33), np.ones((33, 33)),
+              np.diag([3.0, 3.0, 3.0] + [1.0] * 30)):
         w, V = sym_eig_top(A, 3)
         if np.abs(A).max() == 0:
             assert np.all(w == 0) and np.allclose(V.T @ V, np.eye(3))
